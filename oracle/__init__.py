@@ -1,0 +1,261 @@
+"""FP64 CPU oracle for the block-cave muon-tomography posterior (arXiv 2603.28907).
+
+TEST INFRASTRUCTURE ONLY.  Imported by `tests/`, by the smoke check in
+`__graft_entry__.py` and by the CPU-baseline leg of `bench.py`; the product
+path (`paper_2603_28907_amd`) never imports it.  The numerics live in
+`muon_oracle.c` (plain C, FP64), compiled with gcc by `build()`; this module
+only marshals numpy arrays into it.  It shares no code with the HIP path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "muon_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libmuon_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP over chains)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(ct.Structure):
+    _fields_ = [("S", ct.c_int), ("R", ct.c_int), ("C", ct.c_int),
+                ("X", ct.c_double), ("Y", ct.c_double),
+                ("density", ct.c_void_p), ("top", ct.c_void_p), ("car_r", ct.c_void_p),
+                ("n_s", ct.c_int), ("n_pix", ct.c_int),
+                ("pos", ct.c_void_p), ("dirs", ct.c_void_p), ("exposure", ct.c_void_p),
+                ("atten", ct.c_double), ("counts", ct.c_void_p)]
+
+
+class _Stats(ct.Structure):
+    _fields_ = [("cells", ct.c_double), ("tests", ct.c_double), ("roots", ct.c_double),
+                ("crossings", ct.c_double), ("min_fprime", ct.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ct.CDLL(_LIB_PATH)
+    P, D, V, I, I64 = ct.POINTER(_Problem), ct.c_double, ct.c_void_p, ct.c_int, ct.c_int64
+    U64, U32 = ct.c_uint64, ct.c_uint32
+    sig = {
+        "orc_opacity": (None, [P, V, V, V, ct.POINTER(_Stats)]),
+        "orc_loglik": (D, [P, V]),
+        "orc_log_prior": (D, [P, V]),
+        "orc_log_prior_grad": (D, [P, V, V]),
+        "orc_logpost": (D, [P, V]),
+        "orc_logpost_batch": (None, [P, I, V, V]),
+        "orc_grad": (D, [P, V, V]),
+        "orc_grad_batch": (None, [P, I, V, V, V]),
+        "orc_ndtri_lower": (D, [D]),
+        "orc_car_consts": (None, [I, I, D, V, V]),
+        "orc_philox4x32_10": (None, [V, V, V]),
+        "orc_uniform_pair": (None, [U64, U32, U64, U32, U32, V]),
+        "orc_normal_pair": (None, [U64, U32, U64, U32, U32, V]),
+        "orc_raw_philox": (None, [U64, U32, U64, U32, U32, V]),
+        "orc_mcmc_rw": (None, [P, I, V, V, V, I64, U64, D, U64, I, V]),
+        "orc_mcmc_mala": (None, [P, I, V, V, V, I64, U64, D, V, U64, I, V]),
+        "orc_march_one": (D, [P, V, V, V, V, ct.POINTER(_Stats)]),
+        "orc_ray_stats": (None, [P, V, V, V, V]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleProblem:
+    """One problem (geometry + sensors + counts) bound to the C oracle.
+
+    Accepts any object with the attributes of `paper_2603_28907_amd.inputs.Scenario`.
+    """
+
+    def __init__(self, sc, counts: Optional[np.ndarray] = None, density=None, car_r=None,
+                 atten_len: Optional[float] = None):
+        self.lib = _load()
+        self.S, self.R, self.C = int(sc.n_surfaces), int(sc.n_rows), int(sc.n_cols)
+        self._density = _f64(sc.density if density is None else density)
+        self._top = _f64(sc.top)
+        self._car_r = _f64(sc.car_r if car_r is None else car_r)
+        self._pos = _f64(sc.sensor_pos).reshape(-1, 3)
+        n_s = self._pos.shape[0]
+        self._dirs = _f64(sc.dirs).reshape(n_s, -1, 3) if n_s else np.zeros((0, 0, 3))
+        n_pix = self._dirs.shape[1] if n_s else 0
+        self._exp = _f64(sc.exposure).reshape(n_s, n_pix) if n_s else np.zeros((0, 0))
+        c = counts if counts is not None else sc.counts
+        self._counts = (np.ascontiguousarray(c, dtype=np.int32).reshape(n_s, n_pix)
+                        if c is not None else np.zeros((n_s, n_pix), np.int32))
+        self.n_rays = n_s * n_pix
+        self.prob = _Problem(self.S, self.R, self.C, float(sc.extent_x), float(sc.extent_y),
+                             _p(self._density), _p(self._top), _p(self._car_r), n_s, n_pix,
+                             _p(self._pos), _p(self._dirs), _p(self._exp),
+                             float(sc.atten_len if atten_len is None else atten_len),
+                             _p(self._counts))
+        self.M = (self.S - 1) * self.R * self.C
+
+    def _free(self, free) -> np.ndarray:
+        f = _f64(free)
+        assert f.size == self.M, (f.shape, self.M)
+        return f
+
+    def opacity(self, free, with_lengths: bool = False, with_stats: bool = False):
+        f = self._free(free)
+        O = np.empty(self.n_rays)
+        L = np.empty((self.n_rays, self.S)) if with_lengths else None
+        st = _Stats()
+        self.lib.orc_opacity(ct.byref(self.prob), _p(f), _p(O), _p(L), ct.byref(st))
+        out = [O]
+        if with_lengths:
+            out.append(L)
+        if with_stats:
+            out.append(dict(cells=st.cells, tests=st.tests, roots=st.roots,
+                            crossings=st.crossings, min_fprime=st.min_fprime))
+        return out[0] if len(out) == 1 else tuple(out)
+
+    def expected_counts(self, free) -> np.ndarray:
+        O = self.opacity(free)
+        return self._exp.reshape(-1) * np.exp(-O / self.prob.atten)
+
+    def loglik(self, O) -> float:
+        O = _f64(O)
+        return float(self.lib.orc_loglik(ct.byref(self.prob), _p(O)))
+
+    def log_prior(self, free) -> float:
+        return float(self.lib.orc_log_prior(ct.byref(self.prob), _p(self._free(free))))
+
+    def log_prior_grad(self, free):
+        g = np.zeros((self.S, self.R, self.C))
+        v = self.lib.orc_log_prior_grad(ct.byref(self.prob), _p(self._free(free)), _p(g))
+        return float(v), g
+
+    def logpost(self, free) -> float:
+        return float(self.lib.orc_logpost(ct.byref(self.prob), _p(self._free(free))))
+
+    def logpost_batch(self, states) -> np.ndarray:
+        s = _f64(states)
+        n = s.size // self.M
+        lp = np.empty(n)
+        self.lib.orc_logpost_batch(ct.byref(self.prob), n, _p(s), _p(lp))
+        return lp
+
+    def grad(self, free):
+        g = np.empty((self.S, self.R, self.C))
+        lp = self.lib.orc_grad(ct.byref(self.prob), _p(self._free(free)), _p(g))
+        return float(lp), g
+
+    def grad_batch(self, states):
+        s = _f64(states)
+        n = s.size // self.M
+        lp = np.empty(n)
+        g = np.empty((n, self.S, self.R, self.C))
+        self.lib.orc_grad_batch(ct.byref(self.prob), n, _p(s), _p(lp), _p(g))
+        return lp, g
+
+    def march_one(self, free, q, d):
+        L = np.empty(self.S)
+        st = _Stats()
+        O = self.lib.orc_march_one(ct.byref(self.prob), _p(self._free(free)), _p(_f64(q)),
+                                   _p(_f64(d)), _p(L), ct.byref(st))
+        return float(O), L, dict(cells=st.cells, tests=st.tests, roots=st.roots,
+                                 crossings=st.crossings, min_fprime=st.min_fprime)
+
+    def ray_stats(self, free):
+        cr, mf, ce = np.empty(self.n_rays), np.empty(self.n_rays), np.empty(self.n_rays)
+        self.lib.orc_ray_stats(ct.byref(self.prob), _p(self._free(free)), _p(cr), _p(mf), _p(ce))
+        return dict(crossings=cr, min_fprime=mf, cells=ce)
+
+    def mcmc_rw(self, states, lp, n_accept, n_steps, step_offset, sigma, seed,
+                state_f32=False, want_margins=False):
+        """Runs in place on float64 copies; returns (states, lp, n_accept, margins)."""
+        s = _f64(states).copy()
+        n = s.size // self.M
+        lpa = _f64(lp).copy()
+        acc = np.ascontiguousarray(n_accept, dtype=np.int64).copy()
+        marg = np.empty((n, n_steps)) if want_margins else None
+        self.lib.orc_mcmc_rw(ct.byref(self.prob), n, _p(s), _p(lpa), _p(acc), int(n_steps),
+                             int(step_offset), float(sigma), int(seed), int(bool(state_f32)), _p(marg))
+        return s.reshape(np.shape(states)), lpa, acc, marg
+
+    def mcmc_mala(self, states, lp, n_accept, n_steps, step_offset, eps, seed, inv_mass=None,
+                  state_f32=False, want_margins=False):
+        s = _f64(states).copy()
+        n = s.size // self.M
+        lpa = _f64(lp).copy()
+        acc = np.ascontiguousarray(n_accept, dtype=np.int64).copy()
+        marg = np.empty((n, n_steps)) if want_margins else None
+        im = None if inv_mass is None else _f64(inv_mass)
+        self.lib.orc_mcmc_mala(ct.byref(self.prob), n, _p(s), _p(lpa), _p(acc), int(n_steps),
+                               int(step_offset), float(eps), _p(im), int(seed),
+                               int(bool(state_f32)), _p(marg))
+        return s.reshape(np.shape(states)), lpa, acc, marg
+
+
+def ndtri_lower(u: float) -> float:
+    return float(_load().orc_ndtri_lower(float(u)))
+
+
+def car_consts(R: int, C: int, r: float):
+    a, b = ct.c_double(), ct.c_double()
+    _load().orc_car_consts(int(R), int(C), float(r), ct.byref(a), ct.byref(b))
+    return a.value, b.value
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    _load().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def raw_philox(seed, chain, step, tag, j) -> np.ndarray:
+    out = np.empty(4, np.uint32)
+    _load().orc_raw_philox(int(seed), int(chain), int(step), int(tag), int(j), _p(out))
+    return out
+
+
+def uniform_pair(seed, chain, step, tag, j) -> np.ndarray:
+    out = np.empty(2)
+    _load().orc_uniform_pair(int(seed), int(chain), int(step), int(tag), int(j), _p(out))
+    return out
+
+
+def normal_pair(seed, chain, step, tag, j) -> np.ndarray:
+    out = np.empty(2)
+    _load().orc_normal_pair(int(seed), int(chain), int(step), int(tag), int(j), _p(out))
+    return out
+
+
+def make_counts(sc, seed: int, mode: str = "poisson") -> np.ndarray:
+    """Observed counts for a scenario: expected counts of the true surfaces from
+    the oracle's forward model, then a seeded draw (inputs.draw_counts)."""
+    from paper_2603_28907_amd.inputs import draw_counts
+    lam = OracleProblem(sc).expected_counts(sc.truth)
+    return draw_counts(lam, seed, mode).reshape(sc.n_sensors, sc.n_pix)

@@ -1,0 +1,659 @@
+/*
+ * muon_oracle.c -- plain FP64 CPU oracle for the block-cave muon-tomography
+ * posterior (arXiv 2603.28907).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled and called by the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg.  The product
+ * (HIP) path never links, loads or calls it, and it shares no code with it.
+ *
+ * Everything here is written for clarity over speed: one ray at a time, one
+ * cell at a time, FP64 throughout.  Each function names the passage of the
+ * paper it follows.
+ *
+ * Readings of the paper taken here (each is listed in the design doc):
+ *  - Geometry: vertex-centred nodes x_i = i*X/(R-1), y_j = j*Y/(C-1); row i
+ *    runs along x, column j along y, H[l][i][j] in C order (Sec. 2.1.1, the
+ *    array-indexing figure).  Surfaces are bilinear inside each cell.
+ *  - Density: unit l lies between surface l-1 and l (surface 0 = floor z=0)
+ *    with density rho[l-1]; zero above the top surface and outside the box
+ *    [0,X]x[0,Y]x[0,Z_top], Z_top = max of the top surface (the continuum
+ *    form of the layer density eq. def_LM_density_grid with the Heaviside
+ *    indicator).
+ *  - Opacity: O = int rho du along the ray (Sec. 2.1.1) evaluated exactly:
+ *    O = sum_l (rho_l - rho_{l+1}) * L_l, where L_l is the length of ray
+ *    inside the box lying below surface l.
+ *  - Expected counts: lambda_p = E_p * exp(-O_p / Lambda), one ray per pixel
+ *    (eq. expected_counts with the intensity replaced by an exponential
+ *    attenuation and the solid-angle integral by its midpoint value).
+ *  - Likelihood: independent Poisson counts (eq. def_likelihood), normalised
+ *    (the -lgamma(C+1) term is kept).
+ *  - Prior: Gaussian copula over a periodic proper CAR field per free
+ *    surface (Sec. 2.2.1): H_l = (1-u) H_{l-1} + u H_top, u = Phi(x/sqrt(S11)),
+ *    x ~ N(0, Q^-1), Q = diag(A1) - r A on the periodic 4-neighbour grid.
+ *    Its density in H-space is written out by change of variables.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    int S, R, C;              /* surfaces incl. the fixed top; node grid rows x cols */
+    double X, Y;              /* footprint extents (m) */
+    const double *density;    /* [S]   density of unit l = 1..S (g/cm^3) */
+    const double *top;        /* [R*C] fixed top surface (m) */
+    const double *car_r;      /* [S-1] CAR dependence per free surface */
+    int n_s, n_pix;           /* sensors, pixels per sensor */
+    const double *pos;        /* [n_s*3] */
+    const double *dirs;       /* [n_s*n_pix*3] unit vectors, d_z > 0 */
+    const double *exposure;   /* [n_s*n_pix] */
+    double atten;             /* Lambda, in the opacity unit (g/cm^3 * m) */
+    const int32_t *counts;    /* [n_s*n_pix] observed counts (may be NULL) */
+} orc_problem;
+
+typedef struct {
+    double cells;       /* cells visited with positive length */
+    double tests;       /* (cell, surface) pairs examined */
+    double roots;       /* quadratic roots found strictly inside a cell interval */
+    double crossings;   /* sign changes of z - h along the ray */
+    double min_fprime;  /* smallest |d(z-h)/dt| at a crossing (conditioning) */
+} orc_stats;
+
+/* ------------------------------------------------------------------------- */
+/* Geometry helpers                                                            */
+/* ------------------------------------------------------------------------- */
+
+static double top_max(const orc_problem *p) {
+    double m = -INFINITY;
+    for (int i = 0; i < p->R * p->C; ++i) if (p->top[i] > m) m = p->top[i];
+    return m;
+}
+
+/* Bilinear surface value at local cell coordinates (s, w) in [0,1]^2. */
+static double bilinear(const double *Hl, int C, int a, int b, double s, double w) {
+    double h00 = Hl[a * C + b], h10 = Hl[(a + 1) * C + b];
+    double h01 = Hl[a * C + b + 1], h11 = Hl[(a + 1) * C + b + 1];
+    return h00 * (1 - s) * (1 - w) + h10 * s * (1 - w) + h01 * (1 - s) * w + h11 * s * w;
+}
+
+/* Ray parameter at which the ray leaves the box (Sec. 2.1.1: the domain is a box). */
+static double exit_param(const orc_problem *p, const double q[3], const double d[3], double ztop) {
+    double T = (ztop - q[2]) / d[2];
+    if (d[0] > 0) T = fmin(T, (p->X - q[0]) / d[0]);
+    if (d[0] < 0) T = fmin(T, -q[0] / d[0]);
+    if (d[1] > 0) T = fmin(T, (p->Y - q[1]) / d[1]);
+    if (d[1] < 0) T = fmin(T, -q[1] / d[1]);
+    return T > 0 ? T : 0.0;
+}
+
+/* Real roots of c2 t^2 + c1 t + c0 strictly inside (0, tmax), sorted. */
+static int roots_in(double c2, double c1, double c0, double tmax, double out[2]) {
+    double r[2];
+    int n = 0;
+    if (c2 == 0.0) {
+        if (c1 != 0.0) r[n++] = -c0 / c1;
+    } else {
+        double disc = c1 * c1 - 4.0 * c2 * c0;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double q = -0.5 * (c1 + (c1 >= 0 ? sq : -sq));
+            if (q != 0.0) { r[n++] = q / c2; r[n++] = c0 / q; }
+            else r[n++] = 0.0; /* c1 = c0 = 0: double root at 0 */
+        }
+    }
+    int k = 0;
+    for (int i = 0; i < n; ++i) if (r[i] > 0.0 && r[i] < tmax) out[k++] = r[i];
+    if (k == 2 && out[0] > out[1]) { double t = out[0]; out[0] = out[1]; out[1] = t; }
+    if (k == 2 && out[0] == out[1]) k = 1;
+    return k;
+}
+
+/*
+ * March one ray through all S surfaces.
+ *
+ * surf: [S][R][C] all surfaces (free ones then the top).
+ * L:    [S] output, L[l] = length of ray (inside the box) below surface l+1.
+ * gO:   optional [S][R][C] accumulator; if non-NULL, gscale * dO/dH is added
+ *       (the crossing form of the derivative: each crossing t_c of surface l
+ *       moves with dt_c/dH_n = w_n / f'(t_c), where f = z - h and w_n is the
+ *       bilinear weight of node n at the crossing point).
+ * Returns the opacity O = sum_l (rho_l - rho_{l+1}) L_l.
+ *
+ * Method: walk the cells crossed by the ray's xy-projection in order
+ * (Amanatides & Woo 2-D traversal).  In a cell the surface restricted to the
+ * ray is a quadratic in t, so f(t) = z(t) - h(t) is a quadratic; its roots
+ * split the cell interval into pieces, and each piece is classified by the
+ * sign of f evaluated directly (not through the quadratic) at its midpoint.
+ */
+static double march_ray(const orc_problem *p, const double *surf, const double q[3],
+                        const double d[3], double ztop, double *L, double *gO, double gscale,
+                        orc_stats *st) {
+    const int S = p->S, R = p->R, C = p->C;
+    const double hx = p->X / (R - 1), hy = p->Y / (C - 1);
+    const double T = exit_param(p, q, d, ztop);
+    int prev_below[16];
+    for (int l = 0; l < S; ++l) { L[l] = 0.0; prev_below[l] = -1; }
+
+    int a = (int)floor(q[0] / hx), b = (int)floor(q[1] / hy);
+    if (a > R - 2) a = R - 2;
+    if (a < 0) a = 0;
+    if (b > C - 2) b = C - 2;
+    if (b < 0) b = 0;
+    double t0 = 0.0;
+    while (t0 < T) {
+        double tnx = INFINITY, tny = INFINITY;
+        if (d[0] > 0) tnx = ((a + 1) * hx - q[0]) / d[0];
+        if (d[0] < 0) tnx = (a * hx - q[0]) / d[0];
+        if (d[1] > 0) tny = ((b + 1) * hy - q[1]) / d[1];
+        if (d[1] < 0) tny = (b * hy - q[1]) / d[1];
+        double t1 = fmin(fmin(tnx, tny), T);
+        if (t1 > t0) {
+            if (st) st->cells += 1;
+            /* local coordinates at the cell entry and their rates along the ray */
+            double s0 = (q[0] + t0 * d[0]) / hx - a, w0 = (q[1] + t0 * d[1]) / hy - b;
+            double z0 = q[2] + t0 * d[2];
+            double ds = d[0] / hx, dw = d[1] / hy, tau1 = t1 - t0;
+            for (int l = 0; l < S; ++l) {
+                const double *Hl = surf + (size_t)l * R * C;
+                double h00 = Hl[a * C + b], h10 = Hl[(a + 1) * C + b];
+                double h01 = Hl[a * C + b + 1], h11 = Hl[(a + 1) * C + b + 1];
+                double A = h10 - h00, B = h01 - h00, D = h11 - h10 - h01 + h00;
+                /* f(tau) = c0 + c1 tau + c2 tau^2, tau = t - t0 */
+                double c0 = z0 - (h00 + A * s0 + B * w0 + D * s0 * w0);
+                double c1 = d[2] - (A * ds + B * dw + D * (s0 * dw + w0 * ds));
+                double c2 = -D * ds * dw;
+                double r[2];
+                int nr = roots_in(c2, c1, c0, tau1, r);
+                if (st) { st->tests += 1; st->roots += nr; }
+                double cuts[4];
+                int nc = 0;
+                cuts[nc++] = 0.0;
+                for (int k = 0; k < nr; ++k) cuts[nc++] = r[k];
+                cuts[nc++] = tau1;
+                for (int k = 0; k + 1 < nc; ++k) {
+                    double len = cuts[k + 1] - cuts[k];
+                    /* pieces at the rounding scale of t carry no sign information
+                       (e.g. a root within rounding of a cell edge or of the exit
+                       point); skipping them changes L by at most 1e-12 (1 + T) */
+                    if (!(len > 1e-12 * (1.0 + T))) continue;
+                    double tm = 0.5 * (cuts[k] + cuts[k + 1]);
+                    double sm = s0 + tm * ds, wm = w0 + tm * dw;
+                    double fm = (z0 + tm * d[2]) - bilinear(Hl, C, a, b, sm, wm);
+                    int below = fm < 0.0;
+                    if (below) L[l] += len;
+                    if (prev_below[l] >= 0 && prev_below[l] != below) {
+                        /* a crossing at the start of this piece */
+                        double tc = cuts[k];
+                        double fp = c1 + 2.0 * c2 * tc;
+                        if (st) {
+                            st->crossings += 1;
+                            if (fabs(fp) < st->min_fprime) st->min_fprime = fabs(fp);
+                        }
+                        if (gO && fp != 0.0) {
+                            double sc = s0 + tc * ds, wc = w0 + tc * dw;
+                            double g = gscale * (p->density[l] - (l + 1 < S ? p->density[l + 1] : 0.0)) / fabs(fp);
+                            double *G = gO + (size_t)l * R * C;
+                            G[a * C + b] += g * (1 - sc) * (1 - wc);
+                            G[(a + 1) * C + b] += g * sc * (1 - wc);
+                            G[a * C + b + 1] += g * (1 - sc) * wc;
+                            G[(a + 1) * C + b + 1] += g * sc * wc;
+                        }
+                    }
+                    prev_below[l] = below;
+                }
+            }
+        }
+        if (t1 >= T) break;
+        if (tnx <= tny) a += d[0] > 0 ? 1 : -1;
+        else b += d[1] > 0 ? 1 : -1;
+        if (a < 0 || a > R - 2 || b < 0 || b > C - 2) break;
+        t0 = t1;
+    }
+    double O = 0.0;
+    for (int l = 0; l < S; ++l) {
+        double rho_above = (l + 1 < S) ? p->density[l + 1] : 0.0;
+        O += (p->density[l] - rho_above) * L[l];
+    }
+    return O;
+}
+
+/* Build [S][R][C] from the free surfaces [S-1][R][C] and the fixed top. */
+static double *stack_surfaces(const orc_problem *p, const double *free_h) {
+    size_t N = (size_t)p->R * p->C;
+    double *s = (double *)malloc(sizeof(double) * N * p->S);
+    memcpy(s, free_h, sizeof(double) * N * (p->S - 1));
+    memcpy(s + N * (p->S - 1), p->top, sizeof(double) * N);
+    return s;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Forward model: opacity, expected counts, likelihood                        */
+/* ------------------------------------------------------------------------- */
+
+/* Opacity of every ray for one state of the free surfaces.
+   O: [n_s*n_pix]; Lout: optional [n_s*n_pix][S]; st: optional totals. */
+void orc_opacity(const orc_problem *p, const double *free_h, double *O, double *Lout, orc_stats *st) {
+    double *surf = stack_surfaces(p, free_h);
+    double ztop = top_max(p);
+    double L[16];
+    if (st) { memset(st, 0, sizeof(*st)); st->min_fprime = INFINITY; }
+    for (int s = 0; s < p->n_s; ++s)
+        for (int k = 0; k < p->n_pix; ++k) {
+            int ray = s * p->n_pix + k;
+            O[ray] = march_ray(p, surf, p->pos + 3 * s, p->dirs + 3 * (size_t)ray, ztop, L, NULL, 0.0, st);
+            if (Lout) for (int l = 0; l < p->S; ++l) Lout[(size_t)ray * p->S + l] = L[l];
+        }
+    free(surf);
+}
+
+/* Poisson log-likelihood of the counts given opacities (eq. def_likelihood):
+   sum_p C_p log(lambda_p) - lambda_p - log(C_p!),  lambda_p = E_p exp(-O_p/Lambda). */
+double orc_loglik(const orc_problem *p, const double *O) {
+    double ll = 0.0;
+    int n = p->n_s * p->n_pix;
+    for (int i = 0; i < n; ++i) {
+        double lam = p->exposure[i] * exp(-O[i] / p->atten);
+        double c = (double)p->counts[i];
+        ll += c * (log(p->exposure[i]) - O[i] / p->atten) - lam - lgamma(c + 1.0);
+    }
+    return ll;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Prior: Gaussian copula over a periodic proper CAR field (Sec. 2.2.1)       */
+/* ------------------------------------------------------------------------- */
+
+/* Standard normal c.d.f. through the complementary error function. */
+static double Phi(double w) { return 0.5 * erfc(-w / sqrt(2.0)); }
+
+/* Inverse standard normal c.d.f. for u in (0, 0.5]: safeguarded Newton
+   iteration on log Phi(w) = log u (concave in w, so the tails converge as
+   fast as the centre) inside the bracket [-40, 0]. */
+double orc_ndtri_lower(double u) {
+    if (!(u > 0.0)) return -INFINITY;
+    if (u >= 0.5) return 0.0;
+    double lu = log(u);
+    double lo = -40.0, hi = 0.0, w = -1.0;
+    for (int it = 0; it < 400; ++it) {
+        double P = Phi(w);
+        double g = log(P) - lu; /* increasing in w */
+        if (g > 0) hi = w; else lo = w;
+        double pdf = exp(-0.5 * w * w) / sqrt(2.0 * M_PI);
+        double wn = (P > 0 && pdf > 0) ? w - g * P / pdf : 0.5 * (lo + hi);
+        if (!(wn > lo && wn < hi)) wn = 0.5 * (lo + hi);
+        if (fabs(wn - w) <= 4e-16 * fabs(w)) { w = wn; break; }
+        w = wn;
+    }
+    return w;
+}
+
+/* Phi^-1(u) where u = (H-a)/(b-a) and v = 1-u = (b-H)/(b-a) are both given:
+   the tail nearer to u is evaluated directly, the other through symmetry. */
+static double ndtri_uv(double u, double v) {
+    return (u <= 0.5) ? orc_ndtri_lower(u) : -orc_ndtri_lower(v);
+}
+
+/* log det Q and Sigma_11 = (Q^-1)_11 for Q = diag(A1) - rA on the periodic
+   R x C grid.  Q is block-circulant, so its eigenvalues are
+   mu_km = 4 - 2r(cos(2 pi k/R) + cos(2 pi m/C)), and by translation
+   invariance the diagonal of Q^-1 is its trace over N. */
+void orc_car_consts(int R, int C, double r, double *logdet, double *sigma11) {
+    double sl = 0.0, si = 0.0;
+    for (int k = 0; k < R; ++k)
+        for (int m = 0; m < C; ++m) {
+            double mu = 4.0 - 2.0 * r * (cos(2.0 * M_PI * k / R) + cos(2.0 * M_PI * m / C));
+            sl += log(mu);
+            si += 1.0 / mu;
+        }
+    *logdet = sl;
+    *sigma11 = si / ((double)R * C);
+}
+
+/*
+ * log prior density of the free surfaces, in H-space.
+ * For free surface l with a = H_{l-1} (0 for l = 1) and b = H_top:
+ *   u = (H_l - a)/(b - a),  w = Phi^-1(u),  x = s w,  s = sqrt(Sigma_11),
+ *   log p(H_l | H_{l-1}) = log N(x; 0, Q^-1) + sum log|dx/du| + sum log|du/dH|
+ *     = 1/2 log det Q - 1/2 x^T Q x + N log s + 1/2 sum w^2 - sum log(b - a)
+ * (the (N/2) log 2 pi terms of the normal density and of phi(w) cancel), with
+ *   x^T Q x = 4(1-r) sum x_i^2 + r sum_{edges} (x_i - x_j)^2
+ * over the 2N right/down edges of the periodic grid.  States outside the
+ * support 0 < H_1 < ... < H_{S-1} < H_top give -inf.
+ * If grad is non-NULL ([S][R][C]), the gradient is added to it.
+ */
+double orc_log_prior_grad(const orc_problem *p, const double *free_h, double *grad) {
+    const int R = p->R, C = p->C, N = R * C;
+    double total = 0.0;
+    double *w = (double *)malloc(sizeof(double) * N);
+    double *u = (double *)malloc(sizeof(double) * N);
+    double *dd = (double *)malloc(sizeof(double) * N);
+    for (int l = 0; l < p->S - 1; ++l) {
+        const double *H = free_h + (size_t)l * N;
+        const double *A = (l == 0) ? NULL : free_h + (size_t)(l - 1) * N;
+        double logdet, s11;
+        double r = p->car_r[l];
+        orc_car_consts(R, C, r, &logdet, &s11);
+        double s = sqrt(s11);
+        double sum_w2 = 0.0, sum_logd = 0.0;
+        for (int i = 0; i < N; ++i) {
+            double a = A ? A[i] : 0.0, b = p->top[i];
+            double d = b - a;
+            double ui = (H[i] - a) / d, vi = (b - H[i]) / d;
+            if (!(d > 0.0) || !(ui > 0.0) || !(vi > 0.0)) {
+                free(w); free(u); free(dd);
+                return -INFINITY;
+            }
+            w[i] = ndtri_uv(ui, vi);
+            u[i] = ui;
+            dd[i] = d;
+            sum_w2 += w[i] * w[i];
+            sum_logd += log(d);
+        }
+        double sx2 = 0.0, sedge = 0.0;
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < C; ++j) {
+                double xi = s * w[i * C + j];
+                double xr = s * w[i * C + (j + 1) % C];
+                double xd = s * w[((i + 1) % R) * C + j];
+                sx2 += xi * xi;
+                sedge += (xi - xr) * (xi - xr) + (xi - xd) * (xi - xd);
+            }
+        double quad = 4.0 * (1.0 - r) * sx2 + r * sedge;
+        total += 0.5 * logdet - 0.5 * quad + N * log(s) + 0.5 * sum_w2 - sum_logd;
+
+        if (grad) {
+            double *gH = grad + (size_t)l * N;
+            double *gA = (l == 0) ? NULL : grad + (size_t)(l - 1) * N;
+            double *gB = grad + (size_t)(p->S - 1) * N;
+            for (int i = 0; i < R; ++i)
+                for (int j = 0; j < C; ++j) {
+                    int n = i * C + j;
+                    double wi = w[n];
+                    double nb = w[i * C + (j + 1) % C] + w[i * C + (j + C - 1) % C] +
+                                w[((i + 1) % R) * C + j] + w[((i + R - 1) % R) * C + j];
+                    /* d/dw_n of the log density in w-space */
+                    double G = -s11 * (4.0 * (1.0 - r) * wi + r * (4.0 * wi - nb)) + wi;
+                    double phi = exp(-0.5 * wi * wi) / sqrt(2.0 * M_PI);
+                    double gu = G / phi; /* d/du_n */
+                    double d = dd[n];
+                    gH[n] += gu / d;
+                    if (gA) gA[n] += gu * (u[n] - 1.0) / d + 1.0 / d;
+                    gB[n] += -gu * u[n] / d - 1.0 / d;
+                }
+        }
+    }
+    free(w); free(u); free(dd);
+    return total;
+}
+
+double orc_log_prior(const orc_problem *p, const double *free_h) {
+    return orc_log_prior_grad(p, free_h, NULL);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Posterior                                                                   */
+/* ------------------------------------------------------------------------- */
+
+/* log posterior (likelihood + prior, normalised) of one state. */
+double orc_logpost(const orc_problem *p, const double *free_h) {
+    double lpr = orc_log_prior(p, free_h);
+    if (lpr == -INFINITY) return -INFINITY;
+    int n = p->n_s * p->n_pix;
+    if (n == 0) return lpr;
+    double *O = (double *)malloc(sizeof(double) * n);
+    orc_opacity(p, free_h, O, NULL, NULL);
+    double ll = orc_loglik(p, O);
+    free(O);
+    return ll + lpr;
+}
+
+/* log posterior of n_chains states [n_chains][S-1][R][C], parallel over chains. */
+void orc_logpost_batch(const orc_problem *p, int n_chains, const double *free_all, double *lp) {
+    size_t M = (size_t)(p->S - 1) * p->R * p->C;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < n_chains; ++c) lp[c] = orc_logpost(p, free_all + M * c);
+}
+
+/*
+ * Gradient of the log posterior with respect to every surface height,
+ * grad: [S][R][C] (the fixed top surface included).  Returns the log
+ * posterior.  Out-of-support states return -inf and a zero gradient.
+ * Likelihood part: dLL/dO_p = (lambda_p - C_p)/Lambda times dO_p/dH from the
+ * crossing form in march_ray; prior part from orc_log_prior_grad.
+ */
+double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
+    size_t NS = (size_t)p->S * p->R * p->C;
+    memset(grad, 0, sizeof(double) * NS);
+    double lpr = orc_log_prior_grad(p, free_h, grad);
+    if (lpr == -INFINITY) { memset(grad, 0, sizeof(double) * NS); return -INFINITY; }
+    int n = p->n_s * p->n_pix;
+    if (n == 0) return lpr;
+    double *surf = stack_surfaces(p, free_h);
+    double ztop = top_max(p);
+    double L[16], ll = 0.0;
+    for (int s = 0; s < p->n_s; ++s)
+        for (int k = 0; k < p->n_pix; ++k) {
+            int ray = s * p->n_pix + k;
+            const double *q = p->pos + 3 * s, *d = p->dirs + 3 * (size_t)ray;
+            double O = march_ray(p, surf, q, d, ztop, L, NULL, 0.0, NULL);
+            double lam = p->exposure[ray] * exp(-O / p->atten);
+            double c = (double)p->counts[ray];
+            ll += c * (log(p->exposure[ray]) - O / p->atten) - lam - lgamma(c + 1.0);
+            double g = (lam - c) / p->atten;
+            march_ray(p, surf, q, d, ztop, L, grad, g, NULL);
+        }
+    free(surf);
+    return ll + lpr;
+}
+
+void orc_grad_batch(const orc_problem *p, int n_chains, const double *free_all, double *lp, double *grad_all) {
+    size_t M = (size_t)(p->S - 1) * p->R * p->C, NS = (size_t)p->S * p->R * p->C;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < n_chains; ++c) lp[c] = orc_grad(p, free_all + M * c, grad_all + NS * c);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Counter-based RNG: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11)      */
+/* ------------------------------------------------------------------------- */
+
+/* One Philox4x32 round: two 32x32->64 multiplications of counter words 0 and
+   2 by the round multipliers, hi/lo halves mixed with words 1, 3 and the key. */
+static void philox_round(uint32_t ctr[4], const uint32_t key[2]) {
+    uint64_t p0 = (uint64_t)0xD2511F53u * ctr[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * ctr[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ ctr[1] ^ key[0];
+    uint32_t n2 = hi0 ^ ctr[3] ^ key[1];
+    ctr[0] = n0; ctr[1] = lo1; ctr[2] = n2; ctr[3] = lo0;
+}
+
+/* Ten rounds; the key is advanced by the Weyl constants between rounds. */
+void orc_philox4x32_10(const uint32_t in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t ctr[4] = {in[0], in[1], in[2], in[3]};
+    uint32_t key[2] = {key_in[0], key_in[1]};
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { key[0] += 0x9E3779B9u; key[1] += 0xBB67AE85u; }
+        philox_round(ctr, key);
+    }
+    memcpy(out, ctr, sizeof(ctr));
+}
+
+/* Counter layout: (j, step lo32, step hi16 | tag << 16, chain); key = seed. */
+static void philox_draw(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t j, uint32_t out[4]) {
+    uint32_t ctr[4] = {j, (uint32_t)step, (uint32_t)((step >> 32) & 0xFFFFu) | (tag << 16), chain};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* 53-bit uniform in [0,1) from two 32-bit words. */
+static double u53(uint32_t a, uint32_t b) {
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+void orc_uniform_pair(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t j, double u[2]) {
+    uint32_t o[4];
+    philox_draw(seed, chain, step, tag, j, o);
+    u[0] = u53(o[0], o[1]);
+    u[1] = u53(o[2], o[3]);
+}
+
+/* Two standard normals by the Box-Muller transform of one uniform pair. */
+void orc_normal_pair(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t j, double z[2]) {
+    double u[2];
+    orc_uniform_pair(seed, chain, step, tag, j, u);
+    double rad = sqrt(-2.0 * log(1.0 - u[0]));
+    double th = 2.0 * M_PI * u[1];
+    z[0] = rad * cos(th);
+    z[1] = rad * sin(th);
+}
+
+void orc_raw_philox(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t j, uint32_t out[4]) {
+    philox_draw(seed, chain, step, tag, j, out);
+}
+
+/* ------------------------------------------------------------------------- */
+/* MCMC: random-walk Metropolis and MALA                                       */
+/* ------------------------------------------------------------------------- */
+
+enum { TAG_PROPOSAL = 0, TAG_ACCEPT = 1, TAG_MOMENTUM = 2 };
+
+static double round_state(double x, int state_f32) { return state_f32 ? (double)(float)x : x; }
+
+/*
+ * Random-walk Metropolis on the free surfaces (Sec. 3.1: MCMC needs the
+ * posterior only up to a constant, so log alpha = lp' - lp).
+ * Proposal H' = H + sigma z with z_i the (i%2)-th normal of pair j = i/2 of
+ * (chain, step, tag 0); accept iff log U < log alpha with U the first uniform
+ * of (chain, step, tag 1, j = 0).  free_all/lp/n_acc are updated in place;
+ * lp entries that are NaN on entry are computed first.  If margins is non-NULL,
+ * margins[c*n_steps + k] = |log U - log alpha| of step k (decision margin).
+ * state_f32 != 0 rounds every proposed state to float32 (states stored in
+ * single precision).
+ */
+void orc_mcmc_rw(const orc_problem *p, int n_chains, double *free_all, double *lp, int64_t *n_acc,
+                 int64_t n_steps, uint64_t step_offset, double sigma, uint64_t seed, int state_f32,
+                 double *margins) {
+    size_t M = (size_t)(p->S - 1) * p->R * p->C;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < n_chains; ++c) {
+        double *H = free_all + M * c;
+        double *prop = (double *)malloc(sizeof(double) * M);
+        if (isnan(lp[c])) lp[c] = orc_logpost(p, H);
+        for (int64_t k = 0; k < n_steps; ++k) {
+            uint64_t step = step_offset + (uint64_t)k;
+            for (size_t i = 0; i < M; i += 2) {
+                double z[2];
+                orc_normal_pair(seed, (uint32_t)c, step, TAG_PROPOSAL, (uint32_t)(i / 2), z);
+                prop[i] = round_state(H[i] + sigma * z[0], state_f32);
+                if (i + 1 < M) prop[i + 1] = round_state(H[i + 1] + sigma * z[1], state_f32);
+            }
+            double lpp = orc_logpost(p, prop);
+            double u[2];
+            orc_uniform_pair(seed, (uint32_t)c, step, TAG_ACCEPT, 0, u);
+            double la = lpp - lp[c];
+            double lu = log(u[0]);
+            if (margins) margins[(size_t)c * n_steps + k] = fabs(lu - la);
+            if (lu < la) {
+                memcpy(H, prop, sizeof(double) * M);
+                lp[c] = lpp;
+                n_acc[c] += 1;
+            }
+        }
+        free(prop);
+    }
+}
+
+/*
+ * Metropolis-adjusted Langevin (HMC with one leapfrog step, Sec. 3.1):
+ *   H' = H + (eps^2/2) M^-1 g(H) + eps M^-1/2 z,   z from tag 2,
+ *   log alpha = lp' - lp + log q(H | H') - log q(H' | H),
+ *   log q(y | x) = -sum_i (y_i - x_i - (eps^2/2) Minv_i g_i(x))^2 / (2 eps^2 Minv_i).
+ * inv_mass: [S-1][R][C] or NULL (= 1).  Only the free surfaces move.
+ */
+void orc_mcmc_mala(const orc_problem *p, int n_chains, double *free_all, double *lp, int64_t *n_acc,
+                   int64_t n_steps, uint64_t step_offset, double eps, const double *inv_mass,
+                   uint64_t seed, int state_f32, double *margins) {
+    size_t M = (size_t)(p->S - 1) * p->R * p->C, NS = (size_t)p->S * p->R * p->C;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < n_chains; ++c) {
+        double *H = free_all + M * c;
+        double *prop = (double *)malloc(sizeof(double) * M);
+        double *g = (double *)malloc(sizeof(double) * NS);
+        double *gp = (double *)malloc(sizeof(double) * NS);
+        lp[c] = orc_grad(p, H, g);
+        for (int64_t k = 0; k < n_steps; ++k) {
+            uint64_t step = step_offset + (uint64_t)k;
+            double lq_fwd = 0.0;
+            for (size_t i = 0; i < M; i += 2) {
+                double z[2];
+                orc_normal_pair(seed, (uint32_t)c, step, TAG_MOMENTUM, (uint32_t)(i / 2), z);
+                for (int e = 0; e < 2 && i + e < M; ++e) {
+                    size_t n = i + e;
+                    double mi = inv_mass ? inv_mass[n] : 1.0;
+                    double mean = H[n] + 0.5 * eps * eps * mi * g[n];
+                    prop[n] = round_state(mean + eps * sqrt(mi) * z[e], state_f32);
+                    double dv = prop[n] - mean;
+                    lq_fwd -= dv * dv / (2.0 * eps * eps * mi);
+                }
+            }
+            double lpp = orc_grad(p, prop, gp);
+            double la = -INFINITY;
+            if (lpp > -INFINITY) {
+                double lq_bwd = 0.0;
+                for (size_t n = 0; n < M; ++n) {
+                    double mi = inv_mass ? inv_mass[n] : 1.0;
+                    double mean = prop[n] + 0.5 * eps * eps * mi * gp[n];
+                    double dv = H[n] - mean;
+                    lq_bwd -= dv * dv / (2.0 * eps * eps * mi);
+                }
+                la = lpp - lp[c] + lq_bwd - lq_fwd;
+            }
+            double u[2];
+            orc_uniform_pair(seed, (uint32_t)c, step, TAG_ACCEPT, 0, u);
+            double lu = log(u[0]);
+            if (margins) margins[(size_t)c * n_steps + k] = fabs(lu - la);
+            if (lu < la) {
+                memcpy(H, prop, sizeof(double) * M);
+                memcpy(g, gp, sizeof(double) * NS);
+                lp[c] = lpp;
+                n_acc[c] += 1;
+            }
+        }
+        free(prop); free(g); free(gp);
+    }
+}
+
+/* Single-ray march exposed for tests: returns O, fills L[S] and stats. */
+double orc_march_one(const orc_problem *p, const double *free_h, const double q[3], const double d[3],
+                     double *L, orc_stats *st) {
+    double *surf = stack_surfaces(p, free_h);
+    if (st) { memset(st, 0, sizeof(*st)); st->min_fprime = INFINITY; }
+    double O = march_ray(p, surf, q, d, top_max(p), L, NULL, 0.0, st);
+    free(surf);
+    return O;
+}
+
+/* Per-ray diagnostics for every ray: crossings and the smallest |f'| at a
+   crossing (used to widen tolerances for ill-conditioned rays). */
+void orc_ray_stats(const orc_problem *p, const double *free_h, double *crossings, double *min_fprime,
+                   double *cells) {
+    double *surf = stack_surfaces(p, free_h);
+    double ztop = top_max(p), L[16];
+    for (int s = 0; s < p->n_s; ++s)
+        for (int k = 0; k < p->n_pix; ++k) {
+            int ray = s * p->n_pix + k;
+            orc_stats st;
+            memset(&st, 0, sizeof(st));
+            st.min_fprime = INFINITY;
+            march_ray(p, surf, p->pos + 3 * s, p->dirs + 3 * (size_t)ray, ztop, L, NULL, 0.0, &st);
+            if (crossings) crossings[ray] = st.crossings;
+            if (min_fprime) min_fprime[ray] = st.min_fprime;
+            if (cells) cells[ray] = st.cells;
+        }
+    free(surf);
+}

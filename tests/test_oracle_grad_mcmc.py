@@ -1,0 +1,185 @@
+"""Pins of the oracle's gradient (the differentiability the paper relies on
+for gradient-based samplers, Sec. 2 and Sec. 3.1), its Metropolis/MALA steps
+and its counter-based RNG."""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+
+from paper_2603_28907_amd import inputs
+from tests.helpers import make_scenario, unit
+
+
+@pytest.fixture(scope="module")
+def tiny(oracle_mod):
+    sc = inputs.tiny_bumps(seed=0)
+    sc.counts = oracle_mod.make_counts(sc, seed=1)
+    return sc
+
+
+def fd_check(f, x0, coords, h, grad, tol_rel, tol_abs):
+    """Central differences with kink detection: a coordinate whose two
+    one-sided differences disagree by more than 10x the tolerance sits on a
+    kink of the piecewise-smooth log posterior and is skipped."""
+    kinks, worst = 0, 0.0
+    f0 = f(x0)
+    scale = np.max(np.abs(grad))
+    for idx in coords:
+        xp, xm = x0.copy(), x0.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fp, fm = f(xp), f(xm)
+        fwd, bwd = (fp - f0) / h, (f0 - fm) / h
+        tol = tol_rel * scale + tol_abs
+        if abs(fwd - bwd) > 10 * tol + 1e-2 * abs(fwd + bwd):
+            kinks += 1
+            continue
+        c = (fp - fm) / (2 * h)
+        err = abs(c - grad[idx])
+        worst = max(worst, err / tol)
+        assert err <= tol, (idx, c, grad[idx], fwd, bwd)
+    return kinks, worst
+
+
+def test_prior_gradient_fd(oracle_mod):
+    rng = np.random.default_rng(0)
+    R, C = 5, 4
+    top = 40 + rng.uniform(0, 3, (R, C))
+    u = rng.uniform(0.1, 0.9, (2, R, C))
+    H1 = u[0] * top
+    H2 = H1 + u[1] * (top - H1)
+    free = np.stack([H1, H2])
+    sc = make_scenario(3, R, C, 30, 30, free, top, (1, 1, 1), np.zeros((0, 3)), None,
+                       car_r=np.array([0.9, 0.6]))
+    prob = oracle_mod.OracleProblem(sc)
+    v, g = prob.log_prior_grad(free)
+    assert v == pytest.approx(prob.log_prior(free))
+    h = 1e-5
+    for idx in np.ndindex(free.shape):
+        xp, xm = free.copy(), free.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (prob.log_prior(xp) - prob.log_prior(xm)) / (2 * h)
+        assert g[idx] == pytest.approx(fd, rel=1e-6, abs=1e-6)
+    # gradient with respect to the fixed top surface
+    for idx in [(0, 0), (2, 3), (4, 1)]:
+        tp, tm = top.copy(), top.copy()
+        tp[idx] += h
+        tm[idx] -= h
+        fp = oracle_mod.OracleProblem(make_scenario(3, R, C, 30, 30, free, tp, (1, 1, 1), np.zeros((0, 3)),
+                                                    None, car_r=np.array([0.9, 0.6]))).log_prior(free)
+        fm = oracle_mod.OracleProblem(make_scenario(3, R, C, 30, 30, free, tm, (1, 1, 1), np.zeros((0, 3)),
+                                                    None, car_r=np.array([0.9, 0.6]))).log_prior(free)
+        assert g[2][idx] == pytest.approx((fp - fm) / (2 * h), rel=1e-6, abs=1e-6)
+
+
+def test_logpost_gradient_fd_tiny(oracle_mod, tiny):
+    """Central differences (h = 1e-3 m) on 64 seeded coordinates of the free
+    surfaces of the tiny cave, at a jittered state."""
+    prob = oracle_mod.OracleProblem(tiny)
+    x0 = inputs.init_states(tiny, 1, seed=3)[0]
+    lp, g = prob.grad(x0)
+    assert lp == pytest.approx(prob.logpost(x0), rel=1e-13)
+    rng = np.random.default_rng(5)
+    flat = [tuple(int(v) for v in np.unravel_index(k, x0.shape)) for k in rng.choice(x0.size, 64, replace=False)]
+    kinks, worst = fd_check(prob.logpost, x0, flat, 1e-3, g[:2], tol_rel=1e-4, tol_abs=1e-3)
+    assert kinks <= 8
+
+
+def test_gradient_partition_of_unity_sum_rule(oracle_mod):
+    """For flat surfaces crossed inside the box, the derivative of the opacity
+    with respect to a uniform lift of surface l is (rho_l - rho_{l+1})/d_z,
+    so the node gradients of that surface sum to it (bilinear weights sum to 1)."""
+    R, C, X, Y = 6, 5, 100.0, 80.0
+    levels = [30.0, 45.0, 90.0]
+    dens = np.array([1.8, 0.0, 2.7])
+    free = np.stack([np.full((R, C), c) for c in levels[:2]])
+    d = unit([0.2, 0.1, 1.0])
+    q = np.array([40.0, 30.0, 0.0])
+    counts = np.array([[100]], np.int32)
+    sc = make_scenario(3, R, C, X, Y, free, np.full((R, C), levels[2]), dens, q[None], d[None, None],
+                       exposure=np.array([[1e4]]), counts=counts, car_r=np.array([0.5, 0.5]))
+    prob = oracle_mod.OracleProblem(sc)
+    lp, g = prob.grad(free)
+    _, gprior = prob.log_prior_grad(free)
+    O = prob.opacity(free)[0]
+    lam = 1e4 * math.exp(-O / 400.0)
+    gO = (lam - 100) / 400.0
+    dOdH = (g - gprior) / gO
+    for l in range(2):
+        assert dOdH[l].sum() == pytest.approx((dens[l] - dens[l + 1]) / d[2], rel=1e-10)
+
+
+def test_rw_zero_step_accepts_all(oracle_mod, tiny):
+    """With sigma = 0 the proposal equals the state, log alpha = 0 and every
+    step is accepted (log U < 0 for U in [0,1))."""
+    prob = oracle_mod.OracleProblem(tiny)
+    st = inputs.init_states(tiny, 2, seed=1)
+    lp = np.full(2, np.nan)
+    s2, lp2, acc, _ = prob.mcmc_rw(st, lp, np.zeros(2, np.int64), 5, 0, 0.0, 123)
+    assert np.all(acc == 5)
+    assert np.array_equal(s2, st)
+    assert np.allclose(lp2, prob.logpost_batch(st))
+
+
+def uniform_prior_problem(oracle_mod, r):
+    R = C = 3
+    top = np.full((R, C), 10.0)
+    sc = make_scenario(2, R, C, 10, 10, np.full((1, R, C), 5.0), top, (1, 1), np.zeros((0, 3)), None,
+                       car_r=np.array([r]))
+    return oracle_mod.OracleProblem(sc)
+
+
+@pytest.mark.parametrize("kind", ["rw", "mala"])
+def test_mcmc_recovers_uniform_marginals(oracle_mod, kind):
+    """With no data the posterior is the prior, whose per-node marginals are
+    U(0, H_top) for any r (the copula keeps uniform marginals, Sec. 2.2.1):
+    mean 5 and variance 100/12 for H_top = 10."""
+    r = 0.0 if kind == "rw" else 0.6
+    prob = uniform_prior_problem(oracle_mod, r)
+    n_chains = 64
+    st = np.full((n_chains, 1, 3, 3), 5.0)
+    lp = np.full(n_chains, np.nan)
+    acc = np.zeros(n_chains, np.int64)
+    samples = []
+    steps = 0
+    for chunk in range(12):
+        if kind == "rw":
+            st, lp, acc, _ = prob.mcmc_rw(st, lp, acc, 150, steps, 2.5, 77)
+        else:
+            st, lp, acc, _ = prob.mcmc_mala(st, lp, acc, 150, steps, 1.2, 77)
+        steps += 150
+        if chunk >= 2:
+            samples.append(st.reshape(-1).copy())
+    x = np.concatenate(samples)
+    assert abs(x.mean() - 5.0) < 0.25
+    assert abs(x.var() - 100 / 12) < 0.9
+    assert 0.1 < acc.mean() / steps < 0.95
+    assert np.all((x > 0) & (x < 10))
+
+
+def test_philox_statistics(oracle_mod):
+    """Uniform pairs are uniform, Box-Muller normals are standard normal, and
+    streams for different (chain, step, tag, j) differ."""
+    u = np.array([oracle_mod.uniform_pair(42, c, s, 1, 0) for c in range(50) for s in range(400)]).reshape(-1)
+    assert scipy.stats.kstest(u, "uniform").pvalue > 1e-3
+    hist, _ = np.histogram(u, bins=20, range=(0, 1))
+    assert scipy.stats.chisquare(hist).pvalue > 1e-3
+    z = np.array([oracle_mod.normal_pair(7, 3, s, 0, j) for s in range(200) for j in range(50)]).reshape(-1)
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 0.05 and abs(z.var() - 1) < 0.05
+    base = oracle_mod.raw_philox(1, 2, 3, 0, 4)
+    for args in [(2, 2, 3, 0, 4), (1, 3, 3, 0, 4), (1, 2, 4, 0, 4), (1, 2, 3, 1, 4), (1, 2, 3, 0, 5),
+                 (1, 2, 3 + (1 << 32), 0, 4), ((1 << 32) + 1, 2, 3, 0, 4)]:
+        assert not np.array_equal(oracle_mod.raw_philox(*args), base)
+
+
+def test_philox_is_a_keyed_bijection_of_the_counter(oracle_mod):
+    """Each Philox round is invertible for a fixed key, so distinct counters
+    give distinct outputs: no collisions over 20000 counters."""
+    seen = set()
+    for c in range(20000):
+        out = tuple(oracle_mod.philox4x32_10([c, 0, 0, 0], [5, 6]))
+        assert out not in seen
+        seen.add(out)
