@@ -1,0 +1,183 @@
+/*
+ * muoncave.h -- C ABI of the MI355X (gfx950) library for batched posterior
+ * evaluation and MCMC over surface-based block-cave geometries from muon
+ * counts (Biron-Lattes et al., arXiv 2603.28907).
+ *
+ * Model (paper Sec. 2):
+ *   - Layer model (Sec. 2.1.3): S height fields H_1 < ... < H_S on an
+ *     n_rows x n_cols node grid over the footprint [0,X] x [0,Y]; H_S (the
+ *     terrain) is known, H_1..H_{S-1} are inferred.  Nodes are vertex-centred,
+ *     x_i = i X/(n_rows-1), y_j = j Y/(n_cols-1); row index i runs along x,
+ *     H[l][i][j] is stored in C order (the array-indexing figure).  Surfaces
+ *     are bilinear inside each grid cell.
+ *   - Density (eq. def_LM_density_grid, continuum form): unit l, between
+ *     surface l-1 and l (surface 0 = the floor z = 0), has density rho_l;
+ *     density is 0 above H_S and outside the box [0,X]x[0,Y]x[0,max H_S].
+ *   - Opacity (Sec. 2.1.1): O = integral of density along the ray from the
+ *     sensor, evaluated exactly through the height fields.
+ *   - Expected counts (eq. expected_counts, one ray per pixel, exponential
+ *     attenuation): lambda_p = E_p exp(-O_p / Lambda).
+ *   - Likelihood (eq. def_likelihood): C_p ~ Poisson(lambda_p), normalised.
+ *   - Prior (Sec. 2.2.1): per free surface, a Gaussian copula over a periodic
+ *     proper CAR field with dependence r_l, H_l = (1-u) H_{l-1} + u H_S,
+ *     written as a density in H-space (normalised).
+ *   - logpost = log-likelihood + log prior; states outside the support
+ *     0 < H_1 < ... < H_{S-1} < H_S give -inf.
+ *
+ * Units: metres for lengths and heights, g/cm^3 for densities, opacity in
+ * (g/cm^3 x m), Lambda in the same unit.
+ *
+ * Ownership: host arrays passed to the set-up calls are copied before the
+ * call returns.  Device arrays passed to the *_batch and run calls belong to
+ * the caller; the library never frees them.  Library-internal device memory
+ * belongs to the handle and is released by mc_destroy.
+ *
+ * Synchrony: the set-up calls are synchronous.  logpost_batch,
+ * logpost_grad_batch and mcmc_run enqueue work on `stream` (a hipStream_t
+ * passed as void*; NULL = the default stream) and return without waiting.
+ *
+ * Errors: every call returns an mc_status; mc_last_error() gives a message
+ * for the last non-OK status of that handle.  MC_ERR_STATE reports a call
+ * made out of order (e.g. logpost_batch before set_counts).
+ *
+ * Threads: one handle is used by one host thread at a time; different
+ * handles may be used concurrently.
+ */
+#ifndef MUONCAVE_H
+#define MUONCAVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mc_problem mc_problem;
+
+typedef enum {
+    MC_OK = 0,
+    MC_ERR_ARG = -1,          /* invalid argument (shape, range, NULL) */
+    MC_ERR_STATE = -2,        /* call out of order */
+    MC_ERR_NOMEM = -3,        /* device allocation failed */
+    MC_ERR_DEVICE = -4,       /* HIP runtime error */
+    MC_ERR_UNSUPPORTED = -5   /* valid request this build does not handle (e.g. grid too large) */
+} mc_status;
+
+typedef enum {
+    MC_F32 = 0,   /* heights, opacities and the ray march in float32; sums in float64 */
+    MC_F64 = 1    /* everything in float64 */
+} mc_precision;
+
+/* Create a handle bound to HIP device `hip_device` computing in `precision`. */
+mc_status mc_create(int hip_device, int precision, mc_problem **out);
+
+/* Release the handle and its device memory (waits for its pending work). */
+void mc_destroy(mc_problem *p);
+
+/* Message for the last non-OK status of `p` (or of the last failed
+   mc_create when p is NULL).  Valid until the next call on the handle. */
+const char *mc_last_error(const mc_problem *p);
+
+/*
+ * Geometry (Sec. 2.1.3 layer model, Sec. 2.2.1 prior parameters).
+ *   n_surfaces S in [2, 4]: S-1 free surfaces plus the known top.
+ *   n_rows, n_cols >= 3 (the periodic 4-neighbour graph needs 3 nodes per
+ *   direction) and <= 256.
+ *   extent_x_m, extent_y_m > 0: footprint size.
+ *   density[S]: density of unit l = 1..S (>= 0).
+ *   top[n_rows*n_cols]: the known top surface H_S (> 0), C order.
+ *   car_r[S-1]: CAR dependence r_l in [0, 1) of each free surface.
+ * Resets sensors and counts.
+ */
+mc_status load_geometry_grid(mc_problem *p, int n_surfaces, int n_rows, int n_cols,
+                             double extent_x_m, double extent_y_m, const double *density,
+                             const double *top, const double *car_r);
+
+/*
+ * Sensors and pixels (Sec. 2.1.1 radiographs; one ray per pixel).
+ *   pos[n_sensors*3]: sensor positions (x,y inside the footprint, 0 <= z < max top).
+ *   dirs[n_sensors*n_pix*3]: unit pixel directions with d_z > 0; ray
+ *   r = s*n_pix + k belongs to sensor s.
+ *   exposure[n_sensors*n_pix] > 0: E_p (exposure time x acceptance x flux scale).
+ *   atten_len > 0: Lambda.
+ * n_sensors = 0 (no data: the posterior is the prior) is allowed.  Resets counts.
+ */
+mc_status set_sensors(mc_problem *p, int n_sensors, const double *pos, int n_pix,
+                      const double *dirs, const double *exposure, double atten_len);
+
+/* Observed counts C_p >= 0, [n_sensors*n_pix] (eq. def_likelihood). */
+mc_status set_counts(mc_problem *p, const int32_t *counts);
+
+/*
+ * Log posterior of n_chains states.
+ *   heights: device, [n_chains][S-1][n_rows][n_cols] in the handle's precision.
+ *   logpost: device, [n_chains] float64 (written).
+ *   opacity: device, [n_chains][n_sensors*n_pix] in the handle's precision, or
+ *            NULL; if given, every ray's opacity is written (also for chains
+ *            outside the support).
+ * n_chains = 0 is a no-op.
+ */
+mc_status logpost_batch(mc_problem *p, int n_chains, const void *heights, double *logpost,
+                        void *opacity, void *stream);
+
+/*
+ * Log posterior and its gradient with respect to every surface height,
+ * including the fixed top surface.
+ *   grad: device, [n_chains][S][n_rows][n_cols] in the handle's precision;
+ *         rows of chains outside the support are zero.
+ * The likelihood part uses the crossing form dO/dH_n = (rho_l - rho_{l+1})
+ * sum over crossings of w_n / |d(z-h)/dt|; lp is piecewise smooth in H.
+ */
+mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, double *logpost,
+                             void *grad, void *stream);
+
+typedef struct {
+    int kernel;             /* 0 = random-walk Metropolis, 1 = MALA */
+    int64_t n_steps;        /* MCMC steps per chain in this call (>= 0) */
+    int graph_steps;        /* steps per captured HIP graph (>= 1; 1 = eager launches) */
+    double step_size;       /* RW: proposal sd sigma (m); MALA: eps */
+    const double *inv_mass; /* device [S-1][n_rows][n_cols] diagonal M^-1 (MALA), or NULL = 1 */
+    uint64_t seed;          /* Philox4x32-10 key */
+    uint64_t step_offset;   /* steps already taken: a resumed run uses the same seed
+                               and offset = steps done, and is bitwise identical */
+} mc_run_config;
+
+/*
+ * Run n_steps MCMC steps of every chain (paper Sec. 3.1: only posterior
+ * ratios are needed; many independent chains run on one device and only the
+ * last state is kept).
+ *   heights:  device, [n_chains][S-1][n_rows][n_cols], in/out.
+ *   logpost:  device, [n_chains] float64, in/out; NaN entries are computed first.
+ *   n_accept: device, [n_chains] int64, in/out (incremented per acceptance).
+ * Random numbers: Philox4x32-10 keyed by `seed`, counter (j, step lo32,
+ * step hi16 | tag << 16, chain) with tag 0 = RW proposal normals,
+ * 1 = accept uniform, 2 = MALA normals; chain = index in this call.
+ */
+mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *heights,
+                   double *logpost, int64_t *n_accept, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Test support                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Writes the Philox4x32-10 draws the samplers use, for n consecutive j
+   starting at j0: out_u32[n*4] raw words and out_normal[n*2] Box-Muller
+   normals (device pointers; either may be NULL).  Synchronous. */
+mc_status mc_debug_philox(int hip_device, uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag,
+                          uint32_t j0, int n, uint32_t *out_u32, double *out_normal);
+
+/* Times the ray-march kernel alone: `iters` back-to-back launches of the
+   march over n_chains states (device `heights`, as in logpost_batch) between
+   two HIP events recorded on `stream`; waits for them and writes the mean
+   milliseconds per launch.  For benchmarks and roofline reports. */
+mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
+                        float *ms_per_launch);
+
+/* Library version string. */
+const char *mc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MUONCAVE_H */

@@ -1,0 +1,247 @@
+"""Thin ctypes binding over the muoncave C ABI (include/muoncave.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.
+Device buffers are torch tensors (PyTorch supplies device memory and streams);
+the library must be built (``python -m paper_2603_28907_amd.build``) and the
+binding raises if it is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmuoncave.so")
+
+MC_F32, MC_F64 = 0, 1
+KERNEL_RW, KERNEL_MALA = 0, 1
+_STATUS = {0: "MC_OK", -1: "MC_ERR_ARG", -2: "MC_ERR_STATE", -3: "MC_ERR_NOMEM",
+           -4: "MC_ERR_DEVICE", -5: "MC_ERR_UNSUPPORTED"}
+
+_lib = None
+
+
+class MuonCaveError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class RunConfig(ct.Structure):
+    _fields_ = [("kernel", ct.c_int), ("n_steps", ct.c_int64), ("graph_steps", ct.c_int),
+                ("step_size", ct.c_double), ("inv_mass", ct.c_void_p), ("seed", ct.c_uint64),
+                ("step_offset", ct.c_uint64)]
+
+
+def load_library(path: Optional[str] = None):
+    """Load libmuoncave.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2603_28907_amd.build`")
+    lib = ct.CDLL(path)
+    V, I, D, P = ct.c_void_p, ct.c_int, ct.c_double, ct.POINTER
+    sigs = {
+        "mc_create": (I, [I, I, P(V)]),
+        "mc_destroy": (None, [V]),
+        "mc_last_error": (ct.c_char_p, [V]),
+        "load_geometry_grid": (I, [V, I, I, I, D, D, V, V, V]),
+        "set_sensors": (I, [V, I, V, I, V, V, D]),
+        "set_counts": (I, [V, V]),
+        "logpost_batch": (I, [V, I, V, V, V, V]),
+        "logpost_grad_batch": (I, [V, I, V, V, V, V]),
+        "mcmc_run": (I, [V, P(RunConfig), I, V, V, V, V]),
+        "mc_debug_philox": (I, [I, ct.c_uint64, ct.c_uint32, ct.c_uint64, ct.c_uint32, ct.c_uint32, I, V, V]),
+        "mc_version": (ct.c_char_p, []),
+        "mc_time_march": (I, [V, I, V, I, V, P(ct.c_float)]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_grid", "set_sensors",
+                    "set_counts", "logpost_batch", "logpost_grad_batch", "mcmc_run", "mc_debug_philox",
+                    "mc_version", "mc_time_march")
+
+
+def _host(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hp(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ct.c_void_p(stream.cuda_stream)
+
+
+class Problem:
+    """One inference problem on one GPU (an mc_problem handle)."""
+
+    def __init__(self, device: int = 0, precision: str = "f32"):
+        self.lib = load_library()
+        self.device = int(device)
+        self.precision = precision
+        self.prec = MC_F64 if precision == "f64" else MC_F32
+        h = ct.c_void_p()
+        st = self.lib.mc_create(self.device, self.prec, ct.byref(h))
+        if st != 0:
+            raise MuonCaveError(st, self.lib.mc_last_error(None).decode())
+        self.h = h
+        self.S = self.R = self.C = 0
+        self.n_rays = 0
+
+    # -- errors -------------------------------------------------------------
+    def _check(self, st):
+        if st != 0:
+            raise MuonCaveError(st, self.lib.mc_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.prec == MC_F64 else torch.float32
+
+    # -- set-up ---------------------------------------------------------------
+    def load_geometry_grid(self, n_surfaces, n_rows, n_cols, extent_x, extent_y, density, top, car_r):
+        d, t, r = _host(density), _host(top), _host(car_r)
+        self._check(self.lib.load_geometry_grid(self.h, int(n_surfaces), int(n_rows), int(n_cols),
+                                                float(extent_x), float(extent_y), _hp(d), _hp(t), _hp(r)))
+        self.S, self.R, self.C = int(n_surfaces), int(n_rows), int(n_cols)
+
+    def set_sensors(self, pos, dirs, exposure, atten_len):
+        pos = _host(pos).reshape(-1, 3)
+        n_s = pos.shape[0]
+        dirs = _host(dirs).reshape(n_s, -1, 3) if n_s else np.zeros((0, 0, 3))
+        n_pix = dirs.shape[1] if n_s else 0
+        e = _host(exposure).reshape(n_s, n_pix) if n_s else np.zeros((0, 0))
+        self._check(self.lib.set_sensors(self.h, n_s, _hp(pos), n_pix, _hp(dirs), _hp(e), float(atten_len)))
+        self.n_rays = n_s * n_pix
+
+    def set_counts(self, counts):
+        c = _host(counts, np.int32).reshape(-1)
+        self._check(self.lib.set_counts(self.h, _hp(c)))
+
+    @classmethod
+    def from_scenario(cls, sc, counts=None, device: int = 0, precision: str = "f32"):
+        p = cls(device, precision)
+        p.load_geometry_grid(sc.n_surfaces, sc.n_rows, sc.n_cols, sc.extent_x, sc.extent_y, sc.density,
+                             sc.top, sc.car_r)
+        p.set_sensors(sc.sensor_pos, sc.dirs, sc.exposure, sc.atten_len)
+        c = counts if counts is not None else sc.counts
+        if p.n_rays:
+            if c is None:
+                raise ValueError("scenario has no counts")
+            p.set_counts(c)
+        return p
+
+    # -- device calls ---------------------------------------------------------
+    def _check_tensor(self, t, shape, dtype, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.device.index != self.device:
+            raise ValueError(f"{name} is on cuda:{t.device.index}, the problem on cuda:{self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def heights_shape(self, n_chains):
+        return (n_chains, self.S - 1, self.R, self.C)
+
+    def logpost_batch(self, heights, logpost=None, opacity=None, stream=None):
+        import torch
+        n = int(heights.shape[0])
+        self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
+        if logpost is None:
+            logpost = torch.empty(n, dtype=torch.float64, device=heights.device)
+        self._check_tensor(logpost, (n,), torch.float64, "logpost")
+        if opacity is not None:
+            self._check_tensor(opacity, (n, self.n_rays), self.torch_dtype, "opacity")
+        self._check(self.lib.logpost_batch(self.h, n, ct.c_void_p(heights.data_ptr()),
+                                           ct.c_void_p(logpost.data_ptr()),
+                                           ct.c_void_p(opacity.data_ptr()) if opacity is not None else None,
+                                           _stream_handle(stream, self.device)))
+        return logpost
+
+    def logpost_grad_batch(self, heights, logpost=None, grad=None, stream=None):
+        import torch
+        n = int(heights.shape[0])
+        self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
+        if logpost is None:
+            logpost = torch.empty(n, dtype=torch.float64, device=heights.device)
+        if grad is None:
+            grad = torch.empty((n, self.S, self.R, self.C), dtype=self.torch_dtype, device=heights.device)
+        self._check_tensor(logpost, (n,), torch.float64, "logpost")
+        self._check_tensor(grad, (n, self.S, self.R, self.C), self.torch_dtype, "grad")
+        self._check(self.lib.logpost_grad_batch(self.h, n, ct.c_void_p(heights.data_ptr()),
+                                                ct.c_void_p(logpost.data_ptr()), ct.c_void_p(grad.data_ptr()),
+                                                _stream_handle(stream, self.device)))
+        return logpost, grad
+
+    def mcmc_run(self, heights, logpost, n_accept, n_steps, step_size, seed, step_offset=0, kernel=KERNEL_RW,
+                 graph_steps=1, inv_mass=None, stream=None):
+        import torch
+        n = int(heights.shape[0])
+        self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
+        self._check_tensor(logpost, (n,), torch.float64, "logpost")
+        self._check_tensor(n_accept, (n,), torch.int64, "n_accept")
+        im = None
+        if inv_mass is not None:
+            self._check_tensor(inv_mass, (self.S - 1, self.R, self.C), torch.float64, "inv_mass")
+            im = inv_mass.data_ptr()
+        cfg = RunConfig(int(kernel), int(n_steps), int(graph_steps), float(step_size), im, int(seed),
+                        int(step_offset))
+        self._check(self.lib.mcmc_run(self.h, ct.byref(cfg), n, ct.c_void_p(heights.data_ptr()),
+                                      ct.c_void_p(logpost.data_ptr()), ct.c_void_p(n_accept.data_ptr()),
+                                      _stream_handle(stream, self.device)))
+
+
+def time_march(problem: "Problem", heights, iters: int = 20, stream=None) -> float:
+    """Mean milliseconds per launch of the ray-march kernel (HIP events on `stream`)."""
+    ms = ct.c_float()
+    n = int(heights.shape[0])
+    problem._check_tensor(heights, problem.heights_shape(n), problem.torch_dtype, "heights")
+    problem._check(problem.lib.mc_time_march(problem.h, n, ct.c_void_p(heights.data_ptr()), int(iters),
+                                             _stream_handle(stream, problem.device), ct.byref(ms)))
+    return float(ms.value)
+
+
+def debug_philox(device, seed, chain, step, tag, j0, n):
+    """Raw Philox words [n,4] (uint32 as int64) and Box-Muller normals [n,2] from the GPU."""
+    import torch
+    lib = load_library()
+    words = torch.empty((n, 4), dtype=torch.int32, device=f"cuda:{device}")
+    normals = torch.empty((n, 2), dtype=torch.float64, device=f"cuda:{device}")
+    st = lib.mc_debug_philox(int(device), int(seed), int(chain), int(step), int(tag), int(j0), int(n),
+                             ct.c_void_p(words.data_ptr()), ct.c_void_p(normals.data_ptr()))
+    if st != 0:
+        raise MuonCaveError(st, "mc_debug_philox failed")
+    w = words.cpu().numpy().view(np.uint32)
+    return w, normals.cpu().numpy()

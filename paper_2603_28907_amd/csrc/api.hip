@@ -1,0 +1,693 @@
+// api.hip -- host side of the muoncave C ABI (include/muoncave.h): handle,
+// validation, float64 precompute, device uploads, kernel launches and the
+// graph-captured MCMC loop.  One translation unit; device code lives in the
+// headers it includes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "muoncave.h"
+#include "march.h"
+#include "prior.h"
+
+using namespace mc;
+
+namespace {
+
+constexpr int kMarchBlock = 256;
+constexpr int kPriorBlock = 256;
+constexpr int kMaxNodes = 16384;   // n_rows * n_cols limit (prior workspace lives in LDS)
+
+std::string g_create_error;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct GraphKey {
+    int n = -1, kernel = -1, G = 0;
+    const void *heights = nullptr, *lp = nullptr, *acc = nullptr, *inv_mass = nullptr;
+    double step_size = 0;
+    uint64_t seed = 0;
+    bool operator==(const GraphKey &o) const {
+        return n == o.n && kernel == o.kernel && G == o.G && heights == o.heights && lp == o.lp &&
+               acc == o.acc && inv_mass == o.inv_mass && step_size == o.step_size && seed == o.seed;
+    }
+};
+
+}  // namespace
+
+struct mc_problem {
+    int device = 0;
+    int prec = MC_F32;
+    std::string err;
+    size_t max_lds = 65536;
+    bool have_geom = false, have_sensors = false, have_counts = false;
+    // geometry
+    int S = 0, R = 0, C = 0;
+    double X = 0, Y = 0, ztop = 0, top_min = 0, top_max = 0;
+    std::vector<double> density, top, car_r, logdet, s11;
+    void *d_top = nullptr;      // [N] in prec
+    double *d_top64 = nullptr;  // [N] f64
+    // sensors
+    int n_s = 0, n_pix = 0, n_ray = 0;
+    double atten = 1.0;
+    std::vector<double> pos, dirs, expo;
+    void *d_sensor = nullptr, *d_dx = nullptr, *d_dy = nullptr, *d_dz = nullptr;
+    double *d_expo = nullptr, *d_coL = nullptr;
+    double kconst = 0.0;
+    // workspaces (grow only)
+    DevBuf partials, prop, lptmp;
+    uint64_t *d_step = nullptr;
+    int rays_per_thread = 4;
+    // graph cache
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int old = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        if (old != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (old >= 0 && hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+    }
+};
+
+mc_status fail(mc_problem *p, mc_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (p) p->err = buf;
+    else g_create_error = buf;
+    return s;
+}
+
+#define HIP_TRY(p, expr)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((p), e_ == hipErrorOutOfMemory ? MC_ERR_NOMEM : MC_ERR_DEVICE, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                           \
+    } while (0)
+
+void free_ptr(void *&ptr) {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+}
+void free_ptr(double *&ptr) {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+}
+
+void drop_graph(mc_problem *p) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey = GraphKey();
+}
+
+// Grow-only workspace.  A reallocation invalidates the cached graph, whose
+// kernel nodes hold the old pointers.
+mc_status ensure(mc_problem *p, DevBuf &b, size_t bytes) {
+    if (b.bytes >= bytes) return MC_OK;
+    drop_graph(p);
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    HIP_TRY(p, hipMalloc(&b.p, bytes));
+    b.bytes = bytes;
+    return MC_OK;
+}
+
+template <typename T>
+mc_status upload(mc_problem *p, void *&dst, const std::vector<double> &src) {
+    free_ptr(dst);
+    if (src.empty()) return MC_OK;
+    std::vector<T> tmp(src.begin(), src.end());
+    HIP_TRY(p, hipMalloc(&dst, sizeof(T) * tmp.size()));
+    HIP_TRY(p, hipMemcpy(dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice));
+    return MC_OK;
+}
+
+mc_status upload_prec(mc_problem *p, void *&dst, const std::vector<double> &src) {
+    return p->prec == MC_F64 ? upload<double>(p, dst, src) : upload<float>(p, dst, src);
+}
+
+size_t elem_size(const mc_problem *p) { return p->prec == MC_F64 ? 8 : 4; }
+
+// Eigenvalues of Q = diag(A1) - rA on the periodic R x C grid are
+// mu_km = 4 - 2r(cos(2 pi k/R) + cos(2 pi m/C)); log det Q is their log-sum
+// and Sigma_11 their mean inverse (the diagonal of Q^-1 is constant).
+void torus_car_constants(int R, int C, double r, double &logdet, double &s11) {
+    const double two_pi = 6.283185307179586476925286766559;
+    std::vector<double> cr(R), cc(C);
+    for (int k = 0; k < R; ++k) cr[k] = std::cos(two_pi * k / R);
+    for (int m = 0; m < C; ++m) cc[m] = std::cos(two_pi * m / C);
+    long double sl = 0, si = 0;
+    for (int k = 0; k < R; ++k)
+        for (int m = 0; m < C; ++m) {
+            double mu = 4.0 - 2.0 * r * (cr[k] + cc[m]);
+            sl += std::log(mu);
+            si += 1.0 / mu;
+        }
+    logdet = (double)sl;
+    s11 = (double)(si / ((long double)R * C));
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+
+struct Tiling {
+    int rays_per_block, n_tiles;
+};
+
+Tiling tiling(const mc_problem *p) {
+    Tiling t;
+    t.rays_per_block = kMarchBlock * p->rays_per_thread;
+    t.n_tiles = p->n_ray > 0 ? (p->n_ray + t.rays_per_block - 1) / t.rays_per_block : 0;
+    return t;
+}
+
+bool top_in_lds(const mc_problem *p) {
+    size_t N = (size_t)p->R * p->C;
+    return N * p->S * elem_size(p) + 4096 <= p->max_lds;
+}
+
+template <typename T>
+MarchParams<T> march_params(const mc_problem *p, const T *heights, T *opacity, double *partials) {
+    MarchParams<T> P;
+    Tiling t = tiling(p);
+    P.R = p->R;
+    P.C = p->C;
+    P.n_ray = p->n_ray;
+    P.n_pix = p->n_pix;
+    P.n_tiles = t.n_tiles;
+    P.rays_per_block = t.rays_per_block;
+    P.hx = (T)(p->X / (p->R - 1));
+    P.hy = (T)(p->Y / (p->C - 1));
+    P.ihx = (T)((p->R - 1) / p->X);
+    P.ihy = (T)((p->C - 1) / p->Y);
+    P.xmax = (T)(p->R - 1) * P.hx;
+    P.ymax = (T)(p->C - 1) * P.hy;
+    P.ztop = (T)p->ztop;
+    // rounding margin for the certain-below / certain-above tests
+    double eps = sizeof(T) == 4 ? 1.1920929e-07 : 2.220446049250313e-16;
+    double zscale = std::fabs(p->ztop) + std::fabs(p->top_min) + 1.0;
+    P.margin = (T)(256.0 * eps * zscale);
+    P.top_min = (T)p->top_min;
+    P.top_max = (T)p->top_max;
+    for (int l = 0; l < kMaxSurfaces; ++l) {
+        double here = l < p->S ? p->density[l] : 0.0;
+        double above = l + 1 < p->S ? p->density[l + 1] : 0.0;
+        P.rho_diff[l] = (T)(here - above);
+    }
+    P.sensor = (const T *)p->d_sensor;
+    P.dx = (const T *)p->d_dx;
+    P.dy = (const T *)p->d_dy;
+    P.dz = (const T *)p->d_dz;
+    P.c_over_L = p->d_coL;
+    P.expo = p->d_expo;
+    P.inv_L = 1.0 / p->atten;
+    P.top = (const T *)p->d_top;
+    P.heights = heights;
+    P.opacity = opacity;
+    P.partials = partials;
+    P.only_nan = nullptr;
+    return P;
+}
+
+template <typename T, int S>
+mc_status launch_march(mc_problem *p, int n, const T *heights, T *opacity, double *partials, hipStream_t st,
+                       const double *only_nan = nullptr) {
+    MarchParams<T> P = march_params<T>(p, heights, opacity, partials);
+    P.only_nan = only_nan;
+    size_t N = (size_t)p->R * p->C;
+    bool tl = top_in_lds(p);
+    size_t lds = N * (tl ? S : S - 1) * sizeof(T);
+    if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+    dim3 grid(P.n_tiles, n), block(kMarchBlock);
+    if (tl) {
+        auto k = k_march_lik<T, S, true, kMarchBlock>;
+        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, grid, block, lds, st, P);
+    } else {
+        auto k = k_march_lik<T, S, false, kMarchBlock>;
+        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, grid, block, lds, st, P);
+    }
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+template <typename T>
+PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double *partials) {
+    PriorParams<T> P;
+    memset(&P, 0, sizeof(P));
+    P.R = p->R;
+    P.C = p->C;
+    P.n_tiles = tiling(p).n_tiles;
+    P.has_lik = p->n_ray > 0 ? 1 : 0;
+    P.heights = heights;
+    P.top64 = p->d_top64;
+    for (int l = 0; l < p->S - 1; ++l) {
+        P.logdet[l] = p->logdet[l];
+        P.s11[l] = p->s11[l];
+        P.r[l] = p->car_r[l];
+    }
+    P.partials = partials;
+    P.kconst = p->kconst;
+    return P;
+}
+
+template <typename T, int S>
+mc_status launch_prior(mc_problem *p, int n, const PriorParams<T> &P, hipStream_t st) {
+    size_t lds = sizeof(double) * (size_t)p->R * p->C;
+    auto k = k_prior_finalize<T, S, kPriorBlock>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(n), dim3(kPriorBlock), lds, st, P);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+mc_status check_ready(mc_problem *p) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_geom) return fail(p, MC_ERR_STATE, "load_geometry_grid has not been called");
+    if (!p->have_sensors) return fail(p, MC_ERR_STATE, "set_sensors has not been called");
+    if (p->n_ray > 0 && !p->have_counts) return fail(p, MC_ERR_STATE, "set_counts has not been called");
+    return MC_OK;
+}
+
+template <typename T, int S>
+mc_status logpost_impl(mc_problem *p, int n, const T *heights, double *lp, T *opacity, hipStream_t st,
+                       const double *only_nan = nullptr) {
+    Tiling t = tiling(p);
+    mc_status s;
+    if (p->n_ray > 0) {
+        if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+        if ((s = launch_march<T, S>(p, n, heights, opacity, (double *)p->partials.p, st, only_nan)) != MC_OK)
+            return s;
+    }
+    PriorParams<T> P = prior_params<T>(p, heights, (const double *)p->partials.p);
+    P.lp_out = lp;
+    P.only_nan = only_nan;
+    return launch_prior<T, S>(p, n, P, st);
+}
+
+template <typename T>
+mc_status logpost_dispatch(mc_problem *p, int n, const void *heights, double *lp, void *opacity, hipStream_t st) {
+    switch (p->S) {
+        case 2: return logpost_impl<T, 2>(p, n, (const T *)heights, lp, (T *)opacity, st);
+        case 3: return logpost_impl<T, 3>(p, n, (const T *)heights, lp, (T *)opacity, st);
+        case 4: return logpost_impl<T, 4>(p, n, (const T *)heights, lp, (T *)opacity, st);
+    }
+    return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
+}
+
+// One random-walk Metropolis step (propose, march the proposals, prior +
+// decision + copy) with the step number read from p->d_step plus k.
+template <typename T, int S>
+mc_status rw_step(mc_problem *p, int n, T *heights, double *lp, int64_t *acc, const mc_run_config *cfg, int k,
+                  hipStream_t st) {
+    const int M = (S - 1) * p->R * p->C;
+    T *prop = (T *)p->prop.p;
+    dim3 pg((M / 2 + 1 + 255) / 256, n);
+    hipLaunchKernelGGL(k_propose_rw<T>, pg, dim3(256), 0, st, (const T *)heights, prop, M, cfg->step_size,
+                       cfg->seed, (const uint64_t *)p->d_step, k);
+    HIP_TRY(p, hipGetLastError());
+    mc_status s;
+    if (p->n_ray > 0) {
+        if ((s = launch_march<T, S>(p, n, prop, nullptr, (double *)p->partials.p, st)) != MC_OK) return s;
+    }
+    PriorParams<T> P = prior_params<T>(p, prop, (const double *)p->partials.p);
+    P.mh = 1;
+    P.lp_cur = lp;
+    P.n_acc = acc;
+    P.state = heights;
+    P.seed = cfg->seed;
+    P.step_base = p->d_step;
+    P.step_k = k;
+    return launch_prior<T, S>(p, n, P, st);
+}
+
+template <typename T, int S>
+mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, double *lp, int64_t *acc,
+                    hipStream_t st) {
+    const int M = (S - 1) * p->R * p->C;
+    Tiling t = tiling(p);
+    mc_status s;
+    if ((s = ensure(p, p->prop, sizeof(T) * (size_t)n * M)) != MC_OK) return s;
+    if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
+    if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+    // initial log posterior where the caller passed NaN (other chains exit at once)
+    if ((s = logpost_impl<T, S>(p, n, heights, (double *)p->lptmp.p, nullptr, st, lp)) != MC_OK) return s;
+    hipLaunchKernelGGL(k_fill_nan, dim3((n + 255) / 256), dim3(256), 0, st, lp, (const double *)p->lptmp.p, n);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, p->d_step, cfg->step_offset);
+    HIP_TRY(p, hipGetLastError());
+    if (cfg->kernel != 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA is not available in this build");
+    const int G = cfg->graph_steps < 1 ? 1 : cfg->graph_steps;
+    int64_t done = 0;
+    if (G > 1 && cfg->n_steps >= G) {
+        GraphKey key;
+        key.n = n;
+        key.kernel = cfg->kernel;
+        key.G = G;
+        key.heights = heights;
+        key.lp = lp;
+        key.acc = acc;
+        key.inv_mass = cfg->inv_mass;
+        key.step_size = cfg->step_size;
+        key.seed = cfg->seed;
+        if (!(p->gexec && p->gkey == key)) {
+            if (p->gexec) {
+                (void)hipGraphExecDestroy(p->gexec);
+                p->gexec = nullptr;
+            }
+            if (!p->cap_stream) HIP_TRY(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+            HIP_TRY(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+            mc_status cs = MC_OK;
+            for (int k = 0; k < G && cs == MC_OK; ++k) cs = rw_step<T, S>(p, n, heights, lp, acc, cfg, k, p->cap_stream);
+            if (cs == MC_OK) hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, p->cap_stream, p->d_step, (uint64_t)G);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+            if (cs != MC_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return cs;
+            }
+            if (e != hipSuccess) return fail(p, MC_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                p->gexec = nullptr;
+                return fail(p, MC_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+            }
+            p->gkey = key;
+        }
+        for (; done + G <= cfg->n_steps; done += G) HIP_TRY(p, hipGraphLaunch(p->gexec, st));
+    }
+    // remaining steps as eager launches
+    const int64_t rest = cfg->n_steps - done;
+    for (int64_t k = 0; k < rest; ++k)
+        if ((s = rw_step<T, S>(p, n, heights, lp, acc, cfg, (int)k, st)) != MC_OK) return s;
+    if (rest > 0) hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, p->d_step, (uint64_t)rest);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+template <typename T, int S>
+mc_status time_march_impl(mc_problem *p, int n, const T *heights, int iters, hipStream_t st, float *ms) {
+    Tiling t = tiling(p);
+    mc_status s;
+    if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+    hipEvent_t e0, e1;
+    HIP_TRY(p, hipEventCreate(&e0));
+    HIP_TRY(p, hipEventCreate(&e1));
+    HIP_TRY(p, hipEventRecord(e0, st));
+    for (int i = 0; i < iters && s == MC_OK; ++i) s = launch_march<T, S>(p, n, heights, nullptr, (double *)p->partials.p, st);
+    HIP_TRY(p, hipEventRecord(e1, st));
+    HIP_TRY(p, hipEventSynchronize(e1));
+    float total = 0.f;
+    HIP_TRY(p, hipEventElapsedTime(&total, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = total / (float)iters;
+    return s;
+}
+
+template <typename T>
+mc_status time_march_dispatch(mc_problem *p, int n, const void *heights, int iters, hipStream_t st, float *ms) {
+    switch (p->S) {
+        case 2: return time_march_impl<T, 2>(p, n, (const T *)heights, iters, st, ms);
+        case 3: return time_march_impl<T, 3>(p, n, (const T *)heights, iters, st, ms);
+        case 4: return time_march_impl<T, 4>(p, n, (const T *)heights, iters, st, ms);
+    }
+    return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
+}
+
+template <typename T>
+mc_status mcmc_dispatch(mc_problem *p, const mc_run_config *cfg, int n, void *heights, double *lp, int64_t *acc,
+                        hipStream_t st) {
+    switch (p->S) {
+        case 2: return mcmc_impl<T, 2>(p, cfg, n, (T *)heights, lp, acc, st);
+        case 3: return mcmc_impl<T, 3>(p, cfg, n, (T *)heights, lp, acc, st);
+        case 4: return mcmc_impl<T, 4>(p, cfg, n, (T *)heights, lp, acc, st);
+    }
+    return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *mc_version(void) { return "muoncave 0.1 (gfx950)"; }
+
+mc_status mc_create(int hip_device, int precision, mc_problem **out) {
+    if (!out) return fail(nullptr, MC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (precision != MC_F32 && precision != MC_F64) return fail(nullptr, MC_ERR_ARG, "precision %d", precision);
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(nullptr, MC_ERR_DEVICE, "no HIP device");
+    if (hip_device < 0 || hip_device >= count) return fail(nullptr, MC_ERR_ARG, "device %d of %d", hip_device, count);
+    mc_problem *p = new mc_problem();
+    p->device = hip_device;
+    p->prec = precision;
+    DeviceGuard g(hip_device);
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess && lds > 0)
+        p->max_lds = (size_t)lds;
+    if (hipMalloc((void **)&p->d_step, sizeof(uint64_t)) != hipSuccess) {
+        delete p;
+        return fail(nullptr, MC_ERR_NOMEM, "hipMalloc failed");
+    }
+    *out = p;
+    return MC_OK;
+}
+
+void mc_destroy(mc_problem *p) {
+    if (!p) return;
+    DeviceGuard g(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    free_ptr(p->d_top);
+    free_ptr(p->d_top64);
+    free_ptr(p->d_sensor);
+    free_ptr(p->d_dx);
+    free_ptr(p->d_dy);
+    free_ptr(p->d_dz);
+    free_ptr(p->d_expo);
+    free_ptr(p->d_coL);
+    for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp})
+        if (b->p) (void)hipFree(b->p);
+    if (p->d_step) (void)hipFree(p->d_step);
+    delete p;
+}
+
+const char *mc_last_error(const mc_problem *p) { return p ? p->err.c_str() : g_create_error.c_str(); }
+
+mc_status load_geometry_grid(mc_problem *p, int n_surfaces, int n_rows, int n_cols, double extent_x_m,
+                             double extent_y_m, const double *density, const double *top, const double *car_r) {
+    if (!p) return MC_ERR_ARG;
+    if (n_surfaces < 2 || n_surfaces > kMaxSurfaces) return fail(p, MC_ERR_ARG, "n_surfaces %d not in [2,4]", n_surfaces);
+    if (n_rows < 3 || n_cols < 3 || n_rows > 256 || n_cols > 256 || n_rows * n_cols > kMaxNodes)
+        return fail(p, MC_ERR_ARG, "grid %dx%d: need 3 <= side <= 256 and rows*cols <= %d", n_rows, n_cols, kMaxNodes);
+    if (!(extent_x_m > 0) || !(extent_y_m > 0) || !std::isfinite(extent_x_m) || !std::isfinite(extent_y_m))
+        return fail(p, MC_ERR_ARG, "extents must be positive");
+    if (!density || !top || !car_r) return fail(p, MC_ERR_ARG, "NULL array");
+    for (int l = 0; l < n_surfaces; ++l)
+        if (!(density[l] >= 0) || !std::isfinite(density[l])) return fail(p, MC_ERR_ARG, "density[%d] invalid", l);
+    for (int l = 0; l < n_surfaces - 1; ++l)
+        if (!(car_r[l] >= 0.0 && car_r[l] < 1.0)) return fail(p, MC_ERR_ARG, "car_r[%d] not in [0,1)", l);
+    const int N = n_rows * n_cols;
+    double tmin = INFINITY, tmax = -INFINITY;
+    for (int i = 0; i < N; ++i) {
+        if (!(top[i] > 0) || !std::isfinite(top[i])) return fail(p, MC_ERR_ARG, "top[%d] must be > 0", i);
+        tmin = std::min(tmin, top[i]);
+        tmax = std::max(tmax, top[i]);
+    }
+    DeviceGuard g(p->device);
+    p->have_geom = p->have_sensors = p->have_counts = false;
+    p->S = n_surfaces;
+    p->R = n_rows;
+    p->C = n_cols;
+    p->X = extent_x_m;
+    p->Y = extent_y_m;
+    p->density.assign(density, density + n_surfaces);
+    p->top.assign(top, top + N);
+    p->car_r.assign(car_r, car_r + n_surfaces - 1);
+    p->ztop = tmax;
+    p->top_min = tmin;
+    p->top_max = tmax;
+    p->logdet.resize(n_surfaces - 1);
+    p->s11.resize(n_surfaces - 1);
+    for (int l = 0; l < n_surfaces - 1; ++l) torus_car_constants(n_rows, n_cols, car_r[l], p->logdet[l], p->s11[l]);
+    mc_status s;
+    if ((s = upload_prec(p, p->d_top, p->top)) != MC_OK) return s;
+    void *t64 = p->d_top64;
+    if ((s = upload<double>(p, t64, p->top)) != MC_OK) return s;
+    p->d_top64 = (double *)t64;
+    drop_graph(p);
+    p->have_geom = true;
+    return MC_OK;
+}
+
+mc_status set_sensors(mc_problem *p, int n_sensors, const double *pos, int n_pix, const double *dirs,
+                      const double *exposure, double atten_len) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_geom) return fail(p, MC_ERR_STATE, "load_geometry_grid has not been called");
+    if (n_sensors < 0 || n_pix < 0) return fail(p, MC_ERR_ARG, "negative sizes");
+    if (n_sensors > 0 && n_pix == 0) return fail(p, MC_ERR_ARG, "n_pix must be > 0 when there are sensors");
+    if ((long long)n_sensors * n_pix > (1LL << 30)) return fail(p, MC_ERR_ARG, "too many rays");
+    if (!(atten_len > 0) || !std::isfinite(atten_len)) return fail(p, MC_ERR_ARG, "atten_len must be > 0");
+    const int n_ray = n_sensors * n_pix;
+    if (n_ray > 0 && (!pos || !dirs || !exposure)) return fail(p, MC_ERR_ARG, "NULL array");
+    for (int s = 0; s < n_sensors; ++s) {
+        double x = pos[3 * s], y = pos[3 * s + 1], z = pos[3 * s + 2];
+        if (!(x >= 0 && x <= p->X && y >= 0 && y <= p->Y && z >= 0 && z < p->ztop))
+            return fail(p, MC_ERR_ARG, "sensor %d outside the box", s);
+    }
+    for (int r = 0; r < n_ray; ++r) {
+        double dx = dirs[3 * r], dy = dirs[3 * r + 1], dz = dirs[3 * r + 2];
+        double nrm = std::sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(dz > 0) || !(std::fabs(nrm - 1.0) < 1e-6)) return fail(p, MC_ERR_ARG, "dirs[%d] must be a unit vector with d_z > 0", r);
+        if (!(exposure[r] > 0) || !std::isfinite(exposure[r])) return fail(p, MC_ERR_ARG, "exposure[%d] must be > 0", r);
+    }
+    DeviceGuard g(p->device);
+    p->have_sensors = p->have_counts = false;
+    p->n_s = n_sensors;
+    p->n_pix = n_pix;
+    p->n_ray = n_ray;
+    p->atten = atten_len;
+    p->pos.assign(pos, pos + 3 * (size_t)n_sensors);
+    std::vector<double> dx(n_ray), dy(n_ray), dz(n_ray);
+    for (int r = 0; r < n_ray; ++r) {
+        dx[r] = dirs[3 * r];
+        dy[r] = dirs[3 * r + 1];
+        dz[r] = dirs[3 * r + 2];
+    }
+    p->expo.assign(exposure, exposure + n_ray);
+    mc_status s;
+    if ((s = upload_prec(p, p->d_sensor, p->pos)) != MC_OK) return s;
+    if ((s = upload_prec(p, p->d_dx, dx)) != MC_OK) return s;
+    if ((s = upload_prec(p, p->d_dy, dy)) != MC_OK) return s;
+    if ((s = upload_prec(p, p->d_dz, dz)) != MC_OK) return s;
+    void *e = p->d_expo;
+    if ((s = upload<double>(p, e, p->expo)) != MC_OK) return s;
+    p->d_expo = (double *)e;
+    drop_graph(p);
+    p->have_sensors = true;
+    return MC_OK;
+}
+
+mc_status set_counts(mc_problem *p, const int32_t *counts) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_sensors) return fail(p, MC_ERR_STATE, "set_sensors has not been called");
+    if (p->n_ray > 0 && !counts) return fail(p, MC_ERR_ARG, "counts is NULL");
+    std::vector<double> coL(p->n_ray);
+    long double K = 0;
+    for (int r = 0; r < p->n_ray; ++r) {
+        if (counts[r] < 0) return fail(p, MC_ERR_ARG, "counts[%d] < 0", r);
+        double c = counts[r];
+        coL[r] = c / p->atten;
+        K += c * std::log(p->expo[r]) - std::lgamma(c + 1.0);
+    }
+    DeviceGuard g(p->device);
+    drop_graph(p);   // the graph holds the old count pointer and constant
+    void *d = p->d_coL;
+    mc_status s;
+    if ((s = upload<double>(p, d, coL)) != MC_OK) return s;
+    p->d_coL = (double *)d;
+    p->kconst = (double)K;
+    p->have_counts = true;
+    return MC_OK;
+}
+
+mc_status logpost_batch(mc_problem *p, int n_chains, const void *heights, double *logpost, void *opacity,
+                        void *stream) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    if (n_chains < 0) return fail(p, MC_ERR_ARG, "n_chains < 0");
+    if (n_chains == 0) return MC_OK;
+    if (!heights || !logpost) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    return p->prec == MC_F64 ? logpost_dispatch<double>(p, n_chains, heights, logpost, opacity, st)
+                             : logpost_dispatch<float>(p, n_chains, heights, logpost, opacity, st);
+}
+
+mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, double *logpost, void *grad,
+                             void *stream) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    (void)n_chains;
+    (void)heights;
+    (void)logpost;
+    (void)grad;
+    (void)stream;
+    return fail(p, MC_ERR_UNSUPPORTED, "logpost_grad_batch is not available in this build");
+}
+
+mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *heights, double *logpost,
+                   int64_t *n_accept, void *stream) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    if (!cfg) return fail(p, MC_ERR_ARG, "cfg is NULL");
+    if (n_chains < 0 || cfg->n_steps < 0) return fail(p, MC_ERR_ARG, "negative sizes");
+    if (n_chains == 0) return MC_OK;
+    if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
+    if (!heights || !logpost || !n_accept) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    if (!(cfg->step_size >= 0) || !std::isfinite(cfg->step_size)) return fail(p, MC_ERR_ARG, "step_size invalid");
+    if (cfg->kernel != 0 && cfg->kernel != 1) return fail(p, MC_ERR_ARG, "kernel %d", cfg->kernel);
+    if (cfg->step_offset + (uint64_t)cfg->n_steps >= (1ULL << 48)) return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    return p->prec == MC_F64 ? mcmc_dispatch<double>(p, cfg, n_chains, heights, logpost, n_accept, st)
+                             : mcmc_dispatch<float>(p, cfg, n_chains, heights, logpost, n_accept, st);
+}
+
+mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
+                        float *ms_per_launch) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    if (n_chains <= 0 || n_chains > 65535 || iters <= 0 || !heights || !ms_per_launch)
+        return fail(p, MC_ERR_ARG, "invalid arguments");
+    if (p->n_ray == 0) return fail(p, MC_ERR_STATE, "no rays");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    return p->prec == MC_F64 ? time_march_dispatch<double>(p, n_chains, heights, iters, st, ms_per_launch)
+                             : time_march_dispatch<float>(p, n_chains, heights, iters, st, ms_per_launch);
+}
+
+mc_status mc_debug_philox(int hip_device, uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t j0,
+                          int n, uint32_t *out_u32, double *out_normal) {
+    if (n < 0) return MC_ERR_ARG;
+    if (n == 0) return MC_OK;
+    DeviceGuard g(hip_device);
+    hipLaunchKernelGGL(k_debug_philox, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)0, seed, chain, step, tag, j0,
+                       n, out_u32, out_normal);
+    if (hipGetLastError() != hipSuccess) return MC_ERR_DEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return MC_ERR_DEVICE;
+    return MC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+"""GPU parity of the forward model and log posterior against the FP64 oracle.
+
+Tolerances: opacities relative 1e-5 in float32 mode (1e-10 in float64 mode),
+widened only for rays whose crossings are ill-conditioned; the float64
+likelihood stage within 1e-6 per pixel; the float64 prior within 1e-9
+relative; end-to-end float32 log posterior within
+sum_p |lambda_p - C_p| |dO_p| / Lambda + 1e-6 n_ray.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_28907_amd import inputs
+from tests.gpu_common import opacity_tolerance, require_gpu, rounded_states, say, to_dev
+from tests.helpers import make_scenario
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def tiny(oracle_mod):
+    sc = inputs.tiny_bumps(seed=0)
+    sc.counts = oracle_mod.make_counts(sc, seed=1)
+    return sc
+
+
+def run_gpu(torch, sc, states, precision, export=True):
+    from paper_2603_28907_amd.binding import Problem
+    prob = Problem.from_scenario(sc, precision=precision)
+    dt = torch.float64 if precision == "f64" else torch.float32
+    H = to_dev(states, dt)
+    n = H.shape[0]
+    O = torch.empty((n, sc.n_rays), dtype=dt, device="cuda:0") if export else None
+    lp = prob.logpost_batch(H, opacity=O)
+    torch.cuda.synchronize()
+    return lp.cpu().numpy(), (O.double().cpu().numpy() if export else None), prob
+
+
+def check_against_oracle(oracle_mod, sc, states, lp_gpu, O_gpu, precision, label):
+    orc = oracle_mod.OracleProblem(sc)
+    st = rounded_states(states, precision)
+    worst_plain = 0.0
+    for c in range(st.shape[0]):
+        O_ref = orc.opacity(st[c])
+        rs = orc.ray_stats(st[c])
+        tol = opacity_tolerance(O_ref, rs["crossings"], rs["min_fprime"], precision)
+        err = np.abs(O_gpu[c] - O_ref)
+        bad = np.nonzero(err > tol)[0]
+        assert bad.size == 0, (label, c, bad[:5], O_gpu[c][bad[:5]], O_ref[bad[:5]], rs["min_fprime"][bad[:5]])
+        rel = err / np.maximum(np.abs(O_ref), 1e-30)
+        worst_plain = max(worst_plain, float(np.quantile(rel, 0.999)))
+        # likelihood stage from the GPU's own opacities (float64 per-pixel terms)
+        lpr = orc.log_prior(st[c])
+        ll_from_gpu_O = orc.loglik(O_gpu[c])
+        n_ray = sc.n_rays
+        if math.isfinite(lpr):
+            assert abs(lp_gpu[c] - (lpr + ll_from_gpu_O)) <= 1e-6 * n_ray + 1e-9 * abs(lpr), (label, c)
+            # end-to-end bound
+            lam = sc.exposure.reshape(-1) * np.exp(-O_ref / sc.atten_len)
+            bound = np.sum(np.abs(lam - sc.counts.reshape(-1)) * np.abs(O_gpu[c] - O_ref)) / sc.atten_len
+            lp_ref = lpr + orc.loglik(O_ref)
+            assert abs(lp_gpu[c] - lp_ref) <= 1.5 * bound + 1e-6 * n_ray, (label, c, lp_gpu[c], lp_ref, bound)
+        else:
+            assert lp_gpu[c] == -math.inf
+    limit = 1e-5 if precision == "f32" else 1e-10
+    assert worst_plain <= limit, (label, worst_plain)
+    say(f"{label}: 99.9th pct relative opacity error {worst_plain:.2e}")
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tiny_cave_parity(torch_mod, oracle_mod, tiny, precision):
+    states = np.concatenate([tiny.truth[None], inputs.init_states(tiny, 5, seed=2)])
+    lp, O, _ = run_gpu(torch_mod, tiny, states, precision)
+    check_against_oracle(oracle_mod, tiny, states, lp, O, precision, f"tiny/{precision}")
+    if precision == "f64":
+        ref = oracle_mod.OracleProblem(tiny).logpost_batch(states)
+        np.testing.assert_allclose(lp, ref, rtol=1e-11, atol=1e-6)
+
+
+def test_repeat_is_bitwise(torch_mod, tiny):
+    states = inputs.init_states(tiny, 8, seed=4)
+    a, Oa, _ = run_gpu(torch_mod, tiny, states, "f32")
+    b, Ob, _ = run_gpu(torch_mod, tiny, states, "f32")
+    assert np.array_equal(a, b) and np.array_equal(Oa, Ob)
+
+
+def test_out_of_support_and_edge_inputs(torch_mod, oracle_mod, tiny):
+    st = inputs.init_states(tiny, 4, seed=5)
+    st[1, 0, 3, 3] = st[1, 1, 3, 3] + 0.5       # muck top above the cave back
+    st[2, 1, 0, 0] = 250.0                        # above the terrain
+    st[3, 0, 5, 5] = -1.0                         # below the floor
+    lp, O, _ = run_gpu(torch_mod, tiny, st, "f64")
+    assert np.isfinite(lp[0]) and np.all(lp[1:] == -math.inf)
+    orc = oracle_mod.OracleProblem(tiny)
+    for c in range(4):   # opacities are still exported for every chain
+        np.testing.assert_allclose(O[c], orc.opacity(st[c]), rtol=1e-10, atol=1e-9)
+
+
+def test_no_sensors_gives_prior(torch_mod, oracle_mod):
+    sc = inputs.tiny_bumps(seed=3)
+    sc0 = make_scenario(3, sc.n_rows, sc.n_cols, sc.extent_x, sc.extent_y, sc.truth, sc.top, sc.density,
+                        np.zeros((0, 3)), None, car_r=sc.car_r)
+    states = inputs.init_states(sc, 3, seed=1)
+    lp, _, _ = run_gpu(torch_mod, sc0, states, "f64", export=False)
+    orc = oracle_mod.OracleProblem(sc0)
+    for c in range(3):
+        assert lp[c] == pytest.approx(orc.log_prior(states[c]), rel=1e-11)
+
+
+@pytest.mark.parametrize("S,R,C,n_pix", [(2, 3, 3, 7), (4, 5, 9, 33), (3, 20, 12, 100)])
+def test_shapes_and_ragged_tiles(torch_mod, oracle_mod, S, R, C, n_pix):
+    """Minimum grid, non-square grids, two and four surfaces, ray counts that
+    leave a ragged last tile."""
+    rng = np.random.default_rng(R * 100 + C)
+    X, Y = 10.0 * (R - 1), 12.0 * (C - 1)
+    top = 100 + rng.uniform(-3, 3, (R, C))
+    lo = np.zeros((R, C))
+    free = []
+    for l in range(S - 1):
+        h = lo + (top - lo) * rng.uniform(0.2, 0.5, (R, C))
+        free.append(h)
+        lo = h
+    free = np.stack(free)
+    n_s = 3
+    pos = np.stack([rng.uniform(0, X, n_s), rng.uniform(0, Y, n_s), np.zeros(n_s)], 1)
+    th = rng.uniform(0, math.radians(40), (n_s, n_pix))
+    ph = rng.uniform(0, 2 * math.pi, (n_s, n_pix))
+    dirs = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], -1)
+    dens = rng.uniform(0.5, 3.0, S)
+    sc = make_scenario(S, R, C, X, Y, free, top, dens, pos, dirs, car_r=np.full(S - 1, 0.8))
+    orc = oracle_mod.OracleProblem(sc)
+    lam = orc.expected_counts(free)
+    sc.counts = inputs.draw_counts(lam, 3).reshape(n_s, -1)
+    states = np.stack([free, free * 0.97, free * 1.01])
+    for precision in ("f64", "f32"):
+        lp, O, _ = run_gpu(torch_mod, sc, states, precision)
+        check_against_oracle(oracle_mod, sc, states, lp, O, precision, f"S{S}_{R}x{C}_{n_pix}/{precision}")
+
+
+def test_paper_scale_sampled_chains(torch_mod, oracle_mod):
+    """64x64 grid, 8 sensors x 64x64 pixels, 1024 chains in the benchmark's
+    launch configuration; 6 sampled chains are compared with the oracle."""
+    sc = inputs.grf_cave(seed=10)
+    sc.counts = oracle_mod.make_counts(sc, seed=11)
+    states = inputs.init_states(sc, 1024, seed=12)
+    say("paper-scale: running GPU logpost on 1024 chains")
+    lp, O, _ = run_gpu(torch_mod, sc, states, "f32")
+    assert np.all(np.isfinite(lp))
+    pick = [0, 1, 511, 777, 1022, 1023]
+    check_against_oracle(oracle_mod, sc, states[pick], lp[pick], O[pick], "f32", "grf_cave_64/f32")
+
+
+def test_large_grid_top_in_global_memory(torch_mod, oracle_mod):
+    """128x128 grid in float32: the top surface does not fit in LDS beside the
+    free surfaces and is read from global memory."""
+    sc = inputs.grf_cave(seed=10, n_grid=128, n_sensors=2, pix_side=24)
+    sc.counts = oracle_mod.make_counts(sc, seed=11)
+    states = inputs.init_states(sc, 3, seed=12)
+    lp, O, _ = run_gpu(torch_mod, sc, states, "f32")
+    check_against_oracle(oracle_mod, sc, states, lp, O, "f32", "grf_cave_128/f32")
+
+
+def test_philox_bitwise_vs_oracle(torch_mod, oracle_mod):
+    from paper_2603_28907_amd.binding import debug_philox
+    for seed, chain, step, tag in [(0, 0, 0, 0), (12345678901234, 7, 99, 1), (5, 3, (1 << 32) + 17, 2)]:
+        w, z = debug_philox(0, seed, chain, step, tag, 1000, 4096)
+        ref_w = np.array([oracle_mod.raw_philox(seed, chain, step, tag, 1000 + i) for i in range(4096)])
+        assert np.array_equal(w, ref_w)
+        ref_z = np.array([oracle_mod.normal_pair(seed, chain, step, tag, 1000 + i) for i in range(4096)])
+        np.testing.assert_allclose(z, ref_z, rtol=1e-14, atol=1e-15)
+
+
+def test_api_errors(torch_mod, tiny):
+    from paper_2603_28907_amd.binding import MuonCaveError, Problem
+    p = Problem(0, "f32")
+    H = to_dev(tiny.truth[None], torch_mod.float32)
+    with pytest.raises(MuonCaveError, match="MC_ERR_STATE"):
+        p.S, p.R, p.C = 3, 16, 16
+        p.logpost_batch(H)
+    with pytest.raises(MuonCaveError, match="MC_ERR_ARG"):
+        p.load_geometry_grid(3, 2, 16, 100, 100, tiny.density, np.ones((2, 16)), tiny.car_r)
+    with pytest.raises(MuonCaveError, match="MC_ERR_ARG"):
+        p.load_geometry_grid(3, 16, 16, 100, 100, tiny.density, tiny.top, [0.5, 1.0])
+    p.load_geometry_grid(3, 16, 16, 100, 100, tiny.density, tiny.top, tiny.car_r)
+    with pytest.raises(MuonCaveError, match="MC_ERR_ARG"):
+        p.set_sensors([[50, 50, 0]], [[[0, 0, -1.0]]], [[1e4]], 400.0)
+    p.set_sensors(tiny.sensor_pos, tiny.dirs, tiny.exposure, tiny.atten_len)
+    with pytest.raises(MuonCaveError, match="MC_ERR_STATE"):
+        p.logpost_batch(H)
+    bad = tiny.counts.copy()
+    bad[0, 0] = -1
+    with pytest.raises(MuonCaveError, match="MC_ERR_ARG"):
+        p.set_counts(bad)
+    p.set_counts(tiny.counts)
+    lp = p.logpost_batch(H)
+    torch_mod.cuda.synchronize()
+    assert np.isfinite(lp.cpu().numpy()).all()
+    # n_chains = 0 is a no-op
+    p.logpost_batch(H[:0], logpost=torch_mod.empty(0, dtype=torch_mod.float64, device="cuda:0"))
