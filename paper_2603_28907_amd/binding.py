@@ -30,6 +30,11 @@ class MuonCaveError(RuntimeError):
         self.status = status
 
 
+class Tuning(ct.Structure):
+    _fields_ = [("march_variant", ct.c_int), ("block", ct.c_int), ("queue", ct.c_int),
+                ("rays_per_thread", ct.c_int), ("top_in_lds", ct.c_int)]
+
+
 class RunConfig(ct.Structure):
     _fields_ = [("kernel", ct.c_int), ("n_steps", ct.c_int64), ("graph_steps", ct.c_int),
                 ("step_size", ct.c_double), ("inv_mass", ct.c_void_p), ("seed", ct.c_uint64),
@@ -59,6 +64,8 @@ def load_library(path: Optional[str] = None):
         "mc_debug_philox": (I, [I, ct.c_uint64, ct.c_uint32, ct.c_uint64, ct.c_uint32, ct.c_uint32, I, V, V]),
         "mc_version": (ct.c_char_p, []),
         "mc_time_march": (I, [V, I, V, I, V, P(ct.c_float)]),
+        "mc_set_tuning": (I, [V, P(Tuning)]),
+        "mc_get_tuning": (I, [V, P(Tuning)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -70,7 +77,7 @@ def load_library(path: Optional[str] = None):
 
 EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_grid", "set_sensors",
                     "set_counts", "logpost_batch", "logpost_grad_batch", "mcmc_run", "mc_debug_philox",
-                    "mc_version", "mc_time_march")
+                    "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning")
 
 
 def _host(a, dtype=np.float64):
@@ -124,6 +131,16 @@ class Problem:
     def torch_dtype(self):
         import torch
         return torch.float64 if self.prec == MC_F64 else torch.float32
+
+    # -- launch shape -------------------------------------------------------
+    def set_tuning(self, march_variant=2, block=256, queue=4, rays_per_thread=4, top_in_lds=1):
+        t = Tuning(int(march_variant), int(block), int(queue), int(rays_per_thread), int(top_in_lds))
+        self._check(self.lib.mc_set_tuning(self.h, ct.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(self.lib.mc_get_tuning(self.h, ct.byref(t)))
+        return {f: getattr(t, f) for f, _ in Tuning._fields_}
 
     # -- set-up ---------------------------------------------------------------
     def load_geometry_grid(self, n_surfaces, n_rows, n_cols, extent_x, extent_y, density, top, car_r):

@@ -13,7 +13,11 @@
 
 #include "muoncave.h"
 #include "march.h"
+#include "march2.h"
+#include "march3.h"
 #include "prior.h"
+
+#include <type_traits>
 
 using namespace mc;
 
@@ -61,11 +65,12 @@ struct mc_problem {
     std::vector<double> pos, dirs, expo;
     void *d_sensor = nullptr, *d_dx = nullptr, *d_dy = nullptr, *d_dz = nullptr;
     double *d_expo = nullptr, *d_coL = nullptr;
+    void *d_rc[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // per-ray constants
     double kconst = 0.0;
     // workspaces (grow only)
     DevBuf partials, prop, lptmp;
     uint64_t *d_step = nullptr;
-    int rays_per_thread = 4;
+    mc_tuning tune = {2, 256, 4, 4, 1};
     // graph cache
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -178,14 +183,80 @@ struct Tiling {
 
 Tiling tiling(const mc_problem *p) {
     Tiling t;
-    t.rays_per_block = kMarchBlock * p->rays_per_thread;
+    const int block = p->tune.march_variant == 1 ? kMarchBlock : p->tune.block;
+    t.rays_per_block = block * p->tune.rays_per_thread;
     t.n_tiles = p->n_ray > 0 ? (p->n_ray + t.rays_per_block - 1) / t.rays_per_block : 0;
     return t;
 }
 
+size_t queue_bytes(const mc_problem *p) {
+    if (p->tune.march_variant != 2) return 0;
+    return (size_t)p->tune.queue * p->tune.block * (2 * elem_size(p) + 4);
+}
+
 bool top_in_lds(const mc_problem *p) {
     size_t N = (size_t)p->R * p->C;
-    return N * p->S * elem_size(p) + 4096 <= p->max_lds;
+    if (!p->tune.top_in_lds) return false;
+    return ((N * p->S * elem_size(p) + 15) & ~(size_t)15) + queue_bytes(p) + 4096 <= p->max_lds;
+}
+
+template <typename T>
+RayConsts<T> ray_consts(const mc_problem *p) {
+    RayConsts<T> K;
+    K.idx = (const T *)p->d_rc[0];
+    K.idy = (const T *)p->d_rc[1];
+    K.idz = (const T *)p->d_rc[2];
+    K.ox = (const T *)p->d_rc[3];
+    K.oy = (const T *)p->d_rc[4];
+    K.texit = (const T *)p->d_rc[5];
+    return K;
+}
+
+template <typename T, int S, bool TL, int B>
+hipError_t launch_v3_shape(dim3 grid, size_t lds, hipStream_t st, const MarchParams<T> &P, const RayConsts<T> &K) {
+    auto k = k_march_lik3<T, S, TL, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P, K);
+    return hipGetLastError();
+}
+
+template <typename T, int S, bool TL>
+hipError_t launch_v3(int block, dim3 grid, size_t lds, hipStream_t st, const MarchParams<T> &P, const RayConsts<T> &K) {
+    if constexpr (std::is_same<T, double>::value) {
+        return launch_v3_shape<T, S, TL, 256>(grid, lds, st, P, K);
+    } else {
+        if (block == 256) return launch_v3_shape<T, S, TL, 256>(grid, lds, st, P, K);
+        if (block == 512) return launch_v3_shape<T, S, TL, 512>(grid, lds, st, P, K);
+        return launch_v3_shape<T, S, TL, 1024>(grid, lds, st, P, K);
+    }
+}
+
+// Instantiated (block, queue) shapes of the band-limited march.
+bool v2_shape_supported(int prec, int block, int queue) {
+    if (prec == MC_F64) return block == 256 && queue == 4;
+    return (block == 256 || block == 512 || block == 1024) && (queue == 4 || queue == 8);
+}
+
+template <typename T, int S, bool TL, int B, int QQ>
+hipError_t launch_v2_shape(dim3 grid, size_t lds, hipStream_t st, const MarchParams<T> &P) {
+    auto k = k_march_lik2<T, S, TL, B, QQ>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P);
+    return hipGetLastError();
+}
+
+template <typename T, int S, bool TL>
+hipError_t launch_v2(int block, int queue, dim3 grid, size_t lds, hipStream_t st, const MarchParams<T> &P) {
+    if constexpr (std::is_same<T, double>::value) {
+        return launch_v2_shape<T, S, TL, 256, 4>(grid, lds, st, P);
+    } else {
+        if (block == 256 && queue == 4) return launch_v2_shape<T, S, TL, 256, 4>(grid, lds, st, P);
+        if (block == 256 && queue == 8) return launch_v2_shape<T, S, TL, 256, 8>(grid, lds, st, P);
+        if (block == 512 && queue == 4) return launch_v2_shape<T, S, TL, 512, 4>(grid, lds, st, P);
+        if (block == 512 && queue == 8) return launch_v2_shape<T, S, TL, 512, 8>(grid, lds, st, P);
+        if (block == 1024 && queue == 4) return launch_v2_shape<T, S, TL, 1024, 4>(grid, lds, st, P);
+        return launch_v2_shape<T, S, TL, 1024, 8>(grid, lds, st, P);
+    }
 }
 
 template <typename T>
@@ -238,6 +309,34 @@ mc_status launch_march(mc_problem *p, int n, const T *heights, T *opacity, doubl
     P.only_nan = only_nan;
     size_t N = (size_t)p->R * p->C;
     bool tl = top_in_lds(p);
+    int variant = p->tune.march_variant;
+    if (variant == 2) {
+        // a queue that does not fit beside the surfaces: use the queue-free walk
+        size_t lds2 = ((N * (tl ? S : S - 1) * sizeof(T) + 15) & ~(size_t)15) + queue_bytes(p);
+        if (lds2 + 2048 > p->max_lds) {
+            variant = 3;
+            tl = N * S * sizeof(T) + 4096 <= p->max_lds && p->tune.top_in_lds;
+        }
+    }
+    if (variant == 3) {
+        size_t lds = N * (tl ? S : S - 1) * sizeof(T);
+        if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+        dim3 grid(P.n_tiles, n);
+        RayConsts<T> K = ray_consts<T>(p);
+        hipError_t e = tl ? launch_v3<T, S, true>(p->tune.block, grid, lds, st, P, K)
+                          : launch_v3<T, S, false>(p->tune.block, grid, lds, st, P, K);
+        HIP_TRY(p, e);
+        return MC_OK;
+    }
+    if (variant == 2) {
+        size_t lds = ((N * (tl ? S : S - 1) * sizeof(T) + 15) & ~(size_t)15) + queue_bytes(p);
+        if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+        dim3 grid(P.n_tiles, n);
+        hipError_t e = tl ? launch_v2<T, S, true>(p->tune.block, p->tune.queue, grid, lds, st, P)
+                          : launch_v2<T, S, false>(p->tune.block, p->tune.queue, grid, lds, st, P);
+        HIP_TRY(p, e);
+        return MC_OK;
+    }
     size_t lds = N * (tl ? S : S - 1) * sizeof(T);
     if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
     dim3 grid(P.n_tiles, n), block(kMarchBlock);
@@ -470,6 +569,9 @@ mc_status mc_create(int hip_device, int precision, mc_problem **out) {
     mc_problem *p = new mc_problem();
     p->device = hip_device;
     p->prec = precision;
+    // default launch shape (best measured on the paper-scale problem for float32)
+    if (precision == MC_F32) p->tune = mc_tuning{3, 256, 4, 16, 0};
+    else p->tune = mc_tuning{3, 256, 4, 4, 1};
     DeviceGuard g(hip_device);
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess && lds > 0)
@@ -496,6 +598,7 @@ void mc_destroy(mc_problem *p) {
     free_ptr(p->d_dz);
     free_ptr(p->d_expo);
     free_ptr(p->d_coL);
+    for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
     for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp})
         if (b->p) (void)hipFree(b->p);
     if (p->d_step) (void)hipFree(p->d_step);
@@ -585,7 +688,30 @@ mc_status set_sensors(mc_problem *p, int n_sensors, const double *pos, int n_pix
         dz[r] = dirs[3 * r + 2];
     }
     p->expo.assign(exposure, exposure + n_ray);
+    // chain-independent per-ray constants of the cell walk, in float64 then
+    // rounded once: reciprocal directions, DDA offsets -q/d, box exit
+    std::vector<double> rc[6];
+    for (auto &v : rc) v.resize(n_ray);
+    const double xmax = (double)(p->R - 1) * (p->X / (p->R - 1)), ymax = (double)(p->C - 1) * (p->Y / (p->C - 1));
+    for (int r = 0; r < n_ray; ++r) {
+        const int sidx = r / n_pix;
+        const double qx = pos[3 * sidx], qy = pos[3 * sidx + 1], qz = pos[3 * sidx + 2];
+        const double ix = dx[r] != 0 ? 1.0 / dx[r] : 0.0, iy = dy[r] != 0 ? 1.0 / dy[r] : 0.0;
+        rc[0][r] = ix;
+        rc[1][r] = iy;
+        rc[2][r] = 1.0 / dz[r];
+        rc[3][r] = dx[r] != 0 ? -qx * ix : INFINITY;
+        rc[4][r] = dy[r] != 0 ? -qy * iy : INFINITY;
+        double T = (p->ztop - qz) / dz[r];
+        if (dx[r] > 0) T = std::min(T, (xmax - qx) / dx[r]);
+        if (dx[r] < 0) T = std::min(T, -qx / dx[r]);
+        if (dy[r] > 0) T = std::min(T, (ymax - qy) / dy[r]);
+        if (dy[r] < 0) T = std::min(T, -qy / dy[r]);
+        rc[5][r] = std::max(T, 0.0);
+    }
     mc_status s;
+    for (int k = 0; k < 6; ++k)
+        if ((s = upload_prec(p, p->d_rc[k], rc[k])) != MC_OK) return s;
     if ((s = upload_prec(p, p->d_sensor, p->pos)) != MC_OK) return s;
     if ((s = upload_prec(p, p->d_dx, dx)) != MC_OK) return s;
     if ((s = upload_prec(p, p->d_dy, dy)) != MC_OK) return s;
@@ -663,6 +789,27 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? mcmc_dispatch<double>(p, cfg, n_chains, heights, logpost, n_accept, st)
                              : mcmc_dispatch<float>(p, cfg, n_chains, heights, logpost, n_accept, st);
+}
+
+mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t) {
+    if (!p || !t) return MC_ERR_ARG;
+    if (t->march_variant < 1 || t->march_variant > 3) return fail(p, MC_ERR_ARG, "march_variant %d", t->march_variant);
+    if (t->march_variant == 3 && !(t->block == 256 || (p->prec == MC_F32 && (t->block == 512 || t->block == 1024))))
+        return fail(p, MC_ERR_UNSUPPORTED, "block %d not built for this precision", t->block);
+    if (t->rays_per_thread < 1 || t->rays_per_thread > 64) return fail(p, MC_ERR_ARG, "rays_per_thread %d", t->rays_per_thread);
+    if (t->march_variant == 2 && !v2_shape_supported(p->prec, t->block, t->queue))
+        return fail(p, MC_ERR_UNSUPPORTED, "block %d / queue %d not built for this precision", t->block, t->queue);
+    DeviceGuard g(p->device);
+    drop_graph(p);
+    p->tune = *t;
+    if (p->tune.march_variant == 1) p->tune.block = kMarchBlock;
+    return MC_OK;
+}
+
+mc_status mc_get_tuning(const mc_problem *p, mc_tuning *t) {
+    if (!p || !t) return MC_ERR_ARG;
+    *t = p->tune;
+    return MC_OK;
 }
 
 mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
