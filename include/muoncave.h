@@ -159,11 +159,14 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
 /*
  * Launch shape of the ray-march kernel (performance only; results agree to
  * rounding).  march_variant: 1 = plain cell walk, 2 = band-limited walk
- * with per-lane crossing queues, 3 = surface-major band walks (queue unused).  block: threads per block (256, 512 or
+ * with per-lane crossing queues, 3 = surface-major band walks (queue unused),
+ * 4 = lean band walks with branch-free inline crossing solves, 5 = lean band
+ * walks whose crossing pieces are solved 64 at a time from a per-wave ring
+ * (4 and 5 are float32 only; float64 handles run variant 3).  block: threads per block (256, 512 or
  * 1024; float64 handles use 256), queue: crossing-queue slots per lane (4 or
  * 8), rays_per_thread: rays each thread marches per launch (1..64),
  * top_in_lds: stage the fixed top surface in LDS when it fits (else it is
- * read from global memory).  Defaults {3, 256, 4, 16, 0} for float32 and
+ * read from global memory).  Defaults {4, 256, 4, 16, 0} for float32 and
  * {3, 256, 4, 4, 1} for float64.  A variant-2 shape whose queue does not fit
  * in LDS beside the surfaces runs as variant 3.  Setting a shape
  * this build does not provide returns MC_ERR_UNSUPPORTED.

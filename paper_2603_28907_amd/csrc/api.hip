@@ -15,6 +15,7 @@
 #include "march.h"
 #include "march2.h"
 #include "march3.h"
+#include "march5.h"
 #include "prior.h"
 
 #include <type_traits>
@@ -231,6 +232,29 @@ hipError_t launch_v3(int block, dim3 grid, size_t lds, hipStream_t st, const Mar
     }
 }
 
+template <int S, bool TL, int B>
+hipError_t launch_v45_shape(int variant, dim3 grid, size_t lds, hipStream_t st, const MarchParams<float> &P,
+                            const RayConsts<float> &K) {
+    if (variant == 4) {
+        auto k = k_march_lik4<S, TL, B>;
+        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P, K);
+    } else {
+        auto k = k_march_lik5<S, TL, B>;
+        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P, K);
+    }
+    return hipGetLastError();
+}
+
+template <int S, bool TL>
+hipError_t launch_v45(int variant, int block, dim3 grid, size_t lds, hipStream_t st, const MarchParams<float> &P,
+                      const RayConsts<float> &K) {
+    if (block == 256) return launch_v45_shape<S, TL, 256>(variant, grid, lds, st, P, K);
+    if (block == 512) return launch_v45_shape<S, TL, 512>(variant, grid, lds, st, P, K);
+    return launch_v45_shape<S, TL, 1024>(variant, grid, lds, st, P, K);
+}
+
 // Instantiated (block, queue) shapes of the band-limited march.
 bool v2_shape_supported(int prec, int block, int queue) {
     if (prec == MC_F64) return block == 256 && queue == 4;
@@ -310,6 +334,23 @@ mc_status launch_march(mc_problem *p, int n, const T *heights, T *opacity, doubl
     size_t N = (size_t)p->R * p->C;
     bool tl = top_in_lds(p);
     int variant = p->tune.march_variant;
+    if (variant >= 4 && sizeof(T) != 4) variant = 3;   // the lean walks are float32 only
+    if (variant >= 4) {
+        size_t lds = N * (tl ? S : S - 1) * sizeof(T);
+        if (lds + 16384 > p->max_lds) {
+            tl = false;
+            lds = N * (S - 1) * sizeof(T);
+        }
+        if (lds + 16384 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+        dim3 grid(P.n_tiles, n);
+        if constexpr (std::is_same<T, float>::value) {
+            RayConsts<float> K = ray_consts<float>(p);
+            hipError_t e = tl ? launch_v45<S, true>(variant, p->tune.block, grid, lds, st, P, K)
+                              : launch_v45<S, false>(variant, p->tune.block, grid, lds, st, P, K);
+            HIP_TRY(p, e);
+        }
+        return MC_OK;
+    }
     if (variant == 2) {
         // a queue that does not fit beside the surfaces: use the queue-free walk
         size_t lds2 = ((N * (tl ? S : S - 1) * sizeof(T) + 15) & ~(size_t)15) + queue_bytes(p);
@@ -570,7 +611,7 @@ mc_status mc_create(int hip_device, int precision, mc_problem **out) {
     p->device = hip_device;
     p->prec = precision;
     // default launch shape (best measured on the paper-scale problem for float32)
-    if (precision == MC_F32) p->tune = mc_tuning{3, 256, 4, 16, 0};
+    if (precision == MC_F32) p->tune = mc_tuning{4, 256, 4, 16, 0};
     else p->tune = mc_tuning{3, 256, 4, 4, 1};
     DeviceGuard g(hip_device);
     int lds = 0;
@@ -793,8 +834,8 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
 
 mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t) {
     if (!p || !t) return MC_ERR_ARG;
-    if (t->march_variant < 1 || t->march_variant > 3) return fail(p, MC_ERR_ARG, "march_variant %d", t->march_variant);
-    if (t->march_variant == 3 && !(t->block == 256 || (p->prec == MC_F32 && (t->block == 512 || t->block == 1024))))
+    if (t->march_variant < 1 || t->march_variant > 5) return fail(p, MC_ERR_ARG, "march_variant %d", t->march_variant);
+    if (t->march_variant >= 3 && !(t->block == 256 || (p->prec == MC_F32 && (t->block == 512 || t->block == 1024))))
         return fail(p, MC_ERR_UNSUPPORTED, "block %d not built for this precision", t->block);
     if (t->rays_per_thread < 1 || t->rays_per_thread > 64) return fail(p, MC_ERR_ARG, "rays_per_thread %d", t->rays_per_thread);
     if (t->march_variant == 2 && !v2_shape_supported(p->prec, t->block, t->queue))

@@ -212,7 +212,12 @@ TUNINGS = [dict(march_variant=1, block=256, queue=4, rays_per_thread=4, top_in_l
            dict(march_variant=2, block=256, queue=8, rays_per_thread=8, top_in_lds=0),
            dict(march_variant=3, block=256, queue=4, rays_per_thread=4, top_in_lds=1),
            dict(march_variant=3, block=512, queue=4, rays_per_thread=2, top_in_lds=0),
-           dict(march_variant=3, block=1024, queue=4, rays_per_thread=8, top_in_lds=1)]
+           dict(march_variant=3, block=1024, queue=4, rays_per_thread=8, top_in_lds=1),
+           dict(march_variant=4, block=256, queue=4, rays_per_thread=16, top_in_lds=0),
+           dict(march_variant=4, block=512, queue=4, rays_per_thread=3, top_in_lds=1),
+           dict(march_variant=5, block=256, queue=4, rays_per_thread=16, top_in_lds=0),
+           dict(march_variant=5, block=512, queue=4, rays_per_thread=5, top_in_lds=1),
+           dict(march_variant=5, block=1024, queue=4, rays_per_thread=2, top_in_lds=0)]
 
 
 @pytest.mark.parametrize("ti", range(len(TUNINGS)))
