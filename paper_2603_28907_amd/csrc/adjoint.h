@@ -1,0 +1,391 @@
+// adjoint.h -- gradient of the log posterior with respect to every surface
+// height, and the MALA step that consumes it.
+//
+// Likelihood part.  L_l (the below-length of surface l along a ray) moves
+// with each crossing t_c of surface l: with f = z - h, a node n of the
+// crossing's patch changes the crossing by dt_c/dH_n = w_n(t_c) / f'(t_c),
+// so dL_l/dH_n = sum over crossings of w_n / |f'(t_c)| (an entry into the
+// region below adds, an exit adds too: both widen it).  With
+// dO/dL_l = rho_l - rho_{l+1} and dLL/dO_p = (lambda_p - C_p)/Lambda, every
+// crossing scatters (rho_l - rho_{l+1}) g_p w_n / |f'| into four nodes.
+//
+// The adjoint kernel re-walks each ray exactly as the forward walk does
+// (same band windows, same boundary values, same crossing decisions), finds
+// the crossing positions of the in-cell quadratic and adds their weighted
+// contributions into a per-chain 64-bit fixed-point accumulator (2^-32 per
+// unit) with global integer atomics, so gradients are bitwise reproducible.
+//
+// Prior part (paper Sec. 2.2.1, written in H-space): with
+//   G_i = d log p / d w_i = -s^2 (4(1-r) w_i + r (4 w_i - sum_{j~i} w_j)) + w_i,
+// dw/du = 1/phi(w), u = (H - a)/d, v = (b - H)/d, d = b - a:
+//   d/dH_l = G/(phi d),  d/da = -G v/(phi d) + 1/d,  d/db = -G u/(phi d) - 1/d.
+#pragma once
+
+#include "march3.h"
+#include "prior.h"
+
+namespace mc {
+
+constexpr double kGradFix = 4294967296.0;   // 2^32 fixed-point units per gradient unit
+constexpr double kGradFixInv = 1.0 / 4294967296.0;
+
+// Crossings of the piece quadratic p(tau) = fe + c1 tau + c2 tau^2 with
+// p(tau1) = fx (the same case analysis as cell_below_length).  Returns the
+// number of crossings (0..2), their positions and |p'| there.
+template <typename T>
+__device__ __forceinline__ int cell_crossings(T fe, T fx, T c2, T tau1, T *tc, T *fp) {
+    const bool be = fe < T(0), bx = fx < T(0);
+    const T c1 = (fx - fe) / tau1 - c2 * tau1;
+    if (be != bx) {
+        T disc = dmax(c1 * c1 - T(4) * c2 * fe, T(0));
+        T sq = dsqrt(disc);
+        T q = T(-0.5) * (c1 + (c1 >= T(0) ? sq : -sq));
+        T r1 = q / c2, r2 = fe / q;
+        T d1 = dmax(dmax(-r1, r1 - tau1), T(0));
+        T d2 = dmax(dmax(-r2, r2 - tau1), T(0));
+        bool use1 = (d1 < d2) || (d2 != d2);
+        T r = use1 ? r1 : r2;
+        if (r != r) r = tau1 * fe / (fe - fx);
+        r = dmin(dmax(r, T(0)), tau1);
+        tc[0] = r;
+        fp[0] = dabs(c1 + T(2) * c2 * r);
+        return 1;
+    }
+    if (c2 != T(0)) {
+        const T tv = -c1 / (T(2) * c2);
+        if (tv > T(0) && tv < tau1) {
+            const T fv = fe + tv * (c1 + c2 * tv);
+            if ((fv < T(0)) != be) {
+                T disc = dmax(c1 * c1 - T(4) * c2 * fe, T(0));
+                T half = dsqrt(disc) / (T(2) * dabs(c2));
+                T ta = dmax(tv - half, T(0)), tb = dmin(tv + half, tau1);
+                tc[0] = ta;
+                tc[1] = tb;
+                fp[0] = dabs(c1 + T(2) * c2 * ta);
+                fp[1] = dabs(c1 + T(2) * c2 * tb);
+                return 2;
+            }
+        }
+    }
+    return 0;
+}
+
+__device__ __forceinline__ void add_fixed(unsigned long long *p, double v) {
+    const double sv = v * kGradFix;
+    // saturate far outside any physical gradient instead of wrapping
+    const double cl = fmin(fmax(sv, -9.0e18), 9.0e18);
+    atomicAdd(p, (unsigned long long)(long long)__builtin_rint(cl));
+}
+
+// Re-walk one surface of one ray and scatter scale * w_n / |f'| per crossing.
+template <typename T>
+__device__ __forceinline__ void walk_surface_adjoint(const MarchParams<T> &P, const T *Hl, T qx, T qy, T qz, T dx,
+                                                     T dy, T dz, T idx, T idy, T ox, T oy, T tl, T th, double scale,
+                                                     unsigned long long *G) {
+    const int R = P.R, C = P.C;
+    const bool xpos = dx > T(0), ypos = dy > T(0);
+    const T x0 = dfma(tl, dx, qx), y0 = dfma(tl, dy, qy);
+    int a = (int)floor(x0 * P.ihx), b = (int)floor(y0 * P.ihy);
+    a = a < 0 ? 0 : (a > R - 2 ? R - 2 : a);
+    b = b < 0 ? 0 : (b > C - 2 ? C - 2 : b);
+    const int sxs = xpos ? 1 : -1, sys = ypos ? 1 : -1;
+    T xn = T(xpos ? a + 1 : a) * P.hx, yn = T(ypos ? b + 1 : b) * P.hy;
+    const T dxn = xpos ? P.hx : -P.hx, dyn = ypos ? P.hy : -P.hy;
+    const T ds = dx * P.ihx, dw = dy * P.ihy;
+    T t0 = tl, z0 = dfma(tl, dz, qz);
+    int ekind = kPoint;
+    for (int it = 0; it < R + C; ++it) {
+        const T tnx = dfma(xn, idx, ox), tny = dfma(yn, idy, oy);
+        const bool stepx = tnx <= tny;
+        const T tn = stepx ? tnx : tny;
+        const int na = stepx ? a + sxs : a, nb = stepx ? b : b + sys;
+        const bool in_range = (unsigned)na <= (unsigned)(R - 2) && (unsigned)nb <= (unsigned)(C - 2);
+        const bool edge = (tn < th) && in_range;
+        const T t1 = dmax(dmin(tn, th), t0);
+        const T z1 = dfma(t1, dz, qz);
+        const int base = a * C + b;
+        const T h00 = Hl[base], h01 = Hl[base + 1], h10 = Hl[base + C], h11 = Hl[base + C + 1];
+        const T hmin = dmin(dmin(h00, h01), dmin(h10, h11));
+        const T hmax = dmax(dmax(h00, h01), dmax(h10, h11));
+        if (!(z1 < hmin - P.margin) && !(z0 > hmax + P.margin) && t1 > t0) {
+            const int xkind = edge ? (stepx ? kXEdge : kYEdge) : kPoint;
+            const T se = dfma(dfma(t0, dx, qx), P.ihx, -T(a)), we = dfma(dfma(t0, dy, qy), P.ihy, -T(b));
+            const T sx = dfma(dfma(t1, dx, qx), P.ihx, -T(a)), wx = dfma(dfma(t1, dy, qy), P.ihy, -T(b));
+            const T fe = boundary_value(ekind, true, xpos, ypos, z0, se, we, h00, h10, h01, h11);
+            const T fx = boundary_value(xkind, false, xpos, ypos, z1, sx, wx, h00, h10, h01, h11);
+            const T c2 = -(h11 - h10 - h01 + h00) * ds * dw;
+            T tc[2], fp[2];
+            const int nc = cell_crossings(fe, fx, c2, t1 - t0, tc, fp);
+            for (int k = 0; k < nc; ++k) {
+                if (!(fp[k] > T(0))) continue;   // tangency: a kink of lp, no derivative
+                const T t = t0 + tc[k];
+                // a crossing on the box lid z = max H_S is the kink of that max
+                // (the ray leaves the box there); it carries no derivative
+                if (dfma(t, dz, qz) >= P.ztop - P.margin) continue;
+                const T s = dmin(dmax(dfma(dfma(t, dx, qx), P.ihx, -T(a)), T(0)), T(1));
+                const T w = dmin(dmax(dfma(dfma(t, dy, qy), P.ihy, -T(b)), T(0)), T(1));
+                const double g = scale / (double)fp[k];
+                const double ws = (double)s, ww = (double)w;
+                add_fixed(G + base, g * (1.0 - ws) * (1.0 - ww));
+                add_fixed(G + base + C, g * ws * (1.0 - ww));
+                add_fixed(G + base + 1, g * (1.0 - ws) * ww);
+                add_fixed(G + base + C + 1, g * ws * ww);
+            }
+        }
+        if (!edge) break;
+        if (stepx) {
+            a = na;
+            xn += dxn;
+            ekind = kXEdge;
+        } else {
+            b = nb;
+            yn += dyn;
+            ekind = kYEdge;
+        }
+        t0 = t1;
+        z0 = z1;
+    }
+}
+
+// One block = one chain x one tile of rays; g_p from the forward opacities.
+// gfix: [n_chains][S][R*C] fixed-point accumulators (zeroed beforehand).
+template <typename T, int S, bool TOP_LDS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T> K, const T *opacity,
+                                                   unsigned long long *gfix) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);
+    __shared__ T band[2 * kMaxSurfaces];
+    const int chain = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int N = P.R * P.C;
+    const T *Hc = P.heights + (size_t)chain * (S - 1) * N;
+    T mn[S], mx[S];
+#pragma unroll
+    for (int l = 0; l < S - 1; ++l) {
+        T a = dev_inf<T>(), b = -dev_inf<T>();
+        for (int i = tid; i < N; i += BLOCK) {
+            T v = Hc[l * N + i];
+            sh[l * N + i] = v;
+            a = dmin(a, v);
+            b = dmax(b, v);
+        }
+        mn[l] = a;
+        mx[l] = b;
+    }
+    if (TOP_LDS) {
+        for (int i = tid; i < N; i += BLOCK) sh[(S - 1) * N + i] = P.top[i];
+    }
+    {
+        __shared__ T wred[2 * kMaxSurfaces][BLOCK / kWave];
+        const int lane = tid % kWave, wid = tid / kWave;
+#pragma unroll
+        for (int l = 0; l < S - 1; ++l) {
+            T a = wave_min(mn[l]), b = wave_max(mx[l]);
+            if (lane == 0) {
+                wred[2 * l][wid] = a;
+                wred[2 * l + 1][wid] = b;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+            for (int l = 0; l < S - 1; ++l) {
+                T a = wred[2 * l][0], b = wred[2 * l + 1][0];
+                for (int w = 1; w < BLOCK / kWave; ++w) {
+                    a = dmin(a, wred[2 * l][w]);
+                    b = dmax(b, wred[2 * l + 1][w]);
+                }
+                band[l] = a - P.margin;
+                band[kMaxSurfaces + l] = b + P.margin;
+            }
+            band[S - 1] = P.top_min - P.margin;
+            band[kMaxSurfaces + S - 1] = P.top_max + P.margin;
+        }
+        __syncthreads();
+    }
+    unsigned long long *Gc = gfix + (size_t)chain * S * N;
+    const int r0 = tile * P.rays_per_block;
+    const int r1 = min(r0 + P.rays_per_block, P.n_ray);
+    for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
+        const int s = ray / P.n_pix;
+        const double Od = (double)opacity[(size_t)chain * P.n_ray + ray];
+        const double lam = P.expo[ray] * exp(-Od * P.inv_L);
+        const double gp = lam * P.inv_L - P.c_over_L[ray];   // dLL/dO = (lambda - C)/Lambda
+        const T qx = P.sensor[3 * s], qy = P.sensor[3 * s + 1], qz = P.sensor[3 * s + 2];
+        const T dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
+        const T idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
+        const T ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            const T *Hl = (l < S - 1 || TOP_LDS) ? sh + l * N : P.top;
+            const T tl = dmin(dmax((band[l] - qz) * idz, T(0)), Texit);
+            const T th = dmin(dmax((band[kMaxSurfaces + l] - qz) * idz, T(0)), Texit);
+            const double scale = gp * (double)P.rho_diff[l];
+            if (tl < th && scale != 0.0)
+                walk_surface_adjoint<T>(P, Hl, qx, qy, qz, dx, dy, dz, idx, idy, ox, oy, tl, th, scale, Gc + l * N);
+        }
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Log prior and its gradient per chain (one block per chain), plus the
+// fixed-order sum of the likelihood partials.  gprior: [n][S][N] float64.
+template <typename T, int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_prior_grad(PriorParams<T> P, double *gprior) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *w = reinterpret_cast<double *>(smem_raw);   // [N]
+    __shared__ double red[16];
+    __shared__ int ired[16];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int R = P.R, C = P.C, N = R * C;
+    const T *H = P.heights + (size_t)c * (S - 1) * N;
+    double *gp = gprior + (size_t)c * S * N;
+    for (int i = tid; i < S * N; i += BLOCK) gp[i] = 0.0;
+    __syncthreads();
+    double lp = 0.0;
+    int ok = 1;
+#pragma unroll
+    for (int l = 0; l < S - 1; ++l) {
+        double sw2 = 0.0, sld = 0.0;
+        for (int n = tid; n < N; n += BLOCK) {
+            const double h = (double)H[l * N + n];
+            const double a = l ? (double)H[(l - 1) * N + n] : 0.0;
+            const double b = P.top64[n];
+            const double d = b - a;
+            const double u = (h - a) / d, v = (b - h) / d;
+            const bool good = (d > 0.0) && (u > 0.0) && (v > 0.0);
+            ok &= good ? 1 : 0;
+            const double wi = good ? probit_uv(u, v) : 0.0;
+            w[n] = wi;
+            sw2 += wi * wi;
+            sld += good ? log(d) : 0.0;
+        }
+        __syncthreads();
+        double se = 0.0;
+        const double r = P.r[l], s11 = P.s11[l];
+        for (int n = tid; n < N; n += BLOCK) {
+            const int i = n / C, j = n - i * C;
+            const double wi = w[n];
+            const double wr = w[i * C + (j + 1 == C ? 0 : j + 1)], wl = w[i * C + (j == 0 ? C - 1 : j - 1)];
+            const double wd = w[(i + 1 == R ? 0 : i + 1) * C + j], wu = w[(i == 0 ? R - 1 : i - 1) * C + j];
+            se += (wi - wr) * (wi - wr) + (wi - wd) * (wi - wd);
+            // gradient of this layer's term (this thread owns node n in every layer)
+            const double h = (double)H[l * N + n];
+            const double a = l ? (double)H[(l - 1) * N + n] : 0.0;
+            const double b = P.top64[n];
+            const double d = b - a;
+            const double u = (h - a) / d, v = (b - h) / d;
+            if ((d > 0.0) && (u > 0.0) && (v > 0.0)) {
+                const double G = -s11 * (4.0 * (1.0 - r) * wi + r * (4.0 * wi - (wr + wl + wd + wu))) + wi;
+                const double phi = exp(-0.5 * wi * wi) * 0.39894228040143267793994605993438;
+                const double gu = G / phi;
+                gp[l * N + n] += gu / d;
+                if (l) gp[(l - 1) * N + n] += -gu * v / d + 1.0 / d;
+                gp[(S - 1) * N + n] += -gu * u / d - 1.0 / d;
+            }
+        }
+        const double SW2 = block_sum<BLOCK>(sw2, red);
+        const double SLD = block_sum<BLOCK>(sld, red);
+        const double SE = block_sum<BLOCK>(se, red);
+        lp += 0.5 * P.logdet[l] - 0.5 * s11 * (4.0 * (1.0 - r) * SW2 + r * SE) + 0.5 * N * log(s11) + 0.5 * SW2 - SLD;
+    }
+    ok = block_and<BLOCK>(ok, ired);
+    if (tid == 0) {
+        double ll = 0.0;
+        if (P.has_lik) {
+            const double *pp = P.partials + (size_t)c * P.n_tiles;
+            for (int t = 0; t < P.n_tiles; ++t) ll += pp[t];
+            ll += P.kconst;
+        }
+        P.lp_out[c] = ok ? lp + ll : -__builtin_huge_val();
+    }
+}
+
+// grad = likelihood (fixed point) + prior; zero rows where lp = -inf.
+template <typename T>
+__global__ void k_grad_combine(const unsigned long long *gfix, const double *gprior, const double *lp, T *grad,
+                               int SN, int n) {
+    const int c = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= SN || c >= n) return;
+    const size_t k = (size_t)c * SN + i;
+    const double v = (double)(long long)gfix[k] * kGradFixInv + gprior[k];
+    grad[k] = (lp[c] == -__builtin_huge_val()) ? T(0) : (T)v;
+}
+
+// MALA proposal: prop = H + (eps^2/2) m g + eps sqrt(m) z, z from tag 2.
+// g: [n][S][N] (free layers used), inv_mass: [S-1][N] float64 or null.
+template <typename T>
+__global__ void k_propose_mala(const T *H, const T *g, T *prop, const double *inv_mass, int M, int SN, double eps,
+                               uint64_t seed, const uint64_t *step_base, int step_k) {
+    const int c = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * j >= M) return;
+    const uint64_t step = *step_base + (uint64_t)step_k;
+    double z[2];
+    rng_normal2(seed, (uint32_t)c, step, kTagMala, (uint32_t)j, z[0], z[1]);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int n = 2 * j + e;
+        if (n >= M) break;
+        const double m = inv_mass ? inv_mass[n] : 1.0;
+        const size_t k = (size_t)c * M + n;
+        const double mean = (double)H[k] + 0.5 * eps * eps * m * (double)g[(size_t)c * SN + n];
+        prop[k] = (T)(mean + eps * sqrt(m) * z[e]);
+    }
+}
+
+// MALA decision per chain (one block per chain):
+//   log alpha = lp' - lp + log q(H | H') - log q(H' | H),
+//   log q(y | x) = -sum (y - x - (eps^2/2) m g(x))^2 / (2 eps^2 m),
+// on acceptance copy the proposal, its gradient and lp.
+template <typename T, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_mala_finalize(T *H, const T *prop, T *g_cur, const T *g_prop,
+                                                         double *lp_cur, const double *lp_prop, int64_t *n_acc,
+                                                         const double *inv_mass, int M, int SN, double eps,
+                                                         uint64_t seed, const uint64_t *step_base, int step_k) {
+    __shared__ double red[16];
+    __shared__ int s_acc;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const T *Hc = H + (size_t)c * M;
+    const T *Pc = prop + (size_t)c * M;
+    const T *gc = g_cur + (size_t)c * SN;
+    const T *gq = g_prop + (size_t)c * SN;
+    double fwd = 0.0, bwd = 0.0;
+    const double e2 = eps * eps;
+    for (int n = tid; n < M; n += BLOCK) {
+        const double m = inv_mass ? inv_mass[n] : 1.0;
+        const double h = (double)Hc[n], q = (double)Pc[n];
+        const double df = q - h - 0.5 * e2 * m * (double)gc[n];
+        const double db = h - q - 0.5 * e2 * m * (double)gq[n];
+        fwd -= df * df / (2.0 * e2 * m);
+        bwd -= db * db / (2.0 * e2 * m);
+    }
+    const double F = block_sum<BLOCK>(fwd, red);
+    const double B = block_sum<BLOCK>(bwd, red);
+    if (tid == 0) {
+        const double lpp = lp_prop[c];
+        double la = -__builtin_huge_val();
+        if (lpp > -__builtin_huge_val()) la = lpp - lp_cur[c] + B - F;
+        const uint64_t step = *step_base + (uint64_t)step_k;
+        const double u = rng_uniform(seed, (uint32_t)c, step, kTagAccept, 0);
+        const int acc = log(u) < la;
+        if (acc) {
+            lp_cur[c] = lpp;
+            n_acc[c] += 1;
+        }
+        s_acc = acc;
+    }
+    __syncthreads();
+    if (s_acc) {
+        T *Hw = H + (size_t)c * M;
+        T *gw = g_cur + (size_t)c * SN;
+        for (int n = tid; n < M; n += BLOCK) Hw[n] = Pc[n];
+        for (int n = tid; n < SN; n += BLOCK) gw[n] = gq[n];
+    }
+}
+
+}  // namespace mc

@@ -16,6 +16,7 @@
 #include "march2.h"
 #include "march3.h"
 #include "march5.h"
+#include "adjoint.h"
 #include "prior.h"
 
 #include <type_traits>
@@ -70,6 +71,7 @@ struct mc_problem {
     double kconst = 0.0;
     // workspaces (grow only)
     DevBuf partials, prop, lptmp;
+    DevBuf obuf, gfix, gprior, gcur, gprop, lpprop;   // gradient and MALA workspaces
     uint64_t *d_step = nullptr;
     mc_tuning tune = {2, 256, 4, 4, 1};
     // graph cache
@@ -458,6 +460,117 @@ mc_status logpost_dispatch(mc_problem *p, int n, const void *heights, double *lp
     return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
 }
 
+// Log posterior and gradient of n states into lp and grad ([n][S][N] in T):
+// forward march with opacities, prior and its gradient, adjoint march,
+// combine.  Workspaces must be ensured by the caller (ensure_grad_ws).
+template <typename T, int S>
+mc_status grad_eval(mc_problem *p, int n, const T *heights, double *lp, T *grad, hipStream_t st) {
+    const size_t N = (size_t)p->R * p->C, SN = (size_t)S * N;
+    unsigned long long *gfix = (unsigned long long *)p->gfix.p;
+    double *gprior = (double *)p->gprior.p;
+    mc_status s;
+    if (p->n_ray > 0) {
+        const size_t tot = SN * n;
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
+        HIP_TRY(p, hipGetLastError());
+        if ((s = launch_march<T, S>(p, n, heights, (T *)p->obuf.p, (double *)p->partials.p, st)) != MC_OK) return s;
+    }
+    PriorParams<T> P = prior_params<T>(p, heights, (const double *)p->partials.p);
+    P.lp_out = lp;
+    {
+        size_t lds = sizeof(double) * N;
+        auto k = k_prior_grad<T, S, kPriorBlock>;
+        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, dim3(n), dim3(kPriorBlock), lds, st, P, gprior);
+        HIP_TRY(p, hipGetLastError());
+    }
+    if (p->n_ray > 0) {
+        MarchParams<T> M = march_params<T>(p, heights, nullptr, (double *)p->partials.p);
+        RayConsts<T> K = ray_consts<T>(p);
+        bool tl = N * S * sizeof(T) + 4096 <= p->max_lds;
+        size_t lds = N * (tl ? S : S - 1) * sizeof(T);
+        if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+        // the adjoint keeps the forward tiling but marches with 256 threads per block
+        M.rays_per_block = tiling(p).rays_per_block;
+        dim3 grid(M.n_tiles, n);
+        if (tl) {
+            auto k = k_adjoint<T, S, true, 256>;
+            if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(k, grid, dim3(256), lds, st, M, K, (const T *)p->obuf.p, gfix);
+        } else {
+            auto k = k_adjoint<T, S, false, 256>;
+            if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(k, grid, dim3(256), lds, st, M, K, (const T *)p->obuf.p, gfix);
+        }
+        HIP_TRY(p, hipGetLastError());
+    }
+    if (p->n_ray == 0) {
+        const size_t tot = SN * n;
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
+        HIP_TRY(p, hipGetLastError());
+    }
+    dim3 cg((unsigned)((SN + 255) / 256), n);
+    hipLaunchKernelGGL(k_grad_combine<T>, cg, dim3(256), 0, st, (const unsigned long long *)gfix,
+                       (const double *)gprior, (const double *)lp, grad, (int)SN, n);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+template <typename T, int S>
+mc_status ensure_grad_ws(mc_problem *p, int n) {
+    const size_t N = (size_t)p->R * p->C, SN = (size_t)S * N;
+    mc_status s;
+    Tiling t = tiling(p);
+    if (p->n_ray > 0) {
+        if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+        if ((s = ensure(p, p->obuf, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK) return s;
+    }
+    if ((s = ensure(p, p->gfix, sizeof(unsigned long long) * SN * n)) != MC_OK) return s;
+    if ((s = ensure(p, p->gprior, sizeof(double) * SN * n)) != MC_OK) return s;
+    return MC_OK;
+}
+
+template <typename T, int S>
+mc_status logpost_grad_impl(mc_problem *p, int n, const T *heights, double *lp, T *grad, hipStream_t st) {
+    mc_status s;
+    if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
+    return grad_eval<T, S>(p, n, heights, lp, grad, st);
+}
+
+template <typename T>
+mc_status logpost_grad_dispatch(mc_problem *p, int n, const void *heights, double *lp, void *grad, hipStream_t st) {
+    switch (p->S) {
+        case 2: return logpost_grad_impl<T, 2>(p, n, (const T *)heights, lp, (T *)grad, st);
+        case 3: return logpost_grad_impl<T, 3>(p, n, (const T *)heights, lp, (T *)grad, st);
+        case 4: return logpost_grad_impl<T, 4>(p, n, (const T *)heights, lp, (T *)grad, st);
+    }
+    return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
+}
+
+// One MALA step: propose from the cached gradient, evaluate lp and gradient
+// at the proposal, decide, copy.
+template <typename T, int S>
+mc_status mala_step(mc_problem *p, int n, T *heights, double *lp, int64_t *acc, const mc_run_config *cfg, int k,
+                    hipStream_t st) {
+    const int M = (S - 1) * p->R * p->C;
+    const int SN = S * p->R * p->C;
+    T *prop = (T *)p->prop.p;
+    T *gcur = (T *)p->gcur.p, *gprop = (T *)p->gprop.p;
+    double *lpp = (double *)p->lpprop.p;
+    dim3 pg((M / 2 + 1 + 255) / 256, n);
+    hipLaunchKernelGGL(k_propose_mala<T>, pg, dim3(256), 0, st, (const T *)heights, (const T *)gcur, prop,
+                       cfg->inv_mass, M, SN, cfg->step_size, cfg->seed, (const uint64_t *)p->d_step, k);
+    HIP_TRY(p, hipGetLastError());
+    mc_status s;
+    if ((s = grad_eval<T, S>(p, n, prop, lpp, gprop, st)) != MC_OK) return s;
+    auto kfin = k_mala_finalize<T, kPriorBlock>;
+    hipLaunchKernelGGL(kfin, dim3(n), dim3(kPriorBlock), 0, st, heights,
+                       (const T *)prop, gcur, (const T *)gprop, lp, (const double *)lpp, acc, cfg->inv_mass, M, SN,
+                       cfg->step_size, cfg->seed, (const uint64_t *)p->d_step, k);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
 // One random-walk Metropolis step (propose, march the proposals, prior +
 // decision + copy) with the step number read from p->d_step plus k.
 template <typename T, int S>
@@ -488,17 +601,30 @@ template <typename T, int S>
 mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, double *lp, int64_t *acc,
                     hipStream_t st) {
     const int M = (S - 1) * p->R * p->C;
+    const size_t SN = (size_t)S * p->R * p->C;
     Tiling t = tiling(p);
     mc_status s;
+    const bool mala = cfg->kernel == 1;
     if ((s = ensure(p, p->prop, sizeof(T) * (size_t)n * M)) != MC_OK) return s;
     if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
     if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
-    // initial log posterior where the caller passed NaN (other chains exit at once)
-    if ((s = logpost_impl<T, S>(p, n, heights, (double *)p->lptmp.p, nullptr, st, lp)) != MC_OK) return s;
-    hipLaunchKernelGGL(k_fill_nan, dim3((n + 255) / 256), dim3(256), 0, st, lp, (const double *)p->lptmp.p, n);
+    if (mala) {
+        if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
+        if ((s = ensure(p, p->gcur, sizeof(T) * SN * n)) != MC_OK) return s;
+        if ((s = ensure(p, p->gprop, sizeof(T) * SN * n)) != MC_OK) return s;
+        if ((s = ensure(p, p->lpprop, sizeof(double) * (size_t)n)) != MC_OK) return s;
+        // MALA needs the gradient of the current states: lp and gradient are recomputed
+        if ((s = grad_eval<T, S>(p, n, heights, lp, (T *)p->gcur.p, st)) != MC_OK) return s;
+    } else {
+        // initial log posterior where the caller passed NaN (other chains exit at once)
+        if ((s = logpost_impl<T, S>(p, n, heights, (double *)p->lptmp.p, nullptr, st, lp)) != MC_OK) return s;
+        hipLaunchKernelGGL(k_fill_nan, dim3((n + 255) / 256), dim3(256), 0, st, lp, (const double *)p->lptmp.p, n);
+    }
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, p->d_step, cfg->step_offset);
     HIP_TRY(p, hipGetLastError());
-    if (cfg->kernel != 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA is not available in this build");
+    auto step_fn = [&](int k, hipStream_t ss) {
+        return mala ? mala_step<T, S>(p, n, heights, lp, acc, cfg, k, ss) : rw_step<T, S>(p, n, heights, lp, acc, cfg, k, ss);
+    };
     const int G = cfg->graph_steps < 1 ? 1 : cfg->graph_steps;
     int64_t done = 0;
     if (G > 1 && cfg->n_steps >= G) {
@@ -520,7 +646,7 @@ mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, 
             if (!p->cap_stream) HIP_TRY(p, hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
             HIP_TRY(p, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
             mc_status cs = MC_OK;
-            for (int k = 0; k < G && cs == MC_OK; ++k) cs = rw_step<T, S>(p, n, heights, lp, acc, cfg, k, p->cap_stream);
+            for (int k = 0; k < G && cs == MC_OK; ++k) cs = step_fn(k, p->cap_stream);
             if (cs == MC_OK) hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, p->cap_stream, p->d_step, (uint64_t)G);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
@@ -542,7 +668,7 @@ mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, 
     // remaining steps as eager launches
     const int64_t rest = cfg->n_steps - done;
     for (int64_t k = 0; k < rest; ++k)
-        if ((s = rw_step<T, S>(p, n, heights, lp, acc, cfg, (int)k, st)) != MC_OK) return s;
+        if ((s = step_fn((int)k, st)) != MC_OK) return s;
     if (rest > 0) hipLaunchKernelGGL(k_add_u64, dim3(1), dim3(1), 0, st, p->d_step, (uint64_t)rest);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
@@ -640,7 +766,8 @@ void mc_destroy(mc_problem *p) {
     free_ptr(p->d_expo);
     free_ptr(p->d_coL);
     for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
-    for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp})
+    for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gprior, &p->gcur, &p->gprop,
+                      &p->lpprop})
         if (b->p) (void)hipFree(b->p);
     if (p->d_step) (void)hipFree(p->d_step);
     delete p;
@@ -806,12 +933,14 @@ mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, d
                              void *stream) {
     mc_status s = check_ready(p);
     if (s != MC_OK) return s;
-    (void)n_chains;
-    (void)heights;
-    (void)logpost;
-    (void)grad;
-    (void)stream;
-    return fail(p, MC_ERR_UNSUPPORTED, "logpost_grad_batch is not available in this build");
+    if (n_chains < 0) return fail(p, MC_ERR_ARG, "n_chains < 0");
+    if (n_chains == 0) return MC_OK;
+    if (!heights || !logpost || !grad) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    return p->prec == MC_F64 ? logpost_grad_dispatch<double>(p, n_chains, heights, logpost, grad, st)
+                             : logpost_grad_dispatch<float>(p, n_chains, heights, logpost, grad, st);
 }
 
 mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *heights, double *logpost,
