@@ -168,7 +168,10 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
  * top_in_lds: stage the fixed top surface in LDS when it fits (else it is
  * read from global memory).  Defaults {4, 256, 4, 16, 0} for float32 and
  * {3, 256, 4, 4, 1} for float64.  A variant-2 shape whose queue does not fit
- * in LDS beside the surfaces runs as variant 3.  Setting a shape
+ * in LDS beside the surfaces runs as variant 3.  multi_blocks_per_cu (0..16,
+ * read from problems[0] by mcmc_run_multi): 0 launches one block per
+ * (problem, chain, ray tile) work item, k > 0 a persistent grid of k blocks
+ * per compute unit that strides over the work table.  Setting a shape
  * this build does not provide returns MC_ERR_UNSUPPORTED.
  */
 typedef struct {
@@ -177,10 +180,30 @@ typedef struct {
     int queue;
     int rays_per_thread;
     int top_in_lds;
+    int multi_blocks_per_cu;
 } mc_tuning;
 
 mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t);
 mc_status mc_get_tuning(const mc_problem *p, mc_tuning *t);
+
+/*
+ * Random-walk Metropolis on many independent problems at once (paper
+ * Sec. 3.2: independent chains vectorised on one device, here across
+ * problems as well).  Problem i runs cfgs[i] on its n_chains[i] chains with
+ * device arrays heights[i], logposts[i], n_accept[i] laid out as in
+ * mcmc_run.  Every step is one proposal launch and one prior/accept launch
+ * for all chains of all problems, plus one persistent march launch per grid
+ * size class over a static work table of (problem, chain, ray tile) items;
+ * cfgs[0].graph_steps steps are captured in one HIP graph.  A chain's
+ * results equal those of mcmc_run on its problem alone with the same
+ * launch shape (the same device code runs for it).
+ * Requirements: the same device, precision and n_surfaces for every problem,
+ * kernel = 0, equal n_steps and graph_steps, distinct handles.  Errors are
+ * reported on problems[0] (mc_last_error(problems[0])).
+ */
+mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_run_config *cfgs,
+                         const int *n_chains, void *const *heights, double *const *logposts,
+                         int64_t *const *n_accept, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Test support                                                              */

@@ -32,7 +32,7 @@ class MuonCaveError(RuntimeError):
 
 class Tuning(ct.Structure):
     _fields_ = [("march_variant", ct.c_int), ("block", ct.c_int), ("queue", ct.c_int),
-                ("rays_per_thread", ct.c_int), ("top_in_lds", ct.c_int)]
+                ("rays_per_thread", ct.c_int), ("top_in_lds", ct.c_int), ("multi_blocks_per_cu", ct.c_int)]
 
 
 class RunConfig(ct.Structure):
@@ -66,6 +66,7 @@ def load_library(path: Optional[str] = None):
         "mc_time_march": (I, [V, I, V, I, V, P(ct.c_float)]),
         "mc_set_tuning": (I, [V, P(Tuning)]),
         "mc_get_tuning": (I, [V, P(Tuning)]),
+        "mcmc_run_multi": (I, [I, P(V), P(RunConfig), P(I), P(V), P(V), P(V), V]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -77,7 +78,7 @@ def load_library(path: Optional[str] = None):
 
 EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_grid", "set_sensors",
                     "set_counts", "logpost_batch", "logpost_grad_batch", "mcmc_run", "mc_debug_philox",
-                    "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning")
+                    "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi")
 
 
 def _host(a, dtype=np.float64):
@@ -133,8 +134,10 @@ class Problem:
         return torch.float64 if self.prec == MC_F64 else torch.float32
 
     # -- launch shape -------------------------------------------------------
-    def set_tuning(self, march_variant=2, block=256, queue=4, rays_per_thread=4, top_in_lds=1):
-        t = Tuning(int(march_variant), int(block), int(queue), int(rays_per_thread), int(top_in_lds))
+    def set_tuning(self, march_variant=4, block=256, queue=4, rays_per_thread=16, top_in_lds=0,
+                   multi_blocks_per_cu=0):
+        t = Tuning(int(march_variant), int(block), int(queue), int(rays_per_thread), int(top_in_lds),
+                   int(multi_blocks_per_cu))
         self._check(self.lib.mc_set_tuning(self.h, ct.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -238,6 +241,38 @@ class Problem:
         self._check(self.lib.mcmc_run(self.h, ct.byref(cfg), n, ct.c_void_p(heights.data_ptr()),
                                       ct.c_void_p(logpost.data_ptr()), ct.c_void_p(n_accept.data_ptr()),
                                       _stream_handle(stream, self.device)))
+
+
+def mcmc_run_multi(problems, heights, logposts, n_accepts, n_steps, step_sizes, seeds, step_offsets=None,
+                   graph_steps=1, stream=None):
+    """Random-walk Metropolis on several problems in shared launches.
+
+    problems, heights, logposts, n_accepts, step_sizes and seeds are per-problem
+    sequences (the tensors as for Problem.mcmc_run); n_steps and graph_steps are
+    common to all."""
+    import torch
+    n = len(problems)
+    if not (len(heights) == len(logposts) == len(n_accepts) == len(step_sizes) == len(seeds) == n) or n == 0:
+        raise ValueError("one entry per problem in every sequence")
+    offs = step_offsets if step_offsets is not None else [0] * n
+    lib = problems[0].lib
+    hs = (ct.c_void_p * n)()
+    cfgs = (RunConfig * n)()
+    nch = (ct.c_int * n)()
+    hp, lpp, ap = (ct.c_void_p * n)(), (ct.c_void_p * n)(), (ct.c_void_p * n)()
+    for i, pr in enumerate(problems):
+        c = int(heights[i].shape[0])
+        pr._check_tensor(heights[i], pr.heights_shape(c), pr.torch_dtype, f"heights[{i}]")
+        pr._check_tensor(logposts[i], (c,), torch.float64, f"logposts[{i}]")
+        pr._check_tensor(n_accepts[i], (c,), torch.int64, f"n_accepts[{i}]")
+        hs[i] = pr.h
+        cfgs[i] = RunConfig(KERNEL_RW, int(n_steps), int(graph_steps), float(step_sizes[i]), None, int(seeds[i]),
+                            int(offs[i]))
+        nch[i] = c
+        hp[i], lpp[i], ap[i] = heights[i].data_ptr(), logposts[i].data_ptr(), n_accepts[i].data_ptr()
+    st = lib.mcmc_run_multi(n, hs, cfgs, nch, hp, lpp, ap, _stream_handle(stream, problems[0].device))
+    if st != 0:
+        raise MuonCaveError(st, lib.mc_last_error(problems[0].h).decode())
 
 
 def time_march(problem: "Problem", heights, iters: int = 20, stream=None) -> float:

@@ -17,6 +17,11 @@
 #include "march3.h"
 #include "march5.h"
 #include "adjoint.h"
+#include "multi.h"
+
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include "prior.h"
 
 #include <type_traits>
@@ -74,6 +79,7 @@ struct mc_problem {
     DevBuf obuf, gfix, gprior, gcur, gprop, lpprop;   // gradient and MALA workspaces
     uint64_t *d_step = nullptr;
     mc_tuning tune = {2, 256, 4, 4, 1};
+    uint64_t gen = 1;   // bumped whenever device pointers or baked constants change
     // graph cache
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -126,6 +132,7 @@ void drop_graph(mc_problem *p) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
     p->gkey = GraphKey();
+    p->gen += 1;
 }
 
 // Grow-only workspace.  A reallocation invalidates the cached graph, whose
@@ -715,6 +722,291 @@ mc_status mcmc_dispatch(mc_problem *p, const mc_run_config *cfg, int n, void *he
     return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
 }
 
+// ---------------------------------------------------------------------------
+// Many problems per launch
+// ---------------------------------------------------------------------------
+
+constexpr int kMultiBlock = 256;
+
+struct MultiClass {
+    void *items = nullptr;   // int4 [n_items]
+    int n_items = 0;
+    size_t lds = 0;
+    bool top_lds = false;
+};
+
+struct MultiPlan {
+    // key
+    std::vector<mc_problem *> ps;
+    std::vector<int> n;
+    std::vector<const void *> H, lp, acc;
+    std::vector<uint64_t> gens, seeds;
+    std::vector<double> sigma;
+    int G = 0, device = 0;
+    // device tables
+    void *d_mp = nullptr, *d_rc = nullptr, *d_pp = nullptr, *d_pd = nullptr, *d_chain_items = nullptr;
+    void *d_step_ptrs = nullptr, *d_step_vals = nullptr;
+    int n_chain_items = 0;
+    size_t prior_lds = 0;
+    std::vector<MultiClass> classes;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap = nullptr;
+    int persistent_blocks = 0;
+    ~MultiPlan() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void *q : {d_mp, d_rc, d_pp, d_pd, d_chain_items, d_step_ptrs, d_step_vals})
+            if (q) (void)hipFree(q);
+        for (auto &c : classes)
+            if (c.items) (void)hipFree(c.items);
+    }
+};
+
+std::vector<MultiPlan *> g_multi_plans;   // small cache of built plans (most recent last)
+std::mutex g_multi_mu;                     // guards g_multi_plans
+
+template <typename X>
+mc_status upload_vec(mc_problem *err, void *&dst, const std::vector<X> &v) {
+    if (dst) (void)hipFree(dst);
+    dst = nullptr;
+    if (v.empty()) return MC_OK;
+    HIP_TRY(err, hipMalloc(&dst, sizeof(X) * v.size()));
+    HIP_TRY(err, hipMemcpy(dst, v.data(), sizeof(X) * v.size(), hipMemcpyHostToDevice));
+    return MC_OK;
+}
+
+template <typename T, int S>
+mc_status build_multi_plan(MultiPlan *pl, const mc_run_config *cfgs) {
+    const int np = (int)pl->ps.size();
+    mc_problem *e = pl->ps[0];
+    std::vector<MarchParams<T>> mp(np);
+    std::vector<RayConsts<T>> rc(np);
+    std::vector<PriorParams<T>> pp(np);
+    std::vector<ProposeDesc<T>> pd(np);
+    std::vector<uint64_t *> steps(np);
+    for (int i = 0; i < np; ++i) {
+        mc_problem *p = pl->ps[i];
+        const T *prop = (const T *)p->prop.p;
+        mp[i] = march_params<T>(p, prop, nullptr, (double *)p->partials.p);
+        rc[i] = ray_consts<T>(p);
+        pp[i] = prior_params<T>(p, prop, (const double *)p->partials.p);
+        pp[i].mh = 1;
+        pp[i].lp_cur = (double *)pl->lp[i];
+        pp[i].n_acc = (int64_t *)pl->acc[i];
+        pp[i].state = (T *)pl->H[i];
+        pp[i].seed = cfgs[i].seed;
+        pp[i].step_base = p->d_step;
+        pd[i].H = (const T *)pl->H[i];
+        pd[i].prop = (T *)p->prop.p;
+        pd[i].M = (S - 1) * p->R * p->C;
+        pd[i].sigma = cfgs[i].step_size;
+        pd[i].seed = cfgs[i].seed;
+        pd[i].step_base = p->d_step;
+        steps[i] = p->d_step;
+    }
+    mc_status s;
+    if ((s = upload_vec(e, pl->d_mp, mp)) != MC_OK) return s;
+    if ((s = upload_vec(e, pl->d_rc, rc)) != MC_OK) return s;
+    if ((s = upload_vec(e, pl->d_pp, pp)) != MC_OK) return s;
+    if ((s = upload_vec(e, pl->d_pd, pd)) != MC_OK) return s;
+    if ((s = upload_vec(e, pl->d_step_ptrs, steps)) != MC_OK) return s;
+    std::vector<uint64_t> zero(np, 0);
+    if ((s = upload_vec(e, pl->d_step_vals, zero)) != MC_OK) return s;
+    // chains, largest grids first
+    std::vector<int> order(np);
+    for (int i = 0; i < np; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (size_t)pl->ps[a]->R * pl->ps[a]->C > (size_t)pl->ps[b]->R * pl->ps[b]->C;
+    });
+    std::vector<int2> chains;
+    size_t prior_lds = 0;
+    for (int i : order) {
+        for (int c = 0; c < pl->n[i]; ++c) chains.push_back(make_int2(i, c));
+        prior_lds = std::max(prior_lds, sizeof(double) * (size_t)pl->ps[i]->R * pl->ps[i]->C);
+    }
+    pl->n_chain_items = (int)chains.size();
+    pl->prior_lds = prior_lds;
+    if ((s = upload_vec(e, pl->d_chain_items, chains)) != MC_OK) return s;
+    // march classes: one per (grid size, top placement); items sorted by decreasing ray count
+    std::map<std::pair<size_t, int>, std::vector<int>> cls;
+    for (int i = 0; i < np; ++i) {
+        mc_problem *p = pl->ps[i];
+        if (p->n_ray == 0) continue;
+        size_t N = (size_t)p->R * p->C;
+        bool tl = N * S * sizeof(T) + 4096 <= p->max_lds;
+        cls[{N, tl ? 1 : 0}].push_back(i);
+    }
+    for (auto &kv : cls) {
+        MultiClass mc_;
+        mc_.top_lds = kv.first.second != 0;
+        mc_.lds = kv.first.first * (mc_.top_lds ? S : S - 1) * sizeof(T);
+        if (mc_.lds + 2048 > e->max_lds) return fail(e, MC_ERR_UNSUPPORTED, "grid too large for LDS");
+        std::vector<int> members = kv.second;
+        std::stable_sort(members.begin(), members.end(), [&](int a, int b) {
+            return tiling(pl->ps[a]).rays_per_block > tiling(pl->ps[b]).rays_per_block;
+        });
+        std::vector<int4> items;
+        for (int i : members) {
+            Tiling t = tiling(pl->ps[i]);
+            for (int tt = 0; tt < t.n_tiles; ++tt)
+                for (int c = 0; c < pl->n[i]; ++c) items.push_back(make_int4(i, c, tt, 0));
+        }
+        mc_.n_items = (int)items.size();
+        if ((s = upload_vec(e, mc_.items, items)) != MC_OK) return s;
+        pl->classes.push_back(mc_);
+    }
+    int ncu = 256;
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device);
+    pl->persistent_blocks = e->tune.multi_blocks_per_cu > 0 ? e->tune.multi_blocks_per_cu * ncu : INT32_MAX;
+    return MC_OK;
+}
+
+template <typename T, int S>
+mc_status multi_step(MultiPlan *pl, int k, hipStream_t st) {
+    mc_problem *e = pl->ps[0];
+    hipLaunchKernelGGL(k_propose_multi<T>, dim3(pl->n_chain_items), dim3(256), 0, st,
+                       (const ProposeDesc<T> *)pl->d_pd, (const int2 *)pl->d_chain_items, k);
+    HIP_TRY(e, hipGetLastError());
+    for (auto &c : pl->classes) {
+        const int grid = std::min(c.n_items, pl->persistent_blocks);
+        if (grid <= 0) continue;
+        if constexpr (std::is_same<T, float>::value) {
+            if (c.top_lds) {
+                auto kk = k_march_multi4<S, true, kMultiBlock>;
+                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<float> *)pl->d_mp,
+                                   (const RayConsts<float> *)pl->d_rc, (const int4 *)c.items, c.n_items);
+            } else {
+                auto kk = k_march_multi4<S, false, kMultiBlock>;
+                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<float> *)pl->d_mp,
+                                   (const RayConsts<float> *)pl->d_rc, (const int4 *)c.items, c.n_items);
+            }
+        } else {
+            if (c.top_lds) {
+                auto kk = k_march_multi3<T, S, true, kMultiBlock>;
+                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<T> *)pl->d_mp,
+                                   (const RayConsts<T> *)pl->d_rc, (const int4 *)c.items, c.n_items);
+            } else {
+                auto kk = k_march_multi3<T, S, false, kMultiBlock>;
+                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<T> *)pl->d_mp,
+                                   (const RayConsts<T> *)pl->d_rc, (const int4 *)c.items, c.n_items);
+            }
+        }
+        HIP_TRY(e, hipGetLastError());
+    }
+    auto kp = k_prior_multi<T, S, kPriorBlock>;
+    if (pl->prior_lds > 65536) (void)hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->prior_lds);
+    hipLaunchKernelGGL(kp, dim3(pl->n_chain_items), dim3(kPriorBlock), pl->prior_lds, st,
+                       (const PriorParams<T> *)pl->d_pp, (const int2 *)pl->d_chain_items, k);
+    HIP_TRY(e, hipGetLastError());
+    return MC_OK;
+}
+
+template <typename T, int S>
+mc_status mcmc_multi_impl(int np, mc_problem *const *ps, const mc_run_config *cfgs, const int *n_chains,
+                          void *const *heights, double *const *lps, int64_t *const *accs, hipStream_t st) {
+    mc_problem *e = ps[0];
+    mc_status s;
+    // workspaces and initial log posteriors, per problem
+    for (int i = 0; i < np; ++i) {
+        mc_problem *p = ps[i];
+        const int n = n_chains[i];
+        const int M = (S - 1) * p->R * p->C;
+        Tiling t = tiling(p);
+        if ((s = ensure(p, p->prop, sizeof(T) * (size_t)n * M)) != MC_OK) return s;
+        if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
+        if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+        if ((s = logpost_impl<T, S>(p, n, (const T *)heights[i], (double *)p->lptmp.p, nullptr, st, lps[i])) != MC_OK)
+            return s;
+        hipLaunchKernelGGL(k_fill_nan, dim3((n + 255) / 256), dim3(256), 0, st, lps[i], (const double *)p->lptmp.p, n);
+        HIP_TRY(p, hipGetLastError());
+    }
+    // find or build the plan
+    MultiPlan *pl = nullptr;
+    const int G = cfgs[0].graph_steps < 1 ? 1 : cfgs[0].graph_steps;
+    for (MultiPlan *q : g_multi_plans) {
+        bool same = (int)q->ps.size() == np && q->G == G;
+        for (int i = 0; same && i < np; ++i)
+            same = q->ps[i] == ps[i] && q->n[i] == n_chains[i] && q->H[i] == heights[i] && q->lp[i] == lps[i] &&
+                   q->acc[i] == accs[i] && q->gens[i] == ps[i]->gen && q->seeds[i] == cfgs[i].seed &&
+                   q->sigma[i] == cfgs[i].step_size;
+        if (same) {
+            pl = q;
+            break;
+        }
+    }
+    if (!pl) {
+        pl = new MultiPlan();
+        pl->G = G;
+        pl->device = e->device;
+        for (int i = 0; i < np; ++i) {
+            pl->ps.push_back(ps[i]);
+            pl->n.push_back(n_chains[i]);
+            pl->H.push_back(heights[i]);
+            pl->lp.push_back(lps[i]);
+            pl->acc.push_back(accs[i]);
+            pl->gens.push_back(ps[i]->gen);
+            pl->seeds.push_back(cfgs[i].seed);
+            pl->sigma.push_back(cfgs[i].step_size);
+        }
+        if ((s = build_multi_plan<T, S>(pl, cfgs)) != MC_OK) {
+            delete pl;
+            return s;
+        }
+        g_multi_plans.push_back(pl);
+        if (g_multi_plans.size() > 4) {
+            delete g_multi_plans.front();
+            g_multi_plans.erase(g_multi_plans.begin());
+        }
+    }
+    // step counters of every problem
+    std::vector<uint64_t> offs(np);
+    for (int i = 0; i < np; ++i) offs[i] = cfgs[i].step_offset;
+    HIP_TRY(e, hipMemcpyAsync(pl->d_step_vals, offs.data(), sizeof(uint64_t) * np, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_set_u64_multi, dim3((np + 255) / 256), dim3(256), 0, st, (uint64_t *const *)pl->d_step_ptrs,
+                       (const uint64_t *)pl->d_step_vals, np);
+    HIP_TRY(e, hipGetLastError());
+    HIP_TRY(e, hipStreamSynchronize(st));   // the host step-offset array goes out of scope
+    const int64_t n_steps = cfgs[0].n_steps;
+    int64_t done = 0;
+    if (G > 1 && n_steps >= G) {
+        if (!pl->gexec) {
+            if (!pl->cap) HIP_TRY(e, hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+            HIP_TRY(e, hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+            mc_status cs = MC_OK;
+            for (int k = 0; k < G && cs == MC_OK; ++k) cs = multi_step<T, S>(pl, k, pl->cap);
+            if (cs == MC_OK)
+                hipLaunchKernelGGL(k_add_u64_multi, dim3((np + 255) / 256), dim3(256), 0, pl->cap,
+                                   (uint64_t *const *)pl->d_step_ptrs, np, (uint64_t)G);
+            hipGraph_t graph = nullptr;
+            hipError_t er = hipStreamEndCapture(pl->cap, &graph);
+            if (cs != MC_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return cs;
+            }
+            if (er != hipSuccess) return fail(e, MC_ERR_DEVICE, "graph capture: %s", hipGetErrorString(er));
+            er = hipGraphInstantiate(&pl->gexec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (er != hipSuccess) {
+                pl->gexec = nullptr;
+                return fail(e, MC_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(er));
+            }
+        }
+        for (; done + G <= n_steps; done += G) HIP_TRY(e, hipGraphLaunch(pl->gexec, st));
+    }
+    const int64_t rest = n_steps - done;
+    for (int64_t k = 0; k < rest; ++k)
+        if ((s = multi_step<T, S>(pl, (int)k, st)) != MC_OK) return s;
+    if (rest > 0)
+        hipLaunchKernelGGL(k_add_u64_multi, dim3((np + 255) / 256), dim3(256), 0, st, (uint64_t *const *)pl->d_step_ptrs,
+                           np, (uint64_t)rest);
+    HIP_TRY(e, hipGetLastError());
+    return MC_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -755,6 +1047,16 @@ void mc_destroy(mc_problem *p) {
     if (!p) return;
     DeviceGuard g(p->device);
     (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lock(g_multi_mu);
+    for (size_t i = 0; i < g_multi_plans.size();) {
+        MultiPlan *q = g_multi_plans[i];
+        if (std::find(q->ps.begin(), q->ps.end(), p) != q->ps.end()) {
+            delete q;
+            g_multi_plans.erase(g_multi_plans.begin() + i);
+        } else {
+            ++i;
+        }
+    }
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     free_ptr(p->d_top);
@@ -961,12 +1263,58 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
                              : mcmc_dispatch<float>(p, cfg, n_chains, heights, logpost, n_accept, st);
 }
 
+mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_run_config *cfgs,
+                         const int *n_chains, void *const *heights, double *const *logposts,
+                         int64_t *const *n_accept, void *stream) {
+    if (n_problems <= 0 || !problems || !cfgs || !n_chains || !heights || !logposts || !n_accept)
+        return fail(nullptr, MC_ERR_ARG, "invalid arguments");
+    mc_problem *e = problems[0];
+    if (!e) return MC_ERR_ARG;
+    for (int i = 0; i < n_problems; ++i) {
+        mc_problem *p = problems[i];
+        if (!p) return fail(e, MC_ERR_ARG, "problem %d is NULL", i);
+        mc_status s = check_ready(p);
+        if (s != MC_OK) return fail(e, s, "problem %d: %s", i, p->err.c_str());
+        if (p->device != e->device || p->prec != e->prec || p->S != e->S)
+            return fail(e, MC_ERR_ARG, "problem %d: device, precision and n_surfaces must match problem 0", i);
+        for (int j = 0; j < i; ++j)
+            if (problems[j] == p) return fail(e, MC_ERR_ARG, "problem %d repeats problem %d", i, j);
+        if (cfgs[i].kernel != 0) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi runs random-walk Metropolis");
+        if (cfgs[i].n_steps != cfgs[0].n_steps || cfgs[i].graph_steps != cfgs[0].graph_steps)
+            return fail(e, MC_ERR_ARG, "n_steps and graph_steps must be equal across problems");
+        if (!(cfgs[i].step_size >= 0) || !std::isfinite(cfgs[i].step_size)) return fail(e, MC_ERR_ARG, "step_size");
+        if (cfgs[i].step_offset + (uint64_t)cfgs[i].n_steps >= (1ULL << 48)) return fail(e, MC_ERR_ARG, "step counter");
+        if (n_chains[i] <= 0 || n_chains[i] > 65535) return fail(e, MC_ERR_ARG, "n_chains[%d]", i);
+        if (!heights[i] || !logposts[i] || !n_accept[i]) return fail(e, MC_ERR_ARG, "NULL device pointer");
+    }
+    if (cfgs[0].n_steps < 0) return fail(e, MC_ERR_ARG, "n_steps < 0");
+    DeviceGuard g(e->device);
+    std::lock_guard<std::mutex> lock(g_multi_mu);
+    hipStream_t st = (hipStream_t)stream;
+    if (e->prec == MC_F64) {
+        switch (e->S) {
+            case 2: return mcmc_multi_impl<double, 2>(n_problems, problems, cfgs, n_chains, heights, logposts, n_accept, st);
+            case 3: return mcmc_multi_impl<double, 3>(n_problems, problems, cfgs, n_chains, heights, logposts, n_accept, st);
+            case 4: return mcmc_multi_impl<double, 4>(n_problems, problems, cfgs, n_chains, heights, logposts, n_accept, st);
+        }
+    } else {
+        switch (e->S) {
+            case 2: return mcmc_multi_impl<float, 2>(n_problems, problems, cfgs, n_chains, heights, logposts, n_accept, st);
+            case 3: return mcmc_multi_impl<float, 3>(n_problems, problems, cfgs, n_chains, heights, logposts, n_accept, st);
+            case 4: return mcmc_multi_impl<float, 4>(n_problems, problems, cfgs, n_chains, heights, logposts, n_accept, st);
+        }
+    }
+    return fail(e, MC_ERR_UNSUPPORTED, "n_surfaces %d", e->S);
+}
+
 mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t) {
     if (!p || !t) return MC_ERR_ARG;
     if (t->march_variant < 1 || t->march_variant > 5) return fail(p, MC_ERR_ARG, "march_variant %d", t->march_variant);
     if (t->march_variant >= 3 && !(t->block == 256 || (p->prec == MC_F32 && (t->block == 512 || t->block == 1024))))
         return fail(p, MC_ERR_UNSUPPORTED, "block %d not built for this precision", t->block);
     if (t->rays_per_thread < 1 || t->rays_per_thread > 64) return fail(p, MC_ERR_ARG, "rays_per_thread %d", t->rays_per_thread);
+    if (t->multi_blocks_per_cu < 0 || t->multi_blocks_per_cu > 16)
+        return fail(p, MC_ERR_ARG, "multi_blocks_per_cu %d", t->multi_blocks_per_cu);
     if (t->march_variant == 2 && !v2_shape_supported(p->prec, t->block, t->queue))
         return fail(p, MC_ERR_UNSUPPORTED, "block %d / queue %d not built for this precision", t->block, t->queue);
     DeviceGuard g(p->device);

@@ -133,13 +133,13 @@ __device__ __forceinline__ T walk_surface(const MarchParams<T> &P, const T *Hl, 
     return len;
 }
 
+// Body of one block: chain `chain`, ray tile `tile`; sh = the block's LDS.
 template <typename T, int S, bool TOP_LDS, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_march_lik3(MarchParams<T> P, RayConsts<T> K) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sh = reinterpret_cast<T *>(smem_raw);
+__device__ __forceinline__ void march_block3(const MarchParams<T> &P, const RayConsts<T> &K, int chain, int tile,
+                                             T *sh) {
     __shared__ double red[16];
     __shared__ T band[2 * kMaxSurfaces];
-    const int chain = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     if (P.only_nan && !(P.only_nan[chain] != P.only_nan[chain])) return;
     const int N = P.R * P.C;
     const T *Hc = P.heights + (size_t)chain * (S - 1) * N;
@@ -212,6 +212,12 @@ __global__ __launch_bounds__(BLOCK) void k_march_lik3(MarchParams<T> P, RayConst
     }
     const double tot = block_sum<BLOCK>(acc, red);
     if (tid == 0) P.partials[(size_t)chain * P.n_tiles + tile] = tot;
+}
+
+template <typename T, int S, bool TOP_LDS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_march_lik3(MarchParams<T> P, RayConsts<T> K) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    march_block3<T, S, TOP_LDS, BLOCK>(P, K, blockIdx.y, blockIdx.x, reinterpret_cast<T *>(smem_raw));
 }
 
 }  // namespace mc

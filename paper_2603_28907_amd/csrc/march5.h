@@ -235,12 +235,11 @@ __device__ __forceinline__ void stage_surfaces(const MarchParams<float> &P, floa
 // v4: inline solves
 // ---------------------------------------------------------------------------
 template <int S, bool TOP_LDS, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_march_lik4(MarchParams<float> P, RayConsts<float> K) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    float *sh = reinterpret_cast<float *>(smem_raw);
+__device__ __forceinline__ void march_block4(const MarchParams<float> &P, const RayConsts<float> &K, int chain,
+                                             int tile, float *sh) {
     __shared__ double red[16];
     __shared__ float band[2 * kMaxSurfaces];
-    const int chain = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     if (P.only_nan && !(P.only_nan[chain] != P.only_nan[chain])) return;
     stage_surfaces<S, TOP_LDS, BLOCK>(P, sh, band, chain);
     const int N = P.R * P.C, C = P.C;
@@ -286,6 +285,12 @@ __global__ __launch_bounds__(BLOCK) void k_march_lik4(MarchParams<float> P, RayC
     }
     const double tot = block_sum<BLOCK>(acc, red);
     if (tid == 0) P.partials[(size_t)chain * P.n_tiles + tile] = tot;
+}
+
+template <int S, bool TOP_LDS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_march_lik4(MarchParams<float> P, RayConsts<float> K) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    march_block4<S, TOP_LDS, BLOCK>(P, K, blockIdx.y, blockIdx.x, reinterpret_cast<float *>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------

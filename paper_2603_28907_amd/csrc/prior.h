@@ -44,14 +44,13 @@ __device__ __forceinline__ double probit_uv(double u, double v) {
     return u <= 0.5 ? normcdfinv(u) : -normcdfinv(v);
 }
 
+// Body of one block for chain c; w = LDS workspace of R*C doubles.
 template <typename T, int S, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_prior_finalize(PriorParams<T> P) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *w = reinterpret_cast<double *>(smem_raw);   // [N]
+__device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, double *w) {
     __shared__ double red[16];
     __shared__ int ired[16];
     __shared__ int s_acc;
-    const int c = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     if (P.only_nan && !(P.only_nan[c] != P.only_nan[c])) return;
     const int R = P.R, C = P.C, N = R * C;
     const T *H = P.heights + (size_t)c * (S - 1) * N;
@@ -120,6 +119,12 @@ __global__ __launch_bounds__(BLOCK) void k_prior_finalize(PriorParams<T> P) {
             for (int n = tid; n < M; n += BLOCK) dst[n] = H[n];
         }
     }
+}
+
+template <typename T, int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_prior_finalize(PriorParams<T> P) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    prior_block<T, S, BLOCK>(P, blockIdx.x, reinterpret_cast<double *>(smem_raw));
 }
 
 // Random-walk proposal: prop = H + sigma z, z_i the (i%2)-th normal of pair
