@@ -54,7 +54,7 @@ def make_workload(name):
     from paper_2603_28907_amd import inputs
     if name == "grf_cave_64":
         sc = inputs.grf_cave(seed=10)
-        return sc, 1024, dict(counts_seed=11, init_seed=12, sigma=0.05)
+        return sc, 1024, dict(counts_seed=11, init_seed=12, sigma=0.005)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -93,6 +93,175 @@ def cpu_baseline(name, budget_s=10.0):
                       f"{name} workload, FP64"}
 
 
+def build_hetero(n_problems, torch, precision="f32"):
+    """The heterogeneous batch: problem i has seed 20+i, grid side in
+    {16,32,64,128} over 400 m, 2-16 sensors, pixel side 32-64, 64-512 chains."""
+    from paper_2603_28907_amd import inputs
+    from paper_2603_28907_amd.binding import Problem
+    probs, H, lp, acc = [], [], [], []
+    dt = torch.float32 if precision == "f32" else torch.float64
+    for i in range(n_problems):
+        sc, n = inputs.heterogeneous_problem(i)
+        sc.counts = gpu_counts(sc, torch)
+        probs.append(Problem.from_scenario(sc, precision=precision))
+        H.append(torch.as_tensor(inputs.init_states(sc, n, seed=500 + i), dtype=dt, device="cuda:0"))
+        lp.append(torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0"))
+        acc.append(torch.zeros(n, dtype=torch.int64, device="cuda:0"))
+    return probs, H, lp, acc
+
+
+def bench_hetero(args, torch):
+    """Batched heterogeneous problems (mcmc_run_multi, autotuned shapes, HIP
+    graphs) against the plain per-problem sampler (one problem at a time, one
+    launch per kernel per step, no graph) on the same GPU and inputs."""
+    from paper_2603_28907_amd import autotune
+    from paper_2603_28907_amd.binding import mcmc_run_multi
+    n_prob = args.problems
+    t0 = time.perf_counter()
+    probs, H, lp, acc = build_hetero(n_prob, torch)
+    sigma = [0.005] * n_prob
+    seeds = [1000 + i for i in range(n_prob)]
+    chain_rays = sum(h.shape[0] * p.n_rays for h, p in zip(H, probs))
+    chains = sum(h.shape[0] for h in H)
+    print(f"[bench] {n_prob} problems, {chains} chains, {chain_rays:.3e} chain-rays per step "
+          f"(set-up {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    # plain sampler with the library's default shapes
+    for i, p in enumerate(probs):
+        p.mcmc_run(H[i], lp[i], acc[i], 1, sigma[i], seeds[i], step_offset=0, graph_steps=1)
+    torch.cuda.synchronize()
+    k_plain = max(1, args.plain_steps)
+    t0 = time.perf_counter()
+    for i, p in enumerate(probs):
+        p.mcmc_run(H[i], lp[i], acc[i], k_plain, sigma[i], seeds[i], step_offset=1, graph_steps=1)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    print(f"[bench] plain sampler: {dt_plain / k_plain * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    # autotuned shapes per grid class
+    t0 = time.perf_counter()
+    tuned = autotune.tune_batch(probs, H)
+    dt_tune = time.perf_counter() - t0
+    print(f"[bench] autotuned {len(tuned)} classes in {dt_tune:.1f} s", file=sys.stderr, flush=True)
+    # plain sampler again, with the autotuned shapes (separates batching from tuning)
+    off = 1 + k_plain
+    for i, p in enumerate(probs):
+        p.mcmc_run(H[i], lp[i], acc[i], 1, sigma[i], seeds[i], step_offset=off, graph_steps=1)
+    torch.cuda.synchronize()
+    off += 1
+    t0 = time.perf_counter()
+    for i, p in enumerate(probs):
+        p.mcmc_run(H[i], lp[i], acc[i], k_plain, sigma[i], seeds[i], step_offset=off, graph_steps=1)
+    torch.cuda.synchronize()
+    dt_plain_tuned = time.perf_counter() - t0
+    off += k_plain
+    G = max(1, min(args.graph_steps, args.steps))
+    mcmc_run_multi(probs, H, lp, acc, args.warmup, sigma, seeds, step_offsets=[off] * n_prob,
+                   graph_steps=min(G, max(args.warmup, 1)))
+    torch.cuda.synchronize()
+    off += args.warmup
+    t0 = time.perf_counter()
+    mcmc_run_multi(probs, H, lp, acc, args.steps, sigma, seeds, step_offsets=[off] * n_prob, graph_steps=G)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("[bench] timed region done", file=sys.stderr, flush=True)
+    for x in lp:
+        assert torch.isfinite(x).all(), "non-finite log posterior"
+    value = chain_rays * args.steps / dt
+    plain_value = chain_rays * k_plain / dt_plain
+    return {
+        "metric": METRIC, "value": value, "unit": "ray-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"hetero_{n_prob}: {n_prob} problems (seeds 20..{19 + n_prob}), grids "
+                               f"{{16,32,64,128}}^2 over 400 m, 2-16 sensors, 32-64 px side, 64-512 chains; "
+                               f"random-walk Metropolis sigma 0.005 m; float32 march, float64 sums; HIP graphs "
+                               f"of {G} steps; autotuned launch shapes",
+                   "problems": n_prob, "chains": chains, "chain_rays_per_step": chain_rays},
+        "logpost_evals_per_s": chains * args.steps / dt,
+        "plain": {"value": plain_value, "unit": "ray-evals/s", "ms_per_step": dt_plain / k_plain * 1e3,
+                  "steps": k_plain, "logpost_evals_per_s": chains * k_plain / dt_plain,
+                  "kind": "per-problem mcmc_run, graph_steps=1, default launch shapes"},
+        "plain_tuned": {"value": chain_rays * k_plain / dt_plain_tuned, "unit": "ray-evals/s",
+                        "ms_per_step": dt_plain_tuned / k_plain * 1e3, "steps": k_plain,
+                        "kind": "per-problem mcmc_run, graph_steps=1, autotuned launch shapes"},
+        "speedup_vs_plain": value / plain_value,
+        "autotune": {"seconds": dt_tune, "classes": {k: {f: v[f] for f in ("block", "rays_per_thread")}
+                                                     for k, v in tuned.items()}},
+    }
+
+
+def bench_serve(args, torch):
+    """Serving: Poisson arrivals of heterogeneous jobs (sizes as the hetero
+    workload), each run to a fixed number of steps per chain; the same
+    arrival stream is served with continuous batching (many resident jobs)
+    and by the plain one-job-at-a-time loop (max_jobs = 1)."""
+    from paper_2603_28907_amd import inputs
+    from paper_2603_28907_amd.binding import JOB_DONE, Server
+    arrivals = inputs.poisson_arrivals(args.rate, args.duration, seed=40)
+    n_jobs = len(arrivals)
+    t0 = time.perf_counter()
+    jobs = []
+    for i in range(n_jobs):
+        sc, n = inputs.heterogeneous_problem(i)
+        sc.counts = gpu_counts(sc, torch)
+        jobs.append((sc, n))
+    print(f"[bench] {n_jobs} jobs generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    work_chain_steps = sum(n for _, n in jobs) * args.job_steps
+    work_ray_steps = sum(n * sc.n_rays for sc, n in jobs) * args.job_steps
+
+    def serve(max_jobs):
+        srv = Server(precision="f32", max_jobs=max_jobs, steps_per_round=args.graph_steps)
+        ids = []
+        start = time.perf_counter()
+        for k, (sc, n) in enumerate(jobs):
+            delay = arrivals[k] - (time.perf_counter() - start)
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(sc, n, args.job_steps, 0.005, 7000 + k))
+        done = 0
+        while True:
+            st = srv.stats()
+            if st["done"] + st["failed"] >= n_jobs:
+                break
+            if st["done"] > done + max(1, n_jobs // 10):
+                done = st["done"]
+                print(f"[bench] max_jobs {max_jobs}: {done}/{n_jobs} jobs done", file=sys.stderr, flush=True)
+            time.sleep(0.05)
+        infos = [srv.poll(j, arrays=False) for j in ids]
+        st = srv.stats()
+        srv.close()
+        assert all(i["status"] == JOB_DONE for i in infos), "a job failed"
+        lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+        wait = np.array([i["t_admit"] - i["t_submit"] for i in infos])
+        serv = np.array([i["t_done"] - i["t_admit"] for i in infos])
+        span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+        q = lambda a, p: float(np.percentile(a, p))
+        return {"max_jobs": max_jobs, "p50_s": q(lat, 50), "p99_s": q(lat, 99),
+                "queue_p50_s": q(wait, 50), "queue_p99_s": q(wait, 99),
+                "service_p50_s": q(serv, 50), "service_p99_s": q(serv, 99),
+                "logpost_evals_per_s": work_chain_steps / span, "ray_evals_per_s": work_ray_steps / span,
+                "makespan_s": span, "busy_s": st["busy_seconds"], "rounds": st["rounds"],
+                "max_resident": st["max_resident"], "peak_gb": st["peak_bytes"] / 1e9}
+
+    batched = serve(args.max_jobs)
+    print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
+    plain = serve(1) if not args.no_plain else None
+    offered = args.rate * (work_chain_steps / n_jobs) / batched["logpost_evals_per_s"]
+    return {
+        "metric": METRIC, "value": batched["ray_evals_per_s"], "unit": "ray-evals/s", "n_gpus": 1,
+        "steps": args.job_steps, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serve: Poisson arrivals at {args.rate} jobs/s for {args.duration} s "
+                               f"({n_jobs} jobs, seed 40), job sizes as the hetero workload, "
+                               f"{args.job_steps} steps per chain, rounds of {args.graph_steps} steps, "
+                               f"up to {args.max_jobs} resident jobs",
+                   "jobs": n_jobs, "rate_per_s": args.rate},
+        "p50_s": batched["p50_s"], "p99_s": batched["p99_s"],
+        "logpost_evals_per_s": batched["logpost_evals_per_s"],
+        "offered_load": offered,
+        "batched": batched, "plain": plain,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +271,13 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--march-iters", type=int, default=20)
+    ap.add_argument("--problems", type=int, default=256, help="problems in the hetero workload")
+    ap.add_argument("--plain-steps", type=int, default=5, help="steps of the plain per-problem sampler")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
+    ap.add_argument("--duration", type=float, default=3.0, help="serve: seconds of arrivals")
+    ap.add_argument("--job-steps", type=int, default=2000, help="serve: steps per chain per job")
+    ap.add_argument("--max-jobs", type=int, default=64, help="serve: resident jobs at once")
+    ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); chains and problems are independent "
@@ -111,6 +287,12 @@ def main():
     from paper_2603_28907_amd import binding, inputs
     from paper_2603_28907_amd.binding import Problem
 
+    if args.workload == "hetero":
+        print(json.dumps(bench_hetero(args, torch)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args, torch)), flush=True)
+        return
     sc, n_chains, w = make_workload(args.workload)
     print(f"[bench] workload {args.workload}: {n_chains} chains x {sc.n_rays} rays", file=sys.stderr, flush=True)
     sc.counts = gpu_counts(sc, torch)
@@ -159,7 +341,7 @@ def main():
         "accept_rate": float(acc.double().mean().item()) / (args.warmup + args.steps),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "k_march_lik", "ms_per_launch": ms_march,
+                     "kernel": "k_march_lik4", "ms_per_launch": ms_march,
                      "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays},
     }
     if not args.no_cpu_baseline:

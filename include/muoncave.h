@@ -166,8 +166,10 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
  * 1024; float64 handles use 256), queue: crossing-queue slots per lane (4 or
  * 8), rays_per_thread: rays each thread marches per launch (1..64),
  * top_in_lds: stage the fixed top surface in LDS when it fits (else it is
- * read from global memory).  Defaults {4, 256, 4, 16, 0} for float32 and
- * {3, 256, 4, 4, 1} for float64.  A variant-2 shape whose queue does not fit
+ * read from global memory).  Until mc_set_tuning is called the shape follows
+ * the grid loaded last: float32 {4, 256, 4, 8, 0} below 48x48 nodes,
+ * {4, 256, 4, 16, 0} up to 128x128, {4, 1024, 4, 16, 0} from 128x128 on;
+ * float64 {3, 256, 4, 4, 1}.  A variant-2 shape whose queue does not fit
  * in LDS beside the surfaces runs as variant 3.  multi_blocks_per_cu (0..16,
  * read from problems[0] by mcmc_run_multi): 0 launches one block per
  * (problem, chain, ray tile) work item, k > 0 a persistent grid of k blocks
@@ -204,6 +206,102 @@ mc_status mc_get_tuning(const mc_problem *p, mc_tuning *t);
 mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_run_config *cfgs,
                          const int *n_chains, void *const *heights, double *const *logposts,
                          int64_t *const *n_accept, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: posterior-inference jobs batched as they arrive                  */
+/* ------------------------------------------------------------------------ */
+/*
+ * A server owns one GPU and a scheduler thread.  Jobs (one inference problem
+ * each: geometry, sensors, counts, chains, steps) are submitted at any time
+ * and wait in a FIFO queue; the scheduler admits the queue head whenever
+ * fewer than max_jobs jobs are resident and the job's device footprint fits
+ * in the memory budget beside the resident ones.  Resident jobs keep their
+ * chain state in device memory and advance together in rounds of
+ * steps_per_round random-walk Metropolis steps (one mcmc_run_multi-style
+ * graph launch per round over every resident job); jobs join and leave at
+ * round boundaries, and admission work (uploads, the initial log posterior)
+ * overlaps the running round.  When a job has taken n_steps steps the
+ * scheduler computes its posterior summary on the device from the last state
+ * of every chain (paper Sec. 3.2 keeps only each chain's last state): the
+ * per-node mean and standard deviation over chains, the chain with the
+ * highest log posterior and its state, and the acceptance rate; copies it to
+ * host memory and frees the job's device memory.
+ *
+ * A job's results depend only on its own description: it draws its random
+ * numbers from its own seed with the step counter it has reached, and its
+ * launch shape is a function of its grid, so it gives the same bits alone
+ * and in any mix.
+ */
+typedef struct mc_server mc_server;
+
+typedef struct {
+    int device;
+    int precision;          /* MC_F32 or MC_F64 */
+    size_t memory_budget;   /* bytes of device memory resident jobs may use; 0 = free memory - reserve */
+    size_t reserve;         /* bytes kept free when memory_budget = 0 */
+    int max_jobs;           /* jobs resident at once (>= 1) */
+    int steps_per_round;    /* steps per round (>= 1), captured as one HIP graph */
+} mc_server_config;
+
+/* Host arrays are copied by mc_server_submit and may be freed on return.
+ * Shapes and units as in load_geometry_grid / set_sensors / set_counts;
+ * init[S-1][R][C] is the common starting state of every chain (the paper's
+ * shared initialisation); block / rays_per_thread = 0 take the default
+ * launch shape for the grid. */
+typedef struct {
+    int n_surfaces, n_rows, n_cols;
+    double extent_x, extent_y;
+    const double *density, *top, *car_r;
+    int n_sensors, n_pix;
+    const double *sensor_pos, *dirs, *exposure;
+    double atten_len;
+    const int32_t *counts;
+    int n_chains;
+    const double *init;
+    int64_t n_steps;
+    double step_size;
+    uint64_t seed;
+    int block, rays_per_thread;
+} mc_job_desc;
+
+enum { MC_JOB_QUEUED = 0, MC_JOB_RUNNING = 1, MC_JOB_DONE = 2, MC_JOB_FAILED = 3 };
+
+typedef struct {
+    int status;                         /* MC_JOB_* */
+    int map_chain;                      /* chain with the highest final log posterior */
+    int64_t steps_done;
+    double t_submit, t_admit, t_done;   /* seconds on the server's steady clock (0 = not yet) */
+    double accept_rate;                 /* accepted / (n_chains * n_steps) */
+    double map_logpost;
+    size_t footprint;                   /* device bytes charged against the budget */
+} mc_job_info;
+
+typedef struct {
+    int64_t submitted, admitted, done, failed, rounds;
+    int resident, queued, max_resident;
+    size_t bytes_in_use, peak_bytes, budget;
+    double busy_seconds;                /* wall time with at least one resident job */
+    double now;                         /* the server clock */
+} mc_server_stats;
+
+mc_status mc_server_create(const mc_server_config *cfg, mc_server **out);
+/* Stops accepting jobs, lets resident and queued jobs finish when drain != 0
+ * (else abandons them), joins the scheduler and frees everything. */
+void mc_server_destroy(mc_server *s, int drain);
+const char *mc_server_last_error(const mc_server *s);
+/* Validates and copies the job; fails with MC_ERR_NOMEM when its footprint
+ * exceeds the whole budget. */
+mc_status mc_server_submit(mc_server *s, const mc_job_desc *job, int64_t *job_id);
+/* State of a job; once MC_JOB_DONE the summary is copied into the non-NULL
+ * host arrays mean, std, map_state (each [S-1][R][C] float64). */
+mc_status mc_server_poll(mc_server *s, int64_t job_id, mc_job_info *info, double *mean, double *std,
+                         double *map_state);
+/* Forget a finished job's summary (host memory). */
+mc_status mc_server_release(mc_server *s, int64_t job_id);
+/* Blocks until every submitted job is done or failed, or timeout_s passes
+ * (MC_ERR_STATE on time-out). */
+mc_status mc_server_wait_idle(mc_server *s, double timeout_s);
+mc_status mc_server_get_stats(mc_server *s, mc_server_stats *st);
 
 /* ------------------------------------------------------------------------ */
 /* Test support                                                              */

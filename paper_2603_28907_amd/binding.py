@@ -41,6 +41,40 @@ class RunConfig(ct.Structure):
                 ("step_offset", ct.c_uint64)]
 
 
+class ServerConfig(ct.Structure):
+    _fields_ = [("device", ct.c_int), ("precision", ct.c_int), ("memory_budget", ct.c_size_t),
+                ("reserve", ct.c_size_t), ("max_jobs", ct.c_int), ("steps_per_round", ct.c_int)]
+
+
+class JobDesc(ct.Structure):
+    _fields_ = [("n_surfaces", ct.c_int), ("n_rows", ct.c_int), ("n_cols", ct.c_int),
+                ("extent_x", ct.c_double), ("extent_y", ct.c_double),
+                ("density", ct.c_void_p), ("top", ct.c_void_p), ("car_r", ct.c_void_p),
+                ("n_sensors", ct.c_int), ("n_pix", ct.c_int),
+                ("sensor_pos", ct.c_void_p), ("dirs", ct.c_void_p), ("exposure", ct.c_void_p),
+                ("atten_len", ct.c_double), ("counts", ct.c_void_p),
+                ("n_chains", ct.c_int), ("init", ct.c_void_p), ("n_steps", ct.c_int64),
+                ("step_size", ct.c_double), ("seed", ct.c_uint64),
+                ("block", ct.c_int), ("rays_per_thread", ct.c_int)]
+
+
+class JobInfo(ct.Structure):
+    _fields_ = [("status", ct.c_int), ("map_chain", ct.c_int), ("steps_done", ct.c_int64),
+                ("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double),
+                ("accept_rate", ct.c_double), ("map_logpost", ct.c_double), ("footprint", ct.c_size_t)]
+
+
+class ServerStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_int64), ("admitted", ct.c_int64), ("done", ct.c_int64),
+                ("failed", ct.c_int64), ("rounds", ct.c_int64), ("resident", ct.c_int),
+                ("queued", ct.c_int), ("max_resident", ct.c_int), ("bytes_in_use", ct.c_size_t),
+                ("peak_bytes", ct.c_size_t), ("budget", ct.c_size_t), ("busy_seconds", ct.c_double),
+                ("now", ct.c_double)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
+
 def load_library(path: Optional[str] = None):
     """Load libmuoncave.so (raises if it has not been built)."""
     global _lib
@@ -67,6 +101,14 @@ def load_library(path: Optional[str] = None):
         "mc_set_tuning": (I, [V, P(Tuning)]),
         "mc_get_tuning": (I, [V, P(Tuning)]),
         "mcmc_run_multi": (I, [I, P(V), P(RunConfig), P(I), P(V), P(V), P(V), V]),
+        "mc_server_create": (I, [P(ServerConfig), P(V)]),
+        "mc_server_destroy": (None, [V, I]),
+        "mc_server_last_error": (ct.c_char_p, [V]),
+        "mc_server_submit": (I, [V, P(JobDesc), P(ct.c_int64)]),
+        "mc_server_poll": (I, [V, ct.c_int64, P(JobInfo), V, V, V]),
+        "mc_server_release": (I, [V, ct.c_int64]),
+        "mc_server_wait_idle": (I, [V, D]),
+        "mc_server_get_stats": (I, [V, P(ServerStats)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -78,7 +120,9 @@ def load_library(path: Optional[str] = None):
 
 EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_grid", "set_sensors",
                     "set_counts", "logpost_batch", "logpost_grad_batch", "mcmc_run", "mc_debug_philox",
-                    "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi")
+                    "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi",
+                    "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
+                    "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats")
 
 
 def _host(a, dtype=np.float64):
@@ -297,3 +341,85 @@ def debug_philox(device, seed, chain, step, tag, j0, n):
         raise MuonCaveError(st, "mc_debug_philox failed")
     w = words.cpu().numpy().view(np.uint32)
     return w, normals.cpu().numpy()
+
+
+class Server:
+    """Serving loop on one GPU (mc_server_*): submit jobs at any time, poll
+    for their posterior summaries.  The scheduler runs in a native thread."""
+
+    def __init__(self, device: int = 0, precision: str = "f32", memory_budget: int = 0,
+                 reserve: int = 8 << 30, max_jobs: int = 64, steps_per_round: int = 50):
+        self.lib = load_library()
+        self.precision = precision
+        cfg = ServerConfig(int(device), MC_F64 if precision == "f64" else MC_F32, int(memory_budget),
+                           int(reserve), int(max_jobs), int(steps_per_round))
+        h = ct.c_void_p()
+        st = self.lib.mc_server_create(ct.byref(cfg), ct.byref(h))
+        if st != 0:
+            raise MuonCaveError(st, self.lib.mc_server_last_error(None).decode())
+        self.h = h
+        self.shapes = {}
+
+    def _check(self, st):
+        if st != 0:
+            raise MuonCaveError(st, self.lib.mc_server_last_error(self.h).decode())
+
+    def submit(self, sc, n_chains, n_steps, step_size, seed, init=None, counts=None, block=0,
+               rays_per_thread=0) -> int:
+        """Queue one job for scenario `sc`; every chain starts at `init`
+        ([S-1, R, C], default the scenario's truth).  Returns the job id."""
+        init = sc.truth if init is None else init
+        c = sc.counts if counts is None else counts
+        keep = dict(density=_host(sc.density), top=_host(sc.top), car_r=_host(sc.car_r),
+                    pos=_host(sc.sensor_pos).reshape(-1), dirs=_host(sc.dirs).reshape(-1),
+                    expo=_host(sc.exposure).reshape(-1), init=_host(init).reshape(-1))
+        n_s = int(np.asarray(sc.sensor_pos).reshape(-1, 3).shape[0])
+        n_pix = int(sc.n_pix) if n_s else 0
+        cnt = _host(c, np.int32).reshape(-1) if n_s else np.zeros(0, np.int32)
+        d = JobDesc(int(sc.n_surfaces), int(sc.n_rows), int(sc.n_cols), float(sc.extent_x), float(sc.extent_y),
+                    _hp(keep["density"]), _hp(keep["top"]), _hp(keep["car_r"]), n_s, n_pix,
+                    _hp(keep["pos"]), _hp(keep["dirs"]), _hp(keep["expo"]), float(sc.atten_len), _hp(cnt),
+                    int(n_chains), _hp(keep["init"]), int(n_steps), float(step_size), int(seed), int(block),
+                    int(rays_per_thread))
+        jid = ct.c_int64()
+        self._check(self.lib.mc_server_submit(self.h, ct.byref(d), ct.byref(jid)))
+        self.shapes[jid.value] = (int(sc.n_surfaces) - 1, int(sc.n_rows), int(sc.n_cols))
+        return jid.value
+
+    def poll(self, job_id: int, arrays: bool = True) -> dict:
+        info = JobInfo()
+        shape = self.shapes[job_id]
+        n = int(np.prod(shape))
+        mean, sd, mp = (np.empty(n), np.empty(n), np.empty(n)) if arrays else (None, None, None)
+        self._check(self.lib.mc_server_poll(self.h, int(job_id), ct.byref(info),
+                                            _hp(mean) if arrays else None, _hp(sd) if arrays else None,
+                                            _hp(mp) if arrays else None))
+        out = {f: getattr(info, f) for f, _ in JobInfo._fields_}
+        if info.status == JOB_FAILED:
+            out["error"] = self.lib.mc_server_last_error(self.h).decode()
+        if arrays and info.status == JOB_DONE:
+            out.update(mean=mean.reshape(shape), std=sd.reshape(shape), map_state=mp.reshape(shape))
+        return out
+
+    def release(self, job_id: int):
+        self._check(self.lib.mc_server_release(self.h, int(job_id)))
+        self.shapes.pop(job_id, None)
+
+    def wait_idle(self, timeout_s: float = 600.0):
+        self._check(self.lib.mc_server_wait_idle(self.h, float(timeout_s)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(self.lib.mc_server_get_stats(self.h, ct.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self, drain: bool = True):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.mc_server_destroy(self.h, 1 if drain else 0)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close(drain=False)
+        except Exception:
+            pass

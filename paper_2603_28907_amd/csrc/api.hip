@@ -4,11 +4,16 @@
 // headers it includes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "muoncave.h"
@@ -18,13 +23,7 @@
 #include "march5.h"
 #include "adjoint.h"
 #include "multi.h"
-
-#include <algorithm>
-#include <map>
-#include <mutex>
 #include "prior.h"
-
-#include <type_traits>
 
 using namespace mc;
 
@@ -54,6 +53,17 @@ struct GraphKey {
 
 }  // namespace
 
+// Default launch shape by precision and grid size (measured on MI355X):
+// float32 uses the lean band walks; grids of 128x128 nodes and more hold the
+// free surfaces in 128 KB of LDS, one block per compute unit, so they take
+// 1024-thread blocks to keep 16 wavefronts resident.
+static mc_tuning default_tuning(int prec, size_t n_nodes) {
+    if (prec == MC_F64) return mc_tuning{3, 256, 4, 4, 1, 0};
+    if (n_nodes >= 128 * 128) return mc_tuning{4, 1024, 4, 16, 0, 0};
+    if (n_nodes >= 48 * 48) return mc_tuning{4, 256, 4, 16, 0, 0};
+    return mc_tuning{4, 256, 4, 8, 0, 0};
+}
+
 struct mc_problem {
     int device = 0;
     int prec = MC_F32;
@@ -79,6 +89,7 @@ struct mc_problem {
     DevBuf obuf, gfix, gprior, gcur, gprop, lpprop;   // gradient and MALA workspaces
     uint64_t *d_step = nullptr;
     mc_tuning tune = {2, 256, 4, 4, 1};
+    bool tune_user = false;   // launch shape set through mc_set_tuning (else chosen per grid)
     uint64_t gen = 1;   // bumped whenever device pointers or baked constants change
     // graph cache
     hipStream_t cap_stream = nullptr;
@@ -733,6 +744,9 @@ struct MultiClass {
     int n_items = 0;
     size_t lds = 0;
     bool top_lds = false;
+    int block = kMultiBlock;
+    hipStream_t side = nullptr;   // classes after the first run on their own stream
+    hipEvent_t done = nullptr;
 };
 
 struct MultiPlan {
@@ -751,14 +765,19 @@ struct MultiPlan {
     std::vector<MultiClass> classes;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr;
     int persistent_blocks = 0;
     ~MultiPlan() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cap) (void)hipStreamDestroy(cap);
+        if (fork) (void)hipEventDestroy(fork);
         for (void *q : {d_mp, d_rc, d_pp, d_pd, d_chain_items, d_step_ptrs, d_step_vals})
             if (q) (void)hipFree(q);
-        for (auto &c : classes)
+        for (auto &c : classes) {
             if (c.items) (void)hipFree(c.items);
+            if (c.side) (void)hipStreamDestroy(c.side);
+            if (c.done) (void)hipEventDestroy(c.done);
+        }
     }
 };
 
@@ -827,21 +846,30 @@ mc_status build_multi_plan(MultiPlan *pl, const mc_run_config *cfgs) {
     pl->n_chain_items = (int)chains.size();
     pl->prior_lds = prior_lds;
     if ((s = upload_vec(e, pl->d_chain_items, chains)) != MC_OK) return s;
-    // march classes: one per (grid size, top placement); items sorted by decreasing ray count
-    std::map<std::pair<size_t, int>, std::vector<int>> cls;
+    // march classes: one per (grid size, top placement, block size), heaviest
+    // first; items within a class sorted by decreasing ray count
+    std::map<std::tuple<size_t, int, int>, std::vector<int>> cls;
+    std::map<std::tuple<size_t, int, int>, double> work;
     for (int i = 0; i < np; ++i) {
         mc_problem *p = pl->ps[i];
         if (p->n_ray == 0) continue;
         size_t N = (size_t)p->R * p->C;
-        bool tl = N * S * sizeof(T) + 4096 <= p->max_lds;
-        cls[{N, tl ? 1 : 0}].push_back(i);
+        bool tl = N * S * sizeof(T) + 16384 <= p->max_lds;
+        int block = std::is_same<T, float>::value ? p->tune.block : kMultiBlock;
+        auto key = std::make_tuple(N, tl ? 1 : 0, block);
+        cls[key].push_back(i);
+        work[key] += (double)pl->n[i] * p->n_ray * std::sqrt((double)N);
     }
-    for (auto &kv : cls) {
+    std::vector<std::tuple<size_t, int, int>> keys;
+    for (auto &kv : cls) keys.push_back(kv.first);
+    std::stable_sort(keys.begin(), keys.end(), [&](const auto &a, const auto &b) { return work[a] > work[b]; });
+    for (auto &key : keys) {
         MultiClass mc_;
-        mc_.top_lds = kv.first.second != 0;
-        mc_.lds = kv.first.first * (mc_.top_lds ? S : S - 1) * sizeof(T);
+        mc_.top_lds = std::get<1>(key) != 0;
+        mc_.block = std::get<2>(key);
+        mc_.lds = std::get<0>(key) * (mc_.top_lds ? S : S - 1) * sizeof(T);
         if (mc_.lds + 2048 > e->max_lds) return fail(e, MC_ERR_UNSUPPORTED, "grid too large for LDS");
-        std::vector<int> members = kv.second;
+        std::vector<int> members = cls[key];
         std::stable_sort(members.begin(), members.end(), [&](int a, int b) {
             return tiling(pl->ps[a]).rays_per_block > tiling(pl->ps[b]).rays_per_block;
         });
@@ -853,50 +881,88 @@ mc_status build_multi_plan(MultiPlan *pl, const mc_run_config *cfgs) {
         }
         mc_.n_items = (int)items.size();
         if ((s = upload_vec(e, mc_.items, items)) != MC_OK) return s;
+        if (!pl->classes.empty()) {
+            HIP_TRY(e, hipStreamCreateWithFlags(&mc_.side, hipStreamNonBlocking));
+            HIP_TRY(e, hipEventCreateWithFlags(&mc_.done, hipEventDisableTiming));
+        }
         pl->classes.push_back(mc_);
     }
+    if (pl->classes.size() > 1) HIP_TRY(e, hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming));
     int ncu = 256;
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device);
     pl->persistent_blocks = e->tune.multi_blocks_per_cu > 0 ? e->tune.multi_blocks_per_cu * ncu : INT32_MAX;
     return MC_OK;
 }
 
+template <int S, bool TL, int B, bool PERSIST>
+void launch_multi4_shape(const MultiPlan *pl, const MultiClass &c, int grid, hipStream_t st) {
+    auto kk = k_march_multi4<S, TL, B, PERSIST>;
+    if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+    hipLaunchKernelGGL(kk, dim3(grid), dim3(B), c.lds, st, (const MarchParams<float> *)pl->d_mp,
+                       (const RayConsts<float> *)pl->d_rc, (const int4 *)c.items, c.n_items);
+}
+
+template <int S, bool TL, int B>
+void launch_multi4(const MultiPlan *pl, const MultiClass &c, int grid, hipStream_t st) {
+    if (grid < c.n_items) launch_multi4_shape<S, TL, B, true>(pl, c, grid, st);
+    else launch_multi4_shape<S, TL, B, false>(pl, c, grid, st);
+}
+
+template <typename T, int S, bool TL, bool PERSIST>
+void launch_multi3_shape(const MultiPlan *pl, const MultiClass &c, int grid, hipStream_t st) {
+    auto kk = k_march_multi3<T, S, TL, kMultiBlock, PERSIST>;
+    if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
+    hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<T> *)pl->d_mp,
+                       (const RayConsts<T> *)pl->d_rc, (const int4 *)c.items, c.n_items);
+}
+
+template <typename T, int S, bool TL>
+void launch_multi3(const MultiPlan *pl, const MultiClass &c, int grid, hipStream_t st) {
+    if (grid < c.n_items) launch_multi3_shape<T, S, TL, true>(pl, c, grid, st);
+    else launch_multi3_shape<T, S, TL, false>(pl, c, grid, st);
+}
+
+template <typename T, int S>
+void launch_multi_class(const MultiPlan *pl, const MultiClass &c, hipStream_t st) {
+    const int grid = std::min(c.n_items, pl->persistent_blocks);
+    if (grid <= 0) return;
+    if constexpr (std::is_same<T, float>::value) {
+        if (c.top_lds) {
+            if (c.block == 256) launch_multi4<S, true, 256>(pl, c, grid, st);
+            else if (c.block == 512) launch_multi4<S, true, 512>(pl, c, grid, st);
+            else launch_multi4<S, true, 1024>(pl, c, grid, st);
+        } else {
+            if (c.block == 256) launch_multi4<S, false, 256>(pl, c, grid, st);
+            else if (c.block == 512) launch_multi4<S, false, 512>(pl, c, grid, st);
+            else launch_multi4<S, false, 1024>(pl, c, grid, st);
+        }
+    } else {
+        if (c.top_lds) launch_multi3<T, S, true>(pl, c, grid, st);
+        else launch_multi3<T, S, false>(pl, c, grid, st);
+    }
+}
+
+// One MCMC step of every chain of every problem: proposal, the march classes
+// (concurrently, on forked streams), then the prior and Metropolis step.
 template <typename T, int S>
 mc_status multi_step(MultiPlan *pl, int k, hipStream_t st) {
     mc_problem *e = pl->ps[0];
     hipLaunchKernelGGL(k_propose_multi<T>, dim3(pl->n_chain_items), dim3(256), 0, st,
                        (const ProposeDesc<T> *)pl->d_pd, (const int2 *)pl->d_chain_items, k);
     HIP_TRY(e, hipGetLastError());
-    for (auto &c : pl->classes) {
-        const int grid = std::min(c.n_items, pl->persistent_blocks);
-        if (grid <= 0) continue;
-        if constexpr (std::is_same<T, float>::value) {
-            if (c.top_lds) {
-                auto kk = k_march_multi4<S, true, kMultiBlock>;
-                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
-                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<float> *)pl->d_mp,
-                                   (const RayConsts<float> *)pl->d_rc, (const int4 *)c.items, c.n_items);
-            } else {
-                auto kk = k_march_multi4<S, false, kMultiBlock>;
-                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
-                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<float> *)pl->d_mp,
-                                   (const RayConsts<float> *)pl->d_rc, (const int4 *)c.items, c.n_items);
-            }
-        } else {
-            if (c.top_lds) {
-                auto kk = k_march_multi3<T, S, true, kMultiBlock>;
-                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
-                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<T> *)pl->d_mp,
-                                   (const RayConsts<T> *)pl->d_rc, (const int4 *)c.items, c.n_items);
-            } else {
-                auto kk = k_march_multi3<T, S, false, kMultiBlock>;
-                if (c.lds > 65536) (void)hipFuncSetAttribute((const void *)kk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.lds);
-                hipLaunchKernelGGL(kk, dim3(grid), dim3(kMultiBlock), c.lds, st, (const MarchParams<T> *)pl->d_mp,
-                                   (const RayConsts<T> *)pl->d_rc, (const int4 *)c.items, c.n_items);
-            }
-        }
-        HIP_TRY(e, hipGetLastError());
+    const size_t nc = pl->classes.size();
+    if (nc > 1) {
+        HIP_TRY(e, hipEventRecord(pl->fork, st));
+        for (size_t c = 1; c < nc; ++c) HIP_TRY(e, hipStreamWaitEvent(pl->classes[c].side, pl->fork, 0));
     }
+    for (size_t c = 0; c < nc; ++c) {
+        const MultiClass &mc_ = pl->classes[c];
+        hipStream_t cs = c == 0 ? st : mc_.side;
+        launch_multi_class<T, S>(pl, mc_, cs);
+        HIP_TRY(e, hipGetLastError());
+        if (c > 0) HIP_TRY(e, hipEventRecord(mc_.done, cs));
+    }
+    for (size_t c = 1; c < nc; ++c) HIP_TRY(e, hipStreamWaitEvent(st, pl->classes[c].done, 0));
     auto kp = k_prior_multi<T, S, kPriorBlock>;
     if (pl->prior_lds > 65536) (void)hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->prior_lds);
     hipLaunchKernelGGL(kp, dim3(pl->n_chain_items), dim3(kPriorBlock), pl->prior_lds, st,
@@ -905,9 +971,12 @@ mc_status multi_step(MultiPlan *pl, int k, hipStream_t st) {
     return MC_OK;
 }
 
+// init_lp: compute the log posterior of chains whose entry is NaN first (the
+// public entry point); the serving loop computes it once at admission.
 template <typename T, int S>
 mc_status mcmc_multi_impl(int np, mc_problem *const *ps, const mc_run_config *cfgs, const int *n_chains,
-                          void *const *heights, double *const *lps, int64_t *const *accs, hipStream_t st) {
+                          void *const *heights, double *const *lps, int64_t *const *accs, hipStream_t st,
+                          bool init_lp = true) {
     mc_problem *e = ps[0];
     mc_status s;
     // workspaces and initial log posteriors, per problem
@@ -919,6 +988,7 @@ mc_status mcmc_multi_impl(int np, mc_problem *const *ps, const mc_run_config *cf
         if ((s = ensure(p, p->prop, sizeof(T) * (size_t)n * M)) != MC_OK) return s;
         if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
         if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+        if (!init_lp) continue;
         if ((s = logpost_impl<T, S>(p, n, (const T *)heights[i], (double *)p->lptmp.p, nullptr, st, lps[i])) != MC_OK)
             return s;
         hipLaunchKernelGGL(k_fill_nan, dim3((n + 255) / 256), dim3(256), 0, st, lps[i], (const double *)p->lptmp.p, n);
@@ -1028,9 +1098,7 @@ mc_status mc_create(int hip_device, int precision, mc_problem **out) {
     mc_problem *p = new mc_problem();
     p->device = hip_device;
     p->prec = precision;
-    // default launch shape (best measured on the paper-scale problem for float32)
-    if (precision == MC_F32) p->tune = mc_tuning{4, 256, 4, 16, 0};
-    else p->tune = mc_tuning{3, 256, 4, 4, 1};
+    p->tune = default_tuning(precision, 64 * 64);
     DeviceGuard g(hip_device);
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess && lds > 0)
@@ -1118,6 +1186,7 @@ mc_status load_geometry_grid(mc_problem *p, int n_surfaces, int n_rows, int n_co
     void *t64 = p->d_top64;
     if ((s = upload<double>(p, t64, p->top)) != MC_OK) return s;
     p->d_top64 = (double *)t64;
+    if (!p->tune_user) p->tune = default_tuning(p->prec, (size_t)N);
     drop_graph(p);
     p->have_geom = true;
     return MC_OK;
@@ -1320,6 +1389,7 @@ mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t) {
     DeviceGuard g(p->device);
     drop_graph(p);
     p->tune = *t;
+    p->tune_user = true;
     if (p->tune.march_variant == 1) p->tune.block = kMarchBlock;
     return MC_OK;
 }
@@ -1356,3 +1426,6 @@ mc_status mc_debug_philox(int hip_device, uint64_t seed, uint32_t chain, uint64_
 }
 
 }  // extern "C"
+
+// serving loop (mc_server_*)
+#include "server.h"

@@ -32,10 +32,18 @@ struct ProposeDesc {
 // static schedule keeps every item on a fixed block, so results do not depend
 // on timing.  Each item's block body ends in a block-wide reduction, after
 // which the staged surfaces may be overwritten by the next item.
-template <int S, bool TOP_LDS, int BLOCK>
+//
+// PERSIST = false is the one-item-per-block form (grid = number of items):
+// without the loop the descriptor stays in scalar registers.
+template <int S, bool TOP_LDS, int BLOCK, bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_march_multi4(const MarchParams<float> *Ps, const RayConsts<float> *Ks,
                                                         const int4 *items, int n_items) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (!PERSIST) {
+        const int4 it = items[blockIdx.x];
+        march_block4<S, TOP_LDS, BLOCK>(Ps[it.x], Ks[it.x], it.y, it.z, reinterpret_cast<float *>(smem_raw));
+        return;
+    }
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const int4 it = items[i];
         const MarchParams<float> P = Ps[it.x];
@@ -45,10 +53,15 @@ __global__ __launch_bounds__(BLOCK) void k_march_multi4(const MarchParams<float>
     }
 }
 
-template <typename T, int S, bool TOP_LDS, int BLOCK>
+template <typename T, int S, bool TOP_LDS, int BLOCK, bool PERSIST>
 __global__ __launch_bounds__(BLOCK) void k_march_multi3(const MarchParams<T> *Ps, const RayConsts<T> *Ks,
                                                         const int4 *items, int n_items) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    if (!PERSIST) {
+        const int4 it = items[blockIdx.x];
+        march_block3<T, S, TOP_LDS, BLOCK>(Ps[it.x], Ks[it.x], it.y, it.z, reinterpret_cast<T *>(smem_raw));
+        return;
+    }
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const int4 it = items[i];
         const MarchParams<T> P = Ps[it.x];

@@ -44,3 +44,23 @@ def test_create_without_gpu_reports_an_error():
     st = lib.mc_create(0, 0, ctypes.byref(h))
     assert st != 0
     assert lib.mc_last_error(None)
+
+
+def test_server_create_without_gpu_reports_an_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2603_28907_amd import binding
+    lib = binding.load_library()
+    h = ctypes.c_void_p()
+    cfg = binding.ServerConfig(0, 0, 0, 0, 4, 10)
+    assert lib.mc_server_create(ctypes.byref(cfg), ctypes.byref(h)) != 0
+    assert lib.mc_server_last_error(None)
+    bad = binding.ServerConfig(0, 0, 0, 0, 0, 10)
+    assert lib.mc_server_create(ctypes.byref(bad), ctypes.byref(h)) == -1   # MC_ERR_ARG before any device call
+
+
+def test_every_declared_symbol_has_a_binding():
+    from paper_2603_28907_amd import binding
+    missing = [n for n in declared_functions() if n not in binding.EXPORTED_SYMBOLS]
+    assert missing == []
