@@ -278,6 +278,9 @@ def main():
     ap.add_argument("--job-steps", type=int, default=2000, help="serve: steps per chain per job")
     ap.add_argument("--max-jobs", type=int, default=64, help="serve: resident jobs at once")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the timed region (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); chains and problems are independent "
@@ -293,6 +296,12 @@ def main():
     if args.workload == "serve":
         print(json.dumps(bench_serve(args, torch)), flush=True)
         return
+    if args.copy_calibration_mb > 0:
+        src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sc, n_chains, w = make_workload(args.workload)
     print(f"[bench] workload {args.workload}: {n_chains} chains x {sc.n_rays} rays", file=sys.stderr, flush=True)
     sc.counts = gpu_counts(sc, torch)
@@ -320,6 +329,8 @@ def main():
     ms_march = binding.time_march(prob, H, iters=args.march_iters)
     opr = ops_per_ray(args.workload)
     achieved = opr * n_chains * sc.n_rays / (ms_march * 1e-3) / 1e12
+    measured_f32 = binding.measure_valu_rate(0, "f32") / 1e12
+    measured_f64 = binding.measure_valu_rate(0, "f64") / 1e12
     out = {
         "metric": METRIC,
         "value": ray_evals / dt,
@@ -342,7 +353,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                      "kernel": "k_march_lik4", "ms_per_launch": ms_march,
-                     "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays},
+                     "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays,
+                     "measured_fma_rate": {"f32": measured_f32, "f64": measured_f64, "unit": "Tlane-op/s"}},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)

@@ -313,6 +313,15 @@ mc_status mc_server_get_stats(mc_server *s, mc_server_stats *st);
 mc_status mc_debug_philox(int hip_device, uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag,
                           uint32_t j0, int n, uint32_t *out_u32, double *out_normal);
 
+/*
+ * Measurement support: the sustained issue rate of non-packed vector FMAs
+ * (kind 0 = float32 v_fma_f32, 1 = float64 v_fma_f64) on `hip_device`, in
+ * lane-operations per second, from a kernel of independent FMA chains that
+ * fills every SIMD (best of 3 timed launches).  Synchronous.  MC_ERR_ARG for
+ * a NULL output or unknown kind.
+ */
+mc_status mc_measure_valu_rate(int hip_device, int kind, double *lane_ops_per_s);
+
 /* Times the ray-march kernel alone: `iters` back-to-back launches of the
    march over n_chains states (device `heights`, as in logpost_batch) between
    two HIP events recorded on `stream`; waits for them and writes the mean

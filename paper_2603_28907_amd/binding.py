@@ -101,6 +101,7 @@ def load_library(path: Optional[str] = None):
         "mc_set_tuning": (I, [V, P(Tuning)]),
         "mc_get_tuning": (I, [V, P(Tuning)]),
         "mcmc_run_multi": (I, [I, P(V), P(RunConfig), P(I), P(V), P(V), P(V), V]),
+        "mc_measure_valu_rate": (I, [I, I, P(D)]),
         "mc_server_create": (I, [P(ServerConfig), P(V)]),
         "mc_server_destroy": (None, [V, I]),
         "mc_server_last_error": (ct.c_char_p, [V]),
@@ -122,7 +123,8 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "set_counts", "logpost_batch", "logpost_grad_batch", "mcmc_run", "mc_debug_philox",
                     "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi",
                     "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
-                    "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats")
+                    "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
+                    "mc_measure_valu_rate")
 
 
 def _host(a, dtype=np.float64):
@@ -327,6 +329,16 @@ def time_march(problem: "Problem", heights, iters: int = 20, stream=None) -> flo
     problem._check(problem.lib.mc_time_march(problem.h, n, ct.c_void_p(heights.data_ptr()), int(iters),
                                              _stream_handle(stream, problem.device), ct.byref(ms)))
     return float(ms.value)
+
+
+def measure_valu_rate(device: int = 0, kind: str = "f32") -> float:
+    """Sustained non-packed FMA issue rate (lane-ops/s) measured on the device."""
+    lib = load_library()
+    v = ct.c_double()
+    st = lib.mc_measure_valu_rate(int(device), 0 if kind == "f32" else 1, ct.byref(v))
+    if st != 0:
+        raise MuonCaveError(st, "mc_measure_valu_rate failed")
+    return float(v.value)
 
 
 def debug_philox(device, seed, chain, step, tag, j0, n):

@@ -24,6 +24,7 @@
 #include "adjoint.h"
 #include "multi.h"
 #include "prior.h"
+#include "probe.h"
 
 using namespace mc;
 
@@ -343,6 +344,7 @@ MarchParams<T> march_params(const mc_problem *p, const T *heights, T *opacity, d
     P.opacity = opacity;
     P.partials = partials;
     P.only_nan = nullptr;
+    P.n_chains = 0;
     return P;
 }
 
@@ -351,6 +353,9 @@ mc_status launch_march(mc_problem *p, int n, const T *heights, T *opacity, doubl
                        const double *only_nan = nullptr) {
     MarchParams<T> P = march_params<T>(p, heights, opacity, partials);
     P.only_nan = only_nan;
+    P.n_chains = n;
+    // variants 3-5: XCD-aware 1-D grid (see xcd_chain_tile)
+    const dim3 grid_xcd((unsigned)P.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
     size_t N = (size_t)p->R * p->C;
     bool tl = top_in_lds(p);
     int variant = p->tune.march_variant;
@@ -362,7 +367,7 @@ mc_status launch_march(mc_problem *p, int n, const T *heights, T *opacity, doubl
             lds = N * (S - 1) * sizeof(T);
         }
         if (lds + 16384 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-        dim3 grid(P.n_tiles, n);
+        const dim3 grid = grid_xcd;
         if constexpr (std::is_same<T, float>::value) {
             RayConsts<float> K = ray_consts<float>(p);
             hipError_t e = tl ? launch_v45<S, true>(variant, p->tune.block, grid, lds, st, P, K)
@@ -382,7 +387,7 @@ mc_status launch_march(mc_problem *p, int n, const T *heights, T *opacity, doubl
     if (variant == 3) {
         size_t lds = N * (tl ? S : S - 1) * sizeof(T);
         if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-        dim3 grid(P.n_tiles, n);
+        const dim3 grid = grid_xcd;
         RayConsts<T> K = ray_consts<T>(p);
         hipError_t e = tl ? launch_v3<T, S, true>(p->tune.block, grid, lds, st, P, K)
                           : launch_v3<T, S, false>(p->tune.block, grid, lds, st, P, K);
@@ -807,6 +812,7 @@ mc_status build_multi_plan(MultiPlan *pl, const mc_run_config *cfgs) {
         mc_problem *p = pl->ps[i];
         const T *prop = (const T *)p->prop.p;
         mp[i] = march_params<T>(p, prop, nullptr, (double *)p->partials.p);
+        mp[i].n_chains = pl->n[i];
         rc[i] = ray_consts<T>(p);
         pp[i] = prior_params<T>(p, prop, (const double *)p->partials.p);
         pp[i].mh = 1;
@@ -873,12 +879,25 @@ mc_status build_multi_plan(MultiPlan *pl, const mc_run_config *cfgs) {
         std::stable_sort(members.begin(), members.end(), [&](int a, int b) {
             return tiling(pl->ps[a]).rays_per_block > tiling(pl->ps[b]).rays_per_block;
         });
-        std::vector<int4> items;
+        // XCD-aware order: item j runs on XCD j % kXcds; each chain's tiles
+        // go to one XCD (the least loaded so far), in consecutive slots, so
+        // its surfaces are read from HBM once.  Short lanes are padded with
+        // items the kernel skips (problem -1).
+        std::vector<int4> lane[kXcds];
         for (int i : members) {
             Tiling t = tiling(pl->ps[i]);
-            for (int tt = 0; tt < t.n_tiles; ++tt)
-                for (int c = 0; c < pl->n[i]; ++c) items.push_back(make_int4(i, c, tt, 0));
+            for (int c = 0; c < pl->n[i]; ++c) {
+                int x = 0;
+                for (int q = 1; q < kXcds; ++q)
+                    if (lane[q].size() < lane[x].size()) x = q;
+                for (int tt = 0; tt < t.n_tiles; ++tt) lane[x].push_back(make_int4(i, c, tt, 0));
+            }
         }
+        size_t L = 0;
+        for (auto &v : lane) L = std::max(L, v.size());
+        std::vector<int4> items(L * kXcds, make_int4(-1, 0, 0, 0));
+        for (int x = 0; x < kXcds; ++x)
+            for (size_t k = 0; k < lane[x].size(); ++k) items[k * kXcds + x] = lane[x][k];
         mc_.n_items = (int)items.size();
         if ((s = upload_vec(e, mc_.items, items)) != MC_OK) return s;
         if (!pl->classes.empty()) {
@@ -1411,6 +1430,49 @@ mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int it
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? time_march_dispatch<double>(p, n_chains, heights, iters, st, ms_per_launch)
                              : time_march_dispatch<float>(p, n_chains, heights, iters, st, ms_per_launch);
+}
+
+mc_status mc_measure_valu_rate(int hip_device, int kind, double *lane_ops_per_s) {
+    if (!lane_ops_per_s || (kind != kProbeF32Fma && kind != kProbeF64Fma)) return MC_ERR_ARG;
+    DeviceGuard g(hip_device);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess || ncu <= 0)
+        return MC_ERR_DEVICE;
+    const int blocks = ncu * 32;   // 256-thread blocks: 32 waves per SIMD over the launch
+    const int iters = 1 << 16;
+    void *out = nullptr;
+    if (hipMalloc(&out, (size_t)blocks * 256 * 8) != hipSuccess) return MC_ERR_NOMEM;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(out);
+        return MC_ERR_DEVICE;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best = 0.f;
+    for (int rep = 0; rep < 4; ++rep) {
+        (void)hipEventRecord(e0, st);
+        if (kind == kProbeF32Fma)
+            hipLaunchKernelGGL(k_valu_probe<float>, dim3(blocks), dim3(256), 0, st, (float *)out, iters,
+                               0.999999f, 1e-7f);
+        else
+            hipLaunchKernelGGL(k_valu_probe<double>, dim3(blocks), dim3(256), 0, st, (double *)out, iters,
+                               0.999999, 1e-7);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && (best == 0.f || ms < best)) best = ms;
+    }
+    const hipError_t e = hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    (void)hipFree(out);
+    if (e != hipSuccess || best <= 0.f) return MC_ERR_DEVICE;
+    *lane_ops_per_s = (double)blocks * 256.0 * iters * 8.0 / (best * 1e-3);
+    return MC_OK;
 }
 
 mc_status mc_debug_philox(int hip_device, uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t j0,

@@ -8,7 +8,23 @@
 namespace mc {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kMaxSurfaces = 4;    // S (including the fixed top) supported by the kernels
+constexpr int kMaxSurfaces = 4;
+
+// MI355X has 8 XCDs, each with its own L2; consecutive workgroups of a
+// launch are dispatched to the XCDs round-robin.
+constexpr int kXcds = 8;
+
+// XCD-aware block -> (chain, tile) map of a 1-D grid of
+// n_tiles * round_up(n_chains, kXcds) blocks: block b runs on XCD b % kXcds
+// and every tile of a chain goes to the same XCD, in consecutive slots, so
+// the chain's surfaces are read from HBM once and then hit that XCD's L2.
+// Returns false for the padding blocks of a ragged last group.
+__device__ __forceinline__ bool xcd_chain_tile(int n_tiles, int n_chains, int &chain, int &tile) {
+    const int b = blockIdx.x, x = b % kXcds, k = b / kXcds;
+    chain = (k / n_tiles) * kXcds + x;
+    tile = k % n_tiles;
+    return chain < n_chains;
+}    // S (including the fixed top) supported by the kernels
 
 enum RngTag : uint32_t { kTagProposal = 0, kTagAccept = 1, kTagMala = 2 };
 

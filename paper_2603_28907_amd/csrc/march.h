@@ -27,6 +27,7 @@ enum BoundaryKind : int { kPoint = 0, kXEdge = 1, kYEdge = 2 };
 template <typename T>
 struct MarchParams {
     int R, C, n_ray, n_pix, n_tiles, rays_per_block;
+    int n_chains;                      // chains in the launch
     T hx, hy, ihx, ihy, xmax, ymax;   // cell sizes, their inverses, (R-1) hx, (C-1) hy
     T ztop;                            // max of the top surface
     T margin;                          // rounding margin for the certain tests

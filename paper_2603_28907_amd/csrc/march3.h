@@ -217,7 +217,9 @@ __device__ __forceinline__ void march_block3(const MarchParams<T> &P, const RayC
 template <typename T, int S, bool TOP_LDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_march_lik3(MarchParams<T> P, RayConsts<T> K) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    march_block3<T, S, TOP_LDS, BLOCK>(P, K, blockIdx.y, blockIdx.x, reinterpret_cast<T *>(smem_raw));
+    int chain, tile;
+    if (!xcd_chain_tile(P.n_tiles, P.n_chains, chain, tile)) return;
+    march_block3<T, S, TOP_LDS, BLOCK>(P, K, chain, tile, reinterpret_cast<T *>(smem_raw));
 }
 
 }  // namespace mc

@@ -290,7 +290,9 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
 template <int S, bool TOP_LDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_march_lik4(MarchParams<float> P, RayConsts<float> K) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    march_block4<S, TOP_LDS, BLOCK>(P, K, blockIdx.y, blockIdx.x, reinterpret_cast<float *>(smem_raw));
+    int chain, tile;
+    if (!xcd_chain_tile(P.n_tiles, P.n_chains, chain, tile)) return;
+    march_block4<S, TOP_LDS, BLOCK>(P, K, chain, tile, reinterpret_cast<float *>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -344,7 +346,9 @@ __global__ __launch_bounds__(BLOCK) void k_march_lik5(MarchParams<float> P, RayC
     __shared__ float ring_t0[NW][kRing], ring_t1[NW][kRing];
     __shared__ uint32_t ring_pk[NW][kRing];
     __shared__ uint32_t ring_acc[NW][S * kWave];
-    const int chain = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
+    int chain, tile;
+    if (!xcd_chain_tile(P.n_tiles, P.n_chains, chain, tile)) return;
     if (P.only_nan && !(P.only_nan[chain] != P.only_nan[chain])) return;
     stage_surfaces<S, TOP_LDS, BLOCK>(P, sh, band, chain);
     const int wid = tid / kWave, lane = tid % kWave;

@@ -27,6 +27,8 @@ struct ProposeDesc {
     const uint64_t *step_base;
 };
 
+// Items with problem index -1 are padding and are skipped.
+//
 // Persistent march over a static work table: block b takes items b, b + grid,
 // b + 2 grid, ... (the table is sorted by decreasing cost on the host).  A
 // static schedule keeps every item on a fixed block, so results do not depend
@@ -41,11 +43,13 @@ __global__ __launch_bounds__(BLOCK) void k_march_multi4(const MarchParams<float>
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (!PERSIST) {
         const int4 it = items[blockIdx.x];
+        if (it.x < 0) return;
         march_block4<S, TOP_LDS, BLOCK>(Ps[it.x], Ks[it.x], it.y, it.z, reinterpret_cast<float *>(smem_raw));
         return;
     }
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const int4 it = items[i];
+        if (it.x < 0) continue;
         const MarchParams<float> P = Ps[it.x];
         const RayConsts<float> K = Ks[it.x];
         march_block4<S, TOP_LDS, BLOCK>(P, K, it.y, it.z, reinterpret_cast<float *>(smem_raw));
@@ -59,11 +63,13 @@ __global__ __launch_bounds__(BLOCK) void k_march_multi3(const MarchParams<T> *Ps
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (!PERSIST) {
         const int4 it = items[blockIdx.x];
+        if (it.x < 0) return;
         march_block3<T, S, TOP_LDS, BLOCK>(Ps[it.x], Ks[it.x], it.y, it.z, reinterpret_cast<T *>(smem_raw));
         return;
     }
     for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
         const int4 it = items[i];
+        if (it.x < 0) continue;
         const MarchParams<T> P = Ps[it.x];
         const RayConsts<T> K = Ks[it.x];
         march_block3<T, S, TOP_LDS, BLOCK>(P, K, it.y, it.z, reinterpret_cast<T *>(smem_raw));
