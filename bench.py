@@ -45,6 +45,45 @@ WORKLOAD_COUNTS = {"grf_cave_64": dict(cells=18.93, crossings=2.94, S=3)}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
+# HBM bytes per launch of the march kernel, from two rocprofv3 --pmc runs of
+# this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what
+# the same counters read for a 256 MiB device-to-device copy in the same run
+# (FETCH_SIZE reads 131089 KiB for 262144 KiB moved: scale 2.0; WRITE_SIZE
+# reads exactly: scale 1.0).  Valid only for the kernel sources they were
+# taken on: the entry is dropped when the hash of those sources changes.
+KERNEL_SOURCES = ("device_common.h", "march.h", "march3.h", "march5.h")
+MEASURED_TRAFFIC = {
+    "grf_cave_64": dict(source_sha="c20b6dbcf6a76a3d", fetch_kib=23169.0, fetch_scale=262144 / 131088.9,
+                        write_kib=64.0, write_scale=1.0),
+}
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_28907_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    m = MEASURED_TRAFFIC.get(name)
+    if m is None or m["source_sha"] != kernel_source_sha():
+        return None
+    return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024
+
+
+def algorithmic_bytes(sc, n_chains):
+    """Bytes one march launch must move at least: every chain's free surfaces
+    (float32), the top surface, the per-ray tables once (9 float32 + 2
+    float64 per ray) and one float64 partial per (chain, tile)."""
+    N = sc.n_rows * sc.n_cols
+    tiles = -(-sc.n_rays // (256 * 16))
+    return (n_chains * (sc.n_surfaces - 1) * N * 4 + N * 4 + sc.n_rays * (9 * 4 + 2 * 8)
+            + n_chains * tiles * 8)
+
+
 def ops_per_ray(name):
     c = WORKLOAD_COUNTS[name]
     return OPS_RAY + c["cells"] * (OPS_CELL_BASE + c["S"] * OPS_TEST) + c["crossings"] * OPS_CROSS
@@ -351,7 +390,8 @@ def main():
         "logpost_evals_per_s": n_chains * args.steps / dt,
         "accept_rate": float(acc.double().mean().item()) / (args.warmup + args.steps),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(args.workload),
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes": algorithmic_bytes(sc, n_chains),
                      "kernel": "k_march_lik4", "ms_per_launch": ms_march,
                      "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays,
                      "measured_fma_rate": {"f32": measured_f32, "f64": measured_f64, "unit": "Tlane-op/s"}},

@@ -81,6 +81,13 @@ def load_library(path: Optional[str] = None):
     if _lib is not None:
         return _lib
     path = path or LIB_PATH
+    # PyTorch brings its own HIP runtime; load it first so that this library
+    # binds to the same one (a second runtime loaded first leaves torch
+    # without devices)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2603_28907_amd.build`")
     lib = ct.CDLL(path)

@@ -234,7 +234,7 @@ __global__ void k_fill_u64(unsigned long long *p, size_t n) {
 // Log prior and its gradient per chain (one block per chain), plus the
 // fixed-order sum of the likelihood partials.  gprior: [n][S][N] float64.
 template <typename T, int S, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_prior_grad(PriorParams<T> P, double *gprior) {
+__global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, double *gprior) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *w = reinterpret_cast<double *>(smem_raw);   // [N]
     __shared__ double red[16];

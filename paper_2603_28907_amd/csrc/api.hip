@@ -74,6 +74,7 @@ struct mc_problem {
     // geometry
     int S = 0, R = 0, C = 0;
     double X = 0, Y = 0, ztop = 0, top_min = 0, top_max = 0;
+    double sum_log_top = 0;   // sum of log(top) over the nodes, in node order
     std::vector<double> density, top, car_r, logdet, s11;
     void *d_top = nullptr;      // [N] in prec
     double *d_top64 = nullptr;  // [N] f64
@@ -434,6 +435,7 @@ PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double 
         P.s11[l] = p->s11[l];
         P.r[l] = p->car_r[l];
     }
+    P.sum_log_top = p->sum_log_top;
     P.partials = partials;
     P.kconst = p->kconst;
     return P;
@@ -1195,6 +1197,8 @@ mc_status load_geometry_grid(mc_problem *p, int n_surfaces, int n_rows, int n_co
     p->top.assign(top, top + N);
     p->car_r.assign(car_r, car_r + n_surfaces - 1);
     p->ztop = tmax;
+    p->sum_log_top = 0.0;
+    for (int i = 0; i < N; ++i) p->sum_log_top += std::log(top[i]);
     p->top_min = tmin;
     p->top_max = tmax;
     p->logdet.resize(n_surfaces - 1);

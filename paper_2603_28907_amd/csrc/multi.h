@@ -78,12 +78,10 @@ __global__ __launch_bounds__(BLOCK) void k_march_multi3(const MarchParams<T> *Ps
 }
 
 template <typename T, int S, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_prior_multi(const PriorParams<T> *Ps, const int2 *items, int step_k) {
+__global__ __launch_bounds__(BLOCK, 4) void k_prior_multi(const PriorParams<T> *Ps, const int2 *items, int step_k) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 it = items[blockIdx.x];
-    PriorParams<T> P = Ps[it.x];
-    P.step_k = step_k;
-    prior_block<T, S, BLOCK>(P, it.y, reinterpret_cast<double *>(smem_raw));
+    prior_block<T, S, BLOCK>(Ps[it.x], it.y, reinterpret_cast<double *>(smem_raw), step_k);
 }
 
 // One block per (problem, chain): the pairs of normals of that chain.

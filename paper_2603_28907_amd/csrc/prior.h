@@ -23,6 +23,7 @@ struct PriorParams {
     double logdet[kMaxSurfaces - 1];   // per free surface
     double s11[kMaxSurfaces - 1];
     double r[kMaxSurfaces - 1];
+    double sum_log_top;                // sum_n log(top_n)
     const double *partials;            // [n][n_tiles]
     double kconst;                     // sum_p C_p log E_p - log C_p!
     double *lp_out;                    // [n] (plain mode)
@@ -39,14 +40,18 @@ struct PriorParams {
 };
 
 // w = Phi^-1(u) with u = (h-a)/d and v = 1-u = (b-h)/d; the tail nearer to u
-// is evaluated directly.
-__device__ __forceinline__ double probit_uv(double u, double v) {
-    return u <= 0.5 ? normcdfinv(u) : -normcdfinv(v);
+// is evaluated directly.  Kept out of line: inlined into a node loop, the
+// compiler hoists the polynomial coefficients of Phi^-1 out of the loop into
+// some 200 vector registers (one wavefront per SIMD).
+__device__ __attribute__((noinline)) double probit_uv(double u, double v) {
+    const bool lower = u <= 0.5;
+    const double w = normcdfinv(lower ? u : v);   // one call: the tails share the code
+    return lower ? w : -w;
 }
 
 // Body of one block for chain c; w = LDS workspace of R*C doubles.
 template <typename T, int S, int BLOCK>
-__device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, double *w) {
+__device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, double *w, int step_k) {
     __shared__ double red[16];
     __shared__ int ired[16];
     __shared__ int s_acc;
@@ -56,24 +61,29 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, doub
     const T *H = P.heights + (size_t)c * (S - 1) * N;
     double lp = 0.0;
     int ok = 1;
-#pragma unroll
+#pragma unroll 1
     for (int l = 0; l < S - 1; ++l) {
         double sw2 = 0.0, sld = 0.0;
+#pragma unroll 1
         for (int n = tid; n < N; n += BLOCK) {
             const double h = (double)H[l * N + n];
             const double a = l ? (double)H[(l - 1) * N + n] : 0.0;
             const double b = P.top64[n];
             const double d = b - a;
-            const double u = (h - a) / d, v = (b - h) / d;
+            const double id = 1.0 / d;
+            const double u = (h - a) * id, v = (b - h) * id;
             const bool good = (d > 0.0) && (u > 0.0) && (v > 0.0);
             ok &= good ? 1 : 0;
             const double wi = good ? probit_uv(u, v) : 0.0;
             w[n] = wi;
             sw2 += wi * wi;
-            sld += good ? log(d) : 0.0;
+            // log(b - a) of the first surface is log(top): summed once on the host
+            if (l) sld += good ? log(d) : 0.0;
         }
+        if (l == 0) sld = tid == 0 ? P.sum_log_top : 0.0;
         __syncthreads();
         double se = 0.0;
+#pragma unroll 1
         for (int n = tid; n < N; n += BLOCK) {
             const int i = n / C, j = n - i * C;
             const double wi = w[n];
@@ -100,7 +110,7 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, doub
         if (!P.mh) {
             P.lp_out[c] = total;
         } else {
-            const uint64_t step = *P.step_base + (uint64_t)P.step_k;
+            const uint64_t step = *P.step_base + (uint64_t)step_k;
             const double u = rng_uniform(P.seed, (uint32_t)c, step, kTagAccept, 0);
             const double la = total - P.lp_cur[c];
             const int acc = log(u) < la;
@@ -122,9 +132,9 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, doub
 }
 
 template <typename T, int S, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_prior_finalize(PriorParams<T> P) {
+__global__ __launch_bounds__(BLOCK, 4) void k_prior_finalize(PriorParams<T> P) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    prior_block<T, S, BLOCK>(P, blockIdx.x, reinterpret_cast<double *>(smem_raw));
+    prior_block<T, S, BLOCK>(P, blockIdx.x, reinterpret_cast<double *>(smem_raw), P.step_k);
 }
 
 // Random-walk proposal: prop = H + sigma z, z_i the (i%2)-th normal of pair
