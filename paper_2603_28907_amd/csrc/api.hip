@@ -441,12 +441,18 @@ PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double 
     return P;
 }
 
+template <typename T, int S, int B>
+void launch_prior_shape(int n, size_t lds, const PriorParams<T> &P, hipStream_t st) {
+    auto k = k_prior_finalize<T, S, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(n), dim3(B), lds, st, P);
+}
+
 template <typename T, int S>
 mc_status launch_prior(mc_problem *p, int n, const PriorParams<T> &P, hipStream_t st) {
-    size_t lds = sizeof(double) * (size_t)p->R * p->C;
-    auto k = k_prior_finalize<T, S, kPriorBlock>;
-    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(n), dim3(kPriorBlock), lds, st, P);
+    const size_t N = (size_t)p->R * p->C, lds = sizeof(T) * N;
+    if (N >= (size_t)kPriorLargeNodes) launch_prior_shape<T, S, kPriorBlockLarge>(n, lds, P, st);
+    else launch_prior_shape<T, S, kPriorBlock>(n, lds, P, st);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
 }
@@ -767,8 +773,8 @@ struct MultiPlan {
     // device tables
     void *d_mp = nullptr, *d_rc = nullptr, *d_pp = nullptr, *d_pd = nullptr, *d_chain_items = nullptr;
     void *d_step_ptrs = nullptr, *d_step_vals = nullptr;
-    int n_chain_items = 0;
-    size_t prior_lds = 0;
+    int n_chain_items = 0, n_chain_items_large = 0;   // items [0, large) have grids of kPriorLargeNodes+
+    size_t prior_lds = 0, prior_lds_large = 0;
     std::vector<MultiClass> classes;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap = nullptr;
@@ -845,14 +851,21 @@ mc_status build_multi_plan(MultiPlan *pl, const mc_run_config *cfgs) {
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return (size_t)pl->ps[a]->R * pl->ps[a]->C > (size_t)pl->ps[b]->R * pl->ps[b]->C;
     });
+    // chain items, large grids (1024-thread prior blocks) first
     std::vector<int2> chains;
-    size_t prior_lds = 0;
+    size_t lds_large = 0, lds_small = 0;
+    int n_large = 0;
     for (int i : order) {
+        const size_t N = (size_t)pl->ps[i]->R * pl->ps[i]->C;
+        const bool large = N >= (size_t)kPriorLargeNodes;
         for (int c = 0; c < pl->n[i]; ++c) chains.push_back(make_int2(i, c));
-        prior_lds = std::max(prior_lds, sizeof(double) * (size_t)pl->ps[i]->R * pl->ps[i]->C);
+        if (large) n_large += pl->n[i];
+        (large ? lds_large : lds_small) = std::max(large ? lds_large : lds_small, sizeof(T) * N);
     }
     pl->n_chain_items = (int)chains.size();
-    pl->prior_lds = prior_lds;
+    pl->n_chain_items_large = n_large;
+    pl->prior_lds = lds_small;
+    pl->prior_lds_large = lds_large;
     if ((s = upload_vec(e, pl->d_chain_items, chains)) != MC_OK) return s;
     // march classes: one per (grid size, top placement, block size), heaviest
     // first; items within a class sorted by decreasing ray count
@@ -984,10 +997,22 @@ mc_status multi_step(MultiPlan *pl, int k, hipStream_t st) {
         if (c > 0) HIP_TRY(e, hipEventRecord(mc_.done, cs));
     }
     for (size_t c = 1; c < nc; ++c) HIP_TRY(e, hipStreamWaitEvent(st, pl->classes[c].done, 0));
-    auto kp = k_prior_multi<T, S, kPriorBlock>;
-    if (pl->prior_lds > 65536) (void)hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->prior_lds);
-    hipLaunchKernelGGL(kp, dim3(pl->n_chain_items), dim3(kPriorBlock), pl->prior_lds, st,
-                       (const PriorParams<T> *)pl->d_pp, (const int2 *)pl->d_chain_items, k);
+    const int2 *items = (const int2 *)pl->d_chain_items;
+    const int nl = pl->n_chain_items_large, ns = pl->n_chain_items - nl;
+    if (nl > 0) {
+        auto kp = k_prior_multi<T, S, kPriorBlockLarge>;
+        if (pl->prior_lds_large > 65536)
+            (void)hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->prior_lds_large);
+        hipLaunchKernelGGL(kp, dim3(nl), dim3(kPriorBlockLarge), pl->prior_lds_large, st,
+                           (const PriorParams<T> *)pl->d_pp, items, k);
+    }
+    if (ns > 0) {
+        auto kp = k_prior_multi<T, S, kPriorBlock>;
+        if (pl->prior_lds > 65536)
+            (void)hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->prior_lds);
+        hipLaunchKernelGGL(kp, dim3(ns), dim3(kPriorBlock), pl->prior_lds, st, (const PriorParams<T> *)pl->d_pp,
+                           items + nl, k);
+    }
     HIP_TRY(e, hipGetLastError());
     return MC_OK;
 }

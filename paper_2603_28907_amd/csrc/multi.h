@@ -81,7 +81,7 @@ template <typename T, int S, int BLOCK>
 __global__ __launch_bounds__(BLOCK, 4) void k_prior_multi(const PriorParams<T> *Ps, const int2 *items, int step_k) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 it = items[blockIdx.x];
-    prior_block<T, S, BLOCK>(Ps[it.x], it.y, reinterpret_cast<double *>(smem_raw), step_k);
+    prior_block<T, S, BLOCK>(Ps[it.x], it.y, reinterpret_cast<T *>(smem_raw), step_k);
 }
 
 // One block per (problem, chain): the pairs of normals of that chain.

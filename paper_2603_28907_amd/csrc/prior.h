@@ -39,6 +39,11 @@ struct PriorParams {
     int step_k;
 };
 
+// Threads per prior block: grids of 8192 nodes and more use 1024 so that a
+// block whose workspace fills much of the LDS still keeps 16 wavefronts.
+constexpr int kPriorBlockLarge = 1024;
+constexpr int kPriorLargeNodes = 8192;
+
 // w = Phi^-1(u) with u = (h-a)/d and v = 1-u = (b-h)/d; the tail nearer to u
 // is evaluated directly.  Kept out of line: inlined into a node loop, the
 // compiler hoists the polynomial coefficients of Phi^-1 out of the loop into
@@ -49,9 +54,13 @@ __device__ __attribute__((noinline)) double probit_uv(double u, double v) {
     return lower ? w : -w;
 }
 
-// Body of one block for chain c; w = LDS workspace of R*C doubles.
+// Body of one block for chain c; w = LDS workspace of R*C values in the
+// state precision T (the Phi^-1 values are formed and summed in float64; the
+// copy kept for the neighbour differences is rounded to T, which in float32
+// mode is far below the float32 march's own rounding and halves the LDS a
+// block holds).
 template <typename T, int S, int BLOCK>
-__device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, double *w, int step_k) {
+__device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, T *w, int step_k) {
     __shared__ double red[16];
     __shared__ int ired[16];
     __shared__ int s_acc;
@@ -75,7 +84,7 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, doub
             const bool good = (d > 0.0) && (u > 0.0) && (v > 0.0);
             ok &= good ? 1 : 0;
             const double wi = good ? probit_uv(u, v) : 0.0;
-            w[n] = wi;
+            w[n] = (T)wi;
             sw2 += wi * wi;
             // log(b - a) of the first surface is log(top): summed once on the host
             if (l) sld += good ? log(d) : 0.0;
@@ -86,9 +95,9 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, doub
 #pragma unroll 1
         for (int n = tid; n < N; n += BLOCK) {
             const int i = n / C, j = n - i * C;
-            const double wi = w[n];
-            const double wr = w[i * C + (j + 1 == C ? 0 : j + 1)];
-            const double wd = w[(i + 1 == R ? 0 : i + 1) * C + j];
+            const double wi = (double)w[n];
+            const double wr = (double)w[i * C + (j + 1 == C ? 0 : j + 1)];
+            const double wd = (double)w[(i + 1 == R ? 0 : i + 1) * C + j];
             se += (wi - wr) * (wi - wr) + (wi - wd) * (wi - wd);
         }
         const double SW2 = block_sum<BLOCK>(sw2, red);
@@ -134,7 +143,7 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, doub
 template <typename T, int S, int BLOCK>
 __global__ __launch_bounds__(BLOCK, 4) void k_prior_finalize(PriorParams<T> P) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    prior_block<T, S, BLOCK>(P, blockIdx.x, reinterpret_cast<double *>(smem_raw), P.step_k);
+    prior_block<T, S, BLOCK>(P, blockIdx.x, reinterpret_cast<T *>(smem_raw), P.step_k);
 }
 
 // Random-walk proposal: prop = H + sigma z, z_i the (i%2)-th normal of pair
