@@ -124,3 +124,31 @@ def test_multi_argument_errors(torch_mod, oracle_mod):
         mcmc_run_multi([p32, p64], [Ha, Hb], lp, acc, 2, [0.1, 0.1], [1, 2])
     with pytest.raises(MuonCaveError, match="repeats"):
         mcmc_run_multi([p32, p32], [Ha, Ha.clone()], lp, acc, 2, [0.1, 0.1], [1, 2])
+
+
+def test_autotune_per_class(torch_mod, oracle_mod, tmp_path):
+    """The tuner picks one launch shape per grid class, applies it to every
+    problem of the class, caches it on disk, and leaves the log posterior
+    unchanged up to float32 rounding."""
+    from paper_2603_28907_amd import autotune
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    batch = _batch(oracle_mod, [0, 3, 5, 10], max_chains=8)   # grids 128, 16, 64, 16
+    probs = [Problem.from_scenario(sc, precision="f32") for sc, _, _, _ in batch]
+    H, _, _ = _states(torch, batch, torch.float32)
+    before = [p.logpost_batch(h).cpu().numpy() for p, h in zip(probs, H)]
+    cache = str(tmp_path / "tune.json")
+    autotune._memo.clear()
+    res = autotune.tune_batch(probs, H, cache_path=cache, iters=2)
+    say("tuned", res)
+    assert len(res) == 3
+    for p in probs:
+        t = res[autotune.class_key(p, torch.cuda.get_device_name(0))]
+        got = p.get_tuning()
+        assert all(got[k] == t[k] for k in ("march_variant", "block", "rays_per_thread"))
+    after = [p.logpost_batch(h).cpu().numpy() for p, h in zip(probs, H)]
+    for a, b in zip(before, after):
+        np.testing.assert_allclose(b, a, rtol=1e-6)
+    autotune._memo.clear()
+    again = autotune.tune_batch(probs, H, cache_path=cache, iters=2)
+    assert again == res
