@@ -74,12 +74,12 @@ def measured_traffic(name):
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024
 
 
-def algorithmic_bytes(sc, n_chains):
+def algorithmic_bytes(sc, n_chains, rays_per_block):
     """Bytes one march launch must move at least: every chain's free surfaces
     (float32), the top surface, the per-ray tables once (9 float32 + 2
     float64 per ray) and one float64 partial per (chain, tile)."""
     N = sc.n_rows * sc.n_cols
-    tiles = -(-sc.n_rays // (256 * 16))
+    tiles = -(-sc.n_rays // rays_per_block)
     return (n_chains * (sc.n_surfaces - 1) * N * 4 + N * 4 + sc.n_rays * (9 * 4 + 2 * 8)
             + n_chains * tiles * 8)
 
@@ -366,6 +366,7 @@ def main():
     ray_evals = n_chains * sc.n_rays * args.steps
     # roofline of the dominant kernel: the ray march, timed alone with HIP events
     ms_march = binding.time_march(prob, H, iters=args.march_iters)
+    tune = prob.get_tuning()
     opr = ops_per_ray(args.workload)
     achieved = opr * n_chains * sc.n_rays / (ms_march * 1e-3) / 1e12
     measured_f32 = binding.measure_valu_rate(0, "f32") / 1e12
@@ -391,8 +392,8 @@ def main():
         "accept_rate": float(acc.double().mean().item()) / (args.warmup + args.steps),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(args.workload),
-                     "traffic_unit": "bytes per launch", "algorithmic_bytes": algorithmic_bytes(sc, n_chains),
-                     "kernel": "k_march_lik4", "ms_per_launch": ms_march,
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes": algorithmic_bytes(sc, n_chains, tune["block"] * tune["rays_per_thread"]),
+                     "kernel": "k_march_lik4", "launch_shape": tune, "ms_per_launch": ms_march,
                      "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays,
                      "measured_fma_rate": {"f32": measured_f32, "f64": measured_f64, "unit": "Tlane-op/s"}},
     }

@@ -168,7 +168,7 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
  * top_in_lds: stage the fixed top surface in LDS when it fits (else it is
  * read from global memory).  Until mc_set_tuning is called the shape follows
  * the grid loaded last: float32 {4, 256, 4, 8, 0} below 48x48 nodes,
- * {4, 256, 4, 16, 0} up to 128x128, {4, 1024, 4, 16, 0} from 128x128 on;
+ * {4, 512, 4, 16, 0} up to 128x128, {4, 1024, 4, 16, 0} from 128x128 on;
  * float64 {3, 256, 4, 4, 1}.  A variant-2 shape whose queue does not fit
  * in LDS beside the surfaces runs as variant 3.  multi_blocks_per_cu (0..16,
  * read from problems[0] by mcmc_run_multi): 0 launches one block per

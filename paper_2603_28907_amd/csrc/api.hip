@@ -55,13 +55,14 @@ struct GraphKey {
 }  // namespace
 
 // Default launch shape by precision and grid size (measured on MI355X):
-// float32 uses the lean band walks; grids of 128x128 nodes and more hold the
-// free surfaces in 128 KB of LDS, one block per compute unit, so they take
-// 1024-thread blocks to keep 16 wavefronts resident.
+// float32 uses the lean band walks; from 48x48 nodes 512-thread blocks let
+// 6 wavefronts per SIMD stay resident under the LDS the surfaces take; grids
+// of 128x128 nodes and more hold the free surfaces in 128 KB of LDS, one block
+// per compute unit, so they take 1024-thread blocks.
 static mc_tuning default_tuning(int prec, size_t n_nodes) {
     if (prec == MC_F64) return mc_tuning{3, 256, 4, 4, 1, 0};
     if (n_nodes >= 128 * 128) return mc_tuning{4, 1024, 4, 16, 0, 0};
-    if (n_nodes >= 48 * 48) return mc_tuning{4, 256, 4, 16, 0, 0};
+    if (n_nodes >= 48 * 48) return mc_tuning{4, 512, 4, 16, 0, 0};
     return mc_tuning{4, 256, 4, 8, 0, 0};
 }
 

@@ -30,28 +30,32 @@ namespace mc {
 __device__ __forceinline__ float raw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Branch-free below-length of a piece of length tau1 with end values fe, fx
-// and curvature c2 of f = z - h (the cases of cell_below_length).
+// and curvature c2 of f = z - h (the cases of cell_below_length).  Solved in
+// the normalised variable s = tau / tau1 on [0, 1]:
+//   f(s) = fe + B s + A s^2,  A = c2 tau1^2,  B = fx - fe - A,
+// which needs two hardware reciprocals and one square root.  The stable root
+// fe / q also covers A = 0 (q = -B there: the straight-line crossing).
 __device__ __forceinline__ float piece_length(float fe, float fx, float c2, float tau1) {
     const bool be = fe < 0.f, bx = fx < 0.f;
-    const float ic2 = __builtin_amdgcn_rcpf(c2);
-    const float c1 = (fx - fe) * __builtin_amdgcn_rcpf(tau1) - c2 * tau1;
-    const float disc = fmaxf(c1 * c1 - 4.f * c2 * fe, 0.f);
+    const float A = c2 * tau1 * tau1;
+    const float B = (fx - fe) - A;
+    const float iA = __builtin_amdgcn_rcpf(A);
+    const float disc = fmaxf(B * B - 4.f * A * fe, 0.f);
     const float sq = raw_sqrt(disc);
-    // one crossing: the stable pair of roots, keep the one nearest the piece
-    const float q = -0.5f * (c1 + (c1 >= 0.f ? sq : -sq));
-    const float r1 = q * ic2, r2 = fe * __builtin_amdgcn_rcpf(q);
-    const float d1 = fmaxf(fmaxf(-r1, r1 - tau1), 0.f);
-    const float d2 = fmaxf(fmaxf(-r2, r2 - tau1), 0.f);
-    float r = ((d1 < d2) || (d2 != d2)) ? r1 : r2;
-    if (r != r) r = tau1 * fe * __builtin_amdgcn_rcpf(fe - fx);
-    r = fminf(fmaxf(r, 0.f), tau1);
+    // one crossing: the stable pair of roots, keep the one nearest [0, 1]
+    const float q = -0.5f * (B + (B >= 0.f ? sq : -sq));
+    const float s1 = q * iA, s2 = fe * __builtin_amdgcn_rcpf(q);
+    const float d1 = fmaxf(fmaxf(-s1, s1 - 1.f), 0.f);
+    const float d2 = fmaxf(fmaxf(-s2, s2 - 1.f), 0.f);
+    const float sr = fminf(fmaxf(((d1 < d2) || (d2 != d2)) ? s1 : s2, 0.f), 1.f);
+    const float r = sr * tau1;
     const float one = be ? r : tau1 - r;
     // same signs: two crossings around an interior vertex of the opposite sign
-    const float tv = -0.5f * c1 * ic2;
-    const float fv = fe + tv * (c1 + c2 * tv);
-    const bool two = (c2 != 0.f) && (tv > 0.f) && (tv < tau1) && ((fv < 0.f) != be);
-    const float half = 0.5f * sq * fabsf(ic2);
-    const float inner = fmaxf(fminf(tv + half, tau1) - fmaxf(tv - half, 0.f), 0.f);
+    const float sv = -0.5f * B * iA;
+    const float fv = fe + sv * (B + A * sv);
+    const bool two = (A != 0.f) && (sv > 0.f) && (sv < 1.f) && ((fv < 0.f) != be);
+    const float half = 0.5f * sq * fabsf(iA);
+    const float inner = fmaxf(fminf(sv + half, 1.f) - fmaxf(sv - half, 0.f), 0.f) * tau1;
     const float none = be ? tau1 : 0.f;
     const float twol = be ? tau1 - inner : inner;
     return (be != bx) ? one : (two ? twol : none);
@@ -287,8 +291,13 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     if (tid == 0) P.partials[(size_t)chain * P.n_tiles + tile] = tot;
 }
 
+// At least 6 wavefronts per SIMD: the walk is latency-bound, and 6 resident
+// waves beat 5 even with a few registers spilled (512-thread blocks keep the
+// LDS from capping residency below 6 on 64x64 grids).
+constexpr int kMarchWavesPerSimd = 6;
+
 template <int S, bool TOP_LDS, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_march_lik4(MarchParams<float> P, RayConsts<float> K) {
+__global__ __launch_bounds__(BLOCK, kMarchWavesPerSimd) void k_march_lik4(MarchParams<float> P, RayConsts<float> K) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int chain, tile;
     if (!xcd_chain_tile(P.n_tiles, P.n_chains, chain, tile)) return;

@@ -38,7 +38,7 @@ struct ProposeDesc {
 // PERSIST = false is the one-item-per-block form (grid = number of items):
 // without the loop the descriptor stays in scalar registers.
 template <int S, bool TOP_LDS, int BLOCK, bool PERSIST>
-__global__ __launch_bounds__(BLOCK) void k_march_multi4(const MarchParams<float> *Ps, const RayConsts<float> *Ks,
+__global__ __launch_bounds__(BLOCK, PERSIST ? 1 : kMarchWavesPerSimd) void k_march_multi4(const MarchParams<float> *Ps, const RayConsts<float> *Ks,
                                                         const int4 *items, int n_items) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (!PERSIST) {
