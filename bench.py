@@ -39,7 +39,12 @@ METRIC = ("ray-opacity evals/s + log-posterior evals/s (chains) at 1 GPU; p50/p9
 # Cells and crossings per ray are the oracle's exact counts on this workload
 # (18.93 and 2.94 per ray over 8 initial states).
 OPS_CELL_BASE, OPS_TEST, OPS_CROSS, OPS_RAY = 8.0, 9.0, 45.0, 80.0
-WORKLOAD_COUNTS = {"grf_cave_64": dict(cells=18.93, crossings=2.94, S=3)}
+WORKLOAD_COUNTS = {"grf_cave_64": dict(cells=18.93, crossings=2.94, S=3),
+                   "grf_cave_128": dict(cells=37.24, crossings=2.92, S=3)}
+# The adjoint re-walks every ray and, per crossing, adds the four bilinear
+# weights times g_p / |f'| converted to fixed point: 32 more lane-operations
+# per crossing (its four 64-bit atomics are memory operations, not counted).
+OPS_CROSS_ADJ = OPS_CROSS + 32.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed VALU lane-op
 # per lane per clock; wave64 instructions issue over 4 clocks)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -51,10 +56,13 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (FETCH_SIZE reads 131089 KiB for 262144 KiB moved: scale 2.0; WRITE_SIZE
 # reads exactly: scale 1.0).  Valid only for the kernel sources they were
 # taken on: the entry is dropped when the hash of those sources changes.
+# At 6 wavefronts per SIMD the march spills ~40 bytes per lane to scratch
+# once per wavefront; the dirty scratch lines written back at the end of the
+# kernel are most of WRITE_SIZE (about 1.7 bytes per ray).
 KERNEL_SOURCES = ("device_common.h", "march.h", "march3.h", "march5.h")
 MEASURED_TRAFFIC = {
-    "grf_cave_64": dict(source_sha="c20b6dbcf6a76a3d", fetch_kib=23169.0, fetch_scale=262144 / 131088.9,
-                        write_kib=64.0, write_scale=1.0),
+    "grf_cave_64": dict(source_sha="19c47320f57e0f33", fetch_kib=30543.7, fetch_scale=262144 / 131088.8,
+                        write_kib=56935.9, write_scale=1.0),
 }
 
 
@@ -87,6 +95,11 @@ def algorithmic_bytes(sc, n_chains, rays_per_block):
 def ops_per_ray(name):
     c = WORKLOAD_COUNTS[name]
     return OPS_RAY + c["cells"] * (OPS_CELL_BASE + c["S"] * OPS_TEST) + c["crossings"] * OPS_CROSS
+
+
+def adjoint_ops_per_ray(name):
+    c = WORKLOAD_COUNTS[name]
+    return OPS_RAY + c["cells"] * (OPS_CELL_BASE + c["S"] * OPS_TEST) + c["crossings"] * OPS_CROSS_ADJ
 
 
 def make_workload(name):
@@ -228,6 +241,62 @@ def bench_hetero(args, torch):
     }
 
 
+def bench_grad(args, torch):
+    """Gradient-driven sampling on the 128x128 geometry: full log-posterior +
+    gradient evaluations (forward march, adjoint march, prior gradient) and
+    MALA steps on 512 chains; roofline of the adjoint kernel."""
+    from paper_2603_28907_amd import binding, inputs
+    from paper_2603_28907_amd.binding import KERNEL_MALA, Problem
+    sc = inputs.grf_cave(seed=10, n_grid=128)
+    n_chains, eps = 512, args.mala_eps
+    sc.counts = gpu_counts(sc, torch)
+    prob = Problem.from_scenario(sc, precision="f32")
+    H = torch.as_tensor(inputs.init_states(sc, n_chains, seed=12), dtype=torch.float32, device="cuda:0")
+    lp = torch.empty(n_chains, dtype=torch.float64, device="cuda:0")
+    g = torch.empty((n_chains, 3, 128, 128), dtype=torch.float32, device="cuda:0")
+    prob.logpost_grad_batch(H, lp, g)
+    torch.cuda.synchronize()
+    k = max(1, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(k):
+        prob.logpost_grad_batch(H, lp, g)
+    torch.cuda.synchronize()
+    dt_grad = (time.perf_counter() - t0) / k
+    print(f"[bench] gradient evaluation: {dt_grad * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    lpm = torch.full((n_chains,), float("nan"), dtype=torch.float64, device="cuda:0")
+    acc = torch.zeros(n_chains, dtype=torch.int64, device="cuda:0")
+    G = max(1, min(args.graph_steps, args.steps))
+    prob.mcmc_run(H, lpm, acc, args.warmup, eps, 3, kernel=KERNEL_MALA, graph_steps=min(G, max(args.warmup, 1)))
+    torch.cuda.synchronize()
+    a0 = acc.clone()
+    t0 = time.perf_counter()
+    prob.mcmc_run(H, lpm, acc, args.steps, eps, 3, step_offset=args.warmup, kernel=KERNEL_MALA, graph_steps=G)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("[bench] timed region done", file=sys.stderr, flush=True)
+    assert torch.isfinite(lpm).all(), "non-finite log posterior"
+    ms_adj = binding.time_adjoint(prob, H, iters=args.march_iters)
+    ms_fwd = binding.time_march(prob, H, iters=args.march_iters)
+    opr = adjoint_ops_per_ray("grf_cave_128")
+    achieved = opr * n_chains * sc.n_rays / (ms_adj * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": n_chains * sc.n_rays * args.steps / dt, "unit": "ray-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"grad128: the paper-scale geometry regenerated on 128x128 nodes (8 sensors x "
+                               f"64x64 pixels, {sc.n_rays} rays), {n_chains} chains, MALA eps {eps} m (one forward "
+                               f"march, one adjoint march and the prior gradient per step), float32 march, float64 "
+                               f"sums, HIP graphs of {G} steps", "chains": n_chains, "rays": sc.n_rays},
+        "logpost_evals_per_s": n_chains * args.steps / dt,
+        "accept_rate": float((acc - a0).double().mean().item()) / args.steps,
+        "gradient_evals_per_s": n_chains / dt_grad, "ms_per_gradient_eval": dt_grad * 1e3,
+        "forward_ms_per_launch": ms_fwd,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_adjoint",
+                     "ms_per_launch": ms_adj, "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays},
+    }
+
+
 def bench_serve(args, torch):
     """Serving: Poisson arrivals of heterogeneous jobs (sizes as the hetero
     workload), each run to a fixed number of steps per chain; the same
@@ -316,6 +385,7 @@ def main():
     ap.add_argument("--duration", type=float, default=3.0, help="serve: seconds of arrivals")
     ap.add_argument("--job-steps", type=int, default=2000, help="serve: steps per chain per job")
     ap.add_argument("--max-jobs", type=int, default=64, help="serve: resident jobs at once")
+    ap.add_argument("--mala-eps", type=float, default=0.004, help="grad128: MALA step size (m)")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed region (a known-size "
@@ -334,6 +404,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args, torch)), flush=True)
+        return
+    if args.workload == "grad128":
+        print(json.dumps(bench_grad(args, torch)), flush=True)
         return
     if args.copy_calibration_mb > 0:
         src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device="cuda:0")

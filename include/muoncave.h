@@ -329,6 +329,13 @@ mc_status mc_measure_valu_rate(int hip_device, int kind, double *lane_ops_per_s)
 mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
                         float *ms_per_launch);
 
+/* Mean milliseconds per launch of the adjoint march kernel alone on
+ * `stream` (HIP events over `iters` launches), after one full gradient
+ * evaluation of the n_chains states has produced its forward opacities.
+ * Synchronous; the handle's gradient workspaces are used and overwritten. */
+mc_status mc_time_adjoint(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
+                          float *ms_per_launch);
+
 /* Library version string. */
 const char *mc_version(void);
 

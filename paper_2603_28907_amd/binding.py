@@ -109,6 +109,7 @@ def load_library(path: Optional[str] = None):
         "mc_get_tuning": (I, [V, P(Tuning)]),
         "mcmc_run_multi": (I, [I, P(V), P(RunConfig), P(I), P(V), P(V), P(V), V]),
         "mc_measure_valu_rate": (I, [I, I, P(D)]),
+        "mc_time_adjoint": (I, [V, I, V, I, V, P(ct.c_float)]),
         "mc_server_create": (I, [P(ServerConfig), P(V)]),
         "mc_server_destroy": (None, [V, I]),
         "mc_server_last_error": (ct.c_char_p, [V]),
@@ -131,7 +132,7 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi",
                     "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
                     "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
-                    "mc_measure_valu_rate")
+                    "mc_measure_valu_rate", "mc_time_adjoint")
 
 
 def _host(a, dtype=np.float64):
@@ -335,6 +336,16 @@ def time_march(problem: "Problem", heights, iters: int = 20, stream=None) -> flo
     problem._check_tensor(heights, problem.heights_shape(n), problem.torch_dtype, "heights")
     problem._check(problem.lib.mc_time_march(problem.h, n, ct.c_void_p(heights.data_ptr()), int(iters),
                                              _stream_handle(stream, problem.device), ct.byref(ms)))
+    return float(ms.value)
+
+
+def time_adjoint(problem: "Problem", heights, iters: int = 10, stream=None) -> float:
+    """Mean milliseconds per launch of the adjoint march kernel (HIP events on `stream`)."""
+    ms = ct.c_float()
+    n = int(heights.shape[0])
+    problem._check_tensor(heights, problem.heights_shape(n), problem.torch_dtype, "heights")
+    problem._check(problem.lib.mc_time_adjoint(problem.h, n, ct.c_void_p(heights.data_ptr()), int(iters),
+                                               _stream_handle(stream, problem.device), ct.byref(ms)))
     return float(ms.value)
 
 

@@ -147,7 +147,8 @@ __device__ __forceinline__ void walk_surface_adjoint(const MarchParams<T> &P, co
     }
 }
 
-// One block = one chain x one tile of rays; g_p from the forward opacities.
+// One block = one chain x one tile of rays (XCD-aware 1-D grid, as the
+// forward march); g_p from the forward opacities.
 // gfix: [n_chains][S][R*C] fixed-point accumulators (zeroed beforehand).
 template <typename T, int S, bool TOP_LDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T> K, const T *opacity,
@@ -155,7 +156,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sh = reinterpret_cast<T *>(smem_raw);
     __shared__ T band[2 * kMaxSurfaces];
-    const int chain = blockIdx.y, tile = blockIdx.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
+    int chain, tile;
+    if (!xcd_chain_tile(P.n_tiles, P.n_chains, chain, tile)) return;
     const int N = P.R * P.C;
     const T *Hc = P.heights + (size_t)chain * (S - 1) * N;
     T mn[S], mx[S];

@@ -492,6 +492,47 @@ mc_status logpost_dispatch(mc_problem *p, int n, const void *heights, double *lp
     return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
 }
 
+template <typename T, int S, int B>
+void launch_prior_grad(int n, size_t lds, const PriorParams<T> &P, double *gprior, hipStream_t st) {
+    auto k = k_prior_grad<T, S, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(n), dim3(B), lds, st, P, gprior);
+}
+
+template <typename T, int S, bool TL, int B>
+void launch_adjoint_shape(dim3 grid, size_t lds, const MarchParams<T> &M, const RayConsts<T> &K, const T *obuf,
+                          unsigned long long *gfix, hipStream_t st) {
+    auto k = k_adjoint<T, S, TL, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, K, obuf, gfix);
+}
+
+// The adjoint march of n states (forward opacities in p->obuf): the forward
+// tiling and XCD-aware grid; 1024-thread blocks when the staged surfaces
+// take more than 64 KB of LDS (one block per compute unit).
+template <typename T, int S>
+mc_status launch_adjoint(mc_problem *p, int n, const T *heights, unsigned long long *gfix, hipStream_t st) {
+    const size_t N = (size_t)p->R * p->C;
+    MarchParams<T> M = march_params<T>(p, heights, nullptr, (double *)p->partials.p);
+    M.n_chains = n;
+    RayConsts<T> K = ray_consts<T>(p);
+    const bool tl = N * S * sizeof(T) + 4096 <= p->max_lds;
+    const size_t lds = N * (tl ? S : S - 1) * sizeof(T);
+    if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+    const dim3 grid((unsigned)M.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+    const T *ob = (const T *)p->obuf.p;
+    const bool big = lds > 65536;
+    if (tl) {
+        if (big) launch_adjoint_shape<T, S, true, 1024>(grid, lds, M, K, ob, gfix, st);
+        else launch_adjoint_shape<T, S, true, 256>(grid, lds, M, K, ob, gfix, st);
+    } else {
+        if (big) launch_adjoint_shape<T, S, false, 1024>(grid, lds, M, K, ob, gfix, st);
+        else launch_adjoint_shape<T, S, false, 256>(grid, lds, M, K, ob, gfix, st);
+    }
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
 // Log posterior and gradient of n states into lp and grad ([n][S][N] in T):
 // forward march with opacities, prior and its gradient, adjoint march,
 // combine.  Workspaces must be ensured by the caller (ensure_grad_ws).
@@ -511,30 +552,12 @@ mc_status grad_eval(mc_problem *p, int n, const T *heights, double *lp, T *grad,
     P.lp_out = lp;
     {
         size_t lds = sizeof(double) * N;
-        auto k = k_prior_grad<T, S, kPriorBlock>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, dim3(n), dim3(kPriorBlock), lds, st, P, gprior);
+        if (N >= (size_t)kPriorLargeNodes) launch_prior_grad<T, S, kPriorBlockLarge>(n, lds, P, gprior, st);
+        else launch_prior_grad<T, S, kPriorBlock>(n, lds, P, gprior, st);
         HIP_TRY(p, hipGetLastError());
     }
     if (p->n_ray > 0) {
-        MarchParams<T> M = march_params<T>(p, heights, nullptr, (double *)p->partials.p);
-        RayConsts<T> K = ray_consts<T>(p);
-        bool tl = N * S * sizeof(T) + 4096 <= p->max_lds;
-        size_t lds = N * (tl ? S : S - 1) * sizeof(T);
-        if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-        // the adjoint keeps the forward tiling but marches with 256 threads per block
-        M.rays_per_block = tiling(p).rays_per_block;
-        dim3 grid(M.n_tiles, n);
-        if (tl) {
-            auto k = k_adjoint<T, S, true, 256>;
-            if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(k, grid, dim3(256), lds, st, M, K, (const T *)p->obuf.p, gfix);
-        } else {
-            auto k = k_adjoint<T, S, false, 256>;
-            if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(k, grid, dim3(256), lds, st, M, K, (const T *)p->obuf.p, gfix);
-        }
-        HIP_TRY(p, hipGetLastError());
+        if ((s = launch_adjoint<T, S>(p, n, heights, gfix, st)) != MC_OK) return s;
     }
     if (p->n_ray == 0) {
         const size_t tot = SN * n;
@@ -724,6 +747,43 @@ mc_status time_march_impl(mc_problem *p, int n, const T *heights, int iters, hip
     (void)hipEventDestroy(e1);
     *ms = total / (float)iters;
     return s;
+}
+
+// Mean time of the adjoint kernel alone: one full gradient evaluation sets
+// up the forward opacities, then `iters` adjoint launches are timed (their
+// accumulations are discarded).
+template <typename T, int S>
+mc_status time_adjoint_impl(mc_problem *p, int n, const T *heights, int iters, hipStream_t st, float *ms) {
+    const size_t SN = (size_t)S * p->R * p->C;
+    mc_status s;
+    if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
+    if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
+    if ((s = ensure(p, p->gcur, sizeof(T) * SN * n)) != MC_OK) return s;
+    if ((s = grad_eval<T, S>(p, n, heights, (double *)p->lptmp.p, (T *)p->gcur.p, st)) != MC_OK) return s;
+    hipEvent_t e0, e1;
+    HIP_TRY(p, hipEventCreate(&e0));
+    HIP_TRY(p, hipEventCreate(&e1));
+    HIP_TRY(p, hipEventRecord(e0, st));
+    for (int i = 0; i < iters && s == MC_OK; ++i)
+        s = launch_adjoint<T, S>(p, n, heights, (unsigned long long *)p->gfix.p, st);
+    HIP_TRY(p, hipEventRecord(e1, st));
+    HIP_TRY(p, hipEventSynchronize(e1));
+    float total = 0.f;
+    HIP_TRY(p, hipEventElapsedTime(&total, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = total / (float)iters;
+    return s;
+}
+
+template <typename T>
+mc_status time_adjoint_dispatch(mc_problem *p, int n, const void *heights, int iters, hipStream_t st, float *ms) {
+    switch (p->S) {
+        case 2: return time_adjoint_impl<T, 2>(p, n, (const T *)heights, iters, st, ms);
+        case 3: return time_adjoint_impl<T, 3>(p, n, (const T *)heights, iters, st, ms);
+        case 4: return time_adjoint_impl<T, 4>(p, n, (const T *)heights, iters, st, ms);
+    }
+    return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
 }
 
 template <typename T>
@@ -1460,6 +1520,19 @@ mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int it
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? time_march_dispatch<double>(p, n_chains, heights, iters, st, ms_per_launch)
                              : time_march_dispatch<float>(p, n_chains, heights, iters, st, ms_per_launch);
+}
+
+mc_status mc_time_adjoint(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
+                          float *ms_per_launch) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    if (n_chains <= 0 || n_chains > 65535 || iters <= 0 || !heights || !ms_per_launch)
+        return fail(p, MC_ERR_ARG, "invalid arguments");
+    if (p->n_ray == 0) return fail(p, MC_ERR_STATE, "no rays");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    return p->prec == MC_F64 ? time_adjoint_dispatch<double>(p, n_chains, heights, iters, st, ms_per_launch)
+                             : time_adjoint_dispatch<float>(p, n_chains, heights, iters, st, ms_per_launch);
 }
 
 mc_status mc_measure_valu_rate(int hip_device, int kind, double *lane_ops_per_s) {
