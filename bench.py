@@ -292,7 +292,7 @@ def bench_grad(args, torch):
         "gradient_evals_per_s": n_chains / dt_grad, "ms_per_gradient_eval": dt_grad * 1e3,
         "forward_ms_per_launch": ms_fwd,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_adjoint",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_adjoint_lds",
                      "ms_per_launch": ms_adj, "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays},
     }
 

@@ -22,6 +22,7 @@
 #pragma once
 
 #include "march3.h"
+#include "march5.h"
 #include "prior.h"
 
 namespace mc {
@@ -226,6 +227,176 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T
             if (tl < th && scale != 0.0)
                 walk_surface_adjoint<T>(P, Hl, qx, qy, qz, dx, dy, dz, idx, idy, ox, oy, tl, th, scale, Gc + l * N);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// float32 adjoint on the lean walk of k_march_lik4
+// ---------------------------------------------------------------------------
+
+// Crossings of a piece in the normalised variable s = tau / tau1 (the cases
+// and the root choice of piece_length): returns 0..2 crossings with their
+// s and |f'(tau)| = |B + 2 A s| / tau1.
+__device__ __forceinline__ int piece_crossings(float fe, float fx, float c2, float tau1, float *sc, float *fp) {
+    const bool be = fe < 0.f, bx = fx < 0.f;
+    const float A = c2 * tau1 * tau1;
+    const float B = (fx - fe) - A;
+    const float iA = __builtin_amdgcn_rcpf(A), it1 = __builtin_amdgcn_rcpf(tau1);
+    const float disc = fmaxf(B * B - 4.f * A * fe, 0.f);
+    const float sq = raw_sqrt(disc);
+    if (be != bx) {
+        const float q = -0.5f * (B + (B >= 0.f ? sq : -sq));
+        const float s1 = q * iA, s2 = fe * __builtin_amdgcn_rcpf(q);
+        const float d1 = fmaxf(fmaxf(-s1, s1 - 1.f), 0.f);
+        const float d2 = fmaxf(fmaxf(-s2, s2 - 1.f), 0.f);
+        const float sr = fminf(fmaxf(((d1 < d2) || (d2 != d2)) ? s1 : s2, 0.f), 1.f);
+        sc[0] = sr;
+        fp[0] = fabsf(B + 2.f * A * sr) * it1;
+        return 1;
+    }
+    const float sv = -0.5f * B * iA;
+    const float fv = fe + sv * (B + A * sv);
+    if ((A != 0.f) && (sv > 0.f) && (sv < 1.f) && ((fv < 0.f) != be)) {
+        const float half = 0.5f * sq * fabsf(iA);
+        const float sa = fmaxf(sv - half, 0.f), sb = fminf(sv + half, 1.f);
+        sc[0] = sa;
+        sc[1] = sb;
+        fp[0] = fabsf(B + 2.f * A * sa) * it1;
+        fp[1] = fabsf(B + 2.f * A * sb) * it1;
+        return 2;
+    }
+    return 0;
+}
+
+// float32 adjoint, per-node sums formed in LDS.  One block = one
+// (chain, ray tile, surface l, window of node rows): it stages surface l,
+// zeroes 64-bit fixed-point accumulators for the window's nodes, walks the
+// tile's rays through surface l (the walk and classification of
+// k_march_lik4), adds each crossing's four node contributions that fall in
+// the window with LDS integer atomics, and finally adds every accumulator to
+// the chain's gradient with one global atomic (a global atomic per crossing
+// and node would cost 12 per ray: the L2 atomic rate, not the walk, would
+// set the time).  Integer sums are order-independent, so the result is
+// bitwise reproducible.  The window keeps surface + accumulators inside the
+// LDS; a surface split into w windows is walked w times.
+struct AdjointLdsShape {
+    int n_windows, window_rows;
+};
+
+template <int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, RayConsts<float> K, const float *opacity,
+                                                       unsigned long long *gfix, AdjointLdsShape W_) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ float band[2];
+    __shared__ float wred[2][BLOCK / kWave];
+    const int tid = threadIdx.x;
+    const int n_sub = P.n_tiles * S * W_.n_windows;
+    int chain, sub;
+    if (!xcd_chain_tile(n_sub, P.n_chains, chain, sub)) return;
+    const int tile = sub / (S * W_.n_windows);
+    const int rem = sub - tile * S * W_.n_windows;
+    const int l = rem / W_.n_windows, win = rem - l * W_.n_windows;
+    const int N = P.R * P.C, C = P.C;
+    const int row0 = win * W_.window_rows;
+    const int rows = min(W_.window_rows, P.R - row0);
+    float *Hl = reinterpret_cast<float *>(smem_raw);
+    unsigned long long *acc =
+        reinterpret_cast<unsigned long long *>(smem_raw + (((size_t)N * sizeof(float) + 15) & ~(size_t)15));
+    // stage surface l and its band
+    const float *src = l < S - 1 ? P.heights + ((size_t)chain * (S - 1) + l) * N : P.top;
+    float mn = __builtin_huge_valf(), mx = -__builtin_huge_valf();
+    for (int i = tid; i < N; i += BLOCK) {
+        const float v = src[i];
+        Hl[i] = v;
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+    }
+    for (int i = tid; i < rows * C; i += BLOCK) acc[i] = 0ull;
+    {
+        const float a = wave_min(mn), b = wave_max(mx);
+        if (tid % kWave == 0) {
+            wred[0][tid / kWave] = a;
+            wred[1][tid / kWave] = b;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            float a2 = wred[0][0], b2 = wred[1][0];
+            for (int w = 1; w < BLOCK / kWave; ++w) {
+                a2 = fminf(a2, wred[0][w]);
+                b2 = fmaxf(b2, wred[1][w]);
+            }
+            band[0] = (l < S - 1 ? a2 : P.top_min) - P.margin;
+            band[1] = (l < S - 1 ? b2 : P.top_max) + P.margin;
+        }
+        __syncthreads();
+    }
+    const float rho = P.rho_diff[l];
+    const int lo = row0 * C, hi = (row0 + rows) * C;   // node offsets of the window
+    const int r0 = tile * P.rays_per_block;
+    const int r1 = min(r0 + P.rays_per_block, P.n_ray);
+    for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
+        const int sidx = ray / P.n_pix;
+        const double Od = (double)opacity[(size_t)chain * P.n_ray + ray];
+        const double gp = P.expo[ray] * exp(-Od * P.inv_L) * P.inv_L - P.c_over_L[ray];   // (lambda - C)/Lambda
+        const float scale = (float)(gp * (double)rho);
+        const float qx = P.sensor[3 * sidx], qy = P.sensor[3 * sidx + 1], qz = P.sensor[3 * sidx + 2];
+        const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
+        const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
+        const float ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
+        const float tl = fminf(fmaxf((band[0] - qz) * idz, 0.f), Texit);
+        const float th = fminf(fmaxf((band[1] - qz) * idz, 0.f), Texit);
+        if (!(tl < th) || scale == 0.f) continue;
+        const bool xpos = dx > 0.f, ypos = dy > 0.f;
+        Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, tl);
+        for (int it = 0; it < P.R + P.C; ++it) {
+            const Step st = walk_step(W, qz, dz, idx, idy, ox, oy, th);
+            const int off = W.off;
+            const float h00 = Hl[off], h01 = Hl[off + 1], h10 = Hl[off + C], h11 = Hl[off + C + 1];
+            const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));
+            const float hmax = fmaxf(fmaxf(h00, h01), fmaxf(h10, h11));
+            // the cell's node rows a, a+1 must meet the window
+            if (off + C + 1 >= lo && off < hi && !(st.z1 < hmin - P.margin) && !(W.z0 > hmax + P.margin) &&
+                st.t1 > W.t0) {
+                const Patch pt = make_patch(h00, h01, h10, h11);
+                const float t0 = W.t0, t1 = st.t1;
+                const float z0 = W.z0, z1 = st.z1;
+                const float se = __builtin_fmaf(__builtin_fmaf(t0, dx, qx), P.ihx, -W.af);
+                const float we = __builtin_fmaf(__builtin_fmaf(t0, dy, qy), P.ihy, -W.bf);
+                const float sx = __builtin_fmaf(__builtin_fmaf(t1, dx, qx), P.ihx, -W.af);
+                const float wx = __builtin_fmaf(__builtin_fmaf(t1, dy, qy), P.ihy, -W.bf);
+                const float fe = end_value(pt, W.ekind, !xpos, !ypos, z0, se, we);
+                const float fx = end_value(pt, st.xkind, xpos, ypos, z1, sx, wx);
+                const float c2 = -(pt.dr1 - pt.dr0) * (dx * P.ihx) * (dy * P.ihy);
+                const float tau1 = t1 - t0;
+                float sc[2], fp[2];
+                const int nc = piece_crossings(fe, fx, c2, tau1, sc, fp);
+                for (int k = 0; k < nc; ++k) {
+                    if (!(fp[k] > 0.f)) continue;   // tangency: a kink of lp, no derivative
+                    const float t = __builtin_fmaf(sc[k], tau1, t0);
+                    if (__builtin_fmaf(t, dz, qz) >= P.ztop - P.margin) continue;   // the box lid: a kink
+                    const float s = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -W.af), 0.f), 1.f);
+                    const float w = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -W.bf), 0.f), 1.f);
+                    const float g = scale * __builtin_amdgcn_rcpf(fp[k]);
+                    const float cv[4] = {g * (1.f - s) * (1.f - w), g * (1.f - s) * w, g * s * (1.f - w), g * s * w};
+                    const int no[4] = {off, off + 1, off + C, off + C + 1};
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        if (no[m] >= lo && no[m] < hi) {
+                            const float sv = fminf(fmaxf(cv[m] * 4294967296.0f, -9.0e18f), 9.0e18f);
+                            atomicAdd(acc + (no[m] - lo), (unsigned long long)(long long)__builtin_rintf(sv));
+                        }
+                    }
+                }
+            }
+            if (!st.edge) break;
+            walk_advance(W, st);
+        }
+    }
+    __syncthreads();
+    unsigned long long *G = gfix + ((size_t)chain * S + l) * N + lo;
+    for (int i = tid; i < rows * C; i += BLOCK) {
+        const unsigned long long v = acc[i];
+        if (v) atomicAdd(G + i, v);
     }
 }
 

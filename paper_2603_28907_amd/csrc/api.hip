@@ -507,30 +507,58 @@ void launch_adjoint_shape(dim3 grid, size_t lds, const MarchParams<T> &M, const 
     hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, K, obuf, gfix);
 }
 
-// The adjoint march of n states (forward opacities in p->obuf): the forward
-// tiling and XCD-aware grid; 1024-thread blocks when the staged surfaces
-// take more than 64 KB of LDS (one block per compute unit).
+template <int S, int B>
+void launch_adjoint_lds_shape(dim3 grid, size_t lds, const MarchParams<float> &M, const RayConsts<float> &K,
+                              const float *obuf, unsigned long long *gfix, AdjointLdsShape w, hipStream_t st) {
+    auto k = k_adjoint_lds<S, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, K, obuf, gfix, w);
+}
+
+// The adjoint march of n states (forward opacities in p->obuf).  float32:
+// k_adjoint_lds with node-row windows sized so that one surface and the
+// window's 64-bit accumulators fit the LDS; float64: the direct scatter.
+// Forward tiling and XCD-aware grids; 1024-thread blocks when a block takes
+// more than 64 KB of LDS (one block per compute unit).
 template <typename T, int S>
 mc_status launch_adjoint(mc_problem *p, int n, const T *heights, unsigned long long *gfix, hipStream_t st) {
     const size_t N = (size_t)p->R * p->C;
     MarchParams<T> M = march_params<T>(p, heights, nullptr, (double *)p->partials.p);
     M.n_chains = n;
     RayConsts<T> K = ray_consts<T>(p);
-    const bool tl = N * S * sizeof(T) + 4096 <= p->max_lds;
-    const size_t lds = N * (tl ? S : S - 1) * sizeof(T);
-    if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-    const dim3 grid((unsigned)M.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
-    const T *ob = (const T *)p->obuf.p;
-    const bool big = lds > 65536;
-    if (tl) {
-        if (big) launch_adjoint_shape<T, S, true, 1024>(grid, lds, M, K, ob, gfix, st);
-        else launch_adjoint_shape<T, S, true, 256>(grid, lds, M, K, ob, gfix, st);
-    } else {
-        if (big) launch_adjoint_shape<T, S, false, 1024>(grid, lds, M, K, ob, gfix, st);
-        else launch_adjoint_shape<T, S, false, 256>(grid, lds, M, K, ob, gfix, st);
+    if constexpr (std::is_same<T, float>::value) {   // float32: LDS sums
+        const size_t surf = (N * sizeof(float) + 15) & ~(size_t)15;
+        const size_t row_bytes = (size_t)p->C * sizeof(unsigned long long);
+        if (surf + 4096 + row_bytes > p->max_lds)
+            return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+        const size_t budget = p->max_lds - surf - 4096;
+        AdjointLdsShape w;
+        w.n_windows = (int)(((size_t)p->R * row_bytes + budget - 1) / budget);
+        w.window_rows = (p->R + w.n_windows - 1) / w.n_windows;
+        w.n_windows = (p->R + w.window_rows - 1) / w.window_rows;
+        const size_t lds = surf + (size_t)w.window_rows * row_bytes;
+        const dim3 grid((unsigned)(M.n_tiles * S * w.n_windows) * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+        if (lds > 65536) launch_adjoint_lds_shape<S, 1024>(grid, lds, M, K, (const float *)p->obuf.p, gfix, w, st);
+        else launch_adjoint_lds_shape<S, 256>(grid, lds, M, K, (const float *)p->obuf.p, gfix, w, st);
+        HIP_TRY(p, hipGetLastError());
+        return MC_OK;
+    } else {   // float64: the direct scatter
+        const bool tl = N * S * sizeof(T) + 4096 <= p->max_lds;
+        const size_t lds = N * (tl ? S : S - 1) * sizeof(T);
+        if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+        const dim3 grid((unsigned)M.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+        const T *ob = (const T *)p->obuf.p;
+        const bool big = lds > 65536;
+        if (tl) {
+            if (big) launch_adjoint_shape<T, S, true, 1024>(grid, lds, M, K, ob, gfix, st);
+            else launch_adjoint_shape<T, S, true, 256>(grid, lds, M, K, ob, gfix, st);
+        } else {
+            if (big) launch_adjoint_shape<T, S, false, 1024>(grid, lds, M, K, ob, gfix, st);
+            else launch_adjoint_shape<T, S, false, 256>(grid, lds, M, K, ob, gfix, st);
+        }
+        HIP_TRY(p, hipGetLastError());
+        return MC_OK;
     }
-    HIP_TRY(p, hipGetLastError());
-    return MC_OK;
 }
 
 // Log posterior and gradient of n states into lp and grad ([n][S][N] in T):
