@@ -386,6 +386,8 @@ def main():
     ap.add_argument("--job-steps", type=int, default=2000, help="serve: steps per chain per job")
     ap.add_argument("--max-jobs", type=int, default=64, help="serve: resident jobs at once")
     ap.add_argument("--mala-eps", type=float, default=0.004, help="grad128: MALA step size (m)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the short hetero / grad128 / serve runs summarised after the headline line")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed region (a known-size "
@@ -473,7 +475,48 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
+    if not args.no_extras:
+        out["workloads"] = run_extras(args, torch)
     print(json.dumps(out), flush=True)
+
+
+def run_extras(args, torch):
+    """Short runs of the other workloads (batched heterogeneous problems,
+    gradient sampling at 128x128, serving), summarised beside the headline
+    line; each is independent and a failure is reported, not raised."""
+    import copy
+    res = {}
+    jobs = [
+        ("hetero_256", bench_hetero, dict(steps=20, warmup=3, plain_steps=2, graph_steps=20, problems=256)),
+        ("grad128", bench_grad, dict(steps=20, warmup=4, graph_steps=10, march_iters=5, mala_eps=0.004)),
+        ("serve_20_per_s", bench_serve, dict(rate=20.0, duration=1.0, job_steps=2000, max_jobs=8, graph_steps=50,
+                                             no_plain=True)),
+    ]
+    keep = {
+        "hetero_256": ("value", "ms_per_step", "logpost_evals_per_s", "speedup_vs_plain"),
+        "grad128": ("value", "ms_per_step", "logpost_evals_per_s", "accept_rate", "gradient_evals_per_s"),
+        "serve_20_per_s": ("value", "p50_s", "p99_s", "logpost_evals_per_s", "offered_load"),
+    }
+    for name, fn, over in jobs:
+        a = copy.copy(args)
+        for k, v in over.items():
+            setattr(a, k, v)
+        print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
+        try:
+            r = fn(a, torch)
+            d = {k: r.get(k) for k in keep[name]}
+            d["unit"] = r["unit"]
+            d["workload"] = r["config"]["workload"]
+            if "roofline" in r:
+                d["roofline_frac"] = r["roofline"]["frac"]
+                d["kernel"] = r["roofline"]["kernel"]
+            if "plain" in r and r["plain"]:
+                d["plain_logpost_evals_per_s"] = r["plain"]["logpost_evals_per_s"]
+            res[name] = d
+        except Exception as e:  # noqa: BLE001 -- a report, the headline line stands
+            res[name] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.synchronize()
+    return res
 
 
 if __name__ == "__main__":
