@@ -160,3 +160,56 @@ def test_arrivals_join_running_jobs(torch_mod, oracle_mod):
     say("long", a, "short", b)
     assert a["status"] == JOB_DONE and b["status"] == JOB_DONE
     assert b["t_admit"] < a["t_done"] and b["t_done"] < a["t_done"]
+
+
+def test_mixed_surface_counts_and_request_errors(torch_mod, oracle_mod):
+    """Jobs with 2 and 3 surfaces share a server (one batched launch group per
+    surface count); each equals its run alone.  Invalid requests are refused
+    at submission, unknown ids and early releases are errors."""
+    from paper_2603_28907_amd.binding import JOB_DONE, MuonCaveError, Server
+    from tests.helpers import make_scenario
+    t = inputs.tiny_bumps(seed=4)
+    s2 = make_scenario(2, t.n_rows, t.n_cols, t.extent_x, t.extent_y, t.truth[:1], t.top, (1.8, 2.7),
+                       t.sensor_pos, t.dirs, car_r=t.car_r[:1])
+    s2.counts = oracle_mod.make_counts(s2, seed=5)
+    s3 = inputs.tiny_bumps(seed=6)
+    s3.counts = oracle_mod.make_counts(s3, seed=7)
+    from paper_2603_28907_amd.binding import JOB_RUNNING
+    runs = []
+    for mix in (False, True):
+        srv = Server(precision="f32", max_jobs=4, steps_per_round=10)
+        b = None
+        if mix:   # a long 3-surface job is running when the 2-surface one arrives
+            b = srv.submit(s3, 8, 600, 0.05, 12)
+            _wait_status(srv, b, JOB_RUNNING)
+        a = srv.submit(s2, 8, 30, 0.05, 11)
+        srv.wait_idle(120)
+        ra = srv.poll(a)
+        rb = srv.poll(b) if mix else None
+        if mix:
+            with pytest.raises(MuonCaveError, match="n_chains"):
+                srv.submit(s3, 0, 30, 0.05, 1)
+            with pytest.raises(MuonCaveError, match="unknown"):
+                srv.release(10 ** 9)
+            st = srv.stats()
+            assert st["max_resident"] == 2
+        srv.close()
+        assert ra["status"] == JOB_DONE and (rb is None or rb["status"] == JOB_DONE)
+        runs.append(ra)
+    for k in ("mean", "std", "map_state"):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+    assert runs[0]["accept_rate"] == runs[1]["accept_rate"] and 0 < runs[0]["accept_rate"] < 1
+
+
+def test_release_before_done_is_refused(torch_mod, oracle_mod):
+    from paper_2603_28907_amd.binding import JOB_DONE, MuonCaveError, Server
+    sc = inputs.tiny_bumps(seed=8)
+    sc.counts = oracle_mod.make_counts(sc, seed=9)
+    srv = Server(precision="f32", max_jobs=1, steps_per_round=10)
+    j = srv.submit(sc, 8, 2000, 0.05, 3)
+    with pytest.raises(MuonCaveError, match="not finished"):
+        srv.release(j)
+    srv.wait_idle(120)
+    assert srv.poll(j, arrays=False)["status"] == JOB_DONE
+    srv.release(j)
+    srv.close()
