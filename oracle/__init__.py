@@ -71,6 +71,8 @@ def _load():
         "orc_normal_pair": (None, [U64, U32, U64, U32, U32, V]),
         "orc_raw_philox": (None, [U64, U32, U64, U32, U32, V]),
         "orc_mcmc_rw": (None, [P, I, V, V, V, I64, U64, D, U64, I, V]),
+        "orc_mcmc_rw_r": (None, [P, I, V, V, V, V, V, I64, U64, D, D, U64, I, V]),
+        "orc_log_prior_r": (D, [P, V, V]),
         "orc_mcmc_mala": (None, [P, I, V, V, V, I64, U64, D, V, U64, I, V]),
         "orc_march_one": (D, [P, V, V, V, V, ct.POINTER(_Stats)]),
         "orc_ray_stats": (None, [P, V, V, V, V]),
@@ -150,6 +152,10 @@ class OracleProblem:
     def log_prior(self, free) -> float:
         return float(self.lib.orc_log_prior(ct.byref(self.prob), _p(self._free(free))))
 
+    def log_prior_r(self, free, r) -> float:
+        """log p(H | r) with the per-surface dependence parameters r[S-1] given."""
+        return float(self.lib.orc_log_prior_r(ct.byref(self.prob), _p(self._free(free)), _p(_f64(r))))
+
     def log_prior_grad(self, free):
         g = np.zeros((self.S, self.R, self.C))
         v = self.lib.orc_log_prior_grad(ct.byref(self.prob), _p(self._free(free)), _p(g))
@@ -202,6 +208,22 @@ class OracleProblem:
         self.lib.orc_mcmc_rw(ct.byref(self.prob), n, _p(s), _p(lpa), _p(acc), int(n_steps),
                              int(step_offset), float(sigma), int(seed), int(bool(state_f32)), _p(marg))
         return s.reshape(np.shape(states)), lpa, acc, marg
+
+    def mcmc_rw_r(self, states, r, lp, n_accept, n_steps, step_offset, sigma, tau, seed, n_accept_r=None,
+                  state_f32=False, want_margins=False):
+        """RW on H with Metropolis-within-Gibbs updates of r (logit scale, step tau).
+        Returns (states, r, lp, n_accept, n_accept_r, margins [n, n_steps, S])."""
+        s = _f64(states).copy()
+        n = s.size // self.M
+        rr = _f64(r).reshape(n, self.S - 1).copy()
+        lpa = _f64(lp).copy()
+        acc = np.ascontiguousarray(n_accept, dtype=np.int64).copy()
+        accr = (np.zeros((n, self.S - 1), np.int64) if n_accept_r is None
+                else np.ascontiguousarray(n_accept_r, dtype=np.int64).reshape(n, self.S - 1).copy())
+        marg = np.empty((n, n_steps, self.S)) if want_margins else None
+        self.lib.orc_mcmc_rw_r(ct.byref(self.prob), n, _p(s), _p(rr), _p(lpa), _p(acc), _p(accr), int(n_steps),
+                               int(step_offset), float(sigma), float(tau), int(seed), int(bool(state_f32)), _p(marg))
+        return s.reshape(np.shape(states)), rr, lpa, acc, accr, marg
 
     def mcmc_mala(self, states, lp, n_accept, n_steps, step_offset, eps, seed, inv_mass=None,
                   state_f32=False, want_margins=False):

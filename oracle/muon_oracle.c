@@ -325,7 +325,19 @@ void orc_car_consts(int R, int C, double r, double *logdet, double *sigma11) {
  * support 0 < H_1 < ... < H_{S-1} < H_top give -inf.
  * If grad is non-NULL ([S][R][C]), the gradient is added to it.
  */
+static double log_prior_grad_r(const orc_problem *p, const double *free_h, const double *r_vals, double *grad);
+
 double orc_log_prior_grad(const orc_problem *p, const double *free_h, double *grad) {
+    return log_prior_grad_r(p, free_h, p->car_r, grad);
+}
+
+/* The same density with the dependence parameters r_vals[S-1] given
+   explicitly (the hierarchical model treats them as unknowns). */
+double orc_log_prior_r(const orc_problem *p, const double *free_h, const double *r_vals) {
+    return log_prior_grad_r(p, free_h, r_vals, NULL);
+}
+
+static double log_prior_grad_r(const orc_problem *p, const double *free_h, const double *r_vals, double *grad) {
     const int R = p->R, C = p->C, N = R * C;
     double total = 0.0;
     double *w = (double *)malloc(sizeof(double) * N);
@@ -335,7 +347,7 @@ double orc_log_prior_grad(const orc_problem *p, const double *free_h, double *gr
         const double *H = free_h + (size_t)l * N;
         const double *A = (l == 0) ? NULL : free_h + (size_t)(l - 1) * N;
         double logdet, s11;
-        double r = p->car_r[l];
+        double r = r_vals[l];
         orc_car_consts(R, C, r, &logdet, &s11);
         double s = sqrt(s11);
         double sum_w2 = 0.0, sum_logd = 0.0;
@@ -520,7 +532,7 @@ void orc_raw_philox(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, 
 /* MCMC: random-walk Metropolis and MALA                                       */
 /* ------------------------------------------------------------------------- */
 
-enum { TAG_PROPOSAL = 0, TAG_ACCEPT = 1, TAG_MOMENTUM = 2 };
+enum { TAG_PROPOSAL = 0, TAG_ACCEPT = 1, TAG_MOMENTUM = 2, TAG_R_PROPOSAL = 3, TAG_R_ACCEPT = 4 };
 
 static double round_state(double x, int state_f32) { return state_f32 ? (double)(float)x : x; }
 
@@ -629,6 +641,106 @@ void orc_mcmc_mala(const orc_problem *p, int n_chains, double *free_all, double 
 }
 
 /* Single-ray march exposed for tests: returns O, fills L[S] and stats. */
+/*
+ * Random-walk Metropolis on the free surfaces and, within each step, on the
+ * hierarchical dependence parameters r_l of the CAR layers (Sec. 2.2.1:
+ * r_l iid Uniform(0, 1) a priori).  Step k of chain c:
+ *   1. H-update: as orc_mcmc_rw, with the chain's own r in the prior;
+ *   2. for each free surface l in order: eta = logit(r_l), eta' = eta + tau z
+ *      (z: component l % 2 of normal pair l / 2 of tag 3), r' = 1/(1+e^-eta');
+ *      the target density of eta is p(C | H) p(H | r) r (1 - r) (the uniform
+ *      prior carried to eta), so
+ *        log alpha = log p(H | r') - log p(H | r) + log(r'(1-r')) - log(r(1-r))
+ *      (the likelihood does not depend on r); accept iff log U < log alpha with
+ *      U the first uniform of pair l of tag 4; a proposal that rounds to 0 or
+ *      1 is rejected.
+ * r_all: [n_chains][S-1] in/out; n_acc_r: [n_chains][S-1] in/out (may be NULL);
+ * lp: the log posterior log p(C|H) + log p(H|r), NaN entries computed first.
+ * margins (optional, [n_chains][n_steps][S]): |log U - log alpha| of the
+ * H decision and of each r decision.
+ */
+void orc_mcmc_rw_r(const orc_problem *p, int n_chains, double *free_all, double *r_all, double *lp,
+                   int64_t *n_acc, int64_t *n_acc_r, int64_t n_steps, uint64_t step_offset, double sigma,
+                   double tau, uint64_t seed, int state_f32, double *margins) {
+    const int S1 = p->S - 1;
+    size_t M = (size_t)S1 * p->R * p->C;
+    const int n_ray = p->n_s * p->n_pix;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < n_chains; ++c) {
+        double *H = free_all + M * c;
+        double *r = r_all + (size_t)S1 * c;
+        double *prop = (double *)malloc(sizeof(double) * M);
+        double *O = n_ray ? (double *)malloc(sizeof(double) * n_ray) : NULL;
+        if (isnan(lp[c])) {
+            double pr = orc_log_prior_r(p, H, r);
+            double ll = 0.0;
+            if (pr > -INFINITY && n_ray) {
+                orc_opacity(p, H, O, NULL, NULL);
+                ll = orc_loglik(p, O);
+            }
+            lp[c] = pr + ll;
+        }
+        for (int64_t k = 0; k < n_steps; ++k) {
+            uint64_t step = step_offset + (uint64_t)k;
+            double *mg = margins ? margins + ((size_t)c * n_steps + k) * (S1 + 1) : NULL;
+            /* 1. H */
+            for (size_t i = 0; i < M; i += 2) {
+                double z[2];
+                orc_normal_pair(seed, (uint32_t)c, step, TAG_PROPOSAL, (uint32_t)(i / 2), z);
+                prop[i] = round_state(H[i] + sigma * z[0], state_f32);
+                if (i + 1 < M) prop[i + 1] = round_state(H[i + 1] + sigma * z[1], state_f32);
+            }
+            double lpp = orc_log_prior_r(p, prop, r);
+            if (lpp > -INFINITY && n_ray) {
+                orc_opacity(p, prop, O, NULL, NULL);
+                lpp += orc_loglik(p, O);
+            }
+            double u[2];
+            orc_uniform_pair(seed, (uint32_t)c, step, TAG_ACCEPT, 0, u);
+            double la = lpp - lp[c], lu = log(u[0]);
+            if (mg) mg[0] = fabs(lu - la);
+            if (lu < la) {
+                memcpy(H, prop, sizeof(double) * M);
+                lp[c] = lpp;
+                n_acc[c] += 1;
+            }
+            /* 2. r_l, one surface at a time */
+            for (int l = 0; l < S1; ++l) {
+                double z[2];
+                orc_normal_pair(seed, (uint32_t)c, step, TAG_R_PROPOSAL, (uint32_t)(l / 2), z);
+                double rl = r[l];
+                double eta = log(rl / (1.0 - rl)) + tau * z[l % 2];
+                double rn = 1.0 / (1.0 + exp(-eta));
+                double la_r = -INFINITY, d_prior = 0.0;
+                if (rn > 0.0 && rn < 1.0) {
+                    const double jac = log(rn * (1.0 - rn)) - log(rl * (1.0 - rl));
+                    if (lp[c] > -INFINITY) {
+                        double p0 = orc_log_prior_r(p, H, r);
+                        r[l] = rn;
+                        double p1 = orc_log_prior_r(p, H, r);
+                        r[l] = rl;
+                        d_prior = p1 - p0;
+                    }
+                    /* a state outside the support has p(H | r) = 0 for every r:
+                       there r moves under its prior alone and lp stays -inf */
+                    la_r = d_prior + jac;
+                }
+                double ur[2];
+                orc_uniform_pair(seed, (uint32_t)c, step, TAG_R_ACCEPT, (uint32_t)l, ur);
+                double lur = log(ur[0]);
+                if (mg) mg[1 + l] = fabs(lur - la_r);
+                if (lur < la_r) {
+                    r[l] = rn;
+                    lp[c] += d_prior;
+                    if (n_acc_r) n_acc_r[(size_t)S1 * c + l] += 1;
+                }
+            }
+        }
+        free(prop);
+        free(O);
+    }
+}
+
 double orc_march_one(const orc_problem *p, const double *free_h, const double q[3], const double d[3],
                      double *L, orc_stats *st) {
     double *surf = stack_surfaces(p, free_h);
