@@ -140,6 +140,10 @@ typedef struct {
     uint64_t seed;          /* Philox4x32-10 key */
     uint64_t step_offset;   /* steps already taken: a resumed run uses the same seed
                                and offset = steps done, and is bitwise identical */
+    double *r_state;        /* device [n_chains][S-1] float64 in (0, 1), in/out, or NULL:
+                               sample each chain's CAR dependence parameters too */
+    double r_step;          /* sd of the r proposal on the logit scale (r_state set) */
+    int64_t *n_accept_r;    /* device [n_chains][S-1] int64 in/out (r accepts), or NULL */
 } mc_run_config;
 
 /*
@@ -151,7 +155,18 @@ typedef struct {
  *   n_accept: device, [n_chains] int64, in/out (incremented per acceptance).
  * Random numbers: Philox4x32-10 keyed by `seed`, counter (j, step lo32,
  * step hi16 | tag << 16, chain) with tag 0 = RW proposal normals,
- * 1 = accept uniform, 2 = MALA normals; chain = index in this call.
+ * 1 = accept uniform, 2 = MALA normals, 3 = r proposal normals, 4 = r
+ * accept uniforms; chain = index in this call.
+ *
+ * Hierarchical dependence (paper Sec. 2.2.1: r_l iid Uniform(0, 1) a
+ * priori): with cfg->r_state set (random-walk only), every step is followed
+ * by one Metropolis update of each r_l of each chain on the logit scale,
+ * eta' = logit(r_l) + r_step * z (z: component l % 2 of normal pair l / 2 of
+ * tag 3), accepted with probability
+ *   min(1, p(H | r') r'(1 - r') / (p(H | r) r(1 - r)))
+ * (first uniform of pair l of tag 4; a state outside the support moves r
+ * under its prior alone).  logpost then holds log p(C | H) + log p(H | r)
+ * with each chain's own r, and is recomputed for every chain on entry.
  */
 mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *heights,
                    double *logpost, int64_t *n_accept, void *stream);

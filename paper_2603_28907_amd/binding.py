@@ -38,7 +38,8 @@ class Tuning(ct.Structure):
 class RunConfig(ct.Structure):
     _fields_ = [("kernel", ct.c_int), ("n_steps", ct.c_int64), ("graph_steps", ct.c_int),
                 ("step_size", ct.c_double), ("inv_mass", ct.c_void_p), ("seed", ct.c_uint64),
-                ("step_offset", ct.c_uint64)]
+                ("step_offset", ct.c_uint64), ("r_state", ct.c_void_p), ("r_step", ct.c_double),
+                ("n_accept_r", ct.c_void_p)]
 
 
 class ServerConfig(ct.Structure):
@@ -280,7 +281,7 @@ class Problem:
         return logpost, grad
 
     def mcmc_run(self, heights, logpost, n_accept, n_steps, step_size, seed, step_offset=0, kernel=KERNEL_RW,
-                 graph_steps=1, inv_mass=None, stream=None):
+                 graph_steps=1, inv_mass=None, stream=None, r_state=None, r_step=0.0, n_accept_r=None):
         import torch
         n = int(heights.shape[0])
         self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
@@ -290,8 +291,15 @@ class Problem:
         if inv_mass is not None:
             self._check_tensor(inv_mass, (self.S - 1, self.R, self.C), torch.float64, "inv_mass")
             im = inv_mass.data_ptr()
+        rs = ar = None
+        if r_state is not None:
+            self._check_tensor(r_state, (n, self.S - 1), torch.float64, "r_state")
+            rs = r_state.data_ptr()
+        if n_accept_r is not None:
+            self._check_tensor(n_accept_r, (n, self.S - 1), torch.int64, "n_accept_r")
+            ar = n_accept_r.data_ptr()
         cfg = RunConfig(int(kernel), int(n_steps), int(graph_steps), float(step_size), im, int(seed),
-                        int(step_offset))
+                        int(step_offset), rs, float(r_step), ar)
         self._check(self.lib.mcmc_run(self.h, ct.byref(cfg), n, ct.c_void_p(heights.data_ptr()),
                                       ct.c_void_p(logpost.data_ptr()), ct.c_void_p(n_accept.data_ptr()),
                                       _stream_handle(stream, self.device)))
@@ -321,7 +329,7 @@ def mcmc_run_multi(problems, heights, logposts, n_accepts, n_steps, step_sizes, 
         pr._check_tensor(n_accepts[i], (c,), torch.int64, f"n_accepts[{i}]")
         hs[i] = pr.h
         cfgs[i] = RunConfig(KERNEL_RW, int(n_steps), int(graph_steps), float(step_sizes[i]), None, int(seeds[i]),
-                            int(offs[i]))
+                            int(offs[i]), None, 0.0, None)
         nch[i] = c
         hp[i], lpp[i], ap[i] = heights[i].data_ptr(), logposts[i].data_ptr(), n_accepts[i].data_ptr()
     st = lib.mcmc_run_multi(n, hs, cfgs, nch, hp, lpp, ap, _stream_handle(stream, problems[0].device))

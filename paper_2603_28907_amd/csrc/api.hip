@@ -44,11 +44,13 @@ struct DevBuf {
 struct GraphKey {
     int n = -1, kernel = -1, G = 0;
     const void *heights = nullptr, *lp = nullptr, *acc = nullptr, *inv_mass = nullptr;
-    double step_size = 0;
+    const void *r_state = nullptr, *acc_r = nullptr;
+    double step_size = 0, r_step = 0;
     uint64_t seed = 0;
     bool operator==(const GraphKey &o) const {
         return n == o.n && kernel == o.kernel && G == o.G && heights == o.heights && lp == o.lp &&
-               acc == o.acc && inv_mass == o.inv_mass && step_size == o.step_size && seed == o.seed;
+               acc == o.acc && inv_mass == o.inv_mass && step_size == o.step_size && seed == o.seed &&
+               r_state == o.r_state && acc_r == o.acc_r && r_step == o.r_step;
     }
 };
 
@@ -78,6 +80,8 @@ struct mc_problem {
     double sum_log_top = 0;   // sum of log(top) over the nodes, in node order
     std::vector<double> density, top, car_r, logdet, s11;
     void *d_top = nullptr;      // [N] in prec
+    double *d_eig_g = nullptr, *d_eig_w = nullptr;   // distinct torus eigenvalue terms, multiplicities
+    int n_eig = 0;
     double *d_top64 = nullptr;  // [N] f64
     // sensors
     int n_s = 0, n_pix = 0, n_ray = 0;
@@ -89,6 +93,7 @@ struct mc_problem {
     double kconst = 0.0;
     // workspaces (grow only)
     DevBuf partials, prop, lptmp;
+    DevBuf rstat;   // [2][n][S-1] sum w^2 and edge sums of the current states (r sampling)
     DevBuf obuf, gfix, gprior, gcur, gprop, lpprop;   // gradient and MALA workspaces
     uint64_t *d_step = nullptr;
     mc_tuning tune = {2, 256, 4, 4, 1};
@@ -437,6 +442,9 @@ PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double 
         P.r[l] = p->car_r[l];
     }
     P.sum_log_top = p->sum_log_top;
+    P.eig_g = p->d_eig_g;
+    P.eig_w = p->d_eig_w;
+    P.n_eig = p->n_eig;
     P.partials = partials;
     P.kconst = p->kconst;
     return P;
@@ -444,7 +452,7 @@ PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double 
 
 template <typename T, int S, int B>
 void launch_prior_shape(int n, size_t lds, const PriorParams<T> &P, hipStream_t st) {
-    auto k = k_prior_finalize<T, S, B>;
+    auto k = P.r_chain ? k_prior_finalize<T, S, B, true> : k_prior_finalize<T, S, B, false>;
     if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(n), dim3(B), lds, st, P);
 }
@@ -466,9 +474,11 @@ mc_status check_ready(mc_problem *p) {
     return MC_OK;
 }
 
+// r_chain ([n][S-1], optional): per-chain dependence parameters; stat
+// (optional, [2][n][S-1]): receives sum w^2 and the edge sums.
 template <typename T, int S>
 mc_status logpost_impl(mc_problem *p, int n, const T *heights, double *lp, T *opacity, hipStream_t st,
-                       const double *only_nan = nullptr) {
+                       const double *only_nan = nullptr, double *r_chain = nullptr, double *stat = nullptr) {
     Tiling t = tiling(p);
     mc_status s;
     if (p->n_ray > 0) {
@@ -479,6 +489,11 @@ mc_status logpost_impl(mc_problem *p, int n, const T *heights, double *lp, T *op
     PriorParams<T> P = prior_params<T>(p, heights, (const double *)p->partials.p);
     P.lp_out = lp;
     P.only_nan = only_nan;
+    P.r_chain = r_chain;
+    if (stat) {
+        P.stat_sw2 = stat;
+        P.stat_se = stat + (size_t)n * (S - 1);
+    }
     return launch_prior<T, S>(p, n, P, st);
 }
 
@@ -677,6 +692,14 @@ mc_status rw_step(mc_problem *p, int n, T *heights, double *lp, int64_t *acc, co
     P.seed = cfg->seed;
     P.step_base = p->d_step;
     P.step_k = k;
+    if (cfg->r_state) {
+        P.r_chain = cfg->r_state;
+        P.sample_r = 1;
+        P.r_step = cfg->r_step;
+        P.n_acc_r = cfg->n_accept_r;
+        P.stat_sw2 = (double *)p->rstat.p;
+        P.stat_se = (double *)p->rstat.p + (size_t)n * (S - 1);
+    }
     return launch_prior<T, S>(p, n, P, st);
 }
 
@@ -698,6 +721,12 @@ mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, 
         if ((s = ensure(p, p->lpprop, sizeof(double) * (size_t)n)) != MC_OK) return s;
         // MALA needs the gradient of the current states: lp and gradient are recomputed
         if ((s = grad_eval<T, S>(p, n, heights, lp, (T *)p->gcur.p, st)) != MC_OK) return s;
+    } else if (cfg->r_state) {
+        // with r sampled: log posterior and the w-statistics of every chain at its own r
+        if ((s = ensure(p, p->rstat, 2 * sizeof(double) * (size_t)n * (S - 1))) != MC_OK) return s;
+        if ((s = logpost_impl<T, S>(p, n, heights, lp, nullptr, st, nullptr, cfg->r_state, (double *)p->rstat.p)) !=
+            MC_OK)
+            return s;
     } else {
         // initial log posterior where the caller passed NaN (other chains exit at once)
         if ((s = logpost_impl<T, S>(p, n, heights, (double *)p->lptmp.p, nullptr, st, lp)) != MC_OK) return s;
@@ -721,6 +750,9 @@ mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, 
         key.inv_mass = cfg->inv_mass;
         key.step_size = cfg->step_size;
         key.seed = cfg->seed;
+        key.r_state = cfg->r_state;
+        key.acc_r = cfg->n_accept_r;
+        key.r_step = cfg->r_step;
         if (!(p->gexec && p->gkey == key)) {
             if (p->gexec) {
                 (void)hipGraphExecDestroy(p->gexec);
@@ -1264,6 +1296,8 @@ void mc_destroy(mc_problem *p) {
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     free_ptr(p->d_top);
     free_ptr(p->d_top64);
+    free_ptr(p->d_eig_g);
+    free_ptr(p->d_eig_w);
     free_ptr(p->d_sensor);
     free_ptr(p->d_dx);
     free_ptr(p->d_dy);
@@ -1272,7 +1306,7 @@ void mc_destroy(mc_problem *p) {
     free_ptr(p->d_coL);
     for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
     for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gprior, &p->gcur, &p->gprop,
-                      &p->lpprop})
+                      &p->lpprop, &p->rstat})
         if (b->p) (void)hipFree(b->p);
     if (p->d_step) (void)hipFree(p->d_step);
     delete p;
@@ -1319,6 +1353,26 @@ mc_status load_geometry_grid(mc_problem *p, int n_surfaces, int n_rows, int n_co
     p->s11.resize(n_surfaces - 1);
     for (int l = 0; l < n_surfaces - 1; ++l) torus_car_constants(n_rows, n_cols, car_r[l], p->logdet[l], p->s11[l]);
     mc_status s;
+    {
+        // distinct g = cos(2 pi k/R) + cos(2 pi m/C) over k <= R/2, m <= C/2 with
+        // multiplicities (k and R-k give the same cosine), for per-chain r
+        std::vector<double> eg, ew;
+        for (int k = 0; k <= n_rows / 2; ++k) {
+            const double wk = (k == 0 || 2 * k == n_rows) ? 1.0 : 2.0;
+            for (int m = 0; m <= n_cols / 2; ++m) {
+                const double wm = (m == 0 || 2 * m == n_cols) ? 1.0 : 2.0;
+                eg.push_back(std::cos(2.0 * M_PI * k / n_rows) + std::cos(2.0 * M_PI * m / n_cols));
+                ew.push_back(wk * wm);
+            }
+        }
+        void *q = p->d_eig_g;
+        if ((s = upload<double>(p, q, eg)) != MC_OK) return s;
+        p->d_eig_g = (double *)q;
+        q = p->d_eig_w;
+        if ((s = upload<double>(p, q, ew)) != MC_OK) return s;
+        p->d_eig_w = (double *)q;
+        p->n_eig = (int)eg.size();
+    }
     if ((s = upload_prec(p, p->d_top, p->top)) != MC_OK) return s;
     void *t64 = p->d_top64;
     if ((s = upload<double>(p, t64, p->top)) != MC_OK) return s;
@@ -1462,6 +1516,9 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
     if (!heights || !logpost || !n_accept) return fail(p, MC_ERR_ARG, "NULL device pointer");
     if (!(cfg->step_size >= 0) || !std::isfinite(cfg->step_size)) return fail(p, MC_ERR_ARG, "step_size invalid");
     if (cfg->kernel != 0 && cfg->kernel != 1) return fail(p, MC_ERR_ARG, "kernel %d", cfg->kernel);
+    if (cfg->r_state && cfg->kernel != 0) return fail(p, MC_ERR_UNSUPPORTED, "r sampling runs with random-walk Metropolis");
+    if (cfg->r_state && (!(cfg->r_step >= 0) || !std::isfinite(cfg->r_step))) return fail(p, MC_ERR_ARG, "r_step invalid");
+    if (cfg->n_accept_r && !cfg->r_state) return fail(p, MC_ERR_ARG, "n_accept_r without r_state");
     if (cfg->step_offset + (uint64_t)cfg->n_steps >= (1ULL << 48)) return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
@@ -1486,6 +1543,7 @@ mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_r
         for (int j = 0; j < i; ++j)
             if (problems[j] == p) return fail(e, MC_ERR_ARG, "problem %d repeats problem %d", i, j);
         if (cfgs[i].kernel != 0) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi runs random-walk Metropolis");
+        if (cfgs[i].r_state) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi samples with fixed r");
         if (cfgs[i].n_steps != cfgs[0].n_steps || cfgs[i].graph_steps != cfgs[0].graph_steps)
             return fail(e, MC_ERR_ARG, "n_steps and graph_steps must be equal across problems");
         if (!(cfgs[i].step_size >= 0) || !std::isfinite(cfgs[i].step_size)) return fail(e, MC_ERR_ARG, "step_size");

@@ -26,7 +26,7 @@ __device__ __forceinline__ bool xcd_chain_tile(int n_tiles, int n_chains, int &c
     return chain < n_chains;
 }    // S (including the fixed top) supported by the kernels
 
-enum RngTag : uint32_t { kTagProposal = 0, kTagAccept = 1, kTagMala = 2 };
+enum RngTag : uint32_t { kTagProposal = 0, kTagAccept = 1, kTagMala = 2, kTagRProposal = 3, kTagRAccept = 4 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
 // 32x32->64-bit multiplications whose high halves are mixed with the other

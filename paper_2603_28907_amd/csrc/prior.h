@@ -37,7 +37,39 @@ struct PriorParams {
     uint64_t seed;
     const uint64_t *step_base;
     int step_k;
+    // Hierarchical r (Sec. 2.2.1, r_l ~ Uniform(0, 1)): with r_chain set the
+    // CAR constants come per chain from the torus eigenvalue table, and in
+    // Metropolis mode with sample_r each r_l takes a logit-scale Metropolis
+    // step after the H decision.
+    double *r_chain;                   // [n][S-1] or null (problem r)
+    const double *eig_g, *eig_w;       // distinct cos(2 pi k/R) + cos(2 pi m/C), multiplicities
+    int n_eig;
+    double *stat_sw2, *stat_se;        // [n][S-1] sum w^2 and edge sum of the current states
+    int sample_r;
+    double r_step;
+    int64_t *n_acc_r;                  // [n][S-1] or null
 };
+
+// log det Q(r) and Sigma_11(r) on the R x C torus from its eigenvalues
+// mu = 4 - 2 r g (g over the distinct values with their multiplicities),
+// summed by the whole block in a fixed order.
+template <typename T, int BLOCK>
+__device__ __forceinline__ void car_consts_block(const PriorParams<T> &P, double r, int N, double *red,
+                                                 double &logdet, double &s11) {
+    double sl = 0.0, si = 0.0;
+    for (int k = threadIdx.x; k < P.n_eig; k += BLOCK) {
+        const double mu = 4.0 - 2.0 * r * P.eig_g[k];
+        sl += P.eig_w[k] * log(mu);
+        si += P.eig_w[k] / mu;
+    }
+    logdet = block_sum<BLOCK>(sl, red);
+    s11 = block_sum<BLOCK>(si, red) / (double)N;
+}
+
+// The r-dependent part of log p(H_l | H_{l-1}, r) given sum w^2 and the edge sum.
+__device__ __forceinline__ double car_r_terms(double r, double logdet, double s11, double sw2, double se, int N) {
+    return 0.5 * logdet - 0.5 * s11 * (4.0 * (1.0 - r) * sw2 + r * se) + 0.5 * N * log(s11);
+}
 
 // Threads per prior block: grids of 8192 nodes and more use 1024 so that a
 // block whose workspace fills much of the LDS still keeps 16 wavefronts.
@@ -58,12 +90,16 @@ __device__ __attribute__((noinline)) double probit_uv(double u, double v) {
 // state precision T (the Phi^-1 values are formed and summed in float64; the
 // copy kept for the neighbour differences is rounded to T, which in float32
 // mode is far below the float32 march's own rounding and halves the LDS a
-// block holds).
-template <typename T, int S, int BLOCK>
+// block holds).  HIER: every chain carries its own r (P.r_chain), and in MH
+// mode r is updated after the H decision; the fixed-r instance keeps none of
+// that code (and none of its registers).
+template <typename T, int S, int BLOCK, bool HIER = false>
 __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, T *w, int step_k) {
     __shared__ double red[16];
     __shared__ int ired[16];
-    __shared__ int s_acc;
+    __shared__ int s_acc, s_fin;
+    __shared__ double s_sw2[kMaxSurfaces], s_se[kMaxSurfaces], s_ld[kMaxSurfaces], s_s11[kMaxSurfaces],
+        s_r[kMaxSurfaces];
     const int tid = threadIdx.x;
     if (P.only_nan && !(P.only_nan[c] != P.only_nan[c])) return;
     const int R = P.R, C = P.C, N = R * C;
@@ -103,11 +139,27 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, T *w
         const double SW2 = block_sum<BLOCK>(sw2, red);
         const double SLD = block_sum<BLOCK>(sld, red);
         const double SE = block_sum<BLOCK>(se, red);
-        const double r = P.r[l], s11 = P.s11[l];
-        lp += 0.5 * P.logdet[l] - 0.5 * s11 * (4.0 * (1.0 - r) * SW2 + r * SE) + 0.5 * N * log(s11) +
-              0.5 * SW2 - SLD;
+        double r = P.r[l], ld = P.logdet[l], s11 = P.s11[l];
+        if (HIER) {
+            r = P.r_chain[(size_t)c * (S - 1) + l];
+            car_consts_block<T, BLOCK>(P, r, N, red, ld, s11);
+        }
+        lp += car_r_terms(r, ld, s11, SW2, SE, N) + 0.5 * SW2 - SLD;
+        if (tid == 0) {
+            s_sw2[l] = SW2;
+            s_se[l] = SE;
+            s_ld[l] = ld;
+            s_s11[l] = s11;
+            s_r[l] = r;
+        }
     }
     ok = block_and<BLOCK>(ok, ired);
+    if (HIER && !P.mh && P.stat_sw2 && tid == 0) {
+        for (int l = 0; l < S - 1; ++l) {
+            P.stat_sw2[(size_t)c * (S - 1) + l] = s_sw2[l];
+            P.stat_se[(size_t)c * (S - 1) + l] = s_se[l];
+        }
+    }
     if (tid == 0) {
         double ll = 0.0;
         if (P.has_lik) {
@@ -128,6 +180,7 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, T *w
                 P.n_acc[c] += 1;
             }
             s_acc = acc;
+            s_fin = P.lp_cur[c] > -__builtin_huge_val();
         }
     }
     if (P.mh) {
@@ -137,13 +190,49 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, T *w
             T *dst = P.state + (size_t)c * M;
             for (int n = tid; n < M; n += BLOCK) dst[n] = H[n];
         }
+        if (HIER && P.sample_r) {
+            // r_l given the current H, one surface at a time
+            const uint64_t step = *P.step_base + (uint64_t)step_k;
+#pragma unroll 1
+            for (int l = 0; l < S - 1; ++l) {
+                const size_t at = (size_t)c * (S - 1) + l;
+                const double sw2 = s_acc ? s_sw2[l] : P.stat_sw2[at];
+                const double se = s_acc ? s_se[l] : P.stat_se[at];
+                const double r = s_r[l];
+                double z0, z1;
+                rng_normal2(P.seed, (uint32_t)c, step, kTagRProposal, (uint32_t)(l / 2), z0, z1);
+                const double rn = 1.0 / (1.0 + exp(-(log(r / (1.0 - r)) + P.r_step * ((l & 1) ? z1 : z0))));
+                double la = -__builtin_huge_val(), dlp = 0.0;
+                if (rn > 0.0 && rn < 1.0) {   // uniform across the block
+                    double ldn, s11n;
+                    car_consts_block<T, BLOCK>(P, rn, N, red, ldn, s11n);
+                    if (s_fin)
+                        dlp = car_r_terms(rn, ldn, s11n, sw2, se, N) - car_r_terms(r, s_ld[l], s_s11[l], sw2, se, N);
+                    la = dlp + log(rn * (1.0 - rn)) - log(r * (1.0 - r));
+                }
+                if (tid == 0) {
+                    const double u = rng_uniform(P.seed, (uint32_t)c, step, kTagRAccept, (uint32_t)l);
+                    if (log(u) < la) {
+                        P.r_chain[at] = rn;
+                        if (s_fin) P.lp_cur[c] += dlp;
+                        if (P.n_acc_r) P.n_acc_r[at] += 1;
+                    }
+                }
+            }
+            if (tid == 0 && s_acc) {
+                for (int l = 0; l < S - 1; ++l) {
+                    P.stat_sw2[(size_t)c * (S - 1) + l] = s_sw2[l];
+                    P.stat_se[(size_t)c * (S - 1) + l] = s_se[l];
+                }
+            }
+        }
     }
 }
 
-template <typename T, int S, int BLOCK>
+template <typename T, int S, int BLOCK, bool HIER>
 __global__ __launch_bounds__(BLOCK, 4) void k_prior_finalize(PriorParams<T> P) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    prior_block<T, S, BLOCK>(P, blockIdx.x, reinterpret_cast<T *>(smem_raw), P.step_k);
+    prior_block<T, S, BLOCK, HIER>(P, blockIdx.x, reinterpret_cast<T *>(smem_raw), P.step_k);
 }
 
 // Random-walk proposal: prop = H + sigma z, z_i the (i%2)-th normal of pair
