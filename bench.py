@@ -9,11 +9,13 @@ sums, HIP graphs of 50 steps.  Inputs are seeded synthetic stand-ins for the
 paper's (unpublished) cave model and sensor layout; counts are Poisson draws
 from the library's own forward model at the synthetic truth.
 
-Prints one JSON line (see README/DESIGN): value = ray-opacity evaluations
-per second over the timed steps; the line also carries log-posterior
+Prints one JSON line: value = ray-opacity evaluations per second over the
+timed steps; the line also carries log-posterior
 evaluations per second, the roofline of the ray-march kernel (timed alone
 with HIP events on the benchmark's stream) and the FP64 CPU oracle timed on a
-bounded sample on the host cores.
+bounded sample on the host cores.  Other workloads (--workload hetero,
+grad128, hier, serve) print their own line; by default a short run of each is
+summarised under "workloads" on the headline line.
 """
 from __future__ import annotations
 
@@ -37,7 +39,7 @@ METRIC = ("ray-opacity evals/s + log-posterior evals/s (chains) at 1 GPU; p50/p9
 #   per ray: 40 set-up (exit parameter, band window, cell of entry) + 40 for
 #   the float64 Poisson term (exp, 2 FMA, accumulate).
 # Cells and crossings per ray are the oracle's exact counts on this workload
-# (18.93 and 2.94 per ray over 8 initial states).
+# (18.93 and 2.94 per ray, averaged over 8 initial chain states).
 OPS_CELL_BASE, OPS_TEST, OPS_CROSS, OPS_RAY = 8.0, 9.0, 45.0, 80.0
 WORKLOAD_COUNTS = {"grf_cave_64": dict(cells=18.93, crossings=2.94, S=3),
                    "grf_cave_128": dict(cells=37.24, crossings=2.92, S=3)}
@@ -297,6 +299,60 @@ def bench_grad(args, torch):
     }
 
 
+def bench_hier(args, torch):
+    """The paper-scale workload with every chain's CAR dependence r_l sampled
+    (Metropolis-within-Gibbs on logit r after each H decision) beside the same
+    chains at fixed r: the cost of the hierarchical prior."""
+    from paper_2603_28907_amd import inputs
+    from paper_2603_28907_amd.binding import Problem
+    sc, n_chains, w = make_workload("grf_cave_64")
+    sc.counts = gpu_counts(sc, torch)
+    prob = Problem.from_scenario(sc, precision="f32")
+    S1 = sc.n_surfaces - 1
+    H0 = torch.as_tensor(inputs.init_states(sc, n_chains, seed=w["init_seed"]), dtype=torch.float32,
+                         device="cuda:0").contiguous()
+    G = max(1, min(args.graph_steps, args.steps))
+    out = {}
+    for mode in ("fixed", "sampled"):
+        H = H0.clone()
+        lp = torch.full((n_chains,), float("nan"), dtype=torch.float64, device="cuda:0")
+        acc = torch.zeros(n_chains, dtype=torch.int64, device="cuda:0")
+        kw = {}
+        if mode == "sampled":
+            r = torch.full((n_chains, S1), 0.9, dtype=torch.float64, device="cuda:0")
+            acc_r = torch.zeros((n_chains, S1), dtype=torch.int64, device="cuda:0")
+            kw = dict(r_state=r, r_step=args.r_step, n_accept_r=acc_r)
+        prob.mcmc_run(H, lp, acc, args.warmup, w["sigma"], 5, graph_steps=min(G, max(args.warmup, 1)), **kw)
+        torch.cuda.synchronize()
+        a0 = acc.clone()
+        ar0 = kw["n_accept_r"].clone() if kw else None
+        t0 = time.perf_counter()
+        prob.mcmc_run(H, lp, acc, args.steps, w["sigma"], 5, step_offset=args.warmup, graph_steps=G, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert torch.isfinite(lp).all(), "non-finite log posterior"
+        d = {"ms_per_step": dt / args.steps * 1e3, "value": n_chains * sc.n_rays * args.steps / dt,
+             "logpost_evals_per_s": n_chains * args.steps / dt,
+             "accept_rate": float((acc - a0).double().mean().item()) / args.steps}
+        if kw:
+            d["r_accept_rate"] = float((kw["n_accept_r"] - ar0).double().mean().item()) / args.steps
+            d["r_mean"] = kw["r_state"].mean(dim=0).cpu().tolist()
+        out[mode] = d
+    s = out["sampled"]
+    return {
+        "metric": METRIC, "value": s["value"], "unit": "ray-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": s["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"hier_r_64: the grf_cave_64 workload ({n_chains} chains, {sc.n_rays} rays) with "
+                               f"r_l sampled per chain (U(0,1) prior, logit step {args.r_step}, start 0.9), "
+                               f"HIP graphs of {G} steps", "chains": n_chains, "rays": sc.n_rays},
+        "logpost_evals_per_s": s["logpost_evals_per_s"], "accept_rate": s["accept_rate"],
+        "r_accept_rate": s["r_accept_rate"], "r_mean": s["r_mean"],
+        "fixed_r_ms_per_step": out["fixed"]["ms_per_step"],
+        "overhead_vs_fixed_r": s["ms_per_step"] / out["fixed"]["ms_per_step"] - 1.0,
+    }
+
+
 def bench_serve(args, torch):
     """Serving: Poisson arrivals of heterogeneous jobs (sizes as the hetero
     workload), each run to a fixed number of steps per chain; the same
@@ -386,6 +442,7 @@ def main():
     ap.add_argument("--job-steps", type=int, default=2000, help="serve: steps per chain per job")
     ap.add_argument("--max-jobs", type=int, default=64, help="serve: resident jobs at once")
     ap.add_argument("--mala-eps", type=float, default=0.004, help="grad128: MALA step size (m)")
+    ap.add_argument("--r-step", type=float, default=0.3, help="hier: step of the logit-r random walk")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the short hetero / grad128 / serve runs summarised after the headline line")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
@@ -409,6 +466,9 @@ def main():
         return
     if args.workload == "grad128":
         print(json.dumps(bench_grad(args, torch)), flush=True)
+        return
+    if args.workload == "hier":
+        print(json.dumps(bench_hier(args, torch)), flush=True)
         return
     if args.copy_calibration_mb > 0:
         src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device="cuda:0")
@@ -482,19 +542,22 @@ def main():
 
 def run_extras(args, torch):
     """Short runs of the other workloads (batched heterogeneous problems,
-    gradient sampling at 128x128, serving), summarised beside the headline
+    gradient sampling at 128x128, sampled r, serving), summarised beside the headline
     line; each is independent and a failure is reported, not raised."""
     import copy
     res = {}
     jobs = [
         ("hetero_256", bench_hetero, dict(steps=20, warmup=3, plain_steps=2, graph_steps=20, problems=256)),
         ("grad128", bench_grad, dict(steps=20, warmup=4, graph_steps=10, march_iters=5, mala_eps=0.004)),
+        ("hier_r_64", bench_hier, dict(steps=50, warmup=10, graph_steps=50, r_step=0.3)),
         ("serve_20_per_s", bench_serve, dict(rate=20.0, duration=1.0, job_steps=2000, max_jobs=8, graph_steps=50,
                                              no_plain=True)),
     ]
     keep = {
         "hetero_256": ("value", "ms_per_step", "logpost_evals_per_s", "speedup_vs_plain"),
         "grad128": ("value", "ms_per_step", "logpost_evals_per_s", "accept_rate", "gradient_evals_per_s"),
+        "hier_r_64": ("value", "ms_per_step", "fixed_r_ms_per_step", "overhead_vs_fixed_r", "accept_rate",
+                      "r_accept_rate", "r_mean"),
         "serve_20_per_s": ("value", "p50_s", "p99_s", "logpost_evals_per_s", "offered_load"),
     }
     for name, fn, over in jobs:

@@ -10,7 +10,7 @@
  * cell at a time, FP64 throughout.  Each function names the passage of the
  * paper it follows.
  *
- * Readings of the paper taken here (each is listed in the design doc):
+ * Readings of the paper taken here, where it is silent or schematic:
  *  - Geometry: vertex-centred nodes x_i = i*X/(R-1), y_j = j*Y/(C-1); row i
  *    runs along x, column j along y, H[l][i][j] in C order (Sec. 2.1.1, the
  *    array-indexing figure).  Surfaces are bilinear inside each cell.
