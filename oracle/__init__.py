@@ -38,7 +38,8 @@ class _Problem(ct.Structure):
                 ("density", ct.c_void_p), ("top", ct.c_void_p), ("car_r", ct.c_void_p),
                 ("n_s", ct.c_int), ("n_pix", ct.c_int),
                 ("pos", ct.c_void_p), ("dirs", ct.c_void_p), ("exposure", ct.c_void_p),
-                ("atten", ct.c_double), ("counts", ct.c_void_p)]
+                ("atten", ct.c_double), ("counts", ct.c_void_p),
+                ("n_z", ct.c_int), ("gamma", ct.c_double), ("vox_ref", ct.c_void_p)]
 
 
 class _Stats(ct.Structure):
@@ -76,6 +77,12 @@ def _load():
         "orc_mcmc_mala": (None, [P, I, V, V, V, I64, U64, D, V, U64, I, V]),
         "orc_march_one": (D, [P, V, V, V, V, ct.POINTER(_Stats)]),
         "orc_ray_stats": (None, [P, V, V, V, V]),
+        "orc_sigmoid": (D, [D, D]),
+        "orc_voxel_weights": (None, [P, V, I, D, V]),
+        "orc_voxel_density": (None, [P, V, I, D, V]),
+        "orc_voxel_pieces": (I, [P, I, I, V, V]),
+        "orc_voxel_loglik": (D, [P, V, V]),
+        "orc_voxel_logpost_lik": (D, [P, V, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -140,6 +147,44 @@ class OracleProblem:
             out.append(dict(cells=st.cells, tests=st.tests, roots=st.roots,
                             crossings=st.crossings, min_fprime=st.min_fprime))
         return out[0] if len(out) == 1 else tuple(out)
+
+    # -- the paper's smoothed voxel forward model, linearised ----------------
+    def _surf(self, free) -> np.ndarray:
+        return np.concatenate([self._free(free).reshape(self.S - 1, self.R, self.C), self._top[None]])
+
+    def voxel_weights(self, free, n_z: int, gamma: float = 1.0) -> np.ndarray:
+        """Normalised weights [R, C, n_z, S+1] (units 1..S, then the air)."""
+        W = np.empty((self.R, self.C, n_z, self.S + 1))
+        self.lib.orc_voxel_weights(ct.byref(self.prob), _p(self._surf(free)), int(n_z), float(gamma), _p(W))
+        return W
+
+    def voxel_density(self, free, n_z: int, gamma: float = 1.0) -> np.ndarray:
+        R = np.empty((self.R, self.C, n_z))
+        self.lib.orc_voxel_density(ct.byref(self.prob), _p(self._surf(free)), int(n_z), float(gamma), _p(R))
+        return R
+
+    def voxel_pieces(self, ray: int, n_z: int):
+        cap = self.R + self.C + n_z + 1
+        vox = np.empty(cap, np.int32)
+        ln = np.empty(cap)
+        m = self.lib.orc_voxel_pieces(ct.byref(self.prob), int(ray), int(n_z), _p(vox), _p(ln))
+        return vox[:m].copy(), ln[:m].copy()
+
+    def set_voxel_model(self, n_z: int, gamma: float = 1.0, ref_free=None):
+        """Switch the likelihood to the linearised voxel model around
+        R0 = Rhat(ref_free); n_z = 0 switches back to the exact march."""
+        if n_z <= 0:
+            self.prob.n_z, self.prob.gamma, self.prob.vox_ref = 0, 0.0, None
+            self._vox_ref = None
+            return
+        self._vox_ref = np.ascontiguousarray(self.voxel_density(ref_free, n_z, gamma))
+        self.prob.n_z, self.prob.gamma = int(n_z), float(gamma)
+        self.prob.vox_ref = _p(self._vox_ref)
+
+    def voxel_loglik(self, free, with_opacity: bool = False):
+        O = np.empty(self.n_rays)
+        ll = self.lib.orc_voxel_logpost_lik(ct.byref(self.prob), _p(self._free(free)), _p(O))
+        return (float(ll), O) if with_opacity else float(ll)
 
     def expected_counts(self, free) -> np.ndarray:
         O = self.opacity(free)

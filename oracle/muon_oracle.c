@@ -53,6 +53,11 @@ typedef struct {
     const double *exposure;   /* [n_s*n_pix] */
     double atten;             /* Lambda, in the opacity unit (g/cm^3 * m) */
     const int32_t *counts;    /* [n_s*n_pix] observed counts (may be NULL) */
+    /* Smoothed voxel forward model (Sec. 2.1.2, 2.1.4); n_z = 0 selects the
+       exact march.  vox_ref = Rhat(H_ref) [R][C][n_z], the linearisation point. */
+    int n_z;
+    double gamma;
+    const double *vox_ref;
 } orc_problem;
 
 typedef struct {
@@ -410,12 +415,15 @@ double orc_log_prior(const orc_problem *p, const double *free_h) {
 /* Posterior                                                                   */
 /* ------------------------------------------------------------------------- */
 
+double orc_voxel_logpost_lik(const orc_problem *p, const double *free_h, double *O);
+
 /* log posterior (likelihood + prior, normalised) of one state. */
 double orc_logpost(const orc_problem *p, const double *free_h) {
     double lpr = orc_log_prior(p, free_h);
     if (lpr == -INFINITY) return -INFINITY;
     int n = p->n_s * p->n_pix;
     if (n == 0) return lpr;
+    if (p->n_z > 0) return lpr + orc_voxel_logpost_lik(p, free_h, NULL);
     double *O = (double *)malloc(sizeof(double) * n);
     orc_opacity(p, free_h, O, NULL, NULL);
     double ll = orc_loglik(p, O);
@@ -439,6 +447,10 @@ void orc_logpost_batch(const orc_problem *p, int n_chains, const double *free_al
  */
 double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
     size_t NS = (size_t)p->S * p->R * p->C;
+    if (p->n_z > 0) {   /* the gradient here follows the exact march only */
+        for (size_t i = 0; i < NS; ++i) grad[i] = NAN;
+        return NAN;
+    }
     memset(grad, 0, sizeof(double) * NS);
     double lpr = orc_log_prior_grad(p, free_h, grad);
     if (lpr == -INFINITY) { memset(grad, 0, sizeof(double) * NS); return -INFINITY; }
@@ -768,4 +780,170 @@ void orc_ray_stats(const orc_problem *p, const double *free_h, double *crossings
             if (cells) cells[ray] = st.cells;
         }
     free(surf);
+}
+
+/* ------------------------------------------------------------------------- */
+/* The paper's smoothed voxel forward model, linearised (Sec. 2.1.2, 2.1.4)   */
+/* ------------------------------------------------------------------------- */
+/*
+ * Readings taken here:
+ *  - The density grid shares the layer grid's lateral indices (the map
+ *    (i,j) -> (x(i), y(j)) is the identity): voxel column (i,j) is the box
+ *    [x_i - dx/2, x_i + dx/2] x [y_j - dy/2, y_j + dy/2] clipped to the
+ *    footprint, dx = X/(R-1), dy = Y/(C-1).  Vertically n_z voxels of
+ *    dz = Z_top/n_z fill [0, Z_top]; the height the paper writes k*dz is taken
+ *    at the voxel's centre, z_k = (k + 1/2) dz.  Linear voxel index
+ *    (i*C + j)*n_z + k (right-most index fastest).
+ *  - Units: the S units of the layer model plus the air above the top surface
+ *    (density 0; its upper interface is at +infinity, so its smooth indicator
+ *    is 1 - sigma(H_S - z)).  With it the normalised weights form a partition
+ *    of unity that leaves the air empty, as the hard-interface density does.
+ *  - R0 = Rhat(H_ref) for a reference geometry given by the caller.
+ *  - G_pv = d lambda_p / d R_v at R0 = -lambda_p(R0) L_pv / Lambda, with L_pv
+ *    the length of ray p inside voxel v, lambda_p(R) = E_p exp(-O_p(R)/Lambda)
+ *    and O_p(R) = sum_v L_pv R_v (the opacity of a piecewise-constant field).
+ *  - A state whose linearised count lambda-hat_p is <= 0 at some pixel has
+ *    zero likelihood (log posterior -inf).
+ */
+
+/* Scaled sigmoid (eq. def_sigmoid). */
+double orc_sigmoid(double u, double gamma) { return 1.0 / (1.0 + exp(-u / gamma)); }
+
+/* Normalised weights W[(i*C + j)*n_z + k][l], l = 0..S (units 1..S, then the
+   air), from the smooth indicators D (eq. smooth_layer_indicators) divided by
+   their sum (eq. def_LM_density_grid_smooth).  surf: [S][R][C], all surfaces. */
+void orc_voxel_weights(const orc_problem *p, const double *surf, int n_z, double gamma, double *W) {
+    const int S = p->S;
+    const size_t N = (size_t)p->R * p->C;
+    const double dz = top_max(p) / n_z;
+    double D[17];
+    for (size_t n = 0; n < N; ++n)
+        for (int k = 0; k < n_z; ++k) {
+            const double z = (k + 0.5) * dz;
+            double below_prev = orc_sigmoid(0.0 - z, gamma);   /* H_0 = 0, the floor */
+            double sum = 0.0;
+            for (int l = 1; l <= S + 1; ++l) {
+                const double below = l <= S ? orc_sigmoid(surf[(size_t)(l - 1) * N + n] - z, gamma) : 1.0;
+                D[l - 1] = below - below_prev;
+                sum += D[l - 1];
+                below_prev = below;
+            }
+            double *w = W + ((size_t)n * n_z + k) * (S + 1);
+            for (int l = 0; l <= S; ++l) w[l] = D[l] / sum;
+        }
+}
+
+/* Smoothed density Rhat [R][C][n_z] = sum_l W_l R^(l) (eq. def_LM_density_grid_smooth). */
+void orc_voxel_density(const orc_problem *p, const double *surf, int n_z, double gamma, double *Rhat) {
+    const int S = p->S;
+    const size_t V = (size_t)p->R * p->C * n_z;
+    double *W = (double *)malloc(sizeof(double) * V * (S + 1));
+    orc_voxel_weights(p, surf, n_z, gamma, W);
+    for (size_t v = 0; v < V; ++v) {
+        double r = 0.0;
+        for (int l = 0; l < S; ++l) r += W[v * (S + 1) + l] * p->density[l];
+        Rhat[v] = r;   /* the air (l = S) has density 0 */
+    }
+    free(W);
+}
+
+static int cmp_double(const void *a, const void *b) {
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Pieces of ray (q, d) inside the box, split at every voxel boundary plane
+   (x = (i+1/2) dx, y = (j+1/2) dy, z = k dz) crossed inside (0, T): the
+   crossing parameters are sorted and each interval's midpoint names its
+   voxel.  vox/len hold at least R + C + n_z + 1 entries; returns the count. */
+static int voxel_pieces(const orc_problem *p, const double q[3], const double d[3], int n_z, int *vox,
+                        double *len) {
+    const double ztop = top_max(p), T = exit_param(p, q, d, ztop);
+    const double dx = p->X / (p->R - 1), dy = p->Y / (p->C - 1), dz = ztop / n_z;
+    double *t = (double *)malloc(sizeof(double) * (p->R + p->C + n_z + 2));
+    int m = 0;
+    t[m++] = 0.0;
+    t[m++] = T;
+    for (int i = 0; i + 1 < p->R; ++i)
+        if (d[0] != 0.0) {
+            double tc = ((i + 0.5) * dx - q[0]) / d[0];
+            if (tc > 0.0 && tc < T) t[m++] = tc;
+        }
+    for (int j = 0; j + 1 < p->C; ++j)
+        if (d[1] != 0.0) {
+            double tc = ((j + 0.5) * dy - q[1]) / d[1];
+            if (tc > 0.0 && tc < T) t[m++] = tc;
+        }
+    for (int k = 1; k < n_z; ++k) {
+        double tc = (k * dz - q[2]) / d[2];
+        if (tc > 0.0 && tc < T) t[m++] = tc;
+    }
+    qsort(t, m, sizeof(double), cmp_double);
+    int n = 0;
+    for (int a = 0; a + 1 < m; ++a) {
+        const double l = t[a + 1] - t[a];
+        if (!(l > 0.0)) continue;
+        const double tm = 0.5 * (t[a] + t[a + 1]);
+        const double x = q[0] + tm * d[0], y = q[1] + tm * d[1], z = q[2] + tm * d[2];
+        int i = (int)floor(x / dx + 0.5), j = (int)floor(y / dy + 0.5), k = (int)floor(z / dz);
+        i = i < 0 ? 0 : (i > p->R - 1 ? p->R - 1 : i);
+        j = j < 0 ? 0 : (j > p->C - 1 ? p->C - 1 : j);
+        k = k < 0 ? 0 : (k > n_z - 1 ? n_z - 1 : k);
+        vox[n] = (i * p->C + j) * n_z + k;
+        len[n] = l;
+        ++n;
+    }
+    free(t);
+    return n;
+}
+
+/* Pieces of ray `ray` for the problem's n_z (tests). */
+int orc_voxel_pieces(const orc_problem *p, int ray, int n_z, int *vox, double *len) {
+    const int s = ray / p->n_pix;
+    return voxel_pieces(p, p->pos + 3 * s, p->dirs + 3 * (size_t)ray, n_z, vox, len);
+}
+
+/* Linearised Poisson log-likelihood (eq. expected_counts_linearized_approx in
+   eq. def_likelihood) of the smoothed density Rhat [R][C][n_z]:
+   lambda-hat = lambda(R0) + G (Rhat - R0).  O (optional) receives the
+   voxel opacity O_p(Rhat) of every ray. */
+double orc_voxel_loglik(const orc_problem *p, const double *Rhat, double *O) {
+    const int n_z = p->n_z, nr = p->n_s * p->n_pix;
+    const double *R0 = p->vox_ref;
+    int *vox = (int *)malloc(sizeof(int) * (p->R + p->C + n_z + 1));
+    double *len = (double *)malloc(sizeof(double) * (p->R + p->C + n_z + 1));
+    double ll = 0.0;
+    for (int ray = 0; ray < nr; ++ray) {
+        const int m = orc_voxel_pieces(p, ray, n_z, vox, len);
+        double o = 0.0, o0 = 0.0;
+        for (int a = 0; a < m; ++a) {
+            o += len[a] * Rhat[vox[a]];
+            o0 += len[a] * R0[vox[a]];
+        }
+        if (O) O[ray] = o;
+        const double lam0 = p->exposure[ray] * exp(-o0 / p->atten);
+        double lam = lam0;
+        for (int a = 0; a < m; ++a) {
+            const double g = -lam0 * len[a] / p->atten;   /* G_pv */
+            lam += g * (Rhat[vox[a]] - R0[vox[a]]);
+        }
+        const double c = (double)p->counts[ray];
+        if (!(lam > 0.0)) ll = -INFINITY;
+        else ll += c * log(lam) - lam - lgamma(c + 1.0);
+    }
+    free(vox);
+    free(len);
+    return ll;
+}
+
+/* Likelihood part of the log posterior under the voxel model; O as above. */
+double orc_voxel_logpost_lik(const orc_problem *p, const double *free_h, double *O) {
+    double *surf = stack_surfaces(p, free_h);
+    const size_t V = (size_t)p->R * p->C * p->n_z;
+    double *Rhat = (double *)malloc(sizeof(double) * V);
+    orc_voxel_density(p, surf, p->n_z, p->gamma, Rhat);
+    const double ll = orc_voxel_loglik(p, Rhat, O);
+    free(Rhat);
+    free(surf);
+    return ll;
 }
