@@ -109,6 +109,35 @@ mc_status set_sensors(mc_problem *p, int n_sensors, const double *pos, int n_pix
 mc_status set_counts(mc_problem *p, const int32_t *counts);
 
 /*
+ * Likelihood backend: the paper's own forward model (Sec. 2.1.2 and 2.1.4) in
+ * place of the exact ray march.  The density is the sigmoid-smoothed voxel
+ * grid R-hat(H) (eqs. def_sigmoid, smooth_layer_indicators,
+ * def_LM_density_grid_smooth) and the expected counts are linearised around
+ * R0 = R-hat(H_ref) with the sensitivity matrix G = d lambda / dR at R0
+ * (eq. expected_counts_linearized_approx):
+ *   lambda-hat_p = lambda_p(R0) (1 - (O_p(R-hat) - O_p(R0)) / Lambda),
+ *   O_p(R) = sum_v L_pv R_v, L_pv the length of ray p inside voxel v.
+ * Voxel columns are centred on the grid nodes (x(i) = i), n_z levels of
+ * dz = max(top)/n_z fill [0, max(top)], and the indicator heights are the
+ * level centres (k + 1/2) dz.  The air above the top surface is a unit of
+ * density 0.  A state with lambda-hat_p <= 0 at some pixel has log
+ * posterior -inf.  The prior is unchanged.
+ *   n_z in [1, 4096]: voxel levels; 0 switches back to the exact march.
+ *   gamma > 0: sigmoid scale in metres (the paper uses 1).
+ *   ref_heights[(S-1)*R*C]: host array, the free surfaces of H_ref (the top
+ *   is the problem's); copied.
+ * Needs geometry and sensors; load_geometry_grid and set_sensors switch the
+ * model off again.  While it is on, logpost_batch and mcmc_run (random walk,
+ * with or without sampled r) use it; logpost_grad_batch, MALA,
+ * mcmc_run_multi, mc_time_march and mc_time_adjoint return
+ * MC_ERR_UNSUPPORTED or MC_ERR_STATE.  The opacity output of logpost_batch
+ * then holds O_p(R-hat).  Device memory: the ray-voxel lists (8 or 12 bytes
+ * per piece) and, per call, R*C*n_z*round_up(n_chains, 64) smoothed
+ * densities in the state precision.
+ */
+mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *ref_heights);
+
+/*
  * Log posterior of n_chains states.
  *   heights: device, [n_chains][S-1][n_rows][n_cols] in the handle's precision.
  *   logpost: device, [n_chains] float64 (written).
@@ -343,6 +372,15 @@ mc_status mc_measure_valu_rate(int hip_device, int kind, double *lane_ops_per_s)
    milliseconds per launch.  For benchmarks and roofline reports. */
 mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
                         float *ms_per_launch);
+
+/*
+ * Timing of the voxel model's two kernels alone (HIP events on `stream`,
+ * `iters` back-to-back launches each): the smoothed-density kernel and the
+ * linearised-likelihood kernel, mean milliseconds per launch.  Needs
+ * set_voxel_model; heights as for logpost_batch.
+ */
+mc_status mc_time_voxel(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
+                        float *ms_density, float *ms_likelihood);
 
 /* Mean milliseconds per launch of the adjoint march kernel alone on
  * `stream` (HIP events over `iters` launches), after one full gradient

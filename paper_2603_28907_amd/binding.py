@@ -111,6 +111,8 @@ def load_library(path: Optional[str] = None):
         "mcmc_run_multi": (I, [I, P(V), P(RunConfig), P(I), P(V), P(V), P(V), V]),
         "mc_measure_valu_rate": (I, [I, I, P(D)]),
         "mc_time_adjoint": (I, [V, I, V, I, V, P(ct.c_float)]),
+        "set_voxel_model": (I, [V, I, D, V]),
+        "mc_time_voxel": (I, [V, I, V, I, V, P(ct.c_float), P(ct.c_float)]),
         "mc_server_create": (I, [P(ServerConfig), P(V)]),
         "mc_server_destroy": (None, [V, I]),
         "mc_server_last_error": (ct.c_char_p, [V]),
@@ -133,7 +135,7 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi",
                     "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
                     "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
-                    "mc_measure_valu_rate", "mc_time_adjoint")
+                    "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel")
 
 
 def _host(a, dtype=np.float64):
@@ -219,6 +221,17 @@ class Problem:
     def set_counts(self, counts):
         c = _host(counts, np.int32).reshape(-1)
         self._check(self.lib.set_counts(self.h, _hp(c)))
+
+    def set_voxel_model(self, n_z: int, gamma: float = 1.0, ref_heights=None):
+        """Switch the likelihood to the paper's smoothed voxel model linearised
+        around R-hat(ref_heights) [S-1, R, C]; n_z = 0 switches back."""
+        if n_z == 0:
+            self._check(self.lib.set_voxel_model(self.h, 0, 0.0, None))
+            return
+        ref = _host(ref_heights).reshape(-1)
+        if ref.size != (self.S - 1) * self.R * self.C:
+            raise ValueError("ref_heights must hold (S-1)*R*C values")
+        self._check(self.lib.set_voxel_model(self.h, int(n_z), float(gamma), _hp(ref)))
 
     @classmethod
     def from_scenario(cls, sc, counts=None, device: int = 0, precision: str = "f32"):
@@ -355,6 +368,17 @@ def time_adjoint(problem: "Problem", heights, iters: int = 10, stream=None) -> f
     problem._check(problem.lib.mc_time_adjoint(problem.h, n, ct.c_void_p(heights.data_ptr()), int(iters),
                                                _stream_handle(stream, problem.device), ct.byref(ms)))
     return float(ms.value)
+
+
+def time_voxel(problem: "Problem", heights, iters: int = 10, stream=None):
+    """Mean milliseconds per launch of the voxel model's density and
+    likelihood kernels (HIP events on `stream`)."""
+    a, b = ct.c_float(), ct.c_float()
+    n = int(heights.shape[0])
+    problem._check_tensor(heights, problem.heights_shape(n), problem.torch_dtype, "heights")
+    problem._check(problem.lib.mc_time_voxel(problem.h, n, ct.c_void_p(heights.data_ptr()), int(iters),
+                                             _stream_handle(stream, problem.device), ct.byref(a), ct.byref(b)))
+    return float(a.value), float(b.value)
 
 
 def measure_valu_rate(device: int = 0, kind: str = "f32") -> float:

@@ -25,6 +25,7 @@
 #include "multi.h"
 #include "prior.h"
 #include "probe.h"
+#include "voxel.h"
 
 using namespace mc;
 
@@ -91,6 +92,17 @@ struct mc_problem {
     double *d_expo = nullptr, *d_coL = nullptr;
     void *d_rc[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};   // per-ray constants
     double kconst = 0.0;
+    double *d_cnt64 = nullptr;   // [n_ray] counts as f64
+    double kconst_vox = 0.0;     // -sum lgamma(C + 1)
+    // the paper's smoothed voxel model (vox_nz = 0: exact march)
+    int vox_nz = 0;
+    double vox_gamma = 1.0, vox_dz = 0.0;
+    std::vector<double> vox_drho;   // [S] rho_l - rho_{l+1}
+    int *d_vox_off = nullptr, *d_vox_idx = nullptr;
+    void *d_vox_len = nullptr;   // [nnz] in prec
+    double *d_vox_lam0 = nullptr, *d_vox_o0 = nullptr, *d_vox_fsig = nullptr, *d_vox_inorm = nullptr;
+    size_t vox_nnz = 0;
+    DevBuf rhat;   // [R*C*n_z][n_pad] smoothed densities of the chains
     // workspaces (grow only)
     DevBuf partials, prop, lptmp;
     DevBuf rstat;   // [2][n][S-1] sum w^2 and edge sums of the current states (r sampling)
@@ -154,6 +166,18 @@ void drop_graph(mc_problem *p) {
     p->gen += 1;
 }
 
+void clear_voxel_model(mc_problem *p) {
+    if (p->vox_nz > 0) drop_graph(p);
+    p->vox_nz = 0;
+    p->vox_nnz = 0;
+    free_ptr(p->d_vox_len);
+    for (double **q : {&p->d_vox_lam0, &p->d_vox_o0, &p->d_vox_fsig, &p->d_vox_inorm}) free_ptr(*q);
+    for (int **q : {&p->d_vox_off, &p->d_vox_idx}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+}
+
 // Grow-only workspace.  A reallocation invalidates the cached graph, whose
 // kernel nodes hold the old pointers.
 mc_status ensure(mc_problem *p, DevBuf &b, size_t bytes) {
@@ -212,6 +236,11 @@ struct Tiling {
 
 Tiling tiling(const mc_problem *p) {
     Tiling t;
+    if (p->vox_nz > 0) {
+        t.rays_per_block = kVoxRaysPerTile;
+        t.n_tiles = p->n_ray > 0 ? (p->n_ray + kVoxRaysPerTile - 1) / kVoxRaysPerTile : 0;
+        return t;
+    }
     const int block = p->tune.march_variant == 1 ? kMarchBlock : p->tune.block;
     t.rays_per_block = block * p->tune.rays_per_thread;
     t.n_tiles = p->n_ray > 0 ? (p->n_ray + t.rays_per_block - 1) / t.rays_per_block : 0;
@@ -446,7 +475,7 @@ PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double 
     P.eig_w = p->d_eig_w;
     P.n_eig = p->n_eig;
     P.partials = partials;
-    P.kconst = p->kconst;
+    P.kconst = p->vox_nz > 0 ? p->kconst_vox : p->kconst;
     return P;
 }
 
@@ -462,6 +491,75 @@ mc_status launch_prior(mc_problem *p, int n, const PriorParams<T> &P, hipStream_
     const size_t N = (size_t)p->R * p->C, lds = sizeof(T) * N;
     if (N >= (size_t)kPriorLargeNodes) launch_prior_shape<T, S, kPriorBlockLarge>(n, lds, P, st);
     else launch_prior_shape<T, S, kPriorBlock>(n, lds, P, st);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The smoothed voxel model
+// ---------------------------------------------------------------------------
+
+int vox_n_pad(int n) { return (n + kVoxLanes - 1) / kVoxLanes * kVoxLanes; }
+
+template <typename T>
+VoxParams<T> vox_params(const mc_problem *p, int n, const T *heights, T *opacity, double *partials,
+                        const double *only_nan) {
+    VoxParams<T> V;
+    memset(&V, 0, sizeof(V));
+    V.R = p->R;
+    V.C = p->C;
+    V.N = p->R * p->C;
+    V.n_z = p->vox_nz;
+    V.M = (p->S - 1) * V.N;
+    V.n_chains = n;
+    V.n_pad = vox_n_pad(n);
+    V.heights = heights;
+    V.top = (const T *)p->d_top;
+    V.rhat = (T *)p->rhat.p;
+    V.dz = p->vox_dz;
+    V.inv_gamma = 1.0 / p->vox_gamma;
+    for (int l = 0; l < p->S; ++l) V.drho[l] = p->vox_drho[l];
+    V.rho1 = p->density[0];
+    V.floor_sig = p->d_vox_fsig;
+    V.inv_norm = p->d_vox_inorm;
+    V.n_ray = p->n_ray;
+    V.n_tiles = tiling(p).n_tiles;
+    V.ray_off = p->d_vox_off;
+    V.vox = p->d_vox_idx;
+    V.len = (const T *)p->d_vox_len;
+    V.lam0 = p->d_vox_lam0;
+    V.o0 = p->d_vox_o0;
+    V.cnt = p->d_cnt64;
+    V.inv_atten = 1.0 / p->atten;
+    V.partials = partials;
+    V.opacity = opacity;
+    V.only_nan = only_nan;
+    return V;
+}
+
+size_t rhat_bytes(const mc_problem *p, int n) {
+    return (size_t)p->R * p->C * p->vox_nz * vox_n_pad(n) * elem_size(p);
+}
+
+template <typename T, int S>
+void launch_vox_density(const VoxParams<T> &V, hipStream_t st) {
+    hipLaunchKernelGGL((k_vox_density<T, S>), dim3(V.N, (V.n_pad + 255) / 256), dim3(256), 0, st, V);
+}
+
+template <typename T>
+void launch_vox_lik(const VoxParams<T> &V, hipStream_t st) {
+    const int groups = V.n_pad / kVoxLanes;
+    const dim3 grid((unsigned)V.n_tiles * (unsigned)((groups + kXcds - 1) / kXcds * kXcds));
+    hipLaunchKernelGGL((k_vox_lik<T>), grid, dim3(kVoxWaves * kVoxLanes), 0, st, V);
+}
+
+// rhat must already hold rhat_bytes(p, n).
+template <typename T, int S>
+mc_status launch_voxel(mc_problem *p, int n, const T *heights, T *opacity, double *partials, hipStream_t st,
+                       const double *only_nan) {
+    VoxParams<T> V = vox_params<T>(p, n, heights, opacity, partials, only_nan);
+    launch_vox_density<T, S>(V, st);
+    launch_vox_lik<T>(V, st);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
 }
@@ -483,8 +581,14 @@ mc_status logpost_impl(mc_problem *p, int n, const T *heights, double *lp, T *op
     mc_status s;
     if (p->n_ray > 0) {
         if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
-        if ((s = launch_march<T, S>(p, n, heights, opacity, (double *)p->partials.p, st, only_nan)) != MC_OK)
+        if (p->vox_nz > 0) {
+            if ((s = ensure(p, p->rhat, rhat_bytes(p, n))) != MC_OK) return s;
+            if ((s = launch_voxel<T, S>(p, n, heights, opacity, (double *)p->partials.p, st, only_nan)) != MC_OK)
+                return s;
+        } else if ((s = launch_march<T, S>(p, n, heights, opacity, (double *)p->partials.p, st, only_nan)) !=
+                   MC_OK) {
             return s;
+        }
     }
     PriorParams<T> P = prior_params<T>(p, heights, (const double *)p->partials.p);
     P.lp_out = lp;
@@ -682,7 +786,11 @@ mc_status rw_step(mc_problem *p, int n, T *heights, double *lp, int64_t *acc, co
     HIP_TRY(p, hipGetLastError());
     mc_status s;
     if (p->n_ray > 0) {
-        if ((s = launch_march<T, S>(p, n, prop, nullptr, (double *)p->partials.p, st)) != MC_OK) return s;
+        if (p->vox_nz > 0)
+            s = launch_voxel<T, S>(p, n, prop, nullptr, (double *)p->partials.p, st, nullptr);
+        else
+            s = launch_march<T, S>(p, n, prop, nullptr, (double *)p->partials.p, st);
+        if (s != MC_OK) return s;
     }
     PriorParams<T> P = prior_params<T>(p, prop, (const double *)p->partials.p);
     P.mh = 1;
@@ -714,6 +822,7 @@ mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, 
     if ((s = ensure(p, p->prop, sizeof(T) * (size_t)n * M)) != MC_OK) return s;
     if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
     if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+    if (p->n_ray > 0 && p->vox_nz > 0 && (s = ensure(p, p->rhat, rhat_bytes(p, n))) != MC_OK) return s;
     if (mala) {
         if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
         if ((s = ensure(p, p->gcur, sizeof(T) * SN * n)) != MC_OK) return s;
@@ -1304,9 +1413,11 @@ void mc_destroy(mc_problem *p) {
     free_ptr(p->d_dz);
     free_ptr(p->d_expo);
     free_ptr(p->d_coL);
+    free_ptr(p->d_cnt64);
+    clear_voxel_model(p);
     for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
     for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gprior, &p->gcur, &p->gprop,
-                      &p->lpprop, &p->rstat})
+                      &p->lpprop, &p->rstat, &p->rhat})
         if (b->p) (void)hipFree(b->p);
     if (p->d_step) (void)hipFree(p->d_step);
     delete p;
@@ -1336,6 +1447,7 @@ mc_status load_geometry_grid(mc_problem *p, int n_surfaces, int n_rows, int n_co
     }
     DeviceGuard g(p->device);
     p->have_geom = p->have_sensors = p->have_counts = false;
+    clear_voxel_model(p);
     p->S = n_surfaces;
     p->R = n_rows;
     p->C = n_cols;
@@ -1406,6 +1518,7 @@ mc_status set_sensors(mc_problem *p, int n_sensors, const double *pos, int n_pix
     }
     DeviceGuard g(p->device);
     p->have_sensors = p->have_counts = false;
+    clear_voxel_model(p);
     p->n_s = n_sensors;
     p->n_pix = n_pix;
     p->n_ray = n_ray;
@@ -1418,6 +1531,7 @@ mc_status set_sensors(mc_problem *p, int n_sensors, const double *pos, int n_pix
         dz[r] = dirs[3 * r + 2];
     }
     p->expo.assign(exposure, exposure + n_ray);
+    p->dirs.assign(dirs, dirs + 3 * (size_t)n_ray);
     // chain-independent per-ray constants of the cell walk, in float64 then
     // rounded once: reciprocal directions, DDA offsets -q/d, box exit
     std::vector<double> rc[6];
@@ -1458,13 +1572,15 @@ mc_status set_counts(mc_problem *p, const int32_t *counts) {
     if (!p) return MC_ERR_ARG;
     if (!p->have_sensors) return fail(p, MC_ERR_STATE, "set_sensors has not been called");
     if (p->n_ray > 0 && !counts) return fail(p, MC_ERR_ARG, "counts is NULL");
-    std::vector<double> coL(p->n_ray);
-    long double K = 0;
+    std::vector<double> coL(p->n_ray), c64(p->n_ray);
+    long double K = 0, KV = 0;
     for (int r = 0; r < p->n_ray; ++r) {
         if (counts[r] < 0) return fail(p, MC_ERR_ARG, "counts[%d] < 0", r);
         double c = counts[r];
         coL[r] = c / p->atten;
+        c64[r] = c;
         K += c * std::log(p->expo[r]) - std::lgamma(c + 1.0);
+        KV -= std::lgamma(c + 1.0);
     }
     DeviceGuard g(p->device);
     drop_graph(p);   // the graph holds the old count pointer and constant
@@ -1472,7 +1588,11 @@ mc_status set_counts(mc_problem *p, const int32_t *counts) {
     mc_status s;
     if ((s = upload<double>(p, d, coL)) != MC_OK) return s;
     p->d_coL = (double *)d;
+    d = p->d_cnt64;
+    if ((s = upload<double>(p, d, c64)) != MC_OK) return s;
+    p->d_cnt64 = (double *)d;
     p->kconst = (double)K;
+    p->kconst_vox = (double)KV;
     p->have_counts = true;
     return MC_OK;
 }
@@ -1499,6 +1619,7 @@ mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, d
     if (n_chains == 0) return MC_OK;
     if (!heights || !logpost || !grad) return fail(p, MC_ERR_ARG, "NULL device pointer");
     if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
+    if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients follow the exact march; the voxel model is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? logpost_grad_dispatch<double>(p, n_chains, heights, logpost, grad, st)
@@ -1517,6 +1638,7 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
     if (!(cfg->step_size >= 0) || !std::isfinite(cfg->step_size)) return fail(p, MC_ERR_ARG, "step_size invalid");
     if (cfg->kernel != 0 && cfg->kernel != 1) return fail(p, MC_ERR_ARG, "kernel %d", cfg->kernel);
     if (cfg->r_state && cfg->kernel != 0) return fail(p, MC_ERR_UNSUPPORTED, "r sampling runs with random-walk Metropolis");
+    if (cfg->kernel == 1 && p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA needs the exact march; the voxel model is set");
     if (cfg->r_state && (!(cfg->r_step >= 0) || !std::isfinite(cfg->r_step))) return fail(p, MC_ERR_ARG, "r_step invalid");
     if (cfg->n_accept_r && !cfg->r_state) return fail(p, MC_ERR_ARG, "n_accept_r without r_state");
     if (cfg->step_offset + (uint64_t)cfg->n_steps >= (1ULL << 48)) return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
@@ -1544,6 +1666,7 @@ mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_r
             if (problems[j] == p) return fail(e, MC_ERR_ARG, "problem %d repeats problem %d", i, j);
         if (cfgs[i].kernel != 0) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi runs random-walk Metropolis");
         if (cfgs[i].r_state) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi samples with fixed r");
+        if (p->vox_nz > 0) return fail(e, MC_ERR_UNSUPPORTED, "problem %d: mcmc_run_multi runs the exact march", i);
         if (cfgs[i].n_steps != cfgs[0].n_steps || cfgs[i].graph_steps != cfgs[0].graph_steps)
             return fail(e, MC_ERR_ARG, "n_steps and graph_steps must be equal across problems");
         if (!(cfgs[i].step_size >= 0) || !std::isfinite(cfgs[i].step_size)) return fail(e, MC_ERR_ARG, "step_size");
@@ -1569,6 +1692,181 @@ mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_r
         }
     }
     return fail(e, MC_ERR_UNSUPPORTED, "n_surfaces %d", e->S);
+}
+
+namespace {
+
+// Voxel walk of one ray inside the box [0,X]x[0,Y]x[0,Z_top]: a 3-D DDA
+// over the column boundaries x = (i+1/2) dx, y = (j+1/2) dy (voxel columns
+// are centred on the nodes) and the level boundaries z = k dz.  Appends
+// (voxel index, length) for every piece of positive length.
+void voxel_walk(const mc_problem *p, int n_z, double dz, const double q[3], const double u[3],
+                std::vector<int> &vi, std::vector<double> &vl) {
+    const int R = p->R, C = p->C;
+    const double dx = p->X / (R - 1), dy = p->Y / (C - 1);
+    double T = (p->ztop - q[2]) / u[2];
+    if (u[0] > 0) T = std::min(T, (p->X - q[0]) / u[0]);
+    if (u[0] < 0) T = std::min(T, -q[0] / u[0]);
+    if (u[1] > 0) T = std::min(T, (p->Y - q[1]) / u[1]);
+    if (u[1] < 0) T = std::min(T, -q[1] / u[1]);
+    if (!(T > 0)) return;
+    int i = std::min(std::max((int)std::floor(q[0] / dx + 0.5), 0), R - 1);
+    int j = std::min(std::max((int)std::floor(q[1] / dy + 0.5), 0), C - 1);
+    int k = std::min(std::max((int)std::floor(q[2] / dz), 0), n_z - 1);
+    auto next_x = [&](int a) {
+        if (u[0] > 0 && a < R - 1) return ((a + 0.5) * dx - q[0]) / u[0];
+        if (u[0] < 0 && a > 0) return ((a - 0.5) * dx - q[0]) / u[0];
+        return (double)INFINITY;
+    };
+    auto next_y = [&](int b) {
+        if (u[1] > 0 && b < C - 1) return ((b + 0.5) * dy - q[1]) / u[1];
+        if (u[1] < 0 && b > 0) return ((b - 0.5) * dy - q[1]) / u[1];
+        return (double)INFINITY;
+    };
+    auto next_z = [&](int c) { return c < n_z - 1 ? ((c + 1) * dz - q[2]) / u[2] : (double)INFINITY; };
+    double tx = next_x(i), ty = next_y(j), tz = next_z(k), t = 0.0;
+    for (int guard = 0; guard < R + C + n_z + 4 && t < T; ++guard) {
+        const double tn = std::min(std::min(tx, ty), std::min(tz, T));
+        if (tn > t) {
+            vi.push_back((i * C + j) * n_z + k);
+            vl.push_back(tn - t);
+        }
+        if (tn >= T) break;
+        if (tx == tn) tx = next_x(i += u[0] > 0 ? 1 : -1);
+        if (ty == tn) ty = next_y(j += u[1] > 0 ? 1 : -1);
+        if (tz == tn) tz = next_z(++k);
+        t = tn;
+    }
+}
+
+}  // namespace
+
+mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *ref_heights) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_geom) return fail(p, MC_ERR_STATE, "load_geometry_grid has not been called");
+    if (!p->have_sensors) return fail(p, MC_ERR_STATE, "set_sensors has not been called");
+    if (n_z < 0 || n_z > 4096) return fail(p, MC_ERR_ARG, "n_z %d not in [0, 4096]", n_z);
+    DeviceGuard g(p->device);
+    if (n_z == 0) {
+        clear_voxel_model(p);
+        return MC_OK;
+    }
+    if (!(gamma > 0) || !std::isfinite(gamma)) return fail(p, MC_ERR_ARG, "gamma must be > 0");
+    if (!ref_heights) return fail(p, MC_ERR_ARG, "ref_heights is NULL");
+    const int S = p->S, N = p->R * p->C;
+    for (size_t i = 0; i < (size_t)(S - 1) * N; ++i)
+        if (!std::isfinite(ref_heights[i])) return fail(p, MC_ERR_ARG, "ref_heights[%zu] not finite", i);
+    clear_voxel_model(p);
+    const double dz = p->ztop / n_z;
+    std::vector<double> drho(S);
+    for (int l = 0; l < S; ++l) drho[l] = p->density[l] - (l + 1 < S ? p->density[l + 1] : 0.0);
+    // the floor's smooth indicator and the normaliser per level
+    std::vector<double> fsig(n_z), inorm(n_z);
+    for (int k = 0; k < n_z; ++k) {
+        const double z = (k + 0.5) * dz;
+        fsig[k] = 1.0 / (1.0 + std::exp(z / gamma));
+        inorm[k] = 1.0 + std::exp(-z / gamma);
+    }
+    // R0 = R-hat(H_ref), float64
+    const size_t V = (size_t)N * n_z;
+    std::vector<double> r0(V);
+    for (int n = 0; n < N; ++n) {
+        double h[kMaxSurfaces];
+        for (int l = 0; l < S - 1; ++l) h[l] = ref_heights[(size_t)l * N + n];
+        h[S - 1] = p->top[n];
+        for (int k = 0; k < n_z; ++k) {
+            const double z = (k + 0.5) * dz;
+            double acc = -p->density[0] * fsig[k];
+            for (int l = 0; l < S; ++l) acc += drho[l] / (1.0 + std::exp((z - h[l]) / gamma));
+            r0[(size_t)n * n_z + k] = acc * inorm[k];
+        }
+    }
+    // voxel walks of every ray, lambda(R0) and O(R0)
+    std::vector<int> off(p->n_ray + 1), vi;
+    std::vector<double> vl, lam0(p->n_ray), o0(p->n_ray);
+    vi.reserve((size_t)p->n_ray * (p->R + p->C + n_z) / 2);
+    vl.reserve(vi.capacity());
+    for (int r = 0; r < p->n_ray; ++r) {
+        off[r] = (int)vi.size();
+        const size_t b0 = vi.size();
+        voxel_walk(p, n_z, dz, p->pos.data() + 3 * (r / p->n_pix), p->dirs.data() + 3 * (size_t)r, vi, vl);
+        if (vi.size() > (size_t)INT32_MAX) return fail(p, MC_ERR_UNSUPPORTED, "more than 2^31 ray-voxel pieces");
+        double o = 0.0;
+        for (size_t e = b0; e < vi.size(); ++e) o += vl[e] * r0[vi[e]];
+        o0[r] = o;
+        lam0[r] = p->expo[r] * std::exp(-o / p->atten);
+    }
+    off[p->n_ray] = (int)vi.size();
+    mc_status s;
+    void *q = nullptr;
+    HIP_TRY(p, hipMalloc(&q, sizeof(int) * off.size()));
+    p->d_vox_off = (int *)q;
+    HIP_TRY(p, hipMemcpy(q, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
+    if (!vi.empty()) {
+        q = nullptr;
+        HIP_TRY(p, hipMalloc(&q, sizeof(int) * vi.size()));
+        p->d_vox_idx = (int *)q;
+        HIP_TRY(p, hipMemcpy(q, vi.data(), sizeof(int) * vi.size(), hipMemcpyHostToDevice));
+        if ((s = upload_prec(p, p->d_vox_len, vl)) != MC_OK) return s;
+    }
+    for (auto pr : {std::make_pair(&p->d_vox_lam0, &lam0), std::make_pair(&p->d_vox_o0, &o0),
+                    std::make_pair(&p->d_vox_fsig, &fsig), std::make_pair(&p->d_vox_inorm, &inorm)}) {
+        void *d = nullptr;
+        if ((s = upload<double>(p, d, *pr.second)) != MC_OK) return s;
+        *pr.first = (double *)d;
+    }
+    p->vox_nnz = vi.size();
+    p->vox_drho = drho;
+    p->vox_gamma = gamma;
+    p->vox_dz = dz;
+    p->vox_nz = n_z;
+    drop_graph(p);
+    return MC_OK;
+}
+
+mc_status mc_time_voxel(mc_problem *p, int n_chains, const void *heights, int iters, void *stream,
+                        float *ms_density, float *ms_likelihood) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    if (n_chains <= 0 || n_chains > 65535 || iters <= 0 || !heights || !ms_density || !ms_likelihood)
+        return fail(p, MC_ERR_ARG, "invalid arguments");
+    if (p->vox_nz == 0 || p->n_ray == 0) return fail(p, MC_ERR_STATE, "no voxel model or no rays");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = ensure(p, p->rhat, rhat_bytes(p, n_chains))) != MC_OK) return s;
+    if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n_chains * tiling(p).n_tiles)) != MC_OK) return s;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    for (auto &e : ev) HIP_TRY(p, hipEventCreate(&e));
+    float ms[2] = {0, 0};
+    hipError_t err = hipSuccess;
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        VoxParams<T> V = vox_params<T>(p, n_chains, (const T *)heights, nullptr, (double *)p->partials.p, nullptr);
+        auto dens = [&]() {
+            switch (p->S) {
+                case 2: launch_vox_density<T, 2>(V, st); break;
+                case 3: launch_vox_density<T, 3>(V, st); break;
+                default: launch_vox_density<T, 4>(V, st); break;
+            }
+        };
+        dens();
+        launch_vox_lik<T>(V, st);   // warm
+        (void)hipEventRecord(ev[0], st);
+        for (int i = 0; i < iters; ++i) dens();
+        (void)hipEventRecord(ev[1], st);
+        for (int i = 0; i < iters; ++i) launch_vox_lik<T>(V, st);
+        (void)hipEventRecord(ev[2], st);
+        err = hipEventSynchronize(ev[2]);
+    };
+    if (p->prec == MC_F64) run(double(0));
+    else run(float(0));
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms[0], ev[0], ev[1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms[1], ev[1], ev[2]);
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    HIP_TRY(p, err);
+    *ms_density = ms[0] / iters;
+    *ms_likelihood = ms[1] / iters;
+    return MC_OK;
 }
 
 mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t) {
@@ -1602,6 +1900,7 @@ mc_status mc_time_march(mc_problem *p, int n_chains, const void *heights, int it
     if (n_chains <= 0 || n_chains > 65535 || iters <= 0 || !heights || !ms_per_launch)
         return fail(p, MC_ERR_ARG, "invalid arguments");
     if (p->n_ray == 0) return fail(p, MC_ERR_STATE, "no rays");
+    if (p->vox_nz > 0) return fail(p, MC_ERR_STATE, "the voxel model is set: use mc_time_voxel");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? time_march_dispatch<double>(p, n_chains, heights, iters, st, ms_per_launch)
@@ -1615,6 +1914,7 @@ mc_status mc_time_adjoint(mc_problem *p, int n_chains, const void *heights, int 
     if (n_chains <= 0 || n_chains > 65535 || iters <= 0 || !heights || !ms_per_launch)
         return fail(p, MC_ERR_ARG, "invalid arguments");
     if (p->n_ray == 0) return fail(p, MC_ERR_STATE, "no rays");
+    if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients follow the exact march; the voxel model is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? time_adjoint_dispatch<double>(p, n_chains, heights, iters, st, ms_per_launch)

@@ -8,7 +8,7 @@
 namespace mc {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kMaxSurfaces = 4;
+constexpr int kMaxSurfaces = 4;    // S (including the fixed top) supported by the kernels
 
 // MI355X has 8 XCDs, each with its own L2; consecutive workgroups of a
 // launch are dispatched to the XCDs round-robin.
@@ -24,7 +24,7 @@ __device__ __forceinline__ bool xcd_chain_tile(int n_tiles, int n_chains, int &c
     chain = (k / n_tiles) * kXcds + x;
     tile = k % n_tiles;
     return chain < n_chains;
-}    // S (including the fixed top) supported by the kernels
+}
 
 enum RngTag : uint32_t { kTagProposal = 0, kTagAccept = 1, kTagMala = 2, kTagRProposal = 3, kTagRAccept = 4 };
 

@@ -1,0 +1,137 @@
+// The paper's own forward model as an alternate likelihood backend: the
+// sigmoid-smoothed voxel density R-hat(H) (eqs. smooth_layer_indicators and
+// def_LM_density_grid_smooth) and the linearised expected counts
+// lambda-hat = lambda(R0) + G (R-hat - R0) (eq. expected_counts_linearized_approx),
+// with G_pv = -lambda_p(R0) L_pv / Lambda and L_pv the length of ray p in
+// voxel v.  Since G's row p is a multiple of the ray's voxel lengths,
+// lambda-hat_p = lambda_p(R0) (1 - (O_p(R-hat) - O_p(R0)) / Lambda), where
+// O_p(R) = sum_v L_pv R_v: one gather-and-sum along the ray's voxel list.
+//
+// Layout: the smoothed density of every chain is kept chain-fastest,
+// rhat[v * n_pad + c], so that a wavefront walking one ray for 64 chains
+// reads 64 consecutive values per voxel (one 256-byte line pair in float32)
+// while the ray's voxel list is the same for every lane.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace mc {
+
+constexpr int kVoxLanes = 64;          // chains per wavefront
+constexpr int kVoxWaves = 4;           // wavefronts per block
+constexpr int kVoxRaysPerWave = 32;    // rays one wavefront walks in turn
+constexpr int kVoxRaysPerTile = kVoxWaves * kVoxRaysPerWave;
+
+template <typename T>
+struct VoxParams {
+    int R, C, N, n_z, M;       // grid, nodes, levels, heights per chain ((S-1)*N)
+    int n_chains, n_pad;       // chains, chain stride of rhat (multiple of 64)
+    const T *heights;          // [n][S-1][R][C]
+    const T *top;              // [N]
+    T *rhat;                   // [N*n_z][n_pad]
+    double dz, inv_gamma;
+    double drho[kMaxSurfaces];   // rho_l - rho_{l+1} for units l = 1..S (rho_{S+1} = 0, the air)
+    double rho1;
+    const double *floor_sig;     // [n_z] sigma(-z_k / gamma): the floor's smooth indicator
+    const double *inv_norm;      // [n_z] 1 / (1 - sigma(-z_k / gamma)): 1 / sum_l D_l
+    // linearised likelihood
+    int n_ray, n_tiles;
+    const int *ray_off;          // [n_ray + 1] CSR offsets of the rays' voxel lists
+    const int *vox;              // [nnz] voxel index (i*C + j)*n_z + k
+    const T *len;                // [nnz] length of the ray inside that voxel (m)
+    const double *lam0, *o0;     // [n_ray] lambda_p(R0), O_p(R0)
+    const double *cnt;           // [n_ray] observed counts
+    double inv_atten;
+    double *partials;            // [n][n_tiles] per-chain, per-tile sums of C log(lambda) - lambda
+    T *opacity;                  // optional [n][n_ray]: O_p(R-hat)
+    const double *only_nan;      // optional [n]: chains whose value is not NaN are skipped
+};
+
+__device__ __forceinline__ float vox_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double vox_exp(double x) { return exp(x); }
+__device__ __forceinline__ float vox_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double vox_rcp(double x) { return 1.0 / x; }
+
+// R-hat for every voxel of one column and one chain per thread.  Block:
+// 256 threads = 4 wavefronts of 64 consecutive chains of one column; grid:
+// (column, group of 256 chains).  Writes are 64 consecutive chains per level.
+//   R-hat = (sum_{l=1..S} (rho_l - rho_{l+1}) sigma_l - rho_1 sigma_0) / (1 - sigma_0)
+// is the normalised mixture sum_l W_l rho_l with the floor (sigma_0) and the
+// air (indicator 1) as the outer interfaces, telescoped.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_vox_density(VoxParams<T> P) {
+    const int col = blockIdx.x;
+    const int c = blockIdx.y * 256 + threadIdx.x;
+    if (c >= P.n_pad) return;
+    const bool live = c < P.n_chains && !(P.only_nan && !(P.only_nan[c] != P.only_nan[c]));
+    T h[S];
+#pragma unroll
+    for (int l = 0; l < S - 1; ++l) h[l] = live ? P.heights[(size_t)c * P.M + (size_t)l * P.N + col] : T(0);
+    h[S - 1] = P.top[col];
+    T drho[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) drho[l] = (T)P.drho[l];
+    const T rho1 = (T)P.rho1, ig = (T)P.inv_gamma, dz = (T)P.dz;
+    T *out = P.rhat + (size_t)col * P.n_z * P.n_pad + c;
+#pragma unroll 2
+    for (int k = 0; k < P.n_z; ++k) {
+        const T z = ((T)k + T(0.5)) * dz;
+        T acc = -rho1 * (T)P.floor_sig[k];
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            const T e = vox_exp((z - h[l]) * ig);    // sigma_l = 1 / (1 + e)
+            acc += drho[l] * vox_rcp(T(1) + e);
+        }
+        out[(size_t)k * P.n_pad] = live ? acc * (T)P.inv_norm[k] : T(0);
+    }
+}
+
+// Linearised likelihood.  One wavefront walks kVoxRaysPerWave consecutive
+// rays for 64 chains (lane = chain); the voxel list of the current ray is
+// read once per wavefront.  Grid: XCD-aware (chain group, tile) map, so a
+// group's tiles share one XCD's L2.  Each block writes one partial sum per
+// chain of its group, summed over its rays in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> P) {
+    __shared__ double red[kVoxWaves][kVoxLanes];
+    const int n_groups = P.n_pad / kVoxLanes;
+    int group, tile;
+    xcd_chain_tile(P.n_tiles, n_groups, group, tile);
+    if (group >= n_groups) return;
+    const int lane = threadIdx.x & (kVoxLanes - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kVoxLanes);
+    const int c = group * kVoxLanes + lane;
+    const bool live = c < P.n_chains && !(P.only_nan && !(P.only_nan[c] != P.only_nan[c]));
+    const T *rh = P.rhat + c;
+    double tsum = 0.0;
+    const int p0 = tile * kVoxRaysPerTile + wave * kVoxRaysPerWave;
+    const int p1 = min(p0 + kVoxRaysPerWave, P.n_ray);
+    for (int p = p0; p < p1; ++p) {
+        const int beg = P.ray_off[p], end = P.ray_off[p + 1];
+        double o = 0.0;
+        int e = beg;
+        for (; e + 8 <= end; e += 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = rh[(size_t)P.vox[e + u] * P.n_pad];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) o += (double)(P.len[e + u] * v[u]);
+        }
+        for (; e < end; ++e) o += (double)(P.len[e] * rh[(size_t)P.vox[e] * P.n_pad]);
+        if (P.opacity && live) P.opacity[(size_t)c * P.n_ray + p] = (T)o;
+        const double l0 = P.lam0[p];
+        const double lam = l0 - (o - P.o0[p]) * (l0 * P.inv_atten);
+        tsum += lam > 0.0 ? P.cnt[p] * log(lam) - lam : -__builtin_huge_val();
+    }
+    red[wave][lane] = tsum;
+    __syncthreads();
+    if (wave == 0 && live) {
+        double s = red[0][lane];
+#pragma unroll
+        for (int w = 1; w < kVoxWaves; ++w) s += red[w][lane];
+        P.partials[(size_t)c * P.n_tiles + tile] = s;
+    }
+}
+
+}  // namespace mc
