@@ -14,7 +14,7 @@ timed steps; the line also carries log-posterior
 evaluations per second, the roofline of the ray-march kernel (timed alone
 with HIP events on the benchmark's stream) and the FP64 CPU oracle timed on a
 bounded sample on the host cores.  Other workloads (--workload hetero,
-grad128, hier, serve) print their own line; by default a short run of each is
+grad128, hier, voxel, serve) print their own line; by default a short run of each is
 summarised under "workloads" on the headline line.
 """
 from __future__ import annotations
@@ -50,6 +50,7 @@ OPS_CROSS_ADJ = OPS_CROSS + 32.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed VALU lane-op
 # per lane per clock; wave64 instructions issue over 4 clocks)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 
 # HBM bytes per launch of the march kernel, from two rocprofv3 --pmc runs of
@@ -61,17 +62,18 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # At 6 wavefronts per SIMD the march spills ~40 bytes per lane to scratch
 # once per wavefront; the dirty scratch lines written back at the end of the
 # kernel are most of WRITE_SIZE (about 1.7 bytes per ray).
-KERNEL_SOURCES = ("device_common.h", "march.h", "march3.h", "march5.h")
+KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march.h", "march3.h", "march5.h"),
+                  "voxel64": ("device_common.h", "voxel.h")}
 MEASURED_TRAFFIC = {
     "grf_cave_64": dict(source_sha="19c47320f57e0f33", fetch_kib=30543.7, fetch_scale=262144 / 131088.8,
                         write_kib=56935.9, write_scale=1.0),
 }
 
 
-def kernel_source_sha():
+def kernel_source_sha(name):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[name]:
         with open(os.path.join(ROOT, "paper_2603_28907_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -79,7 +81,7 @@ def kernel_source_sha():
 
 def measured_traffic(name):
     m = MEASURED_TRAFFIC.get(name)
-    if m is None or m["source_sha"] != kernel_source_sha():
+    if m is None or m["source_sha"] != kernel_source_sha(name):
         return None
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024
 
@@ -353,6 +355,82 @@ def bench_hier(args, torch):
     }
 
 
+def bench_voxel(args, torch):
+    """The paper's own forward model on the paper-scale workload: the
+    sigmoid-smoothed voxel density (n_z levels, gamma 1 m) and the likelihood
+    linearised around the synthetic truth, random-walk Metropolis on 1024
+    chains.  Roofline of each of its two kernels against HBM: the density
+    kernel writes R-hat once; the likelihood kernel's minimum traffic is one
+    read of R-hat plus the ray-voxel lists."""
+    from paper_2603_28907_amd import binding, inputs
+    from paper_2603_28907_amd.binding import Problem
+    sc, n_chains, w = make_workload("grf_cave_64")
+    sc.counts = gpu_counts(sc, torch)
+    prob = Problem.from_scenario(sc, precision="f32")
+    prob.set_voxel_model(args.n_z, 1.0, sc.truth)
+    n_z, n_pieces = prob.voxel_info()
+    H = torch.as_tensor(inputs.init_states(sc, n_chains, seed=w["init_seed"]), dtype=torch.float32,
+                        device="cuda:0").contiguous()
+    lp = torch.full((n_chains,), float("nan"), dtype=torch.float64, device="cuda:0")
+    acc = torch.zeros(n_chains, dtype=torch.int64, device="cuda:0")
+    G = max(1, min(args.graph_steps, args.steps))
+    prob.mcmc_run(H, lp, acc, args.warmup, w["sigma"], 1, graph_steps=min(G, max(args.warmup, 1)))
+    torch.cuda.synchronize()
+    a0 = acc.clone()
+    t0 = time.perf_counter()
+    prob.mcmc_run(H, lp, acc, args.steps, w["sigma"], 1, step_offset=args.warmup, graph_steps=G)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("[bench] timed region done", file=sys.stderr, flush=True)
+    assert torch.isfinite(lp).all(), "non-finite log posterior"
+    ms_dens, ms_lik = binding.time_voxel(prob, H, iters=args.march_iters)
+    n_pad = (n_chains + 63) // 64 * 64
+    n_vox = sc.n_rows * sc.n_cols * n_z
+    rhat_bytes = n_vox * n_pad * 4
+    lik_bytes = rhat_bytes + n_pieces * 8 + sc.n_rays * (4 + 3 * 8)
+    dens_gbs = rhat_bytes / (ms_dens * 1e-3) / 1e9
+    lik_gbs = lik_bytes / (ms_lik * 1e-3) / 1e9
+    dom = "k_vox_lik" if ms_lik >= ms_dens else "k_vox_density"
+    achieved = lik_gbs if dom == "k_vox_lik" else dens_gbs
+    out = {
+        "metric": METRIC, "value": n_chains * sc.n_rays * args.steps / dt, "unit": "ray-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"voxel64: the grf_cave_64 workload ({n_chains} chains, {sc.n_rays} rays) under "
+                               f"the paper's smoothed voxel model ({sc.n_rows}x{sc.n_cols}x{n_z} voxels, gamma 1 m) "
+                               f"linearised around the synthetic truth; random-walk Metropolis sigma {w['sigma']} m, "
+                               f"float32 densities, float64 sums, HIP graphs of {G} steps",
+                   "chains": n_chains, "rays": sc.n_rays, "voxels": n_vox, "ray_voxel_pieces": n_pieces},
+        "logpost_evals_per_s": n_chains * args.steps / dt,
+        "accept_rate": float((acc - a0).double().mean().item()) / args.steps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("voxel64") if dom == "k_vox_lik" else None,
+                     "traffic_unit": "bytes per launch (L2 to fabric: memory-side cache hits included)",
+                     "algorithmic_bytes": lik_bytes if dom == "k_vox_lik" else rhat_bytes, "kernel": dom,
+                     "ms_per_launch": max(ms_dens, ms_lik)},
+        "kernels": {"k_vox_density": {"ms_per_launch": ms_dens, "algorithmic_bytes": rhat_bytes,
+                                      "GB_per_s": dens_gbs, "frac_hbm": dens_gbs / HBM_PEAK_GBS},
+                    "k_vox_lik": {"ms_per_launch": ms_lik, "algorithmic_bytes": lik_bytes, "GB_per_s": lik_gbs,
+                                  "frac_hbm": lik_gbs / HBM_PEAK_GBS,
+                                  "gathered_bytes": n_pieces * n_pad * 4}},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.OracleProblem(sc)
+        orc.set_voxel_model(n_z, 1.0, sc.truth)
+        cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+        k = max(cores, 8)
+        states = H[:k].double().cpu().numpy()
+        t0 = time.perf_counter()
+        orc.logpost_batch(states)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": k * sc.n_rays / t, "unit": "ray-evals/s", "cores": cores, "kind": "oracle",
+                               "logpost_evals_per_s": k / t,
+                               "sample": f"{k} chains x 1 log-posterior evaluation of the voxel64 workload, FP64"}
+    return out
+
+
 def bench_serve(args, torch):
     """Serving: Poisson arrivals of heterogeneous jobs (sizes as the hetero
     workload), each run to a fixed number of steps per chain; the same
@@ -443,6 +521,7 @@ def main():
     ap.add_argument("--max-jobs", type=int, default=64, help="serve: resident jobs at once")
     ap.add_argument("--mala-eps", type=float, default=0.004, help="grad128: MALA step size (m)")
     ap.add_argument("--r-step", type=float, default=0.3, help="hier: step of the logit-r random walk")
+    ap.add_argument("--n-z", type=int, default=100, help="voxel: levels of the voxel grid")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the short hetero / grad128 / serve runs summarised after the headline line")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
@@ -458,6 +537,12 @@ def main():
     from paper_2603_28907_amd import binding, inputs
     from paper_2603_28907_amd.binding import Problem
 
+    if args.copy_calibration_mb > 0:
+        src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "hetero":
         print(json.dumps(bench_hetero(args, torch)), flush=True)
         return
@@ -467,15 +552,12 @@ def main():
     if args.workload == "grad128":
         print(json.dumps(bench_grad(args, torch)), flush=True)
         return
+    if args.workload == "voxel":
+        print(json.dumps(bench_voxel(args, torch)), flush=True)
+        return
     if args.workload == "hier":
         print(json.dumps(bench_hier(args, torch)), flush=True)
         return
-    if args.copy_calibration_mb > 0:
-        src = torch.ones(args.copy_calibration_mb << 20, dtype=torch.uint8, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     sc, n_chains, w = make_workload(args.workload)
     print(f"[bench] workload {args.workload}: {n_chains} chains x {sc.n_rays} rays", file=sys.stderr, flush=True)
     sc.counts = gpu_counts(sc, torch)
@@ -542,7 +624,7 @@ def main():
 
 def run_extras(args, torch):
     """Short runs of the other workloads (batched heterogeneous problems,
-    gradient sampling at 128x128, sampled r, serving), summarised beside the headline
+    gradient sampling at 128x128, sampled r, the voxel model, serving), summarised beside the headline
     line; each is independent and a failure is reported, not raised."""
     import copy
     res = {}
@@ -550,6 +632,8 @@ def run_extras(args, torch):
         ("hetero_256", bench_hetero, dict(steps=20, warmup=3, plain_steps=2, graph_steps=20, problems=256)),
         ("grad128", bench_grad, dict(steps=20, warmup=4, graph_steps=10, march_iters=5, mala_eps=0.004)),
         ("hier_r_64", bench_hier, dict(steps=50, warmup=10, graph_steps=50, r_step=0.3)),
+        ("voxel64", bench_voxel, dict(steps=20, warmup=4, graph_steps=10, march_iters=5, n_z=100,
+                                      no_cpu_baseline=True)),
         ("serve_20_per_s", bench_serve, dict(rate=20.0, duration=1.0, job_steps=2000, max_jobs=8, graph_steps=50,
                                              no_plain=True)),
     ]
@@ -558,6 +642,7 @@ def run_extras(args, torch):
         "grad128": ("value", "ms_per_step", "logpost_evals_per_s", "accept_rate", "gradient_evals_per_s"),
         "hier_r_64": ("value", "ms_per_step", "fixed_r_ms_per_step", "overhead_vs_fixed_r", "accept_rate",
                       "r_accept_rate", "r_mean"),
+        "voxel64": ("value", "ms_per_step", "logpost_evals_per_s", "accept_rate", "kernels"),
         "serve_20_per_s": ("value", "p50_s", "p99_s", "logpost_evals_per_s", "offered_load"),
     }
     for name, fn, over in jobs:

@@ -137,6 +137,10 @@ mc_status set_counts(mc_problem *p, const int32_t *counts);
  */
 mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *ref_heights);
 
+/* The voxel model's levels (0 when it is off) and the number of ray-voxel
+   pieces over all rays (the non-zeros of the sensitivity matrix G). */
+mc_status mc_voxel_info(const mc_problem *p, int *n_z, int64_t *n_pieces);
+
 /*
  * Log posterior of n_chains states.
  *   heights: device, [n_chains][S-1][n_rows][n_cols] in the handle's precision.

@@ -113,6 +113,7 @@ def load_library(path: Optional[str] = None):
         "mc_time_adjoint": (I, [V, I, V, I, V, P(ct.c_float)]),
         "set_voxel_model": (I, [V, I, D, V]),
         "mc_time_voxel": (I, [V, I, V, I, V, P(ct.c_float), P(ct.c_float)]),
+        "mc_voxel_info": (I, [V, P(I), P(ct.c_int64)]),
         "mc_server_create": (I, [P(ServerConfig), P(V)]),
         "mc_server_destroy": (None, [V, I]),
         "mc_server_last_error": (ct.c_char_p, [V]),
@@ -135,7 +136,7 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi",
                     "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
                     "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
-                    "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel")
+                    "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel", "mc_voxel_info")
 
 
 def _host(a, dtype=np.float64):
@@ -232,6 +233,12 @@ class Problem:
         if ref.size != (self.S - 1) * self.R * self.C:
             raise ValueError("ref_heights must hold (S-1)*R*C values")
         self._check(self.lib.set_voxel_model(self.h, int(n_z), float(gamma), _hp(ref)))
+
+    def voxel_info(self):
+        """(levels, ray-voxel pieces) of the voxel model; (0, 0) when it is off."""
+        nz, npc = ct.c_int(), ct.c_int64()
+        self._check(self.lib.mc_voxel_info(self.h, ct.byref(nz), ct.byref(npc)))
+        return int(nz.value), int(npc.value)
 
     @classmethod
     def from_scenario(cls, sc, counts=None, device: int = 0, precision: str = "f32"):

@@ -549,7 +549,8 @@ void launch_vox_density(const VoxParams<T> &V, hipStream_t st) {
 template <typename T>
 void launch_vox_lik(const VoxParams<T> &V, hipStream_t st) {
     const int groups = V.n_pad / kVoxLanes;
-    const dim3 grid((unsigned)V.n_tiles * (unsigned)((groups + kXcds - 1) / kXcds * kXcds));
+    const int tpx = (V.n_tiles + kXcds - 1) / kXcds;   // tiles per XCD and group
+    const dim3 grid((unsigned)groups * (unsigned)tpx * kXcds);
     hipLaunchKernelGGL((k_vox_lik<T>), grid, dim3(kVoxWaves * kVoxLanes), 0, st, V);
 }
 
@@ -1401,7 +1402,7 @@ void mc_destroy(mc_problem *p) {
             ++i;
         }
     }
-    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    drop_graph(p);   // destroys and clears the graph, so nothing below destroys it again
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     free_ptr(p->d_top);
     free_ptr(p->d_top64);
@@ -1821,6 +1822,13 @@ mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *re
     p->vox_dz = dz;
     p->vox_nz = n_z;
     drop_graph(p);
+    return MC_OK;
+}
+
+mc_status mc_voxel_info(const mc_problem *p, int *n_z, int64_t *n_pieces) {
+    if (!p || !n_z || !n_pieces) return MC_ERR_ARG;
+    *n_z = p->vox_nz;
+    *n_pieces = (int64_t)p->vox_nnz;
     return MC_OK;
 }
 

@@ -154,6 +154,14 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, T *w
         }
     }
     ok = block_and<BLOCK>(ok, ired);
+    // sum of the likelihood partials of the chain's tiles: strided per thread,
+    // then a block sum (fixed order for a given BLOCK)
+    double llp = 0.0;
+    if (P.has_lik) {
+        const double *pp = P.partials + (size_t)c * P.n_tiles;
+        for (int t = tid; t < P.n_tiles; t += BLOCK) llp += pp[t];
+    }
+    const double ll_sum = block_sum<BLOCK>(llp, red);
     if (HIER && !P.mh && P.stat_sw2 && tid == 0) {
         for (int l = 0; l < S - 1; ++l) {
             P.stat_sw2[(size_t)c * (S - 1) + l] = s_sw2[l];
@@ -161,12 +169,7 @@ __device__ __forceinline__ void prior_block(const PriorParams<T> &P, int c, T *w
         }
     }
     if (tid == 0) {
-        double ll = 0.0;
-        if (P.has_lik) {
-            const double *pp = P.partials + (size_t)c * P.n_tiles;
-            for (int t = 0; t < P.n_tiles; ++t) ll += pp[t];
-            ll += P.kconst;
-        }
+        const double ll = P.has_lik ? ll_sum + P.kconst : 0.0;
         const double total = ok ? lp + ll : -__builtin_huge_val();
         if (!P.mh) {
             P.lp_out[c] = total;

@@ -7,10 +7,11 @@
 // lambda-hat_p = lambda_p(R0) (1 - (O_p(R-hat) - O_p(R0)) / Lambda), where
 // O_p(R) = sum_v L_pv R_v: one gather-and-sum along the ray's voxel list.
 //
-// Layout: the smoothed density of every chain is kept chain-fastest,
-// rhat[v * n_pad + c], so that a wavefront walking one ray for 64 chains
-// reads 64 consecutive values per voxel (one 256-byte line pair in float32)
-// while the ray's voxel list is the same for every lane.
+// Layout: the smoothed densities are kept in groups of 64 chains, each group
+// contiguous and chain-fastest inside: rhat[((c/64) * V + v) * 64 + c%64]
+// for V = R*C*n_z voxels.  A wavefront walking one ray for the 64 chains of
+// a group reads 64 consecutive values per voxel (256 bytes in float32) while
+// the ray's voxel list is the same for every lane.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -20,16 +21,20 @@ namespace mc {
 
 constexpr int kVoxLanes = 64;          // chains per wavefront
 constexpr int kVoxWaves = 4;           // wavefronts per block
-constexpr int kVoxRaysPerWave = 32;    // rays one wavefront walks in turn
+constexpr int kVoxRaysPerWave = 4;     // rays one wavefront walks in turn
 constexpr int kVoxRaysPerTile = kVoxWaves * kVoxRaysPerWave;
+// float32 sigmoids whose argument exceeds this in magnitude are taken as
+// exactly 0 or 1: the neglected part, below exp(-30) = 9.4e-14, is far
+// under the float32 rounding of the density.
+constexpr float kVoxSatF32 = 30.0f;
 
 template <typename T>
 struct VoxParams {
     int R, C, N, n_z, M;       // grid, nodes, levels, heights per chain ((S-1)*N)
-    int n_chains, n_pad;       // chains, chain stride of rhat (multiple of 64)
+    int n_chains, n_pad;       // chains, chains rounded up to a multiple of 64
     const T *heights;          // [n][S-1][R][C]
     const T *top;              // [N]
-    T *rhat;                   // [N*n_z][n_pad]
+    T *rhat;                   // [n_pad/64][N*n_z][64]
     double dz, inv_gamma;
     double drho[kMaxSurfaces];   // rho_l - rho_{l+1} for units l = 1..S (rho_{S+1} = 0, the air)
     double rho1;
@@ -48,10 +53,13 @@ struct VoxParams {
     const double *only_nan;      // optional [n]: chains whose value is not NaN are skipped
 };
 
-__device__ __forceinline__ float vox_exp(float x) { return __expf(x); }
-__device__ __forceinline__ double vox_exp(double x) { return exp(x); }
-__device__ __forceinline__ float vox_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double vox_rcp(double x) { return 1.0 / x; }
+// sigma = 1 / (1 + exp(x)), x = (z - H) / gamma
+__device__ __forceinline__ double vox_sigma(double x) { return 1.0 / (1.0 + exp(x)); }
+__device__ __forceinline__ float vox_sigma(float x) {
+    if (x >= kVoxSatF32) return 0.0f;
+    if (x <= -kVoxSatF32) return 1.0f;
+    return __builtin_amdgcn_rcpf(1.0f + __expf(x));
+}
 
 // R-hat for every voxel of one column and one chain per thread.  Block:
 // 256 threads = 4 wavefronts of 64 consecutive chains of one column; grid:
@@ -73,37 +81,40 @@ __global__ __launch_bounds__(256) void k_vox_density(VoxParams<T> P) {
 #pragma unroll
     for (int l = 0; l < S; ++l) drho[l] = (T)P.drho[l];
     const T rho1 = (T)P.rho1, ig = (T)P.inv_gamma, dz = (T)P.dz;
-    T *out = P.rhat + (size_t)col * P.n_z * P.n_pad + c;
+    const size_t V = (size_t)P.N * P.n_z;
+    T *out = P.rhat + ((size_t)(c / kVoxLanes) * V + (size_t)col * P.n_z) * kVoxLanes + c % kVoxLanes;
 #pragma unroll 2
     for (int k = 0; k < P.n_z; ++k) {
         const T z = ((T)k + T(0.5)) * dz;
         T acc = -rho1 * (T)P.floor_sig[k];
 #pragma unroll
-        for (int l = 0; l < S; ++l) {
-            const T e = vox_exp((z - h[l]) * ig);    // sigma_l = 1 / (1 + e)
-            acc += drho[l] * vox_rcp(T(1) + e);
-        }
-        out[(size_t)k * P.n_pad] = live ? acc * (T)P.inv_norm[k] : T(0);
+        for (int l = 0; l < S; ++l) acc += drho[l] * vox_sigma((z - h[l]) * ig);
+        out[(size_t)k * kVoxLanes] = live ? acc * (T)P.inv_norm[k] : T(0);
     }
 }
 
 // Linearised likelihood.  One wavefront walks kVoxRaysPerWave consecutive
 // rays for 64 chains (lane = chain); the voxel list of the current ray is
-// read once per wavefront.  Grid: XCD-aware (chain group, tile) map, so a
-// group's tiles share one XCD's L2.  Each block writes one partial sum per
-// chain of its group, summed over its rays in a fixed order.
+// wavefront-uniform (scalar loads) and each voxel is one 64-chain row of
+// rhat.  Block order: chain groups one after another, and within a group
+// XCD x takes the contiguous tile range [x*tpx, (x+1)*tpx) (one sensor's
+// neighbouring rays per L2), so the blocks in flight read about one group's
+// densities, which then stay in the memory-side cache.  Each block writes
+// one partial sum per chain, summed over its rays in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> P) {
     __shared__ double red[kVoxWaves][kVoxLanes];
     const int n_groups = P.n_pad / kVoxLanes;
-    int group, tile;
-    xcd_chain_tile(P.n_tiles, n_groups, group, tile);
-    if (group >= n_groups) return;
+    const int b = blockIdx.x, x = b % kXcds, k = b / kXcds;
+    const int tpx = (P.n_tiles + kXcds - 1) / kXcds;
+    const int group = k / tpx, tile = x * tpx + k % tpx;
+    if (group >= n_groups || tile >= P.n_tiles) return;
     const int lane = threadIdx.x & (kVoxLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kVoxLanes);
     const int c = group * kVoxLanes + lane;
     const bool live = c < P.n_chains && !(P.only_nan && !(P.only_nan[c] != P.only_nan[c]));
-    const T *rh = P.rhat + c;
+    const T *grp = P.rhat + (size_t)group * P.N * P.n_z * kVoxLanes + lane;
+    auto row_at = [&](int v) -> T { return grp[(size_t)v * kVoxLanes]; };
     double tsum = 0.0;
     const int p0 = tile * kVoxRaysPerTile + wave * kVoxRaysPerWave;
     const int p1 = min(p0 + kVoxRaysPerWave, P.n_ray);
@@ -114,11 +125,11 @@ __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> 
         for (; e + 8 <= end; e += 8) {
             T v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = rh[(size_t)P.vox[e + u] * P.n_pad];
+            for (int u = 0; u < 8; ++u) v[u] = row_at(P.vox[e + u]);
 #pragma unroll
             for (int u = 0; u < 8; ++u) o += (double)(P.len[e + u] * v[u]);
         }
-        for (; e < end; ++e) o += (double)(P.len[e] * rh[(size_t)P.vox[e] * P.n_pad]);
+        for (; e < end; ++e) o += (double)(P.len[e] * row_at(P.vox[e]));
         if (P.opacity && live) P.opacity[(size_t)c * P.n_ray + p] = (T)o;
         const double l0 = P.lam0[p];
         const double lam = l0 - (o - P.o0[p]) * (l0 * P.inv_atten);

@@ -231,3 +231,21 @@ def test_paper_scale_sampled_chains(torch_mod, oracle_mod):
     ms_d, ms_l = time_voxel(prob, Hf, iters=3)
     say("ms density", ms_d, "ms likelihood", ms_l)
     assert ms_d > 0 and ms_l > 0
+
+
+def test_close_after_graph_capture_with_voxel_model(torch_mod, tiny):
+    """Destroying a problem that holds both a captured graph and the voxel
+    model releases each once (regression: the graph was destroyed twice)."""
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    states = inputs.init_states(tiny, 4, seed=11)
+    for _ in range(3):
+        prob = Problem.from_scenario(tiny, precision="f32")
+        prob.set_voxel_model(20, 1.0, tiny.truth)
+        H = to_dev(states, torch.float32)
+        lp = to_dev(np.full(4, np.nan), torch.float64)
+        acc = to_dev(np.zeros(4, np.int64), torch.int64)
+        prob.mcmc_run(H, lp, acc, 8, 0.05, 5, graph_steps=4)
+        torch.cuda.synchronize()
+        prob.close()
+    assert np.all(np.isfinite(lp.cpu().numpy()))
