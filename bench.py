@@ -65,8 +65,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march.h", "march3.h", "march5.h"),
                   "voxel64": ("device_common.h", "voxel.h")}
 MEASURED_TRAFFIC = {
-    "grf_cave_64": dict(source_sha="19c47320f57e0f33", fetch_kib=30543.7, fetch_scale=262144 / 131088.8,
-                        write_kib=56935.9, write_scale=1.0),
+    "grf_cave_64": dict(source_sha="9b722cd35d001b36", fetch_kib=30673.8, fetch_scale=262144 / 131093.4,
+                        write_kib=56985.9, write_scale=1.0),
+    # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
+    # in the memory-side cache are included
+    "voxel64": dict(source_sha="344071297b08c061", fetch_kib=2449389.3, fetch_scale=262144 / 131092.25,
+                    write_kib=70379.2, write_scale=1.0),
 }
 
 
