@@ -83,6 +83,10 @@ def _load():
         "orc_voxel_pieces": (I, [P, I, I, V, V]),
         "orc_voxel_loglik": (D, [P, V, V]),
         "orc_voxel_logpost_lik": (D, [P, V, V]),
+        "orc_nuts": (None, [P, ct.c_size_t, V, I, V, V, V, V, I, D, I64, I64, D, U64, U64, I, V, V, V, V, V]),
+        "orc_nested_rhat": (None, [I, I, ct.c_size_t, V, V]),
+        "orc_warmup_window_end": (I, [I64, I64]),
+        "orc_warmup_in_slow": (I, [I64, I64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -270,6 +274,18 @@ class OracleProblem:
                                int(step_offset), float(sigma), float(tau), int(seed), int(bool(state_f32)), _p(marg))
         return s.reshape(np.shape(states)), rr, lpa, acc, accr, marg
 
+    def nuts(self, states, lp, eps, inv_mass=None, max_depth=8, max_dh=1000.0, n_warmup=0, n_steps=1,
+             target_accept=0.8, seed=0, step_offset=0, state_f32=False):
+        """NUTS on this posterior; states [n, S-1, R, C]; eps [n]; inv_mass [n, S-1, R, C] or None."""
+        s = _f64(states).reshape(-1, self.M)
+        im = None if inv_mass is None else _f64(inv_mass).reshape(-1, self.M)
+        out = _nuts_call(ct.byref(self.prob), self.M, None, s, lp, eps, im, max_depth, max_dh, n_warmup, n_steps,
+                         target_accept, seed, step_offset, state_f32)
+        out["x"] = out["x"].reshape(np.shape(states))
+        if im is not None:
+            out["inv_mass"] = out["inv_mass"].reshape(np.shape(states))
+        return out
+
     def mcmc_mala(self, states, lp, n_accept, n_steps, step_offset, eps, seed, inv_mass=None,
                   state_f32=False, want_margins=False):
         s = _f64(states).copy()
@@ -282,6 +298,50 @@ class OracleProblem:
                                int(step_offset), float(eps), _p(im), int(seed),
                                int(bool(state_f32)), _p(marg))
         return s.reshape(np.shape(states)), lpa, acc, marg
+
+
+def _nuts_call(prob, n_dim, sd, x, lp, eps, inv_mass, max_depth, max_dh, n_warmup, n_steps, target_accept, seed,
+               step_offset, state_f32):
+    lib = _load()
+    n = x.shape[0]
+    x = _f64(x).copy()
+    lpa = _f64(lp).copy()
+    ea = _f64(eps).copy()
+    im = None if inv_mass is None else _f64(inv_mass).copy()
+    total = n_warmup + n_steps
+    depth = np.zeros((n, total), np.int32)
+    nl = np.zeros((n, total), np.int32)
+    dv = np.zeros((n, total), np.int32)
+    acc = np.zeros((n, total))
+    marg = np.zeros(n)
+    lib.orc_nuts(prob, int(n_dim), _p(sd), n, _p(x), _p(lpa), _p(ea), _p(im), int(max_depth), float(max_dh),
+                 int(n_warmup), int(n_steps), float(target_accept), int(seed), int(step_offset), int(bool(state_f32)),
+                 _p(depth), _p(nl), _p(dv), _p(acc), _p(marg))
+    return dict(x=x, lp=lpa, eps=ea, inv_mass=im, depth=depth, n_leap=nl, diverged=dv, accept_stat=acc,
+                margin=marg)
+
+
+def nuts_gauss(sd, x0, eps, inv_mass=None, max_depth=8, max_dh=1000.0, n_warmup=0, n_steps=1,
+               target_accept=0.8, seed=0, step_offset=0):
+    """NUTS on the test target N(0, diag(sd^2)); x0: [n_chains, dim]."""
+    sd = _f64(sd)
+    x0 = _f64(x0)
+    return _nuts_call(None, sd.size, sd, x0, np.full(x0.shape[0], np.nan), eps, inv_mass, max_depth, max_dh,
+                      n_warmup, n_steps, target_accept, seed, step_offset, False)
+
+
+def nested_rhat(x, n_super, n_within):
+    """Nested R-hat per coordinate from one draw per chain; x: [n_super*n_within, dim]."""
+    x = _f64(x)
+    x2 = x.reshape(x.shape[0], -1)
+    out = np.empty(x2.shape[1])
+    _load().orc_nested_rhat(int(n_super), int(n_within), x2.shape[1], _p(x2), _p(out))
+    return out.reshape(x.shape[1:])
+
+
+def warmup_window_ends(n_warmup):
+    lib = _load()
+    return [k for k in range(n_warmup) if lib.orc_warmup_window_end(int(n_warmup), k)]
 
 
 def ndtri_lower(u: float) -> float:

@@ -544,7 +544,8 @@ void orc_raw_philox(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, 
 /* MCMC: random-walk Metropolis and MALA                                       */
 /* ------------------------------------------------------------------------- */
 
-enum { TAG_PROPOSAL = 0, TAG_ACCEPT = 1, TAG_MOMENTUM = 2, TAG_R_PROPOSAL = 3, TAG_R_ACCEPT = 4 };
+enum { TAG_PROPOSAL = 0, TAG_ACCEPT = 1, TAG_MOMENTUM = 2, TAG_R_PROPOSAL = 3, TAG_R_ACCEPT = 4,
+       TAG_NUTS_MOMENTUM = 5, TAG_NUTS_DIRECTION = 6, TAG_NUTS_LEAF = 7, TAG_NUTS_MERGE = 8 };
 
 static double round_state(double x, int state_f32) { return state_f32 ? (double)(float)x : x; }
 
@@ -946,4 +947,439 @@ double orc_voxel_logpost_lik(const orc_problem *p, const double *free_h, double 
     free(Rhat);
     free(surf);
     return ll;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The paper's sampler: NUTS with step-size and diagonal-mass adaptation,     */
+/* and nested R-hat (Sec. 3.1, 3.2)                                            */
+/* ------------------------------------------------------------------------- */
+/*
+ * One NUTS transition (Hoffman & Gelman 2014) in its multinomial form with
+ * the generalised no-U-turn criterion (Betancourt 2017), as the paper's
+ * sampler library runs it.  The paper fixes the sampler, the 256-step
+ * trajectory cap (tree depth 8), the 0.8 acceptance target and diagonal
+ * preconditioning; the remaining details are read as follows.
+ *  - Momentum p ~ N(0, M), M = diag(1/inv_mass): p_i = z_i / sqrt(inv_mass_i),
+ *    z_i the (i%2)-th normal of pair i/2 of (chain, step, tag 5).
+ *    H = -lp + p.(inv_mass p)/2.  Leapfrog of step v*eps (v = +-1):
+ *    p += v eps/2 g;  x += v eps inv_mass p;  g = grad lp(x);  p += v eps/2 g.
+ *  - The tree doubles up to max_depth times.  Doubling d extends the end on
+ *    side v by a subtree of 2^d leaves, v = -1 iff the first uniform of
+ *    (tag 6, j = d) is below 1/2.
+ *  - A leaf with H - H0 > max_dH (or NaN) is a divergence: the subtree is
+ *    dropped and the transition ends.
+ *  - Inside a subtree the proposal is drawn leaf by leaf: leaf k replaces
+ *    it with probability w_k / (w_1 + ... + w_k), w = exp(H0 - H), using the
+ *    first uniform of (tag 7, j = index of the leaf in the trajectory); a
+ *    valid subtree's proposal replaces the tree's with probability
+ *    min(1, W_subtree / W_tree) (tag 8, j = d), and W_tree += W_subtree.
+ *  - U-turns: whenever two adjacent halves A (grown first) and B of a block
+ *    are complete (inside the subtree, and the old tree with the subtree),
+ *    the block is turning unless crit(a_far, b_far, rho_A + rho_B),
+ *    crit(a_far, b_near, rho_A + p_b_near) and crit(a_near, b_far,
+ *    p_a_near + rho_B) all hold; crit(x, y, rho) = (x.M^-1 rho > 0 and
+ *    y.M^-1 rho > 0), rho = sum of the momenta in the span, a_far/b_far the
+ *    outer ends, a_near/b_near the adjacent ones.  A turning subtree is
+ *    dropped; a turning tree ends the transition after its merge.
+ *  - Acceptance statistic: mean over all leaves computed of min(1, w).
+ * Random numbers come from the same Philox4x32-10 streams as the other
+ * samplers (key = seed, counter (j, step, tag, chain)).
+ */
+#define ORC_NUTS_MAX_DEPTH 12
+
+typedef double (*orc_target_fn)(const void *ctx, const double *x, double *grad);
+
+typedef struct {
+    int depth, n_leap, diverged, turned;
+    double accept_stat, margin;
+} orc_nuts_stats;
+
+static double crit_dot(const double *x, const double *im, const double *rho, size_t M) {
+    double s = 0.0;
+    for (size_t i = 0; i < M; ++i) s += x[i] * (im ? im[i] : 1.0) * rho[i];
+    return s;
+}
+
+static double nrm2(const double *x, size_t M) {
+    double s = 0.0;
+    for (size_t i = 0; i < M; ++i) s += x[i] * x[i];
+    return sqrt(s);
+}
+
+/* One criterion: both ends' sharp momenta have a positive projection on rho.
+   The margin records how close each dot product came to zero, relative. */
+static int crit_ok(const double *x, const double *y, const double *rho, const double *im, size_t M,
+                   double *margin) {
+    double dx = crit_dot(x, im, rho, M), dy = crit_dot(y, im, rho, M);
+    double sc = nrm2(rho, M) + 1e-300;
+    double mx = fabs(dx) / (sc * (nrm2(x, M) + 1e-300)), my = fabs(dy) / (sc * (nrm2(y, M) + 1e-300));
+    if (mx < *margin) *margin = mx;
+    if (my < *margin) *margin = my;
+    return dx > 0.0 && dy > 0.0;
+}
+
+/* turning of the merge of A (grown first) and B; tmp: M scratch */
+static int turning3(const double *rho_a, const double *a_far, const double *a_near, const double *rho_b,
+                    const double *b_near, const double *b_far, const double *im, size_t M, double *tmp,
+                    double *margin) {
+    int ok = 1;
+    for (size_t i = 0; i < M; ++i) tmp[i] = rho_a[i] + rho_b[i];
+    ok &= crit_ok(a_far, b_far, tmp, im, M, margin);
+    for (size_t i = 0; i < M; ++i) tmp[i] = rho_a[i] + b_near[i];
+    ok &= crit_ok(a_far, b_near, tmp, im, M, margin);
+    for (size_t i = 0; i < M; ++i) tmp[i] = a_near[i] + rho_b[i];
+    ok &= crit_ok(a_near, b_far, tmp, im, M, margin);
+    return !ok;
+}
+
+static double logaddexp(double a, double b) {
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    double m = a > b ? a : b;
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+static double first_uniform(uint64_t seed, uint32_t chain, uint64_t step, uint32_t tag, uint32_t j) {
+    double u[2];
+    orc_uniform_pair(seed, chain, step, tag, j, u);
+    return u[0];
+}
+
+/* x, lp, g: the chain's state (updated in place); im: inverse mass or NULL */
+static void nuts_transition(orc_target_fn target, const void *ctx, size_t M, double *x, double *lp, double *g,
+                            double eps, const double *im, int max_depth, double max_dh, uint64_t seed,
+                            uint32_t chain, uint64_t step, int state_f32, orc_nuts_stats *st) {
+    const int L = max_depth + 1;
+    /* ends of the tree: [0] = backward (v = -1) side, [1] = forward side */
+    double *xe[2], *pe[2], *ge[2];
+    double *xs = malloc(sizeof(double) * M), *gs = malloc(sizeof(double) * M);     /* subtree proposal */
+    double *xp = malloc(sizeof(double) * M), *gp = malloc(sizeof(double) * M);     /* tree proposal */
+    double *rho = malloc(sizeof(double) * M), *p_near = malloc(sizeof(double) * M), *tmp = malloc(sizeof(double) * M);
+    double *R = malloc(sizeof(double) * M * L), *F = malloc(sizeof(double) * M * L);
+    double *sR = malloc(sizeof(double) * M * L), *sF = malloc(sizeof(double) * M * L), *sL = malloc(sizeof(double) * M * L);
+    for (int e = 0; e < 2; ++e) {
+        xe[e] = malloc(sizeof(double) * M);
+        pe[e] = malloc(sizeof(double) * M);
+        ge[e] = malloc(sizeof(double) * M);
+    }
+    /* momentum and the initial energy */
+    double kin = 0.0;
+    for (size_t i = 0; i < M; i += 2) {
+        double z[2];
+        orc_normal_pair(seed, chain, step, TAG_NUTS_MOMENTUM, (uint32_t)(i / 2), z);
+        for (int e = 0; e < 2 && i + e < M; ++e) {
+            double mi = im ? im[i + e] : 1.0;
+            pe[0][i + e] = z[e] / sqrt(mi);
+            kin += mi * pe[0][i + e] * pe[0][i + e];
+        }
+    }
+    const double H0 = -*lp + 0.5 * kin;
+    memcpy(pe[1], pe[0], sizeof(double) * M);
+    for (int e = 0; e < 2; ++e) {
+        memcpy(xe[e], x, sizeof(double) * M);
+        memcpy(ge[e], g, sizeof(double) * M);
+    }
+    memcpy(xp, x, sizeof(double) * M);
+    memcpy(gp, g, sizeof(double) * M);
+    double lpp = *lp, logW = 0.0, sum_acc = 0.0, margin = INFINITY;
+    memcpy(rho, pe[0], sizeof(double) * M);
+    int depth = 0, n_leap = 0, diverged = 0, turned = 0;
+    uint32_t leaf = 0;
+    while (depth < max_depth) {
+        const double ud = first_uniform(seed, chain, step, TAG_NUTS_DIRECTION, (uint32_t)depth);
+        if (fabs(ud - 0.5) < margin) margin = fabs(ud - 0.5);
+        const int side = ud < 0.5 ? 0 : 1;
+        const double v = side ? 1.0 : -1.0;
+        memcpy(p_near, pe[side], sizeof(double) * M);
+        double logWs = -INFINITY, lps = 0.0;
+        int valid = 1;
+        const int n_sub = 1 << depth;
+        for (int i = 0; i < n_sub && valid; ++i) {
+            /* leapfrog from this side's end */
+            double *xx = xe[side], *pp = pe[side], *gg = ge[side];
+            for (size_t k = 0; k < M; ++k) {
+                pp[k] += 0.5 * v * eps * gg[k];
+                xx[k] = round_state(xx[k] + v * eps * (im ? im[k] : 1.0) * pp[k], state_f32);
+            }
+            double lpl = target(ctx, xx, gg);
+            double kl = 0.0;
+            for (size_t k = 0; k < M; ++k) {
+                pp[k] += 0.5 * v * eps * gg[k];
+                kl += (im ? im[k] : 1.0) * pp[k] * pp[k];
+            }
+            ++n_leap;
+            const double dH = (-lpl + 0.5 * kl) - H0;
+            if (isfinite(dH) && fabs(dH - max_dh) < margin) margin = fabs(dH - max_dh);
+            if (!(dH <= max_dh)) {          /* divergence (NaN included) */
+                diverged = 1;
+                valid = 0;
+                if (dH == dH) sum_acc += fmin(1.0, exp(-dH));
+                break;
+            }
+            const double lw = -dH;
+            sum_acc += fmin(1.0, exp(lw));
+            const double logWs_new = logaddexp(logWs, lw);
+            const double ul = first_uniform(seed, chain, step, TAG_NUTS_LEAF, leaf);
+            ++leaf;
+            if (i > 0 && fabs(log(ul) - (lw - logWs_new)) < margin) margin = fabs(log(ul) - (lw - logWs_new));
+            if (i == 0 || log(ul) < lw - logWs_new) {
+                memcpy(xs, xx, sizeof(double) * M);
+                memcpy(gs, gg, sizeof(double) * M);
+                lps = lpl;
+            }
+            logWs = logWs_new;
+            /* block bookkeeping: level j blocks hold 2^j consecutive leaves */
+            for (int j = 0; j <= depth; ++j) {
+                double *Rj = R + (size_t)j * M, *Fj = F + (size_t)j * M;
+                if ((i & ((1 << j) - 1)) == 0) {
+                    memset(Rj, 0, sizeof(double) * M);
+                    memcpy(Fj, pp, sizeof(double) * M);
+                }
+                for (size_t k = 0; k < M; ++k) Rj[k] += pp[k];
+            }
+            for (int j = 1; j <= depth; ++j) {
+                if (((i + 1) & ((1 << j) - 1)) != 0) continue;
+                /* a level-j block completed: halves A = saved sibling, B = the level j-1 block */
+                const size_t a = (size_t)(j - 1) * M;
+                if (turning3(sR + a, sF + a, sL + a, R + a, F + a, pp, im, M, tmp, &margin)) {
+                    valid = 0;
+                    break;
+                }
+            }
+            if (!valid) break;
+            for (int j = 0; j < depth; ++j) {
+                if (((i + 1) & ((1 << j) - 1)) != 0 || !(((i + 1) >> j) & 1)) continue;
+                /* a level-j block completed as the first half of its parent */
+                const size_t a = (size_t)j * M;
+                memcpy(sR + a, R + a, sizeof(double) * M);
+                memcpy(sF + a, F + a, sizeof(double) * M);
+                memcpy(sL + a, pp, sizeof(double) * M);
+            }
+        }
+        if (!valid) break;
+        /* merge the subtree into the tree */
+        const double um = first_uniform(seed, chain, step, TAG_NUTS_MERGE, (uint32_t)depth);
+        if (fabs(log(um) - (logWs - logW)) < margin) margin = fabs(log(um) - (logWs - logW));
+        if (log(um) < logWs - logW) {
+            memcpy(xp, xs, sizeof(double) * M);
+            memcpy(gp, gs, sizeof(double) * M);
+            lpp = lps;
+        }
+        logW = logaddexp(logW, logWs);
+        const double *rho_b = R + (size_t)depth * M, *b_near = F + (size_t)depth * M;
+        turned = turning3(rho, pe[1 - side], p_near, rho_b, b_near, pe[side], im, M, tmp, &margin);
+        for (size_t k = 0; k < M; ++k) rho[k] += rho_b[k];
+        ++depth;
+        if (turned) break;
+    }
+    memcpy(x, xp, sizeof(double) * M);
+    memcpy(g, gp, sizeof(double) * M);
+    *lp = lpp;
+    st->depth = depth;
+    st->n_leap = n_leap;
+    st->diverged = diverged;
+    st->turned = turned;
+    st->accept_stat = n_leap ? sum_acc / n_leap : 0.0;
+    st->margin = margin;
+    for (int e = 0; e < 2; ++e) { free(xe[e]); free(pe[e]); free(ge[e]); }
+    free(xs); free(gs); free(xp); free(gp); free(rho); free(p_near); free(tmp);
+    free(R); free(F); free(sR); free(sF); free(sL);
+}
+
+/* The cave posterior as a target: log posterior and its gradient in the free surfaces. */
+typedef struct { const orc_problem *p; double *gfull; } cave_ctx;
+
+static double cave_target(const void *vctx, const double *x, double *grad) {
+    const cave_ctx *c = (const cave_ctx *)vctx;
+    const size_t M = (size_t)(c->p->S - 1) * c->p->R * c->p->C;
+    double lp = orc_grad(c->p, x, c->gfull);
+    memcpy(grad, c->gfull, sizeof(double) * M);
+    return lp;
+}
+
+/* A Gaussian test target N(0, diag(sd^2)) in M dimensions (for pins). */
+typedef struct { size_t M; const double *sd; } gauss_ctx;
+
+static double gauss_target(const void *vctx, const double *x, double *grad) {
+    const gauss_ctx *c = (const gauss_ctx *)vctx;
+    double lp = 0.0;
+    for (size_t i = 0; i < c->M; ++i) {
+        double s2 = c->sd[i] * c->sd[i];
+        lp -= 0.5 * x[i] * x[i] / s2;
+        grad[i] = -x[i] / s2;
+    }
+    return lp;
+}
+
+/* Dual averaging of log(step size) (Hoffman & Gelman 2014, Sec. 3.2), per chain. */
+typedef struct { double log_eps, log_eps_bar, h_bar, mu; int64_t t; } orc_dual_avg;
+
+static void da_restart(orc_dual_avg *d, double eps) {
+    d->mu = log(10.0 * eps);
+    d->log_eps = log(eps);
+    d->log_eps_bar = 0.0;
+    d->h_bar = 0.0;
+    d->t = 0;
+}
+
+static void da_update(orc_dual_avg *d, double accept_stat, double target) {
+    const double gamma = 0.05, t0 = 10.0, kappa = 0.75;
+    d->t += 1;
+    const double t = (double)d->t;
+    d->h_bar = (1.0 - 1.0 / (t + t0)) * d->h_bar + (target - accept_stat) / (t + t0);
+    d->log_eps = d->mu - sqrt(t) / gamma * d->h_bar;
+    const double eta = pow(t, -kappa);
+    d->log_eps_bar = eta * d->log_eps + (1.0 - eta) * d->log_eps_bar;
+}
+
+/* Warm-up windows: an initial buffer (step size only), slow windows that
+   double in length and each end with a mass-matrix update, and a terminal
+   buffer (step size only).  Defaults 75 / 25 / 50; when they do not fit,
+   15 % / 75 % / 10 % of the warm-up.  Returns 1 if the window containing
+   iteration k (0-based) ends at k and is a slow window. */
+static void warmup_layout(int64_t n_warmup, int64_t *init_buf, int64_t *base_win, int64_t *term_buf) {
+    *init_buf = 75; *base_win = 25; *term_buf = 50;
+    if (n_warmup < 20) { *init_buf = n_warmup; *base_win = 0; *term_buf = 0; return; }
+    if (*init_buf + *base_win + *term_buf > n_warmup) {
+        *init_buf = (int64_t)(0.15 * n_warmup);
+        *term_buf = (int64_t)(0.1 * n_warmup);
+        *base_win = n_warmup - *init_buf - *term_buf;
+    }
+}
+
+int orc_warmup_window_end(int64_t n_warmup, int64_t k) {
+    int64_t ib, bw, tb;
+    warmup_layout(n_warmup, &ib, &bw, &tb);
+    if (bw == 0) return 0;
+    const int64_t slow_end = n_warmup - tb;
+    int64_t start = ib, len = bw;
+    while (start < slow_end) {
+        int64_t end = start + len;
+        /* a window that would leave less than twice its length before the terminal buffer absorbs it */
+        if (end + 2 * len > slow_end) end = slow_end;
+        if (k == end - 1) return 1;
+        start = end;
+        len *= 2;
+    }
+    return 0;
+}
+
+int orc_warmup_in_slow(int64_t n_warmup, int64_t k) {
+    int64_t ib, bw, tb;
+    warmup_layout(n_warmup, &ib, &bw, &tb);
+    return bw > 0 && k >= ib && k < n_warmup - tb;
+}
+
+/*
+ * NUTS on the cave posterior (or, with gauss_sd non-NULL, on N(0, diag(sd^2))
+ * in M = n_dim dimensions), chains in parallel.  Chain c: state x[c] (M),
+ * lp[c] (NaN: computed first), step size eps[c] (in/out), inverse mass
+ * inv_mass[c] ([n][M], in/out; NULL = identity, not adapted).
+ * n_warmup > 0 runs that many adapting transitions first (dual averaging to
+ * target_accept; with inv_mass, windowed variance estimates: each slow window
+ * ends with inv_mass = (n/(n+5)) var + 1e-3 * 5/(n+5) of its draws, and every
+ * window end restarts dual averaging from the current step size); then
+ * n_steps transitions at the adapted eps = exp(log_eps_bar).  Step k of the
+ * whole run uses Philox step step_offset + k.  Outputs (optional):
+ * depth/n_leap/diverged [n][n_warmup + n_steps], accept_stat likewise,
+ * margin [n] = smallest decision margin seen.
+ */
+void orc_nuts(const orc_problem *p, size_t n_dim, const double *gauss_sd, int n_chains, double *x_all,
+              double *lp, double *eps, double *inv_mass, int max_depth, double max_dh, int64_t n_warmup,
+              int64_t n_steps, double target_accept, uint64_t seed, uint64_t step_offset, int state_f32,
+              int32_t *depth_out, int32_t *n_leap_out, int32_t *div_out, double *acc_out, double *margin_out) {
+    const size_t M = gauss_sd ? n_dim : (size_t)(p->S - 1) * p->R * p->C;
+    const size_t NS = gauss_sd ? n_dim : (size_t)p->S * p->R * p->C;
+    if (max_depth > ORC_NUTS_MAX_DEPTH) max_depth = ORC_NUTS_MAX_DEPTH;
+    const int64_t total = n_warmup + n_steps;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < n_chains; ++c) {
+        double *x = x_all + M * c;
+        double *im = inv_mass ? inv_mass + M * c : NULL;
+        double *g = malloc(sizeof(double) * M);
+        double *gfull = malloc(sizeof(double) * NS);
+        double *wm = malloc(sizeof(double) * M), *w2 = malloc(sizeof(double) * M);   /* Welford */
+        int64_t wn = 0;
+        cave_ctx cc = {p, gfull};
+        gauss_ctx gc = {M, gauss_sd};
+        orc_target_fn tf = gauss_sd ? gauss_target : cave_target;
+        const void *ctx = gauss_sd ? (const void *)&gc : (const void *)&cc;
+        double l = tf(ctx, x, g);
+        if (isnan(lp[c])) lp[c] = l;
+        orc_dual_avg da;
+        da_restart(&da, eps[c]);
+        double margin = INFINITY;
+        for (int64_t k = 0; k < total; ++k) {
+            const int warm = k < n_warmup;
+            const double e = warm ? exp(da.log_eps) : eps[c];
+            orc_nuts_stats st;
+            nuts_transition(tf, ctx, M, x, &lp[c], g, e, im, max_depth, max_dh, seed, (uint32_t)c,
+                            step_offset + (uint64_t)k, state_f32, &st);
+            if (st.margin < margin) margin = st.margin;
+            const size_t o = (size_t)c * total + k;
+            if (depth_out) depth_out[o] = st.depth;
+            if (n_leap_out) n_leap_out[o] = st.n_leap;
+            if (div_out) div_out[o] = st.diverged;
+            if (acc_out) acc_out[o] = st.accept_stat;
+            if (!warm) continue;
+            da_update(&da, st.accept_stat, target_accept);
+            if (im && orc_warmup_in_slow(n_warmup, k)) {
+                ++wn;
+                for (size_t i = 0; i < M; ++i) {
+                    if (wn == 1) { wm[i] = x[i]; w2[i] = 0.0; continue; }
+                    const double d = x[i] - wm[i];
+                    wm[i] += d / wn;
+                    w2[i] += d * (x[i] - wm[i]);
+                }
+                if (orc_warmup_window_end(n_warmup, k)) {
+                    const double n = (double)wn;
+                    for (size_t i = 0; i < M; ++i) {
+                        const double var = wn > 1 ? w2[i] / (n - 1.0) : 0.0;
+                        im[i] = (n / (n + 5.0)) * var + 1e-3 * (5.0 / (n + 5.0));
+                    }
+                    wn = 0;
+                    da_restart(&da, exp(da.log_eps));
+                }
+            }
+            if (k == n_warmup - 1) eps[c] = exp(da.log_eps_bar);
+        }
+        if (margin_out) margin_out[c] = margin;
+        free(g); free(gfull); free(wm); free(w2);
+    }
+}
+
+/*
+ * Nested R-hat (the paper's convergence diagnostic, Sec. 3.2) from one draw
+ * per chain: chains c = k*n_within + m form n_super super-chains of n_within.
+ * Per coordinate i: super-chain means xk, overall mean x, between-super-chain
+ * variance B = sum_k (xk - x)^2 / (K - 1), within W = mean_k of the variance
+ * of the chains of super-chain k about xk (divisor n_within - 1; the
+ * within-chain variance of a single draw is zero); nR = sqrt(1 + B / W).
+ * x_all: [n_super*n_within][n_dim]; out: [n_dim].
+ */
+void orc_nested_rhat(int n_super, int n_within, size_t n_dim, const double *x_all, double *out) {
+    for (size_t i = 0; i < n_dim; ++i) {
+        double xbar = 0.0, B = 0.0, W = 0.0;
+        double *xk = malloc(sizeof(double) * n_super);
+        for (int k = 0; k < n_super; ++k) {
+            double s = 0.0;
+            for (int m = 0; m < n_within; ++m) s += x_all[(size_t)(k * n_within + m) * n_dim + i];
+            xk[k] = s / n_within;
+            xbar += xk[k];
+        }
+        xbar /= n_super;
+        for (int k = 0; k < n_super; ++k) {
+            B += (xk[k] - xbar) * (xk[k] - xbar);
+            double v = 0.0;
+            for (int m = 0; m < n_within; ++m) {
+                double d = x_all[(size_t)(k * n_within + m) * n_dim + i] - xk[k];
+                v += d * d;
+            }
+            W += v / (n_within - 1);
+        }
+        B /= (n_super - 1);
+        W /= n_super;
+        out[i] = sqrt(1.0 + B / W);
+        free(xk);
+    }
 }
