@@ -237,6 +237,71 @@ mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t);
 mc_status mc_get_tuning(const mc_problem *p, mc_tuning *t);
 
 /*
+ * The paper's sampler (Sec. 3.1, 3.2): NUTS (Hoffman & Gelman 2014) in its
+ * multinomial form with the generalised no-U-turn criterion, dual-averaging
+ * step size adaptation toward target_accept and windowed diagonal
+ * inverse-mass estimation during warm-up, on the exact march's gradient.
+ * Chains run in lock step: one batched log-posterior gradient per leapfrog
+ * step for all chains, doublings stop once every tree is finished.
+ * Definition (shared with the reference implementation in the tests):
+ *   momentum p_i = z_i / sqrt(inv_mass_i), z_i the (i%2)-th normal of pair
+ *   i/2 of Philox (chain, step, tag 5); doubling d grows the side v = -1 iff
+ *   the first uniform of (tag 6, j = d) is < 1/2; inside a subtree leaf k
+ *   becomes the proposal with probability w_k / sum_{j<=k} w_j (tag 7, j =
+ *   leaf index in the trajectory), w = exp(H0 - H); a valid subtree's
+ *   proposal replaces the tree's with probability min(1, W_sub / W_tree)
+ *   (tag 8, j = d); H - H0 > max_delta_h (or NaN) is a divergence, which
+ *   drops the subtree and ends the transition; each completed block of two
+ *   halves, and each merge, passes the three generalised criteria or ends
+ *   the transition (a turning subtree is dropped).  A state of zero density
+ *   does not move.  Warm-up: transition k uses exp(log eps_k) of dual
+ *   averaging (gamma 0.05, t0 10, kappa 0.75); slow windows (initial buffer
+ *   75, windows from 25 doubling, terminal buffer 50; 15/75/10 % below 150
+ *   transitions) end with inv_mass = (n/(n+5)) var + 1e-3 * 5/(n+5) of their
+ *   draws and a restart of dual averaging from the current step; after the
+ *   warm-up eps = exp(log eps_bar).  Step k of the call uses Philox step
+ *   step_offset + k.
+ */
+typedef struct {
+    int64_t n_warmup;       /* adapting transitions first (>= 0) */
+    int64_t n_steps;        /* transitions after the warm-up (>= 0) */
+    int max_depth;          /* tree depth cap in [1, 10]; the paper's 256-step cap is 8 */
+    int adapt_mass;         /* 1: estimate inv_mass during the warm-up (needs inv_mass) */
+    double max_delta_h;     /* divergence threshold on H - H0 (> 0; 1000 is usual) */
+    double target_accept;   /* dual-averaging target in (0, 1); the paper uses 0.8 */
+    uint64_t seed;          /* Philox4x32-10 key */
+    uint64_t step_offset;   /* Philox step of the first transition */
+} mc_nuts_config;
+
+/*
+ * NUTS on n_chains chains (stream-ordered, device arrays):
+ *   heights [n][S-1][R][C] in/out, logpost [n] out (recomputed on entry),
+ *   step_size [n] f64 in/out (in: the start of dual averaging, or the step
+ *   used when n_warmup = 0; out: the adapted step), inv_mass [n][S-1][R][C]
+ *   f64 in/out or NULL (identity), and optional per-transition outputs
+ *   [n][n_warmup + n_steps]: tree_depth, n_leapfrog, diverged (int32) and
+ *   accept_stat (f64, mean of min(1, w) over the leaves computed).
+ * Device memory: about (6 + 5 (max_depth + 1)) * 8 + 9 * sizeof(state)
+ * bytes per chain and free node, plus the gradient workspaces.  Errors:
+ * MC_ERR_ARG for invalid sizes or pointers, MC_ERR_UNSUPPORTED while the
+ * voxel model is set.
+ */
+mc_status nuts_run(mc_problem *p, const mc_nuts_config *cfg, int n_chains, void *heights, double *logpost,
+                   double *step_size, double *inv_mass, int32_t *tree_depth, int32_t *n_leapfrog,
+                   int32_t *diverged, double *accept_stat, void *stream);
+
+/*
+ * Nested R-hat (Sec. 3.2) of every free node from one draw per chain:
+ * chains c = k*n_within + m of heights [n_super*n_within][S-1][R][C] form
+ * n_super super-chains.  rhat[(S-1)*R*C] (device f64) = sqrt(1 + B / W), B
+ * the variance of the super-chain means (divisor n_super - 1), W the mean
+ * over super-chains of the variance of their chains about the super-chain
+ * mean (divisor n_within - 1).  n_super, n_within >= 2.
+ */
+mc_status nested_rhat(mc_problem *p, int n_super, int n_within, const void *heights, double *rhat,
+                      void *stream);
+
+/*
  * Random-walk Metropolis on many independent problems at once (paper
  * Sec. 3.2: independent chains vectorised on one device, here across
  * problems as well).  Problem i runs cfgs[i] on its n_chains[i] chains with

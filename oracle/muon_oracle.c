@@ -982,6 +982,7 @@ double orc_voxel_logpost_lik(const orc_problem *p, const double *free_h, double 
  *    outer ends, a_near/b_near the adjacent ones.  A turning subtree is
  *    dropped; a turning tree ends the transition after its merge.
  *  - Acceptance statistic: mean over all leaves computed of min(1, w).
+ *  - A state of zero density (outside the support) does not move.
  * Random numbers come from the same Philox4x32-10 streams as the other
  * samplers (key = seed, counter (j, step, tag, chain)).
  */
@@ -1050,6 +1051,12 @@ static void nuts_transition(orc_target_fn target, const void *ctx, size_t M, dou
                             double eps, const double *im, int max_depth, double max_dh, uint64_t seed,
                             uint32_t chain, uint64_t step, int state_f32, orc_nuts_stats *st) {
     const int L = max_depth + 1;
+    if (!(*lp > -INFINITY)) {   /* a state of zero density does not move */
+        st->depth = st->n_leap = st->diverged = st->turned = 0;
+        st->accept_stat = 0.0;
+        st->margin = INFINITY;
+        return;
+    }
     /* ends of the tree: [0] = backward (v = -1) side, [1] = forward side */
     double *xe[2], *pe[2], *ge[2];
     double *xs = malloc(sizeof(double) * M), *gs = malloc(sizeof(double) * M);     /* subtree proposal */

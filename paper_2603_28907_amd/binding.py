@@ -42,6 +42,12 @@ class RunConfig(ct.Structure):
                 ("n_accept_r", ct.c_void_p)]
 
 
+class NutsConfig(ct.Structure):
+    _fields_ = [("n_warmup", ct.c_int64), ("n_steps", ct.c_int64), ("max_depth", ct.c_int), ("adapt_mass", ct.c_int),
+                ("max_delta_h", ct.c_double), ("target_accept", ct.c_double), ("seed", ct.c_uint64),
+                ("step_offset", ct.c_uint64)]
+
+
 class ServerConfig(ct.Structure):
     _fields_ = [("device", ct.c_int), ("precision", ct.c_int), ("memory_budget", ct.c_size_t),
                 ("reserve", ct.c_size_t), ("max_jobs", ct.c_int), ("steps_per_round", ct.c_int)]
@@ -114,6 +120,8 @@ def load_library(path: Optional[str] = None):
         "set_voxel_model": (I, [V, I, D, V]),
         "mc_time_voxel": (I, [V, I, V, I, V, P(ct.c_float), P(ct.c_float)]),
         "mc_voxel_info": (I, [V, P(I), P(ct.c_int64)]),
+        "nuts_run": (I, [V, P(NutsConfig), I, V, V, V, V, V, V, V, V, V]),
+        "nested_rhat": (I, [V, I, I, V, V, V]),
         "mc_server_create": (I, [P(ServerConfig), P(V)]),
         "mc_server_destroy": (None, [V, I]),
         "mc_server_last_error": (ct.c_char_p, [V]),
@@ -136,7 +144,8 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "mc_version", "mc_time_march", "mc_set_tuning", "mc_get_tuning", "mcmc_run_multi",
                     "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
                     "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
-                    "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel", "mc_voxel_info")
+                    "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel", "mc_voxel_info",
+                    "nuts_run", "nested_rhat")
 
 
 def _host(a, dtype=np.float64):
@@ -299,6 +308,49 @@ class Problem:
                                                 ct.c_void_p(logpost.data_ptr()), ct.c_void_p(grad.data_ptr()),
                                                 _stream_handle(stream, self.device)))
         return logpost, grad
+
+    def nuts_run(self, heights, logpost, step_size, n_steps, seed, n_warmup=0, max_depth=8, inv_mass=None,
+                 adapt_mass=False, max_delta_h=1000.0, target_accept=0.8, step_offset=0, stats=True, stream=None):
+        """NUTS (with optional warm-up adaptation) on the chains in place.  step_size [n] float64 and
+        inv_mass [n, S-1, R, C] float64 (or None) are device tensors, updated by the warm-up.  With
+        stats, returns dict of per-transition tree_depth, n_leapfrog, diverged, accept_stat tensors."""
+        import torch
+        n = int(heights.shape[0])
+        self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
+        self._check_tensor(logpost, (n,), torch.float64, "logpost")
+        self._check_tensor(step_size, (n,), torch.float64, "step_size")
+        im = None
+        if inv_mass is not None:
+            self._check_tensor(inv_mass, self.heights_shape(n), torch.float64, "inv_mass")
+            im = inv_mass.data_ptr()
+        total = int(n_warmup) + int(n_steps)
+        out = None
+        ptrs = [None] * 4
+        if stats and total > 0:
+            dev = heights.device
+            out = dict(tree_depth=torch.zeros((n, total), dtype=torch.int32, device=dev),
+                       n_leapfrog=torch.zeros((n, total), dtype=torch.int32, device=dev),
+                       diverged=torch.zeros((n, total), dtype=torch.int32, device=dev),
+                       accept_stat=torch.zeros((n, total), dtype=torch.float64, device=dev))
+            ptrs = [out[k].data_ptr() for k in ("tree_depth", "n_leapfrog", "diverged", "accept_stat")]
+        cfg = NutsConfig(int(n_warmup), int(n_steps), int(max_depth), int(bool(adapt_mass)), float(max_delta_h),
+                         float(target_accept), int(seed), int(step_offset))
+        self._check(self.lib.nuts_run(self.h, ct.byref(cfg), n, ct.c_void_p(heights.data_ptr()),
+                                      ct.c_void_p(logpost.data_ptr()), ct.c_void_p(step_size.data_ptr()),
+                                      im, *ptrs, _stream_handle(stream, self.device)))
+        return out
+
+    def nested_rhat(self, heights, n_super, n_within, stream=None):
+        """Nested R-hat of every free node from the chains' current states (one draw per chain)."""
+        import torch
+        n = int(heights.shape[0])
+        if n != int(n_super) * int(n_within):
+            raise ValueError(f"{n} chains are not {n_super} super-chains of {n_within}")
+        self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
+        out = torch.empty(self.heights_shape(1)[1:], dtype=torch.float64, device=heights.device)
+        self._check(self.lib.nested_rhat(self.h, int(n_super), int(n_within), ct.c_void_p(heights.data_ptr()),
+                                         ct.c_void_p(out.data_ptr()), _stream_handle(stream, self.device)))
+        return out
 
     def mcmc_run(self, heights, logpost, n_accept, n_steps, step_size, seed, step_offset=0, kernel=KERNEL_RW,
                  graph_steps=1, inv_mass=None, stream=None, r_state=None, r_step=0.0, n_accept_r=None):

@@ -26,6 +26,7 @@
 #include "prior.h"
 #include "probe.h"
 #include "voxel.h"
+#include "nuts.h"
 
 using namespace mc;
 
@@ -103,6 +104,7 @@ struct mc_problem {
     double *d_vox_lam0 = nullptr, *d_vox_o0 = nullptr, *d_vox_fsig = nullptr, *d_vox_inorm = nullptr;
     size_t vox_nnz = 0;
     DevBuf rhat;   // [R*C*n_z][n_pad] smoothed densities of the chains
+    DevBuf nutsbuf;   // NUTS trees, proposals and warm-up accumulators
     // workspaces (grow only)
     DevBuf partials, prop, lptmp;
     DevBuf rstat;   // [2][n][S-1] sum w^2 and edge sums of the current states (r sampling)
@@ -1418,7 +1420,7 @@ void mc_destroy(mc_problem *p) {
     clear_voxel_model(p);
     for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
     for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gprior, &p->gcur, &p->gprop,
-                      &p->lpprop, &p->rstat, &p->rhat})
+                      &p->lpprop, &p->rstat, &p->rhat, &p->nutsbuf})
         if (b->p) (void)hipFree(b->p);
     if (p->d_step) (void)hipFree(p->d_step);
     delete p;
@@ -1647,6 +1649,247 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? mcmc_dispatch<double>(p, cfg, n_chains, heights, logpost, n_accept, st)
                              : mcmc_dispatch<float>(p, cfg, n_chains, heights, logpost, n_accept, st);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// NUTS
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Warm-up windows (Stan's layout): an initial buffer of 75, slow windows from
+// 25 doubling, the last absorbing what would leave less than twice its
+// length, and a terminal buffer of 50; below 150 warm-up transitions
+// 15 % / 75 % / 10 %, below 20 step size only.
+void nuts_warmup_layout(int64_t n_warmup, int64_t &init_buf, int64_t &base_win, int64_t &term_buf) {
+    init_buf = 75;
+    base_win = 25;
+    term_buf = 50;
+    if (n_warmup < 20) {
+        init_buf = n_warmup;
+        base_win = 0;
+        term_buf = 0;
+        return;
+    }
+    if (init_buf + base_win + term_buf > n_warmup) {
+        init_buf = (int64_t)(0.15 * (double)n_warmup);
+        term_buf = (int64_t)(0.1 * (double)n_warmup);
+        base_win = n_warmup - init_buf - term_buf;
+    }
+}
+
+bool nuts_in_slow(int64_t n_warmup, int64_t k) {
+    int64_t ib, bw, tb;
+    nuts_warmup_layout(n_warmup, ib, bw, tb);
+    return bw > 0 && k >= ib && k < n_warmup - tb;
+}
+
+bool nuts_window_end(int64_t n_warmup, int64_t k) {
+    int64_t ib, bw, tb;
+    nuts_warmup_layout(n_warmup, ib, bw, tb);
+    if (bw == 0) return false;
+    const int64_t slow_end = n_warmup - tb;
+    for (int64_t start = ib, len = bw; start < slow_end; len *= 2) {
+        int64_t end = start + len;
+        if (end + 2 * len > slow_end) end = slow_end;
+        if (k == end - 1) return true;
+        start = end;
+    }
+    return false;
+}
+
+struct NutsLayout {
+    size_t ch, xe[2], ge[2], xw, xs, gs, xp, gp, gw, pe[2], rho, pnear, wm, w2, R, F, sR, sF, sL, lpw, cnt, total;
+};
+
+NutsLayout nuts_layout(size_t n, size_t M, size_t SN, size_t L, size_t esz) {
+    NutsLayout l;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    l.ch = take(n * sizeof(NutsChain));
+    for (int e = 0; e < 2; ++e) l.xe[e] = take(n * M * esz);
+    for (int e = 0; e < 2; ++e) l.ge[e] = take(n * M * esz);
+    l.xw = take(n * M * esz);
+    l.xs = take(n * M * esz);
+    l.gs = take(n * M * esz);
+    l.xp = take(n * M * esz);
+    l.gp = take(n * M * esz);
+    l.gw = take(n * SN * esz);
+    for (int e = 0; e < 2; ++e) l.pe[e] = take(n * M * 8);
+    l.rho = take(n * M * 8);
+    l.pnear = take(n * M * 8);
+    l.wm = take(n * M * 8);
+    l.w2 = take(n * M * 8);
+    l.R = take(L * n * M * 8);
+    l.F = take(L * n * M * 8);
+    l.sR = take(L * n * M * 8);
+    l.sF = take(L * n * M * 8);
+    l.sL = take(L * n * M * 8);
+    l.lpw = take(n * 8);
+    l.cnt = take(sizeof(int));
+    l.total = off;
+    return l;
+}
+
+}  // namespace
+
+template <typename T, int S>
+mc_status nuts_impl(mc_problem *p, const mc_nuts_config *cfg, int n, T *heights, double *lp, double *eps,
+                    double *inv_mass, int32_t *depth_out, int32_t *nleap_out, int32_t *div_out, double *acc_out,
+                    hipStream_t st) {
+    const size_t N = (size_t)p->R * p->C, M = (size_t)(S - 1) * N, SN = (size_t)S * N;
+    const int L = cfg->max_depth + 1;
+    mc_status s;
+    if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
+    if ((s = ensure(p, p->gcur, sizeof(T) * SN * n)) != MC_OK) return s;
+    const NutsLayout lay = nuts_layout(n, M, SN, L, sizeof(T));
+    if ((s = ensure(p, p->nutsbuf, lay.total)) != MC_OK) return s;
+    char *base = (char *)p->nutsbuf.p;
+    NutsParams<T> P;
+    memset(&P, 0, sizeof(P));
+    P.M = (int)M;
+    P.SN = (int)SN;
+    P.n = n;
+    P.L = L;
+    P.max_dh = cfg->max_delta_h;
+    P.target = cfg->target_accept;
+    P.seed = cfg->seed;
+    P.inv_mass = inv_mass;
+    P.ch = (NutsChain *)(base + lay.ch);
+    P.x = heights;
+    P.lp = lp;
+    P.gcur = (T *)p->gcur.p;
+    for (int e = 0; e < 2; ++e) {
+        P.xe[e] = (T *)(base + lay.xe[e]);
+        P.ge[e] = (T *)(base + lay.ge[e]);
+        P.pe[e] = (double *)(base + lay.pe[e]);
+    }
+    P.xw = (T *)(base + lay.xw);
+    P.lpw = (const double *)(base + lay.lpw);
+    P.gw = (const T *)(base + lay.gw);
+    P.xs = (T *)(base + lay.xs);
+    P.gs = (T *)(base + lay.gs);
+    P.xp = (T *)(base + lay.xp);
+    P.gp = (T *)(base + lay.gp);
+    P.rho = (double *)(base + lay.rho);
+    P.pnear = (double *)(base + lay.pnear);
+    P.R = (double *)(base + lay.R);
+    P.F = (double *)(base + lay.F);
+    P.sR = (double *)(base + lay.sR);
+    P.sF = (double *)(base + lay.sF);
+    P.sL = (double *)(base + lay.sL);
+    double *wm = (double *)(base + lay.wm), *w2 = (double *)(base + lay.w2);
+    int *d_cnt = (int *)(base + lay.cnt);
+    // log posterior and gradient of the starting states
+    if ((s = grad_eval<T, S>(p, n, heights, lp, P.gcur, st)) != MC_OK) return s;
+    hipLaunchKernelGGL(k_nuts_da_init, dim3((n + 255) / 256), dim3(256), 0, st, P.ch, (const double *)eps, n,
+                       cfg->n_warmup > 0 ? 1 : 0);
+    HIP_TRY(p, hipGetLastError());
+    const int64_t total = cfg->n_warmup + cfg->n_steps;
+    const dim3 pos_grid((unsigned)((M + 255) / 256), (unsigned)n);
+    int64_t wn = 0;
+    for (int64_t k = 0; k < total; ++k) {
+        P.step = cfg->step_offset + (uint64_t)k;
+        hipLaunchKernelGGL(k_nuts_begin<T>, dim3(n), dim3(kNutsBlock), 0, st, P);
+        HIP_TRY(p, hipGetLastError());
+        for (int d = 0; d < cfg->max_depth; ++d) {
+            for (int i = 0; i < (1 << d); ++i) {
+                hipLaunchKernelGGL(k_nuts_leap_pos<T>, pos_grid, dim3(256), 0, st, P);
+                if ((s = grad_eval<T, S>(p, n, P.xw, (double *)P.lpw, (T *)P.gw, st)) != MC_OK) return s;
+                hipLaunchKernelGGL(k_nuts_leap_fin<T>, dim3(n), dim3(kNutsBlock), 0, st, P, i, d);
+                HIP_TRY(p, hipGetLastError());
+            }
+            if (d + 1 < cfg->max_depth) {
+                // stop doubling once every chain's tree is finished
+                hipLaunchKernelGGL(k_nuts_count_active, dim3(1), dim3(256), 0, st, (const NutsChain *)P.ch, n, d_cnt);
+                int active = 0;
+                HIP_TRY(p, hipMemcpyAsync(&active, d_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+                HIP_TRY(p, hipStreamSynchronize(st));
+                if (active == 0) break;
+            }
+        }
+        hipLaunchKernelGGL(k_nuts_end<T>, dim3(n), dim3(kNutsBlock), 0, st, P, depth_out, nleap_out, div_out,
+                           acc_out, k, total);
+        HIP_TRY(p, hipGetLastError());
+        if (k < cfg->n_warmup) {
+            const bool slow = cfg->adapt_mass && nuts_in_slow(cfg->n_warmup, k);
+            if (slow) ++wn;
+            const bool wend = slow && nuts_window_end(cfg->n_warmup, k);
+            hipLaunchKernelGGL(k_nuts_adapt<T>, dim3(n), dim3(kNutsBlock), 0, st, P, inv_mass, wm, w2, wn,
+                               slow ? 1 : 0, wend ? 1 : 0, k == cfg->n_warmup - 1 ? 1 : 0);
+            HIP_TRY(p, hipGetLastError());
+            if (wend) wn = 0;
+        }
+    }
+    hipLaunchKernelGGL(k_nuts_eps_out, dim3((n + 255) / 256), dim3(256), 0, st, (const NutsChain *)P.ch, eps, n);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+template <typename T>
+mc_status nuts_dispatch(mc_problem *p, const mc_nuts_config *cfg, int n, void *heights, double *lp, double *eps,
+                        double *inv_mass, int32_t *depth, int32_t *nleap, int32_t *div, double *acc, hipStream_t st) {
+    switch (p->S) {
+        case 2: return nuts_impl<T, 2>(p, cfg, n, (T *)heights, lp, eps, inv_mass, depth, nleap, div, acc, st);
+        case 3: return nuts_impl<T, 3>(p, cfg, n, (T *)heights, lp, eps, inv_mass, depth, nleap, div, acc, st);
+        case 4: return nuts_impl<T, 4>(p, cfg, n, (T *)heights, lp, eps, inv_mass, depth, nleap, div, acc, st);
+    }
+    return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
+}
+
+extern "C" {
+
+mc_status nuts_run(mc_problem *p, const mc_nuts_config *cfg, int n_chains, void *heights, double *logpost,
+                   double *step_size, double *inv_mass, int32_t *tree_depth, int32_t *n_leapfrog, int32_t *diverged,
+                   double *accept_stat, void *stream) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    if (!cfg) return fail(p, MC_ERR_ARG, "cfg is NULL");
+    if (n_chains < 0 || cfg->n_warmup < 0 || cfg->n_steps < 0) return fail(p, MC_ERR_ARG, "negative sizes");
+    if (n_chains == 0) return MC_OK;
+    if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
+    if (!heights || !logpost || !step_size) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    if (cfg->max_depth < 1 || cfg->max_depth > kNutsMaxDepth)
+        return fail(p, MC_ERR_ARG, "max_depth %d not in [1, %d]", cfg->max_depth, kNutsMaxDepth);
+    if (!(cfg->max_delta_h > 0) || !std::isfinite(cfg->max_delta_h)) return fail(p, MC_ERR_ARG, "max_delta_h invalid");
+    if (!(cfg->target_accept > 0 && cfg->target_accept < 1)) return fail(p, MC_ERR_ARG, "target_accept not in (0, 1)");
+    if (cfg->adapt_mass && !inv_mass) return fail(p, MC_ERR_ARG, "adapt_mass needs inv_mass");
+    if (cfg->step_offset + (uint64_t)(cfg->n_warmup + cfg->n_steps) >= (1ULL << 48))
+        return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
+    if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "NUTS needs the exact march's gradient; the voxel model is set");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    return p->prec == MC_F64
+               ? nuts_dispatch<double>(p, cfg, n_chains, heights, logpost, step_size, inv_mass, tree_depth,
+                                       n_leapfrog, diverged, accept_stat, st)
+               : nuts_dispatch<float>(p, cfg, n_chains, heights, logpost, step_size, inv_mass, tree_depth,
+                                      n_leapfrog, diverged, accept_stat, st);
+}
+
+mc_status nested_rhat(mc_problem *p, int n_super, int n_within, const void *heights, double *rhat, void *stream) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_geom) return fail(p, MC_ERR_STATE, "load_geometry_grid has not been called");
+    if (n_super < 2 || n_within < 2) return fail(p, MC_ERR_ARG, "need at least 2 super-chains of 2 chains");
+    if ((long long)n_super * n_within > 65535) return fail(p, MC_ERR_ARG, "more than 65535 chains");
+    if (!heights || !rhat) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int M = (p->S - 1) * p->R * p->C;
+    const dim3 grid((M + 255) / 256);
+    if (p->prec == MC_F64)
+        hipLaunchKernelGGL(k_nested_rhat<double>, grid, dim3(256), 0, st, (const double *)heights, M, n_super,
+                           n_within, rhat);
+    else
+        hipLaunchKernelGGL(k_nested_rhat<float>, grid, dim3(256), 0, st, (const float *)heights, M, n_super,
+                           n_within, rhat);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
 }
 
 mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_run_config *cfgs,

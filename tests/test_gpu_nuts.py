@@ -1,0 +1,159 @@
+"""GPU parity of the paper's sampler (NUTS, its warm-up adaptation and
+nested R-hat) against the oracle.
+
+In float64 every decision of a transition (side of each doubling, leaf
+proposals, merges, U-turn criteria, divergences) must agree, so trees have
+identical depths and leapfrog counts, and states, log posteriors, step
+sizes and inverse masses agree up to the rounding of the gradient (the
+adjoint accumulates in 2^-32 fixed point) carried along a trajectory.  A
+chain is compared only when the oracle's smallest decision margin is above
+1e-7 (relative dot products, |log U - log threshold|, |dH - max_dH|)."""
+import numpy as np
+import pytest
+
+from paper_2603_28907_amd import inputs
+from tests.gpu_common import require_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def tiny(oracle_mod):
+    sc = inputs.tiny_bumps(seed=0)
+    sc.counts = oracle_mod.make_counts(sc, seed=1)
+    return sc
+
+
+def gpu_nuts(torch, sc, states, eps, inv_mass, precision="f64", **kw):
+    from paper_2603_28907_amd.binding import Problem
+    prob = Problem.from_scenario(sc, precision=precision)
+    dt = torch.float64 if precision == "f64" else torch.float32
+    n = states.shape[0]
+    H = to_dev(states, dt)
+    lp = to_dev(np.full(n, np.nan), torch.float64)
+    e = to_dev(np.asarray(eps, np.float64), torch.float64)
+    im = None if inv_mass is None else to_dev(inv_mass, torch.float64)
+    st = prob.nuts_run(H, lp, e, inv_mass=im, **kw)
+    torch.cuda.synchronize()
+    out = dict(x=H.double().cpu().numpy(), lp=lp.cpu().numpy(), eps=e.cpu().numpy(),
+               inv_mass=None if im is None else im.cpu().numpy())
+    out.update({k: v.cpu().numpy() for k, v in st.items()})
+    return out, prob
+
+
+def compare(g, o, chains, rtol_x=1e-9, rtol_acc=1e-8, rtol_lp=1e-10):
+    for c in chains:
+        assert np.array_equal(g["tree_depth"][c], o["depth"][c]), (c, g["tree_depth"][c], o["depth"][c])
+        assert np.array_equal(g["n_leapfrog"][c], o["n_leap"][c]), c
+        assert np.array_equal(g["diverged"][c], o["diverged"][c]), c
+        np.testing.assert_allclose(g["accept_stat"][c], o["accept_stat"][c], rtol=rtol_acc, atol=1e-12)
+        np.testing.assert_allclose(g["x"][c], o["x"][c], rtol=rtol_x, atol=1e-9)
+        assert g["lp"][c] == pytest.approx(o["lp"][c], rel=rtol_lp, abs=1e-6)
+
+
+def test_nuts_f64_matches_oracle(torch_mod, oracle_mod, tiny):
+    n = 4
+    states = inputs.init_states(tiny, n, seed=2)
+    eps = np.array([0.01, 0.04, 0.03, 0.02])
+    im = np.random.default_rng(3).uniform(0.5, 1.5, size=states.shape)
+    say("nuts f64: GPU")
+    g, _ = gpu_nuts(torch_mod, tiny, states, eps, im, n_steps=5, seed=31, max_depth=5)
+    orc = oracle_mod.OracleProblem(tiny)
+    o = orc.nuts(states, np.full(n, np.nan), eps, inv_mass=im, max_depth=5, n_steps=5, seed=31)
+    say("depths", o["depth"].tolist(), "margins", o["margin"], "divergences", o["diverged"].sum())
+    ok = [c for c in range(n) if o["margin"][c] > 1e-7]
+    assert len(ok) >= 3, "near-ties in most chains; choose another seed"
+    assert o["depth"].max() >= 3 and o["n_leap"].sum() > 40
+    compare(g, o, ok)
+
+
+def test_nuts_warmup_matches_oracle(torch_mod, oracle_mod, tiny):
+    """40 warm-up transitions (windows 6 / 30 / 4: one mass update at 35) and 3 more.
+
+    Dual averaging feeds each transition's acceptance statistic back into
+    the next step size with a gain of order sqrt(t)/gamma (gamma = 0.05), so
+    the rounding-level differences of the two acceptance statistics grow
+    along the warm-up (to ~1e-4 relative in the step size after 40
+    transitions here).  Every decision must still agree exactly; step sizes,
+    inverse masses, states and statistics are held to 1e-3 relative."""
+    n = 3
+    states = inputs.init_states(tiny, n, seed=5)
+    eps = np.full(n, 0.05)
+    im = np.ones(states.shape)
+    g, _ = gpu_nuts(torch_mod, tiny, states, eps, im, n_warmup=40, n_steps=3, adapt_mass=True, seed=41,
+                    max_depth=4)
+    orc = oracle_mod.OracleProblem(tiny)
+    o = orc.nuts(states, np.full(n, np.nan), eps, inv_mass=im, max_depth=4, n_warmup=40, n_steps=3, seed=41)
+    say("warm-up margins", o["margin"], "eps", o["eps"], g["eps"])
+    ok = [c for c in range(n) if o["margin"][c] > 1e-7]
+    assert len(ok) >= 2, "near-ties in most chains; choose another seed"
+    compare(g, o, ok, rtol_x=1e-3, rtol_acc=1e-3, rtol_lp=1e-3)
+    for c in ok:
+        assert g["eps"][c] == pytest.approx(o["eps"][c], rel=1e-3)
+        np.testing.assert_allclose(g["inv_mass"][c], o["inv_mass"][c], rtol=1e-3)
+        assert not np.allclose(o["inv_mass"][c], 1.0)
+
+
+def test_nuts_chain_outside_support_stays(torch_mod, oracle_mod, tiny):
+    states = inputs.init_states(tiny, 2, seed=6)
+    states[1, 1] = states[1, 0] - 2.0
+    g, _ = gpu_nuts(torch_mod, tiny, states, [0.03, 0.03], None, n_steps=3, seed=7, max_depth=4)
+    assert np.array_equal(g["x"][1], states[1]) and g["lp"][1] == -np.inf
+    assert np.all(g["n_leapfrog"][1] == 0)
+    assert np.all(g["n_leapfrog"][0] > 0)
+
+
+def test_nuts_f32_is_deterministic_and_sane(torch_mod, tiny):
+    states = inputs.init_states(tiny, 8, seed=8)
+    a, _ = gpu_nuts(torch_mod, tiny, states, np.full(8, 0.03), np.ones(states.shape), precision="f32",
+                    n_warmup=30, n_steps=4, adapt_mass=True, seed=9, max_depth=5)
+    b, _ = gpu_nuts(torch_mod, tiny, states, np.full(8, 0.03), np.ones(states.shape), precision="f32",
+                    n_warmup=30, n_steps=4, adapt_mass=True, seed=9, max_depth=5)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    assert np.all(np.isfinite(a["lp"])) and np.all(a["eps"] > 0)
+    # a transition whose first leaf diverges (the ordering boundary) has statistic 0
+    acc = a["accept_stat"][:, 30:]
+    assert np.all((acc >= 0) & (acc <= 1)) and acc.mean() > 0.3, acc
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_nested_rhat_matches_oracle(torch_mod, oracle_mod, tiny, precision):
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    prob = Problem.from_scenario(tiny, precision=precision)
+    rng = np.random.default_rng(10)
+    K, W = 6, 4
+    x = tiny.truth[None] + rng.standard_normal((K * W,) + tiny.truth.shape)
+    x[:W] += 0.5                       # one super-chain off
+    dt = torch.float64 if precision == "f64" else torch.float32
+    xd = to_dev(x, dt)
+    r = prob.nested_rhat(xd, K, W).cpu().numpy()
+    ref = oracle_mod.nested_rhat(xd.double().cpu().numpy().reshape(K * W, -1), K, W).reshape(r.shape)
+    np.testing.assert_allclose(r, ref, rtol=1e-13)
+    with pytest.raises(ValueError):
+        prob.nested_rhat(xd, 5, 4)
+
+
+def test_nuts_errors(torch_mod, tiny):
+    from paper_2603_28907_amd.binding import MuonCaveError, Problem
+    torch = torch_mod
+    prob = Problem.from_scenario(tiny, precision="f32")
+    n = 2
+    H = to_dev(inputs.init_states(tiny, n, seed=1), torch.float32)
+    lp = to_dev(np.full(n, np.nan), torch.float64)
+    e = to_dev(np.full(n, 0.02), torch.float64)
+    with pytest.raises(MuonCaveError, match="max_depth"):
+        prob.nuts_run(H, lp, e, 1, 1, max_depth=11)
+    with pytest.raises(MuonCaveError, match="target_accept"):
+        prob.nuts_run(H, lp, e, 1, 1, target_accept=1.5)
+    with pytest.raises(MuonCaveError, match="inv_mass"):
+        prob.nuts_run(H, lp, e, 1, 1, n_warmup=5, adapt_mass=True)
+    prob.set_voxel_model(10, 1.0, tiny.truth)
+    with pytest.raises(MuonCaveError, match="voxel"):
+        prob.nuts_run(H, lp, e, 1, 1)
