@@ -14,7 +14,7 @@ timed steps; the line also carries log-posterior
 evaluations per second, the roofline of the ray-march kernel (timed alone
 with HIP events on the benchmark's stream) and the FP64 CPU oracle timed on a
 bounded sample on the host cores.  Other workloads (--workload hetero,
-grad128, hier, voxel, serve) print their own line; by default a short run of each is
+grad128, hier, voxel, nuts, serve) print their own line; by default a short run of each is
 summarised under "workloads" on the headline line.
 """
 from __future__ import annotations
@@ -435,6 +435,62 @@ def bench_voxel(args, torch):
     return out
 
 
+def bench_nuts(args, torch):
+    """The paper's sampler on the paper-scale geometry: NUTS with a 256-step
+    trajectory cap (tree depth 8) on 32 super-chains of 8 chains that share
+    their initial states, a short warm-up (dual averaging and windowed
+    diagonal mass), then timed transitions; nested R-hat of the final states.
+    Roofline of the adjoint march, the dominant kernel of each leapfrog step."""
+    from paper_2603_28907_amd import binding, inputs
+    from paper_2603_28907_amd.binding import Problem
+    sc, _, w = make_workload("grf_cave_64")
+    sc.counts = gpu_counts(sc, torch)
+    prob = Problem.from_scenario(sc, precision="f32")
+    n_super, n_within = 32, 8
+    n = n_super * n_within
+    starts = inputs.init_states(sc, n_super, seed=w["init_seed"], jitter=1.0)
+    H = torch.as_tensor(np.repeat(starts, n_within, axis=0), dtype=torch.float32, device="cuda:0").contiguous()
+    lp = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0")
+    eps = torch.full((n,), args.nuts_eps, dtype=torch.float64, device="cuda:0")
+    im = torch.ones((n,) + tuple(H.shape[1:]), dtype=torch.float64, device="cuda:0")
+    t0 = time.perf_counter()
+    prob.nuts_run(H, lp, eps, 0, 1, n_warmup=args.nuts_warmup, max_depth=8, inv_mass=im, adapt_mass=True,
+                  stats=False)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    print(f"[bench] NUTS warm-up {args.nuts_warmup} transitions: {t_warm:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    st = prob.nuts_run(H, lp, eps, args.steps, 2, max_depth=8, inv_mass=im, step_offset=args.nuts_warmup)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("[bench] timed region done", file=sys.stderr, flush=True)
+    leaps = float(st["n_leapfrog"].double().sum().item())
+    lockstep = float(st["n_leapfrog"].max(dim=0).values.double().sum().item()) * n   # gradients evaluated
+    rhat = prob.nested_rhat(H, n_super, n_within)
+    ms_adj = binding.time_adjoint(prob, H, iters=args.march_iters)
+    opr = adjoint_ops_per_ray("grf_cave_64")
+    achieved = opr * n * sc.n_rays / (ms_adj * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": leaps * sc.n_rays / dt, "unit": "ray-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.nuts_warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"nuts64: the grf_cave_64 geometry and rays ({sc.n_rays}), {n_super} super-chains x "
+                               f"{n_within} chains sharing their starts, NUTS with tree depth cap 8 (256 leapfrog "
+                               f"steps), {args.nuts_warmup} warm-up transitions (dual averaging, diagonal mass), "
+                               f"float32 states, float64 sums", "chains": n, "rays": sc.n_rays},
+        "leapfrog_steps_per_s": leaps / dt, "gradient_evals_per_s": lockstep / dt,
+        "useful_fraction": leaps / max(lockstep, 1.0),
+        "mean_tree_depth": float(st["tree_depth"].double().mean().item()),
+        "divergent_fraction": float(st["diverged"].double().mean().item()),
+        "mean_accept_stat": float(st["accept_stat"].mean().item()),
+        "step_size_median": float(eps.median().item()),
+        "nested_rhat_max": float(rhat.max().item()), "warmup_s": t_warm,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_adjoint_lds",
+                     "ms_per_launch": ms_adj, "ops_per_ray": opr, "rays_per_launch": n * sc.n_rays},
+    }
+
+
 def bench_serve(args, torch):
     """Serving: Poisson arrivals of heterogeneous jobs (sizes as the hetero
     workload), each run to a fixed number of steps per chain; the same
@@ -526,6 +582,8 @@ def main():
     ap.add_argument("--mala-eps", type=float, default=0.004, help="grad128: MALA step size (m)")
     ap.add_argument("--r-step", type=float, default=0.3, help="hier: step of the logit-r random walk")
     ap.add_argument("--n-z", type=int, default=100, help="voxel: levels of the voxel grid")
+    ap.add_argument("--nuts-warmup", type=int, default=20, help="nuts: warm-up transitions")
+    ap.add_argument("--nuts-eps", type=float, default=0.002, help="nuts: initial step size (m)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the short hetero / grad128 / serve runs summarised after the headline line")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
@@ -555,6 +613,9 @@ def main():
         return
     if args.workload == "grad128":
         print(json.dumps(bench_grad(args, torch)), flush=True)
+        return
+    if args.workload == "nuts":
+        print(json.dumps(bench_nuts(args, torch)), flush=True)
         return
     if args.workload == "voxel":
         print(json.dumps(bench_voxel(args, torch)), flush=True)
