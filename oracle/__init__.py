@@ -83,7 +83,10 @@ def _load():
         "orc_voxel_pieces": (I, [P, I, I, V, V]),
         "orc_voxel_loglik": (D, [P, V, V]),
         "orc_voxel_logpost_lik": (D, [P, V, V]),
-        "orc_nuts": (None, [P, ct.c_size_t, V, I, V, V, V, V, I, D, I64, I64, D, U64, U64, I, V, V, V, V, V]),
+        "orc_nuts": (None, [P, ct.c_size_t, V, I, I, V, V, V, V, I, D, I64, I64, D, U64, U64, I, V, V, V, V, V]),
+        "orc_latent_to_heights": (None, [P, V, V]),
+        "orc_heights_to_latent": (None, [P, V, V]),
+        "orc_latent_logpost_grad": (D, [P, V, V]),
         "orc_nested_rhat": (None, [I, I, ct.c_size_t, V, V]),
         "orc_warmup_window_end": (I, [I64, I64]),
         "orc_warmup_in_slow": (I, [I64, I64]),
@@ -275,16 +278,37 @@ class OracleProblem:
         return s.reshape(np.shape(states)), rr, lpa, acc, accr, marg
 
     def nuts(self, states, lp, eps, inv_mass=None, max_depth=8, max_dh=1000.0, n_warmup=0, n_steps=1,
-             target_accept=0.8, seed=0, step_offset=0, state_f32=False):
-        """NUTS on this posterior; states [n, S-1, R, C]; eps [n]; inv_mass [n, S-1, R, C] or None."""
+             target_accept=0.8, seed=0, step_offset=0, state_f32=False, latent=False):
+        """NUTS on this posterior; states [n, S-1, R, C] (heights, or the latent CAR fields with
+        latent=True); eps [n]; inv_mass [n, S-1, R, C] or None."""
         s = _f64(states).reshape(-1, self.M)
         im = None if inv_mass is None else _f64(inv_mass).reshape(-1, self.M)
         out = _nuts_call(ct.byref(self.prob), self.M, None, s, lp, eps, im, max_depth, max_dh, n_warmup, n_steps,
-                         target_accept, seed, step_offset, state_f32)
+                         target_accept, seed, step_offset, state_f32, latent)
         out["x"] = out["x"].reshape(np.shape(states))
         if im is not None:
             out["inv_mass"] = out["inv_mass"].reshape(np.shape(states))
         return out
+
+    def latent_to_heights(self, x):
+        x = _f64(x).reshape(-1, self.M)
+        H = np.empty_like(x)
+        for c in range(x.shape[0]):
+            self.lib.orc_latent_to_heights(ct.byref(self.prob), _p(x[c]), _p(H[c]))
+        return H.reshape(-1, self.S - 1, self.R, self.C)
+
+    def heights_to_latent(self, H):
+        H = _f64(H).reshape(-1, self.M)
+        x = np.empty_like(H)
+        for c in range(H.shape[0]):
+            self.lib.orc_heights_to_latent(ct.byref(self.prob), _p(H[c]), _p(x[c]))
+        return x.reshape(-1, self.S - 1, self.R, self.C)
+
+    def latent_logpost(self, x, with_grad=False):
+        x = self._free(x)
+        g = np.empty(self.M) if with_grad else None
+        lp = float(self.lib.orc_latent_logpost_grad(ct.byref(self.prob), _p(x), _p(g)))
+        return (lp, g.reshape(self.S - 1, self.R, self.C)) if with_grad else lp
 
     def mcmc_mala(self, states, lp, n_accept, n_steps, step_offset, eps, seed, inv_mass=None,
                   state_f32=False, want_margins=False):
@@ -301,7 +325,7 @@ class OracleProblem:
 
 
 def _nuts_call(prob, n_dim, sd, x, lp, eps, inv_mass, max_depth, max_dh, n_warmup, n_steps, target_accept, seed,
-               step_offset, state_f32):
+               step_offset, state_f32, latent=False):
     lib = _load()
     n = x.shape[0]
     x = _f64(x).copy()
@@ -314,7 +338,8 @@ def _nuts_call(prob, n_dim, sd, x, lp, eps, inv_mass, max_depth, max_dh, n_warmu
     dv = np.zeros((n, total), np.int32)
     acc = np.zeros((n, total))
     marg = np.zeros(n)
-    lib.orc_nuts(prob, int(n_dim), _p(sd), n, _p(x), _p(lpa), _p(ea), _p(im), int(max_depth), float(max_dh),
+    lib.orc_nuts(prob, int(n_dim), _p(sd), int(bool(latent)), n, _p(x), _p(lpa), _p(ea), _p(im), int(max_depth),
+                 float(max_dh),
                  int(n_warmup), int(n_steps), float(target_accept), int(seed), int(step_offset), int(bool(state_f32)),
                  _p(depth), _p(nl), _p(dv), _p(acc), _p(marg))
     return dict(x=x, lp=lpa, eps=ea, inv_mass=im, depth=depth, n_leap=nl, diverged=dv, accept_stat=acc,

@@ -445,6 +445,8 @@ void orc_logpost_batch(const orc_problem *p, int n_chains, const double *free_al
  * Likelihood part: dLL/dO_p = (lambda_p - C_p)/Lambda times dO_p/dH from the
  * crossing form in march_ray; prior part from orc_log_prior_grad.
  */
+double orc_loglik_grad_add(const orc_problem *p, const double *free_h, double *grad);
+
 double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
     size_t NS = (size_t)p->S * p->R * p->C;
     if (p->n_z > 0) {   /* the gradient here follows the exact march only */
@@ -454,8 +456,14 @@ double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
     memset(grad, 0, sizeof(double) * NS);
     double lpr = orc_log_prior_grad(p, free_h, grad);
     if (lpr == -INFINITY) { memset(grad, 0, sizeof(double) * NS); return -INFINITY; }
+    return lpr + orc_loglik_grad_add(p, free_h, grad);
+}
+
+/* Log-likelihood (eq. def_likelihood) of a state and its gradient in every
+   surface height, added into grad [S][R][C]. */
+double orc_loglik_grad_add(const orc_problem *p, const double *free_h, double *grad) {
     int n = p->n_s * p->n_pix;
-    if (n == 0) return lpr;
+    if (n == 0) return 0.0;
     double *surf = stack_surfaces(p, free_h);
     double ztop = top_max(p);
     double L[16], ll = 0.0;
@@ -471,7 +479,7 @@ double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
             march_ray(p, surf, q, d, ztop, L, grad, g, NULL);
         }
     free(surf);
-    return ll + lpr;
+    return ll;
 }
 
 void orc_grad_batch(const orc_problem *p, int n_chains, const double *free_all, double *lp, double *grad_all) {
@@ -1204,6 +1212,14 @@ static double cave_target(const void *vctx, const double *x, double *grad) {
     return lp;
 }
 
+double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx);
+
+/* The cave posterior in the latent parametrisation. */
+static double latent_target(const void *vctx, const double *x, double *grad) {
+    const cave_ctx *c = (const cave_ctx *)vctx;
+    return orc_latent_logpost_grad(c->p, x, grad);
+}
+
 /* A Gaussian test target N(0, diag(sd^2)) in M dimensions (for pins). */
 typedef struct { size_t M; const double *sd; } gauss_ctx;
 
@@ -1279,7 +1295,8 @@ int orc_warmup_in_slow(int64_t n_warmup, int64_t k) {
 
 /*
  * NUTS on the cave posterior (or, with gauss_sd non-NULL, on N(0, diag(sd^2))
- * in M = n_dim dimensions), chains in parallel.  Chain c: state x[c] (M),
+ * in M = n_dim dimensions), chains in parallel; with latent != 0 the states
+ * are the latent CAR fields x and the target is their log density.  Chain c: state x[c] (M),
  * lp[c] (NaN: computed first), step size eps[c] (in/out), inverse mass
  * inv_mass[c] ([n][M], in/out; NULL = identity, not adapted).
  * n_warmup > 0 runs that many adapting transitions first (dual averaging to
@@ -1291,7 +1308,7 @@ int orc_warmup_in_slow(int64_t n_warmup, int64_t k) {
  * depth/n_leap/diverged [n][n_warmup + n_steps], accept_stat likewise,
  * margin [n] = smallest decision margin seen.
  */
-void orc_nuts(const orc_problem *p, size_t n_dim, const double *gauss_sd, int n_chains, double *x_all,
+void orc_nuts(const orc_problem *p, size_t n_dim, const double *gauss_sd, int latent, int n_chains, double *x_all,
               double *lp, double *eps, double *inv_mass, int max_depth, double max_dh, int64_t n_warmup,
               int64_t n_steps, double target_accept, uint64_t seed, uint64_t step_offset, int state_f32,
               int32_t *depth_out, int32_t *n_leap_out, int32_t *div_out, double *acc_out, double *margin_out) {
@@ -1309,7 +1326,7 @@ void orc_nuts(const orc_problem *p, size_t n_dim, const double *gauss_sd, int n_
         int64_t wn = 0;
         cave_ctx cc = {p, gfull};
         gauss_ctx gc = {M, gauss_sd};
-        orc_target_fn tf = gauss_sd ? gauss_target : cave_target;
+        orc_target_fn tf = gauss_sd ? gauss_target : (latent ? latent_target : cave_target);
         const void *ctx = gauss_sd ? (const void *)&gc : (const void *)&cc;
         double l = tf(ctx, x, g);
         if (isnan(lp[c])) lp[c] = l;
@@ -1389,4 +1406,97 @@ void orc_nested_rhat(int n_super, int n_within, size_t n_dim, const double *x_al
         out[i] = sqrt(1.0 + B / W);
         free(xk);
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* The latent parametrisation the paper's sampler runs on (Sec. 2.2.1, 3.1)   */
+/* ------------------------------------------------------------------------- */
+/*
+ * The unknowns of the model are the CAR fields x_l ~ N(0, Q_l^-1) of the free
+ * surfaces; the heights are their image under the copula map,
+ *   w = x / sqrt(Sigma11_l),  u = Phi(w),  H_l = (1 - u) H_{l-1} + u H_top
+ * (H_0 = 0).  The sampler's latent vector is x.  Its log density is
+ *   log L(H(x)) + sum_l [ log det(Q_l)/2 - x_l' Q_l x_l / 2 - (N/2) log 2 pi ],
+ * the same normalisation as the density in H (which is this one divided by
+ * |det dH/dx|).  For accuracy H is formed from the lower tail u when w <= 0
+ * and from the upper tail 1 - u = Phi(-w) otherwise.
+ */
+void orc_latent_to_heights(const orc_problem *p, const double *x, double *H) {
+    const int N = p->R * p->C;
+    for (int l = 0; l < p->S - 1; ++l) {
+        double logdet, s11;
+        orc_car_consts(p->R, p->C, p->car_r[l], &logdet, &s11);
+        const double s = sqrt(s11);
+        for (int i = 0; i < N; ++i) {
+            const double a = l ? H[(size_t)(l - 1) * N + i] : 0.0, b = p->top[i];
+            const double w = x[(size_t)l * N + i] / s;
+            H[(size_t)l * N + i] = w <= 0.0 ? a + Phi(w) * (b - a) : b - Phi(-w) * (b - a);
+        }
+    }
+}
+
+void orc_heights_to_latent(const orc_problem *p, const double *H, double *x) {
+    const int N = p->R * p->C;
+    for (int l = 0; l < p->S - 1; ++l) {
+        double logdet, s11;
+        orc_car_consts(p->R, p->C, p->car_r[l], &logdet, &s11);
+        const double s = sqrt(s11);
+        for (int i = 0; i < N; ++i) {
+            const double a = l ? H[(size_t)(l - 1) * N + i] : 0.0, b = p->top[i];
+            const double h = H[(size_t)l * N + i];
+            x[(size_t)l * N + i] = s * ndtri_uv((h - a) / (b - a), (b - h) / (b - a));
+        }
+    }
+}
+
+/* Log density of the latent vector and (optional) its gradient [S-1][R][C].
+   Chain rule at each node, top layer first: with a_l = H_{l-1},
+   dH_l/dx_l = (H_top - a_l) phi(w_l) / sqrt(Sigma11_l) and dH_l/da_l = 1 - u_l,
+   D_l = dlogL/dH_l + (1 - u_{l+1}) D_{l+1} and dlogL/dx_l = D_l dH_l/dx_l. */
+double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx) {
+    const int S1 = p->S - 1, N = p->R * p->C, R = p->R, C = p->C;
+    if (p->n_z > 0) {   /* the exact march's gradient only */
+        if (gx) for (size_t i = 0; i < (size_t)S1 * N; ++i) gx[i] = NAN;
+        return NAN;
+    }
+    const size_t M = (size_t)S1 * N, NS = (size_t)p->S * N;
+    double *H = malloc(sizeof(double) * M), *gH = calloc(NS, sizeof(double));
+    double sl[16], ld[16];
+    for (int l = 0; l < S1; ++l) {
+        double s11;
+        orc_car_consts(R, C, p->car_r[l], &ld[l], &s11);
+        sl[l] = sqrt(s11);
+    }
+    orc_latent_to_heights(p, x, H);
+    double lp = orc_loglik_grad_add(p, H, gH);
+    if (gx) {
+        for (int i = 0; i < N; ++i) {
+            double D = 0.0;
+            for (int l = S1 - 1; l >= 0; --l) {
+                const double a = l ? H[(size_t)(l - 1) * N + i] : 0.0, b = p->top[i];
+                const double w = x[(size_t)l * N + i] / sl[l];
+                D = gH[(size_t)l * N + i] + (l < S1 - 1 ? Phi(-x[(size_t)(l + 1) * N + i] / sl[l + 1]) * D : 0.0);
+                const double phi = exp(-0.5 * w * w) / sqrt(2.0 * M_PI);
+                gx[(size_t)l * N + i] = D * (b - a) * phi / sl[l];
+            }
+        }
+    }
+    /* the prior: x_l ~ N(0, Q_l^-1), Q = 4 I - r A on the periodic grid */
+    for (int l = 0; l < S1; ++l) {
+        const double r = p->car_r[l];
+        const double *xl = x + (size_t)l * N;
+        double quad = 0.0;
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < C; ++j) {
+                const int n = i * C + j;
+                const double nb = xl[i * C + (j + 1) % C] + xl[i * C + (j + C - 1) % C] +
+                                  xl[((i + 1) % R) * C + j] + xl[((i + R - 1) % R) * C + j];
+                const double qx = 4.0 * xl[n] - r * nb;
+                quad += xl[n] * qx;
+                if (gx) gx[(size_t)l * N + n] -= qx;
+            }
+        lp += 0.5 * ld[l] - 0.5 * quad - 0.5 * N * log(2.0 * M_PI);
+    }
+    free(H); free(gH);
+    return lp;
 }
