@@ -448,24 +448,30 @@ def bench_nuts(args, torch):
     prob = Problem.from_scenario(sc, precision="f32")
     n_super, n_within = 32, 8
     n = n_super * n_within
-    starts = inputs.init_states(sc, n_super, seed=w["init_seed"], jitter=1.0)
+    starts = inputs.init_states(sc, n_super, seed=w["init_seed"], jitter=args.nuts_jitter)
     H = torch.as_tensor(np.repeat(starts, n_within, axis=0), dtype=torch.float32, device="cuda:0").contiguous()
+    latent = not args.nuts_heights
+    if latent:   # the paper's parametrisation: the CAR fields behind the heights
+        H = prob.heights_to_latent(H)
     lp = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0")
     eps = torch.full((n,), args.nuts_eps, dtype=torch.float64, device="cuda:0")
     im = torch.ones((n,) + tuple(H.shape[1:]), dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
     prob.nuts_run(H, lp, eps, 0, 1, n_warmup=args.nuts_warmup, max_depth=8, inv_mass=im, adapt_mass=True,
-                  stats=False)
+                  stats=False, latent=latent)
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     print(f"[bench] NUTS warm-up {args.nuts_warmup} transitions: {t_warm:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    st = prob.nuts_run(H, lp, eps, args.steps, 2, max_depth=8, inv_mass=im, step_offset=args.nuts_warmup)
+    st = prob.nuts_run(H, lp, eps, args.steps, 2, max_depth=8, inv_mass=im, step_offset=args.nuts_warmup,
+                       latent=latent)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print("[bench] timed region done", file=sys.stderr, flush=True)
     leaps = float(st["n_leapfrog"].double().sum().item())
     lockstep = float(st["n_leapfrog"].max(dim=0).values.double().sum().item()) * n   # gradients evaluated
+    if latent:
+        H = prob.latent_to_heights(H)
     rhat = prob.nested_rhat(H, n_super, n_within)
     ms_adj = binding.time_adjoint(prob, H, iters=args.march_iters)
     opr = adjoint_ops_per_ray("grf_cave_64")
@@ -474,9 +480,11 @@ def bench_nuts(args, torch):
         "metric": METRIC, "value": leaps * sc.n_rays / dt, "unit": "ray-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.nuts_warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"nuts64: the grf_cave_64 geometry and rays ({sc.n_rays}), {n_super} super-chains x "
+        "config": {"workload": f"nuts64: the grf_cave_64 geometry and rays ({sc.n_rays}), "
+                               f"{'latent CAR fields' if latent else 'heights'} sampled, {n_super} super-chains x "
                                f"{n_within} chains sharing their starts, NUTS with tree depth cap 8 (256 leapfrog "
-                               f"steps), {args.nuts_warmup} warm-up transitions (dual averaging, diagonal mass), "
+                               f"steps), starts at the truth + {args.nuts_jitter} m jitter, {args.nuts_warmup} warm-up transitions "
+                               f"(dual averaging, diagonal mass), "
                                f"float32 states, float64 sums", "chains": n, "rays": sc.n_rays},
         "leapfrog_steps_per_s": leaps / dt, "gradient_evals_per_s": lockstep / dt,
         "useful_fraction": leaps / max(lockstep, 1.0),
@@ -584,6 +592,9 @@ def main():
     ap.add_argument("--n-z", type=int, default=100, help="voxel: levels of the voxel grid")
     ap.add_argument("--nuts-warmup", type=int, default=20, help="nuts: warm-up transitions")
     ap.add_argument("--nuts-eps", type=float, default=0.002, help="nuts: initial step size (m)")
+    ap.add_argument("--nuts-jitter", type=float, default=0.3, help="nuts: jitter of the super-chain starts (m)")
+    ap.add_argument("--nuts-heights", action="store_true",
+                    help="nuts: sample the heights instead of the latent CAR fields")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the short hetero / grad128 / serve runs summarised after the headline line")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")

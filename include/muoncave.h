@@ -271,6 +271,8 @@ typedef struct {
     double target_accept;   /* dual-averaging target in (0, 1); the paper uses 0.8 */
     uint64_t seed;          /* Philox4x32-10 key */
     uint64_t step_offset;   /* Philox step of the first transition */
+    int latent;             /* 1: the states are the latent CAR fields x (the paper's sampler
+                               parametrisation, see latent_to_heights); 0: the heights */
 } mc_nuts_config;
 
 /*
@@ -289,6 +291,20 @@ typedef struct {
 mc_status nuts_run(mc_problem *p, const mc_nuts_config *cfg, int n_chains, void *heights, double *logpost,
                    double *step_size, double *inv_mass, int32_t *tree_depth, int32_t *n_leapfrog,
                    int32_t *diverged, double *accept_stat, void *stream);
+
+/*
+ * The latent parametrisation (Sec. 2.2.1, 3.1): the CAR fields x_l ~
+ * N(0, Q_l^-1) of the free surfaces, [n][S-1][R][C] in the state precision,
+ * and the heights H_l = (1 - u) H_{l-1} + u H_top, u = Phi(x_l /
+ * sqrt(Sigma11_l)), H_0 = 0, at the problem's r.  With cfg->latent = 1,
+ * nuts_run samples x with log density log L(H(x)) + sum_l [log det(Q_l)/2 -
+ * x_l' Q_l x_l / 2 - (N/2) log 2 pi], which has no boundaries; logpost then
+ * holds that density.  Both maps are stream-ordered on device arrays; the
+ * inverse takes strictly ordered heights under the top (others give
+ * non-finite x).
+ */
+mc_status latent_to_heights(mc_problem *p, int n_chains, const void *x, void *heights, void *stream);
+mc_status heights_to_latent(mc_problem *p, int n_chains, const void *heights, void *x, void *stream);
 
 /*
  * Nested R-hat (Sec. 3.2) of every free node from one draw per chain:

@@ -45,7 +45,7 @@ class RunConfig(ct.Structure):
 class NutsConfig(ct.Structure):
     _fields_ = [("n_warmup", ct.c_int64), ("n_steps", ct.c_int64), ("max_depth", ct.c_int), ("adapt_mass", ct.c_int),
                 ("max_delta_h", ct.c_double), ("target_accept", ct.c_double), ("seed", ct.c_uint64),
-                ("step_offset", ct.c_uint64)]
+                ("step_offset", ct.c_uint64), ("latent", ct.c_int)]
 
 
 class ServerConfig(ct.Structure):
@@ -122,6 +122,8 @@ def load_library(path: Optional[str] = None):
         "mc_voxel_info": (I, [V, P(I), P(ct.c_int64)]),
         "nuts_run": (I, [V, P(NutsConfig), I, V, V, V, V, V, V, V, V, V]),
         "nested_rhat": (I, [V, I, I, V, V, V]),
+        "latent_to_heights": (I, [V, I, V, V, V]),
+        "heights_to_latent": (I, [V, I, V, V, V]),
         "mc_server_create": (I, [P(ServerConfig), P(V)]),
         "mc_server_destroy": (None, [V, I]),
         "mc_server_last_error": (ct.c_char_p, [V]),
@@ -145,7 +147,7 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
                     "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
                     "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel", "mc_voxel_info",
-                    "nuts_run", "nested_rhat")
+                    "nuts_run", "nested_rhat", "latent_to_heights", "heights_to_latent")
 
 
 def _host(a, dtype=np.float64):
@@ -310,7 +312,8 @@ class Problem:
         return logpost, grad
 
     def nuts_run(self, heights, logpost, step_size, n_steps, seed, n_warmup=0, max_depth=8, inv_mass=None,
-                 adapt_mass=False, max_delta_h=1000.0, target_accept=0.8, step_offset=0, stats=True, stream=None):
+                 adapt_mass=False, max_delta_h=1000.0, target_accept=0.8, step_offset=0, stats=True, latent=False,
+                 stream=None):
         """NUTS (with optional warm-up adaptation) on the chains in place.  step_size [n] float64 and
         inv_mass [n, S-1, R, C] float64 (or None) are device tensors, updated by the warm-up.  With
         stats, returns dict of per-transition tree_depth, n_leapfrog, diverged, accept_stat tensors."""
@@ -334,10 +337,32 @@ class Problem:
                        accept_stat=torch.zeros((n, total), dtype=torch.float64, device=dev))
             ptrs = [out[k].data_ptr() for k in ("tree_depth", "n_leapfrog", "diverged", "accept_stat")]
         cfg = NutsConfig(int(n_warmup), int(n_steps), int(max_depth), int(bool(adapt_mass)), float(max_delta_h),
-                         float(target_accept), int(seed), int(step_offset))
+                         float(target_accept), int(seed), int(step_offset), int(bool(latent)))
         self._check(self.lib.nuts_run(self.h, ct.byref(cfg), n, ct.c_void_p(heights.data_ptr()),
                                       ct.c_void_p(logpost.data_ptr()), ct.c_void_p(step_size.data_ptr()),
                                       im, *ptrs, _stream_handle(stream, self.device)))
+        return out
+
+    def latent_to_heights(self, x, out=None, stream=None):
+        """Heights of latent CAR states x [n, S-1, R, C] (device tensors)."""
+        import torch
+        n = int(x.shape[0])
+        self._check_tensor(x, self.heights_shape(n), self.torch_dtype, "x")
+        out = torch.empty_like(x) if out is None else out
+        self._check_tensor(out, self.heights_shape(n), self.torch_dtype, "heights")
+        self._check(self.lib.latent_to_heights(self.h, n, ct.c_void_p(x.data_ptr()), ct.c_void_p(out.data_ptr()),
+                                               _stream_handle(stream, self.device)))
+        return out
+
+    def heights_to_latent(self, heights, out=None, stream=None):
+        """Latent CAR states of ordered heights [n, S-1, R, C] (device tensors)."""
+        import torch
+        n = int(heights.shape[0])
+        self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
+        out = torch.empty_like(heights) if out is None else out
+        self._check_tensor(out, self.heights_shape(n), self.torch_dtype, "x")
+        self._check(self.lib.heights_to_latent(self.h, n, ct.c_void_p(heights.data_ptr()),
+                                               ct.c_void_p(out.data_ptr()), _stream_handle(stream, self.device)))
         return out
 
     def nested_rhat(self, heights, n_super, n_within, stream=None):

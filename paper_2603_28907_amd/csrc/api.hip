@@ -27,6 +27,7 @@
 #include "probe.h"
 #include "voxel.h"
 #include "nuts.h"
+#include "latent.h"
 
 using namespace mc;
 
@@ -1654,6 +1655,61 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
+// The latent parametrisation
+// ---------------------------------------------------------------------------
+
+template <typename T>
+LatentParams<T> latent_params(const mc_problem *p, int n, const T *x, T *H, double *lp, T *gx) {
+    LatentParams<T> L;
+    memset(&L, 0, sizeof(L));
+    L.R = p->R;
+    L.C = p->C;
+    L.N = p->R * p->C;
+    L.S1 = p->S - 1;
+    L.SN = p->S * L.N;
+    L.n = n;
+    L.n_tiles = tiling(p).n_tiles;
+    L.has_lik = p->n_ray > 0 ? 1 : 0;
+    for (int l = 0; l < p->S - 1; ++l) {
+        L.s[l] = std::sqrt(p->s11[l]);
+        L.r[l] = p->car_r[l];
+        L.logdet[l] = p->logdet[l];
+    }
+    L.kconst = p->kconst;
+    L.top64 = p->d_top64;
+    L.x = x;
+    L.H = H;
+    L.gfix = (const unsigned long long *)p->gfix.p;
+    L.partials = (const double *)p->partials.p;
+    L.lp = lp;
+    L.gx = gx;
+    return L;
+}
+
+// Log density and gradient of the latent states x [n][S-1][R][C]; the
+// heights go to p->prop (which must hold n states), the gradient to gx
+// [n][S][R][C] (the top row zero).
+template <typename T, int S>
+mc_status grad_eval_latent(mc_problem *p, int n, const T *x, double *lp, T *gx, hipStream_t st) {
+    const size_t N = (size_t)p->R * p->C, SN = (size_t)S * N;
+    LatentParams<T> L = latent_params<T>(p, n, x, (T *)p->prop.p, lp, gx);
+    hipLaunchKernelGGL(k_latent_to_heights<T>, dim3((unsigned)((N + 255) / 256), n), dim3(256), 0, st, L);
+    HIP_TRY(p, hipGetLastError());
+    mc_status s;
+    if (p->n_ray > 0) {
+        unsigned long long *gfix = (unsigned long long *)p->gfix.p;
+        const size_t tot = SN * n;
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
+        HIP_TRY(p, hipGetLastError());
+        if ((s = launch_march<T, S>(p, n, L.H, (T *)p->obuf.p, (double *)p->partials.p, st)) != MC_OK) return s;
+        if ((s = launch_adjoint<T, S>(p, n, L.H, gfix, st)) != MC_OK) return s;
+    }
+    hipLaunchKernelGGL((k_latent_finish<T, kPriorBlock>), dim3(n), dim3(kPriorBlock), 0, st, L);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+// ---------------------------------------------------------------------------
 // NUTS
 // ---------------------------------------------------------------------------
 
@@ -1748,6 +1804,10 @@ mc_status nuts_impl(mc_problem *p, const mc_nuts_config *cfg, int n, T *heights,
     mc_status s;
     if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
     if ((s = ensure(p, p->gcur, sizeof(T) * SN * n)) != MC_OK) return s;
+    if (cfg->latent && (s = ensure(p, p->prop, sizeof(T) * M * n)) != MC_OK) return s;
+    auto target = [&](const T *xs, double *lps, T *gs) {
+        return cfg->latent ? grad_eval_latent<T, S>(p, n, xs, lps, gs, st) : grad_eval<T, S>(p, n, xs, lps, gs, st);
+    };
     const NutsLayout lay = nuts_layout(n, M, SN, L, sizeof(T));
     if ((s = ensure(p, p->nutsbuf, lay.total)) != MC_OK) return s;
     char *base = (char *)p->nutsbuf.p;
@@ -1787,7 +1847,7 @@ mc_status nuts_impl(mc_problem *p, const mc_nuts_config *cfg, int n, T *heights,
     double *wm = (double *)(base + lay.wm), *w2 = (double *)(base + lay.w2);
     int *d_cnt = (int *)(base + lay.cnt);
     // log posterior and gradient of the starting states
-    if ((s = grad_eval<T, S>(p, n, heights, lp, P.gcur, st)) != MC_OK) return s;
+    if ((s = target(heights, lp, P.gcur)) != MC_OK) return s;
     hipLaunchKernelGGL(k_nuts_da_init, dim3((n + 255) / 256), dim3(256), 0, st, P.ch, (const double *)eps, n,
                        cfg->n_warmup > 0 ? 1 : 0);
     HIP_TRY(p, hipGetLastError());
@@ -1801,7 +1861,7 @@ mc_status nuts_impl(mc_problem *p, const mc_nuts_config *cfg, int n, T *heights,
         for (int d = 0; d < cfg->max_depth; ++d) {
             for (int i = 0; i < (1 << d); ++i) {
                 hipLaunchKernelGGL(k_nuts_leap_pos<T>, pos_grid, dim3(256), 0, st, P);
-                if ((s = grad_eval<T, S>(p, n, P.xw, (double *)P.lpw, (T *)P.gw, st)) != MC_OK) return s;
+                if ((s = target(P.xw, (double *)P.lpw, (T *)P.gw)) != MC_OK) return s;
                 hipLaunchKernelGGL(k_nuts_leap_fin<T>, dim3(n), dim3(kNutsBlock), 0, st, P, i, d);
                 HIP_TRY(p, hipGetLastError());
             }
@@ -1888,6 +1948,49 @@ mc_status nested_rhat(mc_problem *p, int n_super, int n_within, const void *heig
     else
         hipLaunchKernelGGL(k_nested_rhat<float>, grid, dim3(256), 0, st, (const float *)heights, M, n_super,
                            n_within, rhat);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+mc_status latent_to_heights(mc_problem *p, int n_chains, const void *x, void *heights, void *stream) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_geom) return fail(p, MC_ERR_STATE, "load_geometry_grid has not been called");
+    if (n_chains < 0 || n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains %d", n_chains);
+    if (n_chains == 0) return MC_OK;
+    if (!x || !heights) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int N = p->R * p->C;
+    const dim3 grid((N + 255) / 256, n_chains);
+    if (p->prec == MC_F64) {
+        LatentParams<double> L = latent_params<double>(p, n_chains, (const double *)x, (double *)heights, nullptr, nullptr);
+        hipLaunchKernelGGL(k_latent_to_heights<double>, grid, dim3(256), 0, st, L);
+    } else {
+        LatentParams<float> L = latent_params<float>(p, n_chains, (const float *)x, (float *)heights, nullptr, nullptr);
+        hipLaunchKernelGGL(k_latent_to_heights<float>, grid, dim3(256), 0, st, L);
+    }
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+mc_status heights_to_latent(mc_problem *p, int n_chains, const void *heights, void *x, void *stream) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_geom) return fail(p, MC_ERR_STATE, "load_geometry_grid has not been called");
+    if (n_chains < 0 || n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains %d", n_chains);
+    if (n_chains == 0) return MC_OK;
+    if (!x || !heights) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int N = p->R * p->C, S1 = p->S - 1;
+    double sl[3] = {0, 0, 0};
+    for (int l = 0; l < S1; ++l) sl[l] = std::sqrt(p->s11[l]);
+    const dim3 grid((N + 255) / 256, n_chains);
+    if (p->prec == MC_F64)
+        hipLaunchKernelGGL(k_heights_to_latent<double>, grid, dim3(256), 0, st, (const double *)heights, (double *)x,
+                           (const double *)p->d_top64, N, S1, sl[0], sl[1], sl[2]);
+    else
+        hipLaunchKernelGGL(k_heights_to_latent<float>, grid, dim3(256), 0, st, (const float *)heights, (float *)x,
+                           (const double *)p->d_top64, N, S1, sl[0], sl[1], sl[2]);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
 }

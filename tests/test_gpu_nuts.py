@@ -157,3 +157,52 @@ def test_nuts_errors(torch_mod, tiny):
     prob.set_voxel_model(10, 1.0, tiny.truth)
     with pytest.raises(MuonCaveError, match="voxel"):
         prob.nuts_run(H, lp, e, 1, 1)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_latent_maps_match_oracle(torch_mod, oracle_mod, tiny, precision):
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    prob = Problem.from_scenario(tiny, precision=precision)
+    orc = oracle_mod.OracleProblem(tiny)
+    dt = torch.float64 if precision == "f64" else torch.float32
+    states = inputs.init_states(tiny, 3, seed=12)
+    x_ref = orc.heights_to_latent(states)
+    xd = prob.heights_to_latent(to_dev(states, dt))
+    Hd = prob.latent_to_heights(to_dev(x_ref, dt))
+    torch.cuda.synchronize()
+    if precision == "f64":
+        np.testing.assert_allclose(xd.cpu().numpy(), x_ref, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(Hd.cpu().numpy(), orc.latent_to_heights(x_ref), rtol=1e-14, atol=1e-12)
+    else:
+        # float32 inputs: the oracle maps the same rounded values
+        x32 = orc.heights_to_latent(states.astype(np.float32).astype(np.float64))
+        np.testing.assert_allclose(xd.double().cpu().numpy(), x32, rtol=1e-5, atol=1e-6)
+        H32 = orc.latent_to_heights(x_ref.astype(np.float32).astype(np.float64))
+        np.testing.assert_allclose(Hd.double().cpu().numpy(), H32, rtol=1e-6, atol=1e-5)
+
+
+def test_latent_logpost_and_nuts_match_oracle(torch_mod, oracle_mod, tiny):
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    orc = oracle_mod.OracleProblem(tiny)
+    n = 3
+    x0 = orc.heights_to_latent(inputs.init_states(tiny, n, seed=2))
+    # the log density at entry (no transition)
+    prob = Problem.from_scenario(tiny, precision="f64")
+    lp = to_dev(np.full(n, np.nan), torch.float64)
+    prob.nuts_run(to_dev(x0, torch.float64), lp, to_dev(np.full(n, 0.001), torch.float64), 0, 1, latent=True,
+                  stats=False)
+    ref = [orc.latent_logpost(x0[c]) for c in range(n)]
+    np.testing.assert_allclose(lp.cpu().numpy(), ref, rtol=1e-11)
+    # NUTS on the latent vector: no boundaries, trees to the cap
+    eps = np.array([0.0005, 0.002, 0.003])
+    g, _ = gpu_nuts(torch_mod, tiny, x0, eps, None, n_steps=3, seed=31, max_depth=5, latent=True)
+    o = orc.nuts(x0, np.full(n, np.nan), eps, max_depth=5, n_steps=3, seed=31, latent=True)
+    say("latent depths", o["depth"].tolist(), "margins", o["margin"])
+    ok = [c for c in range(n) if o["margin"][c] > 1e-7]
+    assert len(ok) >= 2, "near-ties in most chains; choose another seed"
+    assert o["diverged"].sum() == 0
+    # the latent gradient multiplies the adjoint's 2^-32 fixed-point rounding by
+    # the map's factor (H_top - H_{l-1}) phi(w) / sqrt(Sigma11) (10 to 100 here)
+    compare(g, o, ok, rtol_x=1e-8, rtol_acc=1e-6, rtol_lp=1e-10)
