@@ -591,7 +591,7 @@ def main():
     ap.add_argument("--r-step", type=float, default=0.3, help="hier: step of the logit-r random walk")
     ap.add_argument("--n-z", type=int, default=100, help="voxel: levels of the voxel grid")
     ap.add_argument("--nuts-warmup", type=int, default=20, help="nuts: warm-up transitions")
-    ap.add_argument("--nuts-eps", type=float, default=0.002, help="nuts: initial step size (m)")
+    ap.add_argument("--nuts-eps", type=float, default=0.0005, help="nuts: initial step size")
     ap.add_argument("--nuts-jitter", type=float, default=0.3, help="nuts: jitter of the super-chain starts (m)")
     ap.add_argument("--nuts-heights", action="store_true",
                     help="nuts: sample the heights instead of the latent CAR fields")
@@ -700,7 +700,7 @@ def main():
 
 def run_extras(args, torch):
     """Short runs of the other workloads (batched heterogeneous problems,
-    gradient sampling at 128x128, sampled r, the voxel model, serving), summarised beside the headline
+    gradient sampling at 128x128, sampled r, the voxel model, NUTS, serving), summarised beside the headline
     line; each is independent and a failure is reported, not raised."""
     import copy
     res = {}
@@ -710,6 +710,8 @@ def run_extras(args, torch):
         ("hier_r_64", bench_hier, dict(steps=50, warmup=10, graph_steps=50, r_step=0.3)),
         ("voxel64", bench_voxel, dict(steps=20, warmup=4, graph_steps=10, march_iters=5, n_z=100,
                                       no_cpu_baseline=True)),
+        ("nuts64", bench_nuts, dict(steps=2, nuts_warmup=10, nuts_eps=0.0005, nuts_jitter=0.3, nuts_heights=False,
+                                    march_iters=3)),
         ("serve_20_per_s", bench_serve, dict(rate=20.0, duration=1.0, job_steps=2000, max_jobs=8, graph_steps=50,
                                              no_plain=True)),
     ]
@@ -719,6 +721,8 @@ def run_extras(args, torch):
         "hier_r_64": ("value", "ms_per_step", "fixed_r_ms_per_step", "overhead_vs_fixed_r", "accept_rate",
                       "r_accept_rate", "r_mean"),
         "voxel64": ("value", "ms_per_step", "logpost_evals_per_s", "accept_rate", "kernels"),
+        "nuts64": ("value", "ms_per_step", "leapfrog_steps_per_s", "useful_fraction", "mean_tree_depth",
+                   "divergent_fraction", "mean_accept_stat", "nested_rhat_max"),
         "serve_20_per_s": ("value", "p50_s", "p99_s", "logpost_evals_per_s", "offered_load"),
     }
     for name, fn, over in jobs:
