@@ -39,7 +39,9 @@ class _Problem(ct.Structure):
                 ("n_s", ct.c_int), ("n_pix", ct.c_int),
                 ("pos", ct.c_void_p), ("dirs", ct.c_void_p), ("exposure", ct.c_void_p),
                 ("atten", ct.c_double), ("counts", ct.c_void_p),
-                ("n_z", ct.c_int), ("gamma", ct.c_double), ("vox_ref", ct.c_void_p)]
+                ("n_z", ct.c_int), ("gamma", ct.c_double), ("vox_ref", ct.c_void_p),
+                ("n_sub", ct.c_int), ("sub_w", ct.c_void_p), ("n_tab", ct.c_int), ("tab_omax", ct.c_double),
+                ("tab_logI", ct.c_void_p)]
 
 
 class _Stats(ct.Structure):
@@ -85,6 +87,8 @@ def _load():
         "orc_voxel_logpost_lik": (D, [P, V, V]),
         "orc_nuts": (None, [P, ct.c_size_t, V, I, I, V, V, V, V, I, D, I64, I64, D, U64, U64, I, V, V, V, V, V]),
         "orc_latent_to_heights": (None, [P, V, V]),
+        "orc_log_intensity": (D, [P, D]),
+        "orc_quad_loglik": (D, [P, V, V]),
         "orc_heights_to_latent": (None, [P, V, V]),
         "orc_latent_logpost_grad": (D, [P, V, V]),
         "orc_nested_rhat": (None, [I, I, ct.c_size_t, V, V]),
@@ -187,6 +191,28 @@ class OracleProblem:
         self._vox_ref = np.ascontiguousarray(self.voxel_density(ref_free, n_z, gamma))
         self.prob.n_z, self.prob.gamma = int(n_z), float(gamma)
         self.prob.vox_ref = _p(self._vox_ref)
+
+    def set_pixel_quadrature(self, n_sub, weights, log_intensity, o_max, pixel_counts):
+        """Solid-angle pixels: this problem's rays become sub-rays, n_sub per pixel
+        with quadrature weights [n_rays]; log I tabulated over [0, o_max];
+        counts per pixel [n_rays / n_sub]."""
+        self._sub_w = _f64(weights).reshape(-1)
+        self._tab = _f64(log_intensity).reshape(-1)
+        self._counts = np.ascontiguousarray(pixel_counts, dtype=np.int32).reshape(-1)
+        assert self._sub_w.size == self.n_rays and self._counts.size * n_sub == self.n_rays
+        self.prob.n_sub, self.prob.sub_w = int(n_sub), _p(self._sub_w)
+        self.prob.n_tab, self.prob.tab_omax, self.prob.tab_logI = self._tab.size, float(o_max), _p(self._tab)
+        self.prob.counts = _p(self._counts)
+
+    def log_intensity(self, O):
+        return np.array([self.lib.orc_log_intensity(ct.byref(self.prob), float(o)) for o in np.ravel(O)])
+
+    def pixel_lambda(self, free):
+        """Expected counts per pixel under the solid-angle quadrature."""
+        O = self.opacity(free)
+        lam = np.empty(self.n_rays // self.prob.n_sub)
+        self.lib.orc_quad_loglik(ct.byref(self.prob), _p(O), _p(lam))
+        return lam
 
     def voxel_loglik(self, free, with_opacity: bool = False):
         O = np.empty(self.n_rays)

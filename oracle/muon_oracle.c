@@ -58,6 +58,15 @@ typedef struct {
     int n_z;
     double gamma;
     const double *vox_ref;
+    /* Solid-angle pixels (eq. expected_counts): with n_sub > 0 the rays are
+       sub-rays, n_sub consecutive ones per pixel, lambda_p = sum_q sub_w[q]
+       I(O_q) with log I tabulated at n_tab uniform nodes over [0, tab_omax];
+       counts then hold one value per pixel. */
+    int n_sub;
+    const double *sub_w;
+    int n_tab;
+    double tab_omax;
+    const double *tab_logI;
 } orc_problem;
 
 typedef struct {
@@ -416,6 +425,7 @@ double orc_log_prior(const orc_problem *p, const double *free_h) {
 /* ------------------------------------------------------------------------- */
 
 double orc_voxel_logpost_lik(const orc_problem *p, const double *free_h, double *O);
+double orc_quad_loglik(const orc_problem *p, const double *O, double *lam);
 
 /* log posterior (likelihood + prior, normalised) of one state. */
 double orc_logpost(const orc_problem *p, const double *free_h) {
@@ -424,6 +434,13 @@ double orc_logpost(const orc_problem *p, const double *free_h) {
     int n = p->n_s * p->n_pix;
     if (n == 0) return lpr;
     if (p->n_z > 0) return lpr + orc_voxel_logpost_lik(p, free_h, NULL);
+    if (p->n_sub > 0) {
+        double *O = (double *)malloc(sizeof(double) * n);
+        orc_opacity(p, free_h, O, NULL, NULL);
+        double ll = orc_quad_loglik(p, O, NULL);
+        free(O);
+        return lpr + ll;
+    }
     double *O = (double *)malloc(sizeof(double) * n);
     orc_opacity(p, free_h, O, NULL, NULL);
     double ll = orc_loglik(p, O);
@@ -449,7 +466,7 @@ double orc_loglik_grad_add(const orc_problem *p, const double *free_h, double *g
 
 double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
     size_t NS = (size_t)p->S * p->R * p->C;
-    if (p->n_z > 0) {   /* the gradient here follows the exact march only */
+    if (p->n_z > 0 || p->n_sub > 0) {   /* the gradient here: exact march, one ray per pixel */
         for (size_t i = 0; i < NS; ++i) grad[i] = NAN;
         return NAN;
     }
@@ -1455,7 +1472,7 @@ void orc_heights_to_latent(const orc_problem *p, const double *H, double *x) {
    D_l = dlogL/dH_l + (1 - u_{l+1}) D_{l+1} and dlogL/dx_l = D_l dH_l/dx_l. */
 double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx) {
     const int S1 = p->S - 1, N = p->R * p->C, R = p->R, C = p->C;
-    if (p->n_z > 0) {   /* the exact march's gradient only */
+    if (p->n_z > 0 || p->n_sub > 0) {   /* the exact march's gradient, one ray per pixel, only */
         if (gx) for (size_t i = 0; i < (size_t)S1 * N; ++i) gx[i] = NAN;
         return NAN;
     }
@@ -1499,4 +1516,44 @@ double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx
     }
     free(H); free(gH);
     return lp;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Solid-angle pixels (eq. expected_counts)                                   */
+/* ------------------------------------------------------------------------- */
+/*
+ * The expected count of pixel p is the exposure-weighted integral of the
+ * muon intensity over the pixel's solid angle.  Here the integral is a
+ * quadrature over n_sub sub-rays whose weights hold Delta t, the solid angle
+ * of each sub-cell and the detector efficiency in its direction, and the
+ * intensity is a function of the opacity given as a table of log I at
+ * uniform nodes O_j = j * tab_omax / (n_tab - 1), interpolated linearly in
+ * log I (beyond the last node, the last segment continued).
+ */
+double orc_log_intensity(const orc_problem *p, double O) {
+    const double dO = p->tab_omax / (p->n_tab - 1);
+    double t = O / dO;
+    int j = (int)floor(t);
+    if (j < 0) j = 0;
+    if (j > p->n_tab - 2) j = p->n_tab - 2;
+    const double f = t - j;
+    return p->tab_logI[j] + f * (p->tab_logI[j + 1] - p->tab_logI[j]);
+}
+
+/* Poisson log-likelihood of the per-pixel counts; lam (optional) receives
+   lambda_p of every pixel.  O: opacities of the sub-rays. */
+double orc_quad_loglik(const orc_problem *p, const double *O, double *lam) {
+    const int nr = p->n_s * p->n_pix, npx = nr / p->n_sub;
+    double ll = 0.0;
+    for (int px = 0; px < npx; ++px) {
+        double l = 0.0;
+        for (int q = 0; q < p->n_sub; ++q) {
+            const int r = px * p->n_sub + q;
+            l += p->sub_w[r] * exp(orc_log_intensity(p, O[r]));
+        }
+        if (lam) lam[px] = l;
+        const double c = (double)p->counts[px];
+        ll += c * log(l) - l - lgamma(c + 1.0);
+    }
+    return ll;
 }

@@ -89,6 +89,42 @@ def pixel_directions(n_zen: int, n_az: int, max_zenith_deg: float = 45.0) -> np.
     return d.reshape(-1, 3).astype(np.float64)
 
 
+def pixel_subrays(n_zen: int, n_az: int, q: int, max_zenith_deg: float = 45.0, exposure: float = 1e4,
+                  efficiency=None):
+    """Sub-rays of the same radiograph for the solid-angle pixel integral:
+    each pixel (as in pixel_directions) is split into q x q zenith/azimuth
+    sub-cells, one ray at each sub-cell centre, pixel-major ([n_pix*q*q, 3]).
+    The weights are exposure * efficiency(zenith) * solid angle of the
+    sub-cell / solid angle of the pixel's centre cell, so that they sum to
+    about exposure * efficiency per pixel.  efficiency defaults to a smooth
+    synthetic detector response 0.9 - 0.3 sin^2(zenith)."""
+    if efficiency is None:
+        efficiency = lambda th: 0.9 - 0.3 * np.sin(th) ** 2   # noqa: E731
+    dth = math.radians(max_zenith_deg) / n_zen
+    dph = 2.0 * math.pi / n_az
+    dirs, w = [], []
+    for k in range(n_zen):
+        pix_sa = dph * (math.cos(k * dth) - math.cos((k + 1) * dth))
+        for m in range(n_az):
+            for a in range(q):
+                lo, hi = (k + a / q) * dth, (k + (a + 1) / q) * dth
+                th = 0.5 * (lo + hi)
+                sa = (dph / q) * (math.cos(lo) - math.cos(hi))
+                for b in range(q):
+                    ph = (m + (b + 0.5) / q) * dph
+                    dirs.append((math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)))
+                    w.append(exposure * efficiency(th) * sa / pix_sa)
+    return np.asarray(dirs, np.float64), np.asarray(w, np.float64)
+
+
+def intensity_table(n_tab: int = 256, o_max: float = 2000.0, atten: float = 400.0) -> np.ndarray:
+    """A synthetic stand-in for the tabulated muon intensity: log I(O) at
+    n_tab uniform opacity nodes over [0, o_max], I(O) = exp(-O/atten) /
+    sqrt(1 + O/100) (smooth, positive, decreasing)."""
+    O = np.linspace(0.0, o_max, n_tab)
+    return -O / atten - 0.5 * np.log1p(O / 100.0)
+
+
 def gaussian_bumps(rng: np.random.Generator, xs: np.ndarray, ys: np.ndarray, n_bumps: int,
                    amp=(5.0, 20.0), width=(10.0, 30.0), centre_lo=20.0, centre_hi=80.0) -> np.ndarray:
     """Sum of isotropic Gaussian bumps on the node grid (xs along rows, ys along columns)."""
