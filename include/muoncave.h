@@ -137,6 +137,26 @@ mc_status set_counts(mc_problem *p, const int32_t *counts);
  */
 mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *ref_heights);
 
+/*
+ * Solid-angle pixels (eq. expected_counts): the expected count of a pixel
+ * is the integral of the muon intensity I(O) times exposure and detector
+ * efficiency over its solid angle, here a quadrature over sub-rays.  The
+ * rays given to set_sensors become sub-rays: each group of n_sub consecutive
+ * rays of a sensor (n_sub divides n_pix) is one pixel, with
+ *   lambda_p = sum_q weights[q] I(O_q),
+ * weights [n_rays] > 0 (Delta t x sub-cell solid angle x efficiency), and
+ * log I tabulated at n_table uniform opacity nodes over [0, o_max] (linear
+ * interpolation in log I; beyond o_max the last segment continues).  After
+ * this call set_counts takes one count per pixel (n_rays / n_sub values) and
+ * must be called again; logpost_batch and random-walk mcmc_run use the
+ * quadrature, and the opacity output holds the sub-rays' opacities.  Gradient
+ * paths, NUTS, mcmc_run_multi and the voxel model are refused while it is
+ * set.  n_sub = 0 switches back to one ray per pixel (counts must be set
+ * again); set_sensors and load_geometry_grid switch it off.
+ */
+mc_status set_pixel_quadrature(mc_problem *p, int n_sub, const double *weights, int n_table, double o_max,
+                               const double *log_intensity);
+
 /* The voxel model's levels (0 when it is off) and the number of ray-voxel
    pieces over all rays (the non-zeros of the sensitivity matrix G). */
 mc_status mc_voxel_info(const mc_problem *p, int *n_z, int64_t *n_pieces);

@@ -120,6 +120,7 @@ def load_library(path: Optional[str] = None):
         "set_voxel_model": (I, [V, I, D, V]),
         "mc_time_voxel": (I, [V, I, V, I, V, P(ct.c_float), P(ct.c_float)]),
         "mc_voxel_info": (I, [V, P(I), P(ct.c_int64)]),
+        "set_pixel_quadrature": (I, [V, I, V, I, D, V]),
         "nuts_run": (I, [V, P(NutsConfig), I, V, V, V, V, V, V, V, V, V]),
         "nested_rhat": (I, [V, I, I, V, V, V]),
         "latent_to_heights": (I, [V, I, V, V, V]),
@@ -147,7 +148,8 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "mc_server_create", "mc_server_destroy", "mc_server_last_error", "mc_server_submit",
                     "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
                     "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel", "mc_voxel_info",
-                    "nuts_run", "nested_rhat", "latent_to_heights", "heights_to_latent")
+                    "nuts_run", "nested_rhat", "latent_to_heights", "heights_to_latent",
+                    "set_pixel_quadrature")
 
 
 def _host(a, dtype=np.float64):
@@ -244,6 +246,18 @@ class Problem:
         if ref.size != (self.S - 1) * self.R * self.C:
             raise ValueError("ref_heights must hold (S-1)*R*C values")
         self._check(self.lib.set_voxel_model(self.h, int(n_z), float(gamma), _hp(ref)))
+
+    def set_pixel_quadrature(self, n_sub: int, weights=None, log_intensity=None, o_max: float = 0.0):
+        """Solid-angle pixels: n_sub consecutive rays per pixel with quadrature weights [n_rays] and log I
+        tabulated over [0, o_max]; set_counts then takes one count per pixel.  n_sub = 0 switches back."""
+        if n_sub == 0:
+            self._check(self.lib.set_pixel_quadrature(self.h, 0, None, 0, 0.0, None))
+            return
+        w = _host(weights).reshape(-1)
+        t = _host(log_intensity).reshape(-1)
+        if w.size != self.n_rays:
+            raise ValueError("one weight per ray")
+        self._check(self.lib.set_pixel_quadrature(self.h, int(n_sub), _hp(w), int(t.size), float(o_max), _hp(t)))
 
     def voxel_info(self):
         """(levels, ray-voxel pieces) of the voxel model; (0, 0) when it is off."""

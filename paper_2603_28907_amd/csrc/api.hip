@@ -105,6 +105,10 @@ struct mc_problem {
     double *d_vox_lam0 = nullptr, *d_vox_o0 = nullptr, *d_vox_fsig = nullptr, *d_vox_inorm = nullptr;
     size_t vox_nnz = 0;
     DevBuf rhat;   // [R*C*n_z][n_pad] smoothed densities of the chains
+    // solid-angle pixels (quad_nsub = 0: one ray per pixel)
+    int quad_nsub = 0, quad_npx = 0, quad_ntab = 0;
+    double quad_omax = 0.0, kconst_quad = 0.0;
+    double *d_quad_w = nullptr, *d_quad_tab = nullptr, *d_quad_cnt = nullptr;
     DevBuf nutsbuf;   // NUTS trees, proposals and warm-up accumulators
     // workspaces (grow only)
     DevBuf partials, prop, lptmp;
@@ -167,6 +171,12 @@ void drop_graph(mc_problem *p) {
     p->gexec = nullptr;
     p->gkey = GraphKey();
     p->gen += 1;
+}
+
+void clear_quadrature(mc_problem *p) {
+    if (p->quad_nsub > 0) drop_graph(p);
+    p->quad_nsub = p->quad_npx = p->quad_ntab = 0;
+    for (double **q : {&p->d_quad_w, &p->d_quad_tab, &p->d_quad_cnt}) free_ptr(*q);
 }
 
 void clear_voxel_model(mc_problem *p) {
@@ -249,6 +259,17 @@ Tiling tiling(const mc_problem *p) {
     t.n_tiles = p->n_ray > 0 ? (p->n_ray + t.rays_per_block - 1) / t.rays_per_block : 0;
     return t;
 }
+
+// Partial sums per chain of the likelihood stage the prior kernel adds up:
+// the march's tiles, or the voxel or solid-angle pixel kernels'.
+int lik_tiles(const mc_problem *p) {
+    if (p->quad_nsub > 0) return (p->quad_npx + 255) / 256;
+    return tiling(p).n_tiles;
+}
+
+// Slots the partials buffer needs per chain (the march writes its own tiles
+// before the pixel kernel writes its).
+int partial_slots(const mc_problem *p) { return std::max(tiling(p).n_tiles, lik_tiles(p)); }
 
 size_t queue_bytes(const mc_problem *p) {
     if (p->tune.march_variant != 2) return 0;
@@ -464,7 +485,7 @@ PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double 
     memset(&P, 0, sizeof(P));
     P.R = p->R;
     P.C = p->C;
-    P.n_tiles = tiling(p).n_tiles;
+    P.n_tiles = lik_tiles(p);
     P.has_lik = p->n_ray > 0 ? 1 : 0;
     P.heights = heights;
     P.top64 = p->d_top64;
@@ -478,7 +499,7 @@ PriorParams<T> prior_params(const mc_problem *p, const T *heights, const double 
     P.eig_w = p->d_eig_w;
     P.n_eig = p->n_eig;
     P.partials = partials;
-    P.kconst = p->vox_nz > 0 ? p->kconst_vox : p->kconst;
+    P.kconst = p->vox_nz > 0 ? p->kconst_vox : (p->quad_nsub > 0 ? p->kconst_quad : p->kconst);
     return P;
 }
 
@@ -568,6 +589,25 @@ mc_status launch_voxel(mc_problem *p, int n, const T *heights, T *opacity, doubl
     return MC_OK;
 }
 
+// Solid-angle pixels: the march over every sub-ray with its opacities to
+// obuf (its own per-ray terms, computed with zero counts, are overwritten),
+// then the per-pixel likelihood.  opacity (optional) receives a copy of the
+// sub-ray opacities.
+template <typename T, int S>
+mc_status launch_quad(mc_problem *p, int n, const T *heights, T *opacity, hipStream_t st, const double *only_nan) {
+    T *ob = (T *)p->obuf.p;
+    mc_status s;
+    if ((s = launch_march<T, S>(p, n, heights, ob, (double *)p->partials.p, st, only_nan)) != MC_OK) return s;
+    const int tiles = lik_tiles(p);
+    hipLaunchKernelGGL(k_quad_lik<T>, dim3(tiles, n), dim3(256), 0, st, (const T *)ob, p->n_ray, p->quad_npx,
+                       p->quad_nsub, (const double *)p->d_quad_w, (const double *)p->d_quad_tab, p->quad_ntab,
+                       (p->quad_ntab - 1) / p->quad_omax, (const double *)p->d_quad_cnt, (double *)p->partials.p,
+                       tiles, only_nan);
+    HIP_TRY(p, hipGetLastError());
+    if (opacity) HIP_TRY(p, hipMemcpyAsync(opacity, ob, sizeof(T) * (size_t)n * p->n_ray, hipMemcpyDeviceToDevice, st));
+    return MC_OK;
+}
+
 mc_status check_ready(mc_problem *p) {
     if (!p) return MC_ERR_ARG;
     if (!p->have_geom) return fail(p, MC_ERR_STATE, "load_geometry_grid has not been called");
@@ -584,8 +624,12 @@ mc_status logpost_impl(mc_problem *p, int n, const T *heights, double *lp, T *op
     Tiling t = tiling(p);
     mc_status s;
     if (p->n_ray > 0) {
-        if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
-        if (p->vox_nz > 0) {
+        if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * partial_slots(p))) != MC_OK) return s;
+        (void)t;
+        if (p->quad_nsub > 0) {
+            if ((s = ensure(p, p->obuf, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK) return s;
+            if ((s = launch_quad<T, S>(p, n, heights, opacity, st, only_nan)) != MC_OK) return s;
+        } else if (p->vox_nz > 0) {
             if ((s = ensure(p, p->rhat, rhat_bytes(p, n))) != MC_OK) return s;
             if ((s = launch_voxel<T, S>(p, n, heights, opacity, (double *)p->partials.p, st, only_nan)) != MC_OK)
                 return s;
@@ -790,7 +834,9 @@ mc_status rw_step(mc_problem *p, int n, T *heights, double *lp, int64_t *acc, co
     HIP_TRY(p, hipGetLastError());
     mc_status s;
     if (p->n_ray > 0) {
-        if (p->vox_nz > 0)
+        if (p->quad_nsub > 0)
+            s = launch_quad<T, S>(p, n, prop, nullptr, st, nullptr);
+        else if (p->vox_nz > 0)
             s = launch_voxel<T, S>(p, n, prop, nullptr, (double *)p->partials.p, st, nullptr);
         else
             s = launch_march<T, S>(p, n, prop, nullptr, (double *)p->partials.p, st);
@@ -825,8 +871,11 @@ mc_status mcmc_impl(mc_problem *p, const mc_run_config *cfg, int n, T *heights, 
     const bool mala = cfg->kernel == 1;
     if ((s = ensure(p, p->prop, sizeof(T) * (size_t)n * M)) != MC_OK) return s;
     if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
-    if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+    if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * partial_slots(p))) != MC_OK) return s;
     if (p->n_ray > 0 && p->vox_nz > 0 && (s = ensure(p, p->rhat, rhat_bytes(p, n))) != MC_OK) return s;
+    if (p->n_ray > 0 && p->quad_nsub > 0 && (s = ensure(p, p->obuf, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK)
+        return s;
+    (void)t;
     if (mala) {
         if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
         if ((s = ensure(p, p->gcur, sizeof(T) * SN * n)) != MC_OK) return s;
@@ -1419,6 +1468,7 @@ void mc_destroy(mc_problem *p) {
     free_ptr(p->d_coL);
     free_ptr(p->d_cnt64);
     clear_voxel_model(p);
+    for (double **q : {&p->d_quad_w, &p->d_quad_tab, &p->d_quad_cnt}) free_ptr(*q);
     for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
     for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gprior, &p->gcur, &p->gprop,
                       &p->lpprop, &p->rstat, &p->rhat, &p->nutsbuf})
@@ -1452,6 +1502,7 @@ mc_status load_geometry_grid(mc_problem *p, int n_surfaces, int n_rows, int n_co
     DeviceGuard g(p->device);
     p->have_geom = p->have_sensors = p->have_counts = false;
     clear_voxel_model(p);
+    clear_quadrature(p);
     p->S = n_surfaces;
     p->R = n_rows;
     p->C = n_cols;
@@ -1523,6 +1574,7 @@ mc_status set_sensors(mc_problem *p, int n_sensors, const double *pos, int n_pix
     DeviceGuard g(p->device);
     p->have_sensors = p->have_counts = false;
     clear_voxel_model(p);
+    clear_quadrature(p);
     p->n_s = n_sensors;
     p->n_pix = n_pix;
     p->n_ray = n_ray;
@@ -1576,6 +1628,32 @@ mc_status set_counts(mc_problem *p, const int32_t *counts) {
     if (!p) return MC_ERR_ARG;
     if (!p->have_sensors) return fail(p, MC_ERR_STATE, "set_sensors has not been called");
     if (p->n_ray > 0 && !counts) return fail(p, MC_ERR_ARG, "counts is NULL");
+    if (p->quad_nsub > 0) {
+        // one count per pixel; the march's own per-ray terms see zero counts
+        std::vector<double> cq(p->quad_npx), zero(p->n_ray, 0.0);
+        long double KQ = 0;
+        for (int i = 0; i < p->quad_npx; ++i) {
+            if (counts[i] < 0) return fail(p, MC_ERR_ARG, "counts[%d] < 0", i);
+            cq[i] = counts[i];
+            KQ -= std::lgamma(cq[i] + 1.0);
+        }
+        DeviceGuard g(p->device);
+        drop_graph(p);
+        mc_status s;
+        void *d = p->d_quad_cnt;
+        if ((s = upload<double>(p, d, cq)) != MC_OK) return s;
+        p->d_quad_cnt = (double *)d;
+        d = p->d_coL;
+        if ((s = upload<double>(p, d, zero)) != MC_OK) return s;
+        p->d_coL = (double *)d;
+        d = p->d_cnt64;
+        if ((s = upload<double>(p, d, zero)) != MC_OK) return s;
+        p->d_cnt64 = (double *)d;
+        p->kconst = 0.0;
+        p->kconst_quad = (double)KQ;
+        p->have_counts = true;
+        return MC_OK;
+    }
     std::vector<double> coL(p->n_ray), c64(p->n_ray);
     long double K = 0, KV = 0;
     for (int r = 0; r < p->n_ray; ++r) {
@@ -1624,6 +1702,7 @@ mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, d
     if (!heights || !logpost || !grad) return fail(p, MC_ERR_ARG, "NULL device pointer");
     if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
     if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients follow the exact march; the voxel model is set");
+    if (p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients take one ray per pixel; pixel quadrature is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? logpost_grad_dispatch<double>(p, n_chains, heights, logpost, grad, st)
@@ -1643,6 +1722,7 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
     if (cfg->kernel != 0 && cfg->kernel != 1) return fail(p, MC_ERR_ARG, "kernel %d", cfg->kernel);
     if (cfg->r_state && cfg->kernel != 0) return fail(p, MC_ERR_UNSUPPORTED, "r sampling runs with random-walk Metropolis");
     if (cfg->kernel == 1 && p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA needs the exact march; the voxel model is set");
+    if (cfg->kernel == 1 && p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA takes one ray per pixel; pixel quadrature is set");
     if (cfg->r_state && (!(cfg->r_step >= 0) || !std::isfinite(cfg->r_step))) return fail(p, MC_ERR_ARG, "r_step invalid");
     if (cfg->n_accept_r && !cfg->r_state) return fail(p, MC_ERR_ARG, "n_accept_r without r_state");
     if (cfg->step_offset + (uint64_t)cfg->n_steps >= (1ULL << 48)) return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
@@ -1923,6 +2003,7 @@ mc_status nuts_run(mc_problem *p, const mc_nuts_config *cfg, int n_chains, void 
     if (cfg->step_offset + (uint64_t)(cfg->n_warmup + cfg->n_steps) >= (1ULL << 48))
         return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
     if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "NUTS needs the exact march's gradient; the voxel model is set");
+    if (p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "NUTS takes one ray per pixel; pixel quadrature is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64
@@ -2013,7 +2094,8 @@ mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_r
             if (problems[j] == p) return fail(e, MC_ERR_ARG, "problem %d repeats problem %d", i, j);
         if (cfgs[i].kernel != 0) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi runs random-walk Metropolis");
         if (cfgs[i].r_state) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi samples with fixed r");
-        if (p->vox_nz > 0) return fail(e, MC_ERR_UNSUPPORTED, "problem %d: mcmc_run_multi runs the exact march", i);
+        if (p->vox_nz > 0 || p->quad_nsub > 0)
+            return fail(e, MC_ERR_UNSUPPORTED, "problem %d: mcmc_run_multi runs the exact march with one ray per pixel", i);
         if (cfgs[i].n_steps != cfgs[0].n_steps || cfgs[i].graph_steps != cfgs[0].graph_steps)
             return fail(e, MC_ERR_ARG, "n_steps and graph_steps must be equal across problems");
         if (!(cfgs[i].step_size >= 0) || !std::isfinite(cfgs[i].step_size)) return fail(e, MC_ERR_ARG, "step_size");
@@ -2104,6 +2186,7 @@ mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *re
     for (size_t i = 0; i < (size_t)(S - 1) * N; ++i)
         if (!std::isfinite(ref_heights[i])) return fail(p, MC_ERR_ARG, "ref_heights[%zu] not finite", i);
     clear_voxel_model(p);
+    if (p->quad_nsub > 0) return fail(p, MC_ERR_STATE, "pixel quadrature is set: switch it off first");
     const double dz = p->ztop / n_z;
     std::vector<double> drho(S);
     for (int l = 0; l < S; ++l) drho[l] = p->density[l] - (l + 1 < S ? p->density[l + 1] : 0.0);
@@ -2167,6 +2250,41 @@ mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *re
     p->vox_gamma = gamma;
     p->vox_dz = dz;
     p->vox_nz = n_z;
+    drop_graph(p);
+    return MC_OK;
+}
+
+mc_status set_pixel_quadrature(mc_problem *p, int n_sub, const double *weights, int n_table, double o_max,
+                               const double *log_intensity) {
+    if (!p) return MC_ERR_ARG;
+    if (!p->have_sensors) return fail(p, MC_ERR_STATE, "set_sensors has not been called");
+    DeviceGuard g(p->device);
+    if (n_sub == 0) {
+        clear_quadrature(p);
+        p->have_counts = false;
+        return MC_OK;
+    }
+    if (n_sub < 0 || p->n_pix % n_sub != 0) return fail(p, MC_ERR_ARG, "n_sub %d does not divide n_pix %d", n_sub, p->n_pix);
+    if (n_table < 2 || !(o_max > 0) || !std::isfinite(o_max)) return fail(p, MC_ERR_ARG, "table: n_table >= 2, o_max > 0");
+    if (!weights || !log_intensity) return fail(p, MC_ERR_ARG, "NULL array");
+    for (int r = 0; r < p->n_ray; ++r)
+        if (!(weights[r] > 0) || !std::isfinite(weights[r])) return fail(p, MC_ERR_ARG, "weights[%d] must be > 0", r);
+    for (int j = 0; j < n_table; ++j)
+        if (!std::isfinite(log_intensity[j])) return fail(p, MC_ERR_ARG, "log_intensity[%d] not finite", j);
+    clear_voxel_model(p);
+    clear_quadrature(p);
+    mc_status s;
+    void *d = nullptr;
+    if ((s = upload<double>(p, d, std::vector<double>(weights, weights + p->n_ray))) != MC_OK) return s;
+    p->d_quad_w = (double *)d;
+    d = nullptr;
+    if ((s = upload<double>(p, d, std::vector<double>(log_intensity, log_intensity + n_table))) != MC_OK) return s;
+    p->d_quad_tab = (double *)d;
+    p->quad_nsub = n_sub;
+    p->quad_npx = p->n_ray / n_sub;
+    p->quad_ntab = n_table;
+    p->quad_omax = o_max;
+    p->have_counts = false;   // counts are per pixel from now on
     drop_graph(p);
     return MC_OK;
 }
@@ -2268,7 +2386,8 @@ mc_status mc_time_adjoint(mc_problem *p, int n_chains, const void *heights, int 
     if (n_chains <= 0 || n_chains > 65535 || iters <= 0 || !heights || !ms_per_launch)
         return fail(p, MC_ERR_ARG, "invalid arguments");
     if (p->n_ray == 0) return fail(p, MC_ERR_STATE, "no rays");
-    if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients follow the exact march; the voxel model is set");
+    if (p->vox_nz > 0 || p->quad_nsub > 0)
+        return fail(p, MC_ERR_UNSUPPORTED, "gradients follow the exact march with one ray per pixel");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? time_adjoint_dispatch<double>(p, n_chains, heights, iters, st, ms_per_launch)
