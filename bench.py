@@ -14,13 +14,14 @@ timed steps; the line also carries log-posterior
 evaluations per second, the roofline of the ray-march kernel (timed alone
 with HIP events on the benchmark's stream) and the FP64 CPU oracle timed on a
 bounded sample on the host cores.  Other workloads (--workload hetero,
-grad128, hier, voxel, nuts, serve) print their own line; by default a short run of each is
+grad128, hier, voxel, nuts, quad, serve) print their own line; by default a short run of each is
 summarised under "workloads" on the headline line.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -499,6 +500,72 @@ def bench_nuts(args, torch):
     }
 
 
+def bench_quad(args, torch):
+    """The solid-angle pixel integral on the paper-scale workload: every pixel
+    of grf_cave_64 split into q x q sub-cells (a sub-ray each, midpoint rule,
+    synthetic efficiency), the tabulated synthetic intensity, random-walk
+    Metropolis on 1024 chains; beside it the one-ray model on the same chains.
+    Roofline of the march over all sub-rays."""
+    from paper_2603_28907_amd import binding, inputs
+    from paper_2603_28907_amd.binding import Problem
+    sc, n_chains, w = make_workload("grf_cave_64")
+    q = args.quad_q
+    side = int(round(math.sqrt(sc.n_pix)))
+    dirs, wq = inputs.pixel_subrays(side, side, q, exposure=1e4)
+    scq = inputs.Scenario(name=sc.name + f"_q{q}", n_surfaces=sc.n_surfaces, n_rows=sc.n_rows, n_cols=sc.n_cols,
+                          extent_x=sc.extent_x, extent_y=sc.extent_y, density=sc.density, top=sc.top,
+                          car_r=sc.car_r, truth=sc.truth, sensor_pos=sc.sensor_pos,
+                          dirs=np.broadcast_to(dirs, (sc.n_sensors,) + dirs.shape).copy(),
+                          exposure=np.ones((sc.n_sensors, dirs.shape[0])), atten_len=sc.atten_len)
+    o_max = 3000.0
+    tab = inputs.intensity_table(513, o_max, sc.atten_len)
+    weights = np.tile(wq, sc.n_sensors)
+    nsub = q * q
+    prob = Problem.from_scenario(scq, counts=np.zeros(scq.n_rays, np.int32), precision="f32")
+    prob.set_pixel_quadrature(nsub, weights, tab, o_max)
+    # counts: Poisson draws from the quadrature's own expected counts at the truth
+    Ht = torch.as_tensor(sc.truth[None], dtype=torch.float32, device="cuda:0")
+    Ot = torch.empty((1, scq.n_rays), dtype=torch.float32, device="cuda:0")
+    prob.set_counts(np.zeros(scq.n_rays // nsub, np.int32))
+    prob.logpost_batch(Ht, opacity=Ot)
+    O = Ot[0].double().cpu().numpy()
+    nodes = np.linspace(0.0, o_max, tab.size)
+    lam = (weights * np.exp(np.interp(O, nodes, tab))).reshape(-1, nsub).sum(axis=1)
+    prob.set_counts(inputs.draw_counts(lam, 11))
+    H = torch.as_tensor(inputs.init_states(sc, n_chains, seed=w["init_seed"]), dtype=torch.float32,
+                        device="cuda:0").contiguous()
+    lp = torch.full((n_chains,), float("nan"), dtype=torch.float64, device="cuda:0")
+    acc = torch.zeros(n_chains, dtype=torch.int64, device="cuda:0")
+    G = max(1, min(args.graph_steps, args.steps))
+    prob.mcmc_run(H, lp, acc, args.warmup, w["sigma"], 1, graph_steps=min(G, max(args.warmup, 1)))
+    torch.cuda.synchronize()
+    a0 = acc.clone()
+    t0 = time.perf_counter()
+    prob.mcmc_run(H, lp, acc, args.steps, w["sigma"], 1, step_offset=args.warmup, graph_steps=G)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("[bench] timed region done", file=sys.stderr, flush=True)
+    assert torch.isfinite(lp).all(), "non-finite log posterior"
+    ms_march = binding.time_march(prob, H, iters=args.march_iters)
+    opr = ops_per_ray("grf_cave_64")
+    achieved = opr * n_chains * scq.n_rays / (ms_march * 1e-3) / 1e12
+    return {
+        "metric": METRIC, "value": n_chains * scq.n_rays * args.steps / dt, "unit": "ray-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"quad64: the grf_cave_64 workload with every pixel integrated over its solid angle "
+                               f"by {q}x{q} sub-rays ({scq.n_rays} rays for {scq.n_rays // nsub} pixels), synthetic "
+                               f"efficiency and tabulated intensity; random-walk Metropolis sigma {w['sigma']} m on "
+                               f"{n_chains} chains, HIP graphs of {G} steps",
+                   "chains": n_chains, "rays": scq.n_rays, "pixels": scq.n_rays // nsub},
+        "logpost_evals_per_s": n_chains * args.steps / dt,
+        "accept_rate": float((acc - a0).double().mean().item()) / args.steps,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_march_lik4",
+                     "ms_per_launch": ms_march, "ops_per_ray": opr, "rays_per_launch": n_chains * scq.n_rays},
+    }
+
+
 def bench_serve(args, torch):
     """Serving: Poisson arrivals of heterogeneous jobs (sizes as the hetero
     workload), each run to a fixed number of steps per chain; the same
@@ -590,6 +657,7 @@ def main():
     ap.add_argument("--mala-eps", type=float, default=0.004, help="grad128: MALA step size (m)")
     ap.add_argument("--r-step", type=float, default=0.3, help="hier: step of the logit-r random walk")
     ap.add_argument("--n-z", type=int, default=100, help="voxel: levels of the voxel grid")
+    ap.add_argument("--quad-q", type=int, default=2, help="quad: sub-cells per pixel side")
     ap.add_argument("--nuts-warmup", type=int, default=20, help="nuts: warm-up transitions")
     ap.add_argument("--nuts-eps", type=float, default=0.0005, help="nuts: initial step size")
     ap.add_argument("--nuts-jitter", type=float, default=0.3, help="nuts: jitter of the super-chain starts (m)")
@@ -624,6 +692,9 @@ def main():
         return
     if args.workload == "grad128":
         print(json.dumps(bench_grad(args, torch)), flush=True)
+        return
+    if args.workload == "quad":
+        print(json.dumps(bench_quad(args, torch)), flush=True)
         return
     if args.workload == "nuts":
         print(json.dumps(bench_nuts(args, torch)), flush=True)

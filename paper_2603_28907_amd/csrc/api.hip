@@ -26,6 +26,7 @@
 #include "prior.h"
 #include "probe.h"
 #include "voxel.h"
+#include "quad.h"
 #include "nuts.h"
 #include "latent.h"
 

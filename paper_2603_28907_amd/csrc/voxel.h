@@ -145,35 +145,4 @@ __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> 
     }
 }
 
-// Solid-angle pixels (eq. expected_counts): lambda_p = sum_q w_q I(O_q) over
-// the pixel's n_sub consecutive sub-rays, log I interpolated linearly on
-// uniform opacity nodes (the last segment continued beyond the table), and
-// the float64 Poisson term C log(lambda) - lambda per (chain, pixel).  Grid
-// (tiles of 256 pixels, chains); one partial sum per block.
-template <typename T>
-__global__ __launch_bounds__(256) void k_quad_lik(const T *opacity, int n_ray, int n_px, int n_sub,
-                                                  const double *w, const double *log_i, int n_tab, double inv_do,
-                                                  const double *cnt, double *partials, int n_tiles,
-                                                  const double *only_nan) {
-    __shared__ double red[16];
-    const size_t c = blockIdx.y;
-    if (only_nan && !(only_nan[c] != only_nan[c])) return;   // uniform over the block
-    const int px = blockIdx.x * 256 + threadIdx.x;
-    double term = 0.0;
-    if (px < n_px) {
-        double lam = 0.0;
-        for (int q = 0; q < n_sub; ++q) {
-            const int r = px * n_sub + q;
-            const double t = (double)opacity[c * n_ray + r] * inv_do;
-            int j = (int)floor(t);
-            j = j < 0 ? 0 : (j > n_tab - 2 ? n_tab - 2 : j);
-            const double f = t - j;
-            lam += w[r] * exp(log_i[j] + f * (log_i[j + 1] - log_i[j]));
-        }
-        term = cnt[px] * log(lam) - lam;
-    }
-    const double s = block_sum<256>(term, red);
-    if (threadIdx.x == 0) partials[c * n_tiles + blockIdx.x] = s;
-}
-
 }  // namespace mc
