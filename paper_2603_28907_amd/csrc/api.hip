@@ -1785,7 +1785,7 @@ mc_status grad_eval_latent(mc_problem *p, int n, const T *x, double *lp, T *gx, 
         if ((s = launch_march<T, S>(p, n, L.H, (T *)p->obuf.p, (double *)p->partials.p, st)) != MC_OK) return s;
         if ((s = launch_adjoint<T, S>(p, n, L.H, gfix, st)) != MC_OK) return s;
     }
-    hipLaunchKernelGGL((k_latent_finish<T, kPriorBlock>), dim3(n), dim3(kPriorBlock), 0, st, L);
+    hipLaunchKernelGGL((k_latent_finish<T, 512>), dim3(n), dim3(512), 0, st, L);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
 }

@@ -73,7 +73,9 @@ __global__ void k_heights_to_latent(const T *H, T *x, const double *top64, int N
     }
 }
 
-// Log density and gradient in x, one block per chain.
+// Log density and gradient in x, one block per chain (512 threads: few
+// chains still keep the compute units busy, without spilling the per-node
+// layer values).
 template <typename T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_latent_finish(LatentParams<T> P) {
     __shared__ double red[16];

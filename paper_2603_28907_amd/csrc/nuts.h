@@ -18,7 +18,7 @@
 
 namespace mc {
 
-constexpr int kNutsBlock = 256;
+constexpr int kNutsBlock = 1024;   // one block per chain: 16 wavefronts keep the CU busy with few chains
 constexpr int kNutsMaxDepth = 10;
 enum NutsTag : uint32_t { kTagNutsMomentum = 5, kTagNutsDirection = 6, kTagNutsLeaf = 7, kTagNutsMerge = 8 };
 
