@@ -206,3 +206,49 @@ def test_latent_logpost_and_nuts_match_oracle(torch_mod, oracle_mod, tiny):
     # the latent gradient multiplies the adjoint's 2^-32 fixed-point rounding by
     # the map's factor (H_top - H_{l-1}) phi(w) / sqrt(Sigma11) (10 to 100 here)
     compare(g, o, ok, rtol_x=1e-8, rtol_acc=1e-6, rtol_lp=1e-10)
+
+
+def _small(oracle_mod, S, n_sensors, seed):
+    from tests.helpers import make_scenario
+    rng = np.random.default_rng(seed)
+    R, C, X, Y = 7, 5, 60.0, 45.0
+    base = 30.0 + 3.0 * rng.standard_normal((R, C))
+    free = np.stack([base + 15.0 * l + 2.0 * rng.random((R, C)) for l in range(S - 1)])
+    top = 120.0 + rng.random((R, C))
+    dens = (1.8, 0.0, 2.7, 2.2)[:S]
+    if n_sensors:
+        pos = np.array([[X * 0.4, Y * 0.55, 0.0], [X * 0.7, Y * 0.3, 2.0]])[:n_sensors]
+        d1 = inputs.pixel_directions(6, 8)
+        dirs = np.broadcast_to(d1, (n_sensors,) + d1.shape).copy()
+    else:
+        pos, dirs = np.zeros((0, 3)), None
+    sc = make_scenario(S, R, C, X, Y, free, top, dens, pos, dirs, car_r=np.full(S - 1, 0.8))
+    sc.counts = oracle_mod.make_counts(sc, seed=seed + 1) if n_sensors else None
+    return sc
+
+
+@pytest.mark.parametrize("S,n_sensors,latent,max_depth", [
+    (2, 2, False, 3),
+    (4, 2, True, 4),
+    (3, 0, True, 5),     # no data: the latent prior alone
+    (4, 1, False, 1),    # the smallest tree: two leaves at most
+])
+def test_nuts_shapes_depths_and_prior_only(torch_mod, oracle_mod, S, n_sensors, latent, max_depth):
+    sc = _small(oracle_mod, S, n_sensors, seed=20 + S)
+    orc = oracle_mod.OracleProblem(sc, counts=sc.counts if n_sensors else np.zeros((0, 0), np.int32))
+    n = 3
+    states = np.stack([sc.truth + 0.2 * np.random.default_rng(c).standard_normal(sc.truth.shape)
+                       for c in range(n)])
+    states = np.sort(states, axis=1)
+    x0 = orc.heights_to_latent(states) if latent else states
+    eps = np.array([0.02, 0.05, 0.1]) if latent else np.array([0.005, 0.01, 0.02])
+    from paper_2603_28907_amd.binding import Problem
+    if not n_sensors:
+        sc.counts = np.zeros((0, 0), np.int32)
+    g, _ = gpu_nuts(torch_mod, sc, x0, eps, None, n_steps=3, seed=50 + S, max_depth=max_depth, latent=latent)
+    o = orc.nuts(x0, np.full(n, np.nan), eps, max_depth=max_depth, n_steps=3, seed=50 + S, latent=latent)
+    ok = [c for c in range(n) if o["margin"][c] > 1e-7]
+    say(f"S{S} latent={latent} depth cap {max_depth}:", o["depth"].tolist(), "margins", o["margin"])
+    assert len(ok) >= 2, "near-ties in most chains; choose another seed"
+    assert o["depth"].max() <= max_depth and o["n_leap"].max() <= 2 ** max_depth - 1
+    compare(g, o, ok, rtol_x=1e-8, rtol_acc=1e-6, rtol_lp=1e-10)
