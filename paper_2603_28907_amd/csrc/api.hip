@@ -706,8 +706,10 @@ mc_status launch_adjoint(mc_problem *p, int n, const T *heights, unsigned long l
         w.n_windows = (p->R + w.window_rows - 1) / w.window_rows;
         const size_t lds = surf + (size_t)w.window_rows * row_bytes;
         const dim3 grid((unsigned)(M.n_tiles * S * w.n_windows) * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+        // up to 64 KB of LDS: 512-thread blocks, so the LDS that limits blocks
+        // per CU still leaves 6 wavefronts per SIMD (256 threads left 3)
         if (lds > 65536) launch_adjoint_lds_shape<S, 1024>(grid, lds, M, K, (const float *)p->obuf.p, gfix, w, st);
-        else launch_adjoint_lds_shape<S, 256>(grid, lds, M, K, (const float *)p->obuf.p, gfix, w, st);
+        else launch_adjoint_lds_shape<S, 512>(grid, lds, M, K, (const float *)p->obuf.p, gfix, w, st);
         HIP_TRY(p, hipGetLastError());
         return MC_OK;
     } else {   // float64: the direct scatter
