@@ -278,7 +278,8 @@ __device__ __forceinline__ int piece_crossings(float fe, float fx, float c2, flo
 // and node would cost 12 per ray: the L2 atomic rate, not the walk, would
 // set the time).  Integer sums are order-independent, so the result is
 // bitwise reproducible.  The window keeps surface + accumulators inside the
-// LDS; a surface split into w windows is walked w times.
+// LDS; with several windows each ray's walk is clipped to the stretch of x
+// over the cells that touch the window's node rows.
 struct AdjointLdsShape {
     int n_windows, window_rows;
 };
@@ -343,8 +344,21 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
         const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
         const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
         const float ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
-        const float tl = fminf(fmaxf((band[0] - qz) * idz, 0.f), Texit);
-        const float th = fminf(fmaxf((band[1] - qz) * idz, 0.f), Texit);
+        float tl = fminf(fmaxf((band[0] - qz) * idz, 0.f), Texit);
+        float th = fminf(fmaxf((band[1] - qz) * idz, 0.f), Texit);
+        if (W_.n_windows > 1) {
+            // only cells whose node rows meet the window can add to it: cell
+            // rows row0-1 .. row0+rows-1, i.e. x in [(row0-1) hx, (row0+rows) hx];
+            // one more cell on each side absorbs rounding of the clip
+            const float xa = (float)(row0 - 2) * P.hx, xb = (float)(row0 + rows + 1) * P.hx;
+            if (dx != 0.f) {
+                const float ta = __builtin_fmaf(xa, idx, ox), tb = __builtin_fmaf(xb, idx, ox);
+                tl = fmaxf(tl, fminf(ta, tb));
+                th = fminf(th, fmaxf(ta, tb));
+            } else if (qx < xa || qx > xb) {
+                continue;
+            }
+        }
         if (!(tl < th) || scale == 0.f) continue;
         const bool xpos = dx > 0.f, ypos = dy > 0.f;
         Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, tl);
