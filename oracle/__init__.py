@@ -92,6 +92,8 @@ def _load():
         "orc_heights_to_latent": (None, [P, V, V]),
         "orc_latent_logpost_grad": (D, [P, V, V]),
         "orc_nested_rhat": (None, [I, I, ct.c_size_t, V, V]),
+        "orc_nuts_dense": (None, [ct.c_size_t, V, I, V, D, V, I, D, I64, U64, U64, V, V, V, V, V, V]),
+        "orc_nuts_set_fault": (None, [I]),
         "orc_warmup_window_end": (I, [I64, I64]),
         "orc_warmup_in_slow": (I, [I64, I64]),
     }
@@ -379,6 +381,32 @@ def nuts_gauss(sd, x0, eps, inv_mass=None, max_depth=8, max_dh=1000.0, n_warmup=
     x0 = _f64(x0)
     return _nuts_call(None, sd.size, sd, x0, np.full(x0.shape[0], np.nan), eps, inv_mass, max_depth, max_dh,
                       n_warmup, n_steps, target_accept, seed, step_offset, False)
+
+
+def nuts_dense(prec, x0, eps, inv_mass=None, max_depth=8, max_dh=1000.0, n_steps=1, seed=0, step_offset=0):
+    """n_steps NUTS transitions at step size eps on the test target
+    N(0, prec^-1) (dense precision matrix); x0: [n_chains, dim], chain c uses
+    Philox chain index c; inv_mass: [dim] shared by the chains, or None."""
+    lib = _load()
+    prec = _f64(prec)
+    x = _f64(x0).copy()
+    n, M = x.shape
+    assert prec.shape == (M, M)
+    im = None if inv_mass is None else _f64(inv_mass)
+    out = {k: np.zeros((n, n_steps), np.int32) for k in ("depth", "n_leap", "diverged", "turned")}
+    acc = np.zeros((n, n_steps))
+    marg = np.zeros(n)
+    lib.orc_nuts_dense(M, _p(prec), n, _p(x), float(eps), _p(im), int(max_depth), float(max_dh), int(n_steps),
+                       int(seed), int(step_offset), _p(out["depth"]), _p(out["n_leap"]), _p(out["diverged"]),
+                       _p(out["turned"]), _p(acc), _p(marg))
+    return dict(x=x, accept_stat=acc, margin=marg, **out)
+
+
+def set_nuts_fault(flags: int) -> None:
+    """Plant a mistake in the oracle's NUTS (tests of the pins' power only):
+    bit 0 skips the U-turn checks inside subtrees, bit 1 merges subtrees that
+    turned inside.  0 restores the correct sampler."""
+    _load().orc_nuts_set_fault(int(flags))
 
 
 def nested_rhat(x, n_super, n_within):

@@ -1013,6 +1013,13 @@ double orc_voxel_logpost_lik(const orc_problem *p, const double *free_h, double 
  */
 #define ORC_NUTS_MAX_DEPTH 12
 
+/* Planted mistakes, for tests that show a pin can see them (0 = none):
+ * bit 0 skips the U-turn checks of the blocks inside a subtree (only the
+ * merges of whole subtrees are checked); bit 1 merges the proposal of a
+ * subtree that turned inside instead of dropping it. */
+static int g_nuts_fault = 0;
+void orc_nuts_set_fault(int flags) { g_nuts_fault = flags; }
+
 typedef double (*orc_target_fn)(const void *ctx, const double *x, double *grad);
 
 typedef struct {
@@ -1124,7 +1131,7 @@ static void nuts_transition(orc_target_fn target, const void *ctx, size_t M, dou
         const double v = side ? 1.0 : -1.0;
         memcpy(p_near, pe[side], sizeof(double) * M);
         double logWs = -INFINITY, lps = 0.0;
-        int valid = 1;
+        int valid = 1, turned_inside = 0;
         const int n_sub = 1 << depth;
         for (int i = 0; i < n_sub && valid; ++i) {
             /* leapfrog from this side's end */
@@ -1169,12 +1176,13 @@ static void nuts_transition(orc_target_fn target, const void *ctx, size_t M, dou
                 }
                 for (size_t k = 0; k < M; ++k) Rj[k] += pp[k];
             }
-            for (int j = 1; j <= depth; ++j) {
+            for (int j = 1; j <= depth && !(g_nuts_fault & 1); ++j) {
                 if (((i + 1) & ((1 << j) - 1)) != 0) continue;
                 /* a level-j block completed: halves A = saved sibling, B = the level j-1 block */
                 const size_t a = (size_t)(j - 1) * M;
                 if (turning3(sR + a, sF + a, sL + a, R + a, F + a, pp, im, M, tmp, &margin)) {
                     valid = 0;
+                    turned_inside = 1;
                     break;
                 }
             }
@@ -1188,7 +1196,7 @@ static void nuts_transition(orc_target_fn target, const void *ctx, size_t M, dou
                 memcpy(sL + a, pp, sizeof(double) * M);
             }
         }
-        if (!valid) break;
+        if (!valid && !(turned_inside && (g_nuts_fault & 2))) break;
         /* merge the subtree into the tree */
         const double um = first_uniform(seed, chain, step, TAG_NUTS_MERGE, (uint32_t)depth);
         if (fabs(log(um) - (logWs - logW)) < margin) margin = fabs(log(um) - (logWs - logW));
@@ -1202,7 +1210,7 @@ static void nuts_transition(orc_target_fn target, const void *ctx, size_t M, dou
         turned = turning3(rho, pe[1 - side], p_near, rho_b, b_near, pe[side], im, M, tmp, &margin);
         for (size_t k = 0; k < M; ++k) rho[k] += rho_b[k];
         ++depth;
-        if (turned) break;
+        if (turned || !valid) break;
     }
     memcpy(x, xp, sizeof(double) * M);
     memcpy(g, gp, sizeof(double) * M);
@@ -1249,6 +1257,54 @@ static double gauss_target(const void *vctx, const double *x, double *grad) {
         grad[i] = -x[i] / s2;
     }
     return lp;
+}
+
+/* A Gaussian test target N(0, P^-1) with a dense precision matrix P
+   (M x M, row-major): lp = -x.P x / 2, grad = -P x (for pins). */
+typedef struct { size_t M; const double *prec; } gauss_dense_ctx;
+
+static double gauss_dense_target(const void *vctx, const double *x, double *grad) {
+    const gauss_dense_ctx *c = (const gauss_dense_ctx *)vctx;
+    double lp = 0.0;
+    for (size_t i = 0; i < c->M; ++i) {
+        double px = 0.0;
+        for (size_t j = 0; j < c->M; ++j) px += c->prec[i * c->M + j] * x[j];
+        grad[i] = -px;
+        lp -= 0.5 * x[i] * px;
+    }
+    return lp;
+}
+
+/* n_steps NUTS transitions at a fixed step size eps on the dense Gaussian
+   target, for every chain c (Philox chain index c); inv_mass [M] shared by
+   the chains or NULL.  Per-transition outputs [n_chains][n_steps]. */
+void orc_nuts_dense(size_t M, const double *prec, int n_chains, double *x_all, double eps, const double *inv_mass,
+                    int max_depth, double max_dh, int64_t n_steps, uint64_t seed, uint64_t step_offset,
+                    int32_t *depth_out, int32_t *n_leap_out, int32_t *div_out, int32_t *turned_out,
+                    double *acc_out, double *margin_out) {
+    if (max_depth > ORC_NUTS_MAX_DEPTH) max_depth = ORC_NUTS_MAX_DEPTH;
+    gauss_dense_ctx gc = {M, prec};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int c = 0; c < n_chains; ++c) {
+        double *x = x_all + M * c;
+        double *g = malloc(sizeof(double) * M);
+        double lp = gauss_dense_target(&gc, x, g);
+        double margin = INFINITY;
+        for (int64_t k = 0; k < n_steps; ++k) {
+            orc_nuts_stats st;
+            nuts_transition(gauss_dense_target, &gc, M, x, &lp, g, eps, inv_mass, max_depth, max_dh, seed,
+                            (uint32_t)c, step_offset + (uint64_t)k, 0, &st);
+            const size_t o = (size_t)c * n_steps + k;
+            if (depth_out) depth_out[o] = st.depth;
+            if (n_leap_out) n_leap_out[o] = st.n_leap;
+            if (div_out) div_out[o] = st.diverged;
+            if (turned_out) turned_out[o] = st.turned;
+            if (acc_out) acc_out[o] = st.accept_stat;
+            if (st.margin < margin) margin = st.margin;
+        }
+        if (margin_out) margin_out[c] = margin;
+        free(g);
+    }
 }
 
 /* Dual averaging of log(step size) (Hoffman & Gelman 2014, Sec. 3.2), per chain. */
