@@ -46,7 +46,9 @@ class _Problem(ct.Structure):
 
 class _Stats(ct.Structure):
     _fields_ = [("cells", ct.c_double), ("tests", ct.c_double), ("roots", ct.c_double),
-                ("crossings", ct.c_double), ("min_fprime", ct.c_double)]
+                ("crossings", ct.c_double), ("min_fprime", ct.c_double), ("gcond", ct.c_void_p),
+                ("cond_g", ct.c_double), ("cond_gerr", ct.c_double), ("eps_z", ct.c_double),
+                ("eps_rel", ct.c_double), ("eps_w", ct.c_double), ("lid_band", ct.c_double)]
 
 
 def _load():
@@ -79,6 +81,7 @@ def _load():
         "orc_mcmc_mala": (None, [P, I, V, V, V, I64, U64, D, V, U64, I, V]),
         "orc_march_one": (D, [P, V, V, V, V, ct.POINTER(_Stats)]),
         "orc_ray_stats": (None, [P, V, V, V, V]),
+        "orc_grad_conditioning": (None, [P, V, D, D, D, D, V, D, V]),
         "orc_sigmoid": (D, [D, D]),
         "orc_voxel_weights": (None, [P, V, I, D, V]),
         "orc_voxel_density": (None, [P, V, I, D, V]),
@@ -276,6 +279,18 @@ class OracleProblem:
         cr, mf, ce = np.empty(self.n_rays), np.empty(self.n_rays), np.empty(self.n_rays)
         self.lib.orc_ray_stats(ct.byref(self.prob), _p(self._free(free)), _p(cr), _p(mf), _p(ce))
         return dict(crossings=cr, min_fprime=mf, cells=ce)
+
+    def grad_conditioning(self, free, eps_z, eps_rel, eps_w=0.0, lid_band=0.0, dO=None, o_rel=1e-5):
+        """Per-node bound [S, R, C] on how far an evaluation of the likelihood
+        gradient that rounds z - h by eps_z, each contribution by eps_rel and
+        each bilinear weight by eps_w, drops crossings within lid_band of the
+        box lid, with opacity errors dO per ray (or the bound o_rel |O| + ...),
+        can move (see orc_grad_conditioning)."""
+        out = np.empty((self.S, self.R, self.C))
+        d = None if dO is None else _f64(dO)
+        self.lib.orc_grad_conditioning(ct.byref(self.prob), _p(self._free(free)), float(eps_z), float(eps_rel),
+                                       float(eps_w), float(lid_band), _p(d), float(o_rel), _p(out))
+        return out
 
     def mcmc_rw(self, states, lp, n_accept, n_steps, step_offset, sigma, seed,
                 state_f32=False, want_margins=False):

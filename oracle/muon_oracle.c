@@ -75,6 +75,16 @@ typedef struct {
     double roots;       /* quadratic roots found strictly inside a cell interval */
     double crossings;   /* sign changes of z - h along the ray */
     double min_fprime;  /* smallest |d(z-h)/dt| at a crossing (conditioning) */
+    /* optional conditioning report of the crossing-form gradient (for the
+       tolerances of tests): per node, a bound on how far an evaluation that
+       rounds z - h by eps_z and each contribution by eps_rel can move the
+       gradient of this ray's term */
+    double *gcond;      /* [S][R][C] accumulator, or NULL */
+    double cond_g;      /* |dLL/dO| of the ray */
+    double cond_gerr;   /* bound on the error of dLL/dO of the ray */
+    double eps_z, eps_rel;
+    double eps_w;       /* absolute rounding of a bilinear weight (local coordinates) */
+    double lid_band;    /* crossings this close below the box lid may be dropped as its kink */
 } orc_stats;
 
 /* ------------------------------------------------------------------------- */
@@ -183,6 +193,21 @@ static double march_ray(const orc_problem *p, const double *surf, const double q
                 double r[2];
                 int nr = roots_in(c2, c1, c0, tau1, r);
                 if (st) { st->tests += 1; st->roots += nr; }
+                if (st && st->gcond && nr == 0 && c2 != 0.0) {
+                    /* a near miss: an extremum of f within eps_z of zero may be a
+                       pair of crossings at rounding depth, |f'| = 2 sqrt(|c2| eps_z) */
+                    double tv = -c1 / (2.0 * c2);
+                    if (tv > 0.0 && tv < tau1 && fabs(c0 + tv * (c1 + c2 * tv)) <= st->eps_z) {
+                        double sv = s0 + tv * ds, wv = w0 + tv * dw;
+                        double drho = fabs(p->density[l] - (l + 1 < S ? p->density[l + 1] : 0.0));
+                        double fpair = 2.0 * sqrt(fabs(c2) * st->eps_z);
+                        double wt[4] = {(1 - sv) * (1 - wv), sv * (1 - wv), (1 - sv) * wv, sv * wv};
+                        size_t nd[4] = {(size_t)a * C + b, (size_t)(a + 1) * C + b, (size_t)a * C + b + 1,
+                                        (size_t)(a + 1) * C + b + 1};
+                        double *G = st->gcond + (size_t)l * R * C;
+                        for (int m = 0; m < 4; ++m) G[nd[m]] += drho * st->cond_g * fabs(wt[m]) * 2.0 / fpair;
+                    }
+                }
                 double cuts[4];
                 int nc = 0;
                 cuts[nc++] = 0.0;
@@ -206,6 +231,57 @@ static double march_ray(const orc_problem *p, const double *surf, const double q
                         if (st) {
                             st->crossings += 1;
                             if (fabs(fp) < st->min_fprime) st->min_fprime = fabs(fp);
+                        }
+                        if (st && st->gcond && fp != 0.0) {
+                            /* the crossing moves by eps_z/|f'|: its bilinear weights by
+                               (|ds|+|dw|) eps_z/|f'| and 1/|f'| by |f''| eps_z/|f'|^3; a
+                               crossing within eps_z of tangency may vanish with its partner */
+                            double sc = s0 + tc * ds, wc = w0 + tc * dw;
+                            double f1 = fabs(fp), f2 = 2.0 * fabs(c2), kw = fabs(ds) + fabs(dw);
+                            double drho = fabs(p->density[l] - (l + 1 < S ? p->density[l + 1] : 0.0));
+                            double pair = f1 * f1 <= 4.0 * fabs(c2) * st->eps_z ? 2.0 / f1 : 0.0;
+                            double wt[4] = {(1 - sc) * (1 - wc), sc * (1 - wc), (1 - sc) * wc, sc * wc};
+                            size_t nd[4] = {(size_t)a * C + b, (size_t)(a + 1) * C + b, (size_t)a * C + b + 1,
+                                            (size_t)(a + 1) * C + b + 1};
+                            /* near a cell edge the float32 walk may place the crossing in the
+                               neighbouring cell, whose patch has another slope: |f'| jumps
+                               there (the bilinear surface is only continuous), so the
+                               contribution can take the neighbour's 1/|f'|.  The band: node
+                               lines rounded by 2^-22 (X + |q| + T) in space, the crossing
+                               by 2 eps_z |d| / |f'|. */
+                            double jump = 0.0;
+                            for (int e = 0; e < 4; ++e) {
+                                int ax = e < 2;                       /* x-edge (s = 0, 1) or y-edge (w = 0, 1) */
+                                int hi = e & 1;
+                                double dist = ax ? (hi ? 1.0 - sc : sc) * hx : (hi ? 1.0 - wc : wc) * hy;
+                                double band = ldexp((ax ? p->X + fabs(q[0]) : p->Y + fabs(q[1])) + T, -22) +
+                                              2.0 * st->eps_z * fabs(ax ? d[0] : d[1]) / f1;
+                                if (!(dist <= band)) continue;
+                                int na = a + (ax ? (hi ? 1 : -1) : 0), nb = b + (ax ? 0 : (hi ? 1 : -1));
+                                if (na < 0 || na > R - 2 || nb < 0 || nb > C - 2) continue;
+                                double sn = sc - (na - a), wn = wc - (nb - b);   /* local coordinates in the neighbour */
+                                double n00 = Hl[na * C + nb], n10 = Hl[(na + 1) * C + nb];
+                                double n01 = Hl[na * C + nb + 1], n11 = Hl[(na + 1) * C + nb + 1];
+                                double Dn = n11 - n10 - n01 + n00;
+                                double slope = ((n10 - n00) + Dn * wn) * ds + ((n01 - n00) + Dn * sn) * dw;
+                                double fn = fabs(d[2] - slope);
+                                double j = fn > 0.0 ? fabs(1.0 / f1 - 1.0 / fn) : INFINITY;
+                                if (j > jump) jump = j;
+                            }
+                            /* a crossing just below the box lid may be taken for the lid's kink
+                               and dropped: its whole contribution */
+                            double zc = z0 + tc * d[2];
+                            double lid = ztop - zc <= st->lid_band + 2.0 * st->eps_z * fabs(d[2]) / f1 ? 1.0 / f1 : 0.0;
+                            double *G = st->gcond + (size_t)l * R * C;
+                            for (int m = 0; m < 4; ++m) {
+                                double w = fabs(wt[m]);
+                                /* |f'| comes from the end values of the cell's piece of length
+                                   tau1: their rounding moves it by 2 eps_z / tau1 */
+                                G[nd[m]] += drho * (st->cond_g * (w * (st->eps_rel / f1 + f2 * st->eps_z / (f1 * f1 * f1) +
+                                                                       2.0 * st->eps_z / (tau1 * f1 * f1) + pair + jump + lid) +
+                                                                  (kw * st->eps_z / f1 + 2.0 * st->eps_w) / f1) +
+                                                    st->cond_gerr * w / f1);
+                            }
                         }
                         if (gO && fp != 0.0) {
                             double sc = s0 + tc * ds, wc = w0 + tc * dw;
@@ -464,16 +540,31 @@ void orc_logpost_batch(const orc_problem *p, int n_chains, const double *free_al
  */
 double orc_loglik_grad_add(const orc_problem *p, const double *free_h, double *grad);
 
+static double voxel_loglik_grad_add(const orc_problem *p, const double *surf, double *grad);
+
+/* Log-likelihood and its gradient (added to grad [S][R][C]) under the
+   problem's forward model: the exact march, or the smoothed voxel model. */
+static double loglik_grad_add_any(const orc_problem *p, const double *free_h, double *grad) {
+    if (p->n_z == 0) return orc_loglik_grad_add(p, free_h, grad);
+    if (p->n_s * p->n_pix == 0) return 0.0;
+    double *surf = stack_surfaces(p, free_h);
+    double ll = voxel_loglik_grad_add(p, surf, grad);
+    free(surf);
+    return ll;
+}
+
 double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
     size_t NS = (size_t)p->S * p->R * p->C;
-    if (p->n_z > 0 || p->n_sub > 0) {   /* the gradient here: exact march, one ray per pixel */
+    if (p->n_sub > 0) {   /* the gradient here: one ray per pixel */
         for (size_t i = 0; i < NS; ++i) grad[i] = NAN;
         return NAN;
     }
     memset(grad, 0, sizeof(double) * NS);
     double lpr = orc_log_prior_grad(p, free_h, grad);
     if (lpr == -INFINITY) { memset(grad, 0, sizeof(double) * NS); return -INFINITY; }
-    return lpr + orc_loglik_grad_add(p, free_h, grad);
+    double ll = loglik_grad_add_any(p, free_h, grad);
+    if (ll == -INFINITY) { memset(grad, 0, sizeof(double) * NS); return -INFINITY; }
+    return lpr + ll;
 }
 
 /* Log-likelihood (eq. def_likelihood) of a state and its gradient in every
@@ -788,6 +879,46 @@ double orc_march_one(const orc_problem *p, const double *free_h, const double q[
     return O;
 }
 
+/* Conditioning report of the likelihood gradient (test tolerances only):
+   out [S][R][C] = per node, the sum over the rays' crossings of the bound
+   described at orc_stats.gcond (weights rounded by eps_w, crossings within
+   lid_band of the box lid dropped), with dL/dO of each ray from its opacity and
+   its error lambda |dO| / Lambda^2 from the opacity error dO of the ray:
+   dO_ray[ray] when given, else o_rel |O| + rho_max n_cross eps_z / min|f'|
+   + 1e-6. */
+void orc_grad_conditioning(const orc_problem *p, const double *free_h, double eps_z, double eps_rel, double eps_w,
+                           double lid_band, const double *dO_ray, double o_rel, double *out) {
+    double *surf = stack_surfaces(p, free_h);
+    double ztop = top_max(p), L[16], rho_max = 0.0;
+    for (int l = 0; l < p->S; ++l) rho_max = fmax(rho_max, fabs(p->density[l]));
+    memset(out, 0, sizeof(double) * (size_t)p->S * p->R * p->C);
+    for (int s = 0; s < p->n_s; ++s)
+        for (int k = 0; k < p->n_pix; ++k) {
+            int ray = s * p->n_pix + k;
+            const double *q = p->pos + 3 * s, *d = p->dirs + 3 * (size_t)ray;
+            orc_stats st;
+            memset(&st, 0, sizeof(st));
+            st.min_fprime = INFINITY;
+            double O = march_ray(p, surf, q, d, ztop, L, NULL, 0.0, &st);
+            double lam = p->exposure[ray] * exp(-O / p->atten);
+            double dO = o_rel * fabs(O) + 1e-6;
+            if (st.crossings > 0) dO += rho_max * st.crossings * eps_z / fmax(st.min_fprime, 1e-12);
+            if (dO_ray) dO = fabs(dO_ray[ray]);
+            orc_stats st2;
+            memset(&st2, 0, sizeof(st2));
+            st2.min_fprime = INFINITY;
+            st2.gcond = out;
+            st2.cond_g = fabs(lam - (double)p->counts[ray]) / p->atten;
+            st2.cond_gerr = lam * dO / (p->atten * p->atten);
+            st2.eps_z = eps_z;
+            st2.eps_rel = eps_rel;
+            st2.eps_w = eps_w;
+            st2.lid_band = lid_band;
+            march_ray(p, surf, q, d, ztop, L, NULL, 0.0, &st2);
+        }
+    free(surf);
+}
+
 /* Per-ray diagnostics for every ray: crossings and the smallest |f'| at a
    crossing (used to widen tolerances for ill-conditioned rays). */
 void orc_ray_stats(const orc_problem *p, const double *free_h, double *crossings, double *min_fprime,
@@ -957,6 +1088,61 @@ double orc_voxel_loglik(const orc_problem *p, const double *Rhat, double *O) {
         if (!(lam > 0.0)) ll = -INFINITY;
         else ll += c * log(lam) - lam - lgamma(c + 1.0);
     }
+    free(vox);
+    free(len);
+    return ll;
+}
+
+/* Gradient of the linearised voxel likelihood with respect to every surface
+   height (the paper smooths the layer indicators so that gradient-based
+   samplers can run on this model, Sec. 2.1.4).  By the chain rule through
+   eq. expected_counts_linearized_approx and eq. def_LM_density_grid_smooth:
+     dLL/dlambda-hat_p = C_p / lambda-hat_p - 1,
+     dlambda-hat_p/dRhat_v = G_pv = -lambda_p(R0) L_pv / Lambda,
+     B_v = dLL/dRhat_v = sum_p (C_p / lambda-hat_p - 1) G_pv,
+   and Rhat of voxel (n, k) depends on the heights of column n only:
+     Rhat = (sum_{l=1..S} (rho_l - rho_{l+1}) sigma_l - rho_1 sigma_0) / (1 - sigma_0),
+     sigma_l = sigmoid((H_l,n - z_k) / gamma), rho_{S+1} = 0 (the air),
+     dRhat/dH_l,n = (rho_l - rho_{l+1}) sigma_l (1 - sigma_l) / (gamma (1 - sigma_0)).
+   So dLL/dH_l,n = sum_k B_(n,k) dRhat_(n,k)/dH_l,n.  grad [S][R][C] (the
+   top surface included) is added to; returns LL (-inf, adding nothing, when
+   some lambda-hat_p <= 0). */
+static double voxel_loglik_grad_add(const orc_problem *p, const double *surf, double *grad) {
+    const int S = p->S, n_z = p->n_z, nr = p->n_s * p->n_pix;
+    const size_t N = (size_t)p->R * p->C, V = N * n_z;
+    const double *R0 = p->vox_ref, gamma = p->gamma, dz = top_max(p) / n_z;
+    double *Rhat = (double *)malloc(sizeof(double) * V), *B = (double *)calloc(V, sizeof(double));
+    int *vox = (int *)malloc(sizeof(int) * (p->R + p->C + n_z + 1));
+    double *len = (double *)malloc(sizeof(double) * (p->R + p->C + n_z + 1));
+    orc_voxel_density(p, surf, n_z, gamma, Rhat);
+    double ll = 0.0;
+    for (int ray = 0; ray < nr; ++ray) {
+        const int m = orc_voxel_pieces(p, ray, n_z, vox, len);
+        double o0 = 0.0;
+        for (int a = 0; a < m; ++a) o0 += len[a] * R0[vox[a]];
+        const double lam0 = p->exposure[ray] * exp(-o0 / p->atten);
+        double lam = lam0;
+        for (int a = 0; a < m; ++a) lam += (-lam0 * len[a] / p->atten) * (Rhat[vox[a]] - R0[vox[a]]);
+        const double c = (double)p->counts[ray];
+        if (!(lam > 0.0)) { ll = -INFINITY; break; }
+        ll += c * log(lam) - lam - lgamma(c + 1.0);
+        const double dl = c / lam - 1.0;
+        for (int a = 0; a < m; ++a) B[vox[a]] += dl * (-lam0 * len[a] / p->atten);
+    }
+    if (ll > -INFINITY) {
+        for (size_t n = 0; n < N; ++n)
+            for (int k = 0; k < n_z; ++k) {
+                const double z = (k + 0.5) * dz;
+                const double norm = 1.0 - orc_sigmoid(0.0 - z, gamma);
+                for (int l = 0; l < S; ++l) {
+                    const double sg = orc_sigmoid(surf[(size_t)l * N + n] - z, gamma);
+                    const double drho = p->density[l] - (l + 1 < S ? p->density[l + 1] : 0.0);
+                    grad[(size_t)l * N + n] += B[n * n_z + k] * drho * sg * (1.0 - sg) / (gamma * norm);
+                }
+            }
+    }
+    free(Rhat);
+    free(B);
     free(vox);
     free(len);
     return ll;
@@ -1528,7 +1714,7 @@ void orc_heights_to_latent(const orc_problem *p, const double *H, double *x) {
    D_l = dlogL/dH_l + (1 - u_{l+1}) D_{l+1} and dlogL/dx_l = D_l dH_l/dx_l. */
 double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx) {
     const int S1 = p->S - 1, N = p->R * p->C, R = p->R, C = p->C;
-    if (p->n_z > 0 || p->n_sub > 0) {   /* the exact march's gradient, one ray per pixel, only */
+    if (p->n_sub > 0) {   /* the gradient here: one ray per pixel */
         if (gx) for (size_t i = 0; i < (size_t)S1 * N; ++i) gx[i] = NAN;
         return NAN;
     }
@@ -1541,7 +1727,7 @@ double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx
         sl[l] = sqrt(s11);
     }
     orc_latent_to_heights(p, x, H);
-    double lp = orc_loglik_grad_add(p, H, gH);
+    double lp = loglik_grad_add_any(p, H, gH);
     if (gx) {
         for (int i = 0; i < N; ++i) {
             double D = 0.0;

@@ -90,3 +90,46 @@ def opacity_from_lengths(L, density):
     S = len(density)
     rho_above = np.append(np.asarray(density[1:], np.float64), 0.0)
     return float(np.sum((np.asarray(density) - rho_above) * L[:S]))
+
+
+def central_differences(oracle_mod, sc, x0, n_coords, h, seed):
+    """Central differences of the oracle's float64 log posterior at the free
+    state x0 [S-1, R, C] on n_coords seeded coordinates of all S surfaces
+    (a coordinate of the fixed top perturbs the problem's top).  Returns a
+    list of (surface, i, j, forward, backward, central) differences."""
+    import copy
+
+    S, R, C = sc.n_surfaces, sc.n_rows, sc.n_cols
+    rng = np.random.default_rng(seed)
+    picks = [np.unravel_index(k, (S, R, C)) for k in rng.choice(S * R * C, n_coords, replace=False)]
+    orc = oracle_mod.OracleProblem(sc)
+    f0 = orc.logpost(x0)
+    free_states, free_idx, out = [], [], []
+    for (l, i, j) in picks:
+        if l < S - 1:
+            xp, xm = x0.copy(), x0.copy()
+            xp[l, i, j] += h
+            xm[l, i, j] -= h
+            free_idx.append((l, i, j))
+            free_states += [xp, xm]
+    vals = orc.logpost_batch(np.stack(free_states)) if free_states else []
+    for k, (l, i, j) in enumerate(free_idx):
+        fp, fm = vals[2 * k], vals[2 * k + 1]
+        out.append((int(l), int(i), int(j), (fp - f0) / h, (f0 - fm) / h, (fp - fm) / (2 * h)))
+    for (l, i, j) in picks:
+        if l < S - 1:
+            continue
+        fv = []
+        for sgn in (1.0, -1.0):
+            sc2 = copy.copy(sc)
+            sc2.top = sc.top.copy()
+            sc2.top[i, j] += sgn * h
+            fv.append(oracle_mod.OracleProblem(sc2).logpost(x0))
+        out.append((int(l), int(i), int(j), (fv[0] - f0) / h, (f0 - fv[1]) / h, (fv[0] - fv[1]) / (2 * h)))
+    return out
+
+
+def is_kink(fwd, bwd, tol):
+    """The two one-sided differences disagree by more than 10x the tolerance:
+    the coordinate sits on a kink of the piecewise-smooth log posterior."""
+    return abs(fwd - bwd) > 10 * tol + 1e-2 * abs(fwd + bwd)

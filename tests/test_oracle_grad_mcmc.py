@@ -183,3 +183,26 @@ def test_philox_is_a_keyed_bijection_of_the_counter(oracle_mod):
         out = tuple(oracle_mod.philox4x32_10([c, 0, 0, 0], [5, 6]))
         assert out not in seen
         seen.add(out)
+
+
+def test_logpost_gradient_fd_128(oracle_mod):
+    """The differentiable workload's geometry (3 surfaces on 128x128 nodes
+    over 400 m, 8 sensors x 64x64 pixels): central differences (h = 1e-3 m)
+    of the float64 log posterior on 64 seeded coordinates of all three
+    surfaces, against the oracle gradient; kinks detected and skipped."""
+    from tests.helpers import central_differences, is_kink
+    sc = inputs.grf_cave(seed=10, n_grid=128)
+    sc.counts = oracle_mod.make_counts(sc, seed=11)
+    x0 = inputs.init_states(sc, 1, seed=12)[0]
+    lp, g = oracle_mod.OracleProblem(sc).grad(x0)
+    fd = central_differences(oracle_mod, sc, x0, 64, 1e-3, seed=13)
+    scale = np.abs(g).max()
+    tol = 1e-4 * scale + 1e-3
+    kinks = 0
+    for (l, i, j, fwd, bwd, c) in fd:
+        if is_kink(fwd, bwd, tol):
+            kinks += 1
+            continue
+        assert abs(c - g[l, i, j]) <= tol, (l, i, j, c, g[l, i, j])
+    assert kinks <= 8
+    assert sum(1 for f in fd if f[0] == 2) > 0   # the top surface is covered

@@ -177,8 +177,84 @@ def test_logpost_and_nonpositive_counts(oracle_mod, tiny):
     low = tiny.truth.copy()
     low[1] = low[0] + 0.5
     assert o2.voxel_loglik(low) == -np.inf
-    # the exact-march gradient does not apply to the voxel model
+    # the gradient of the voxel model: finite, and zero where some linearised
+    # count is not positive (log posterior -inf)
     lp, g = orc.grad(st[0])
-    assert math.isnan(lp) and np.all(np.isnan(g))
+    assert lp == pytest.approx(orc.logpost(st[0]), rel=1e-13) and np.all(np.isfinite(g))
+    lpl, gl = o2.grad(low)
+    assert lpl == -np.inf and np.all(gl == 0.0)
     orc.set_voxel_model(0)
     assert math.isfinite(orc.logpost(st[0]))
+
+
+def test_voxel_gradient_central_differences(oracle_mod, tiny):
+    """The voxel model is smooth in the heights: the oracle's gradient
+    (chain rule through the linearised counts, G and the sigmoid
+    derivatives) equals central differences of its log posterior on 48
+    free and 16 top coordinates (R0 kept fixed)."""
+    import copy
+    n_z, gamma = 25, 2.0
+    tiny = copy.copy(tiny)   # a terrain with one highest node, so the box lid stays put
+    xs = np.linspace(0.0, 1.0, tiny.n_rows)[:, None] + np.linspace(0.0, 0.7, tiny.n_cols)[None, :]
+    tiny.top = 200.0 - 4.0 * xs
+    tiny.counts = oracle_mod.make_counts(tiny, seed=1)
+    orc = oracle_mod.OracleProblem(tiny)
+    orc.set_voxel_model(n_z, gamma, tiny.truth)
+    x0 = inputs.init_states(tiny, 1, seed=21, jitter=1.0)[0]
+    lp, g = orc.grad(x0)
+    assert np.isfinite(lp) and lp == pytest.approx(orc.logpost(x0), rel=1e-13)
+    assert np.abs(g[2]).max() > 0.0   # the top surface has a gradient too
+    rng = np.random.default_rng(22)
+    h = 1e-4
+    scale = np.abs(g).max()
+    free = [np.unravel_index(k, x0.shape) for k in rng.choice(x0.size, 48, replace=False)]
+    for idx in free:
+        xp, xm = x0.copy(), x0.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (orc.logpost(xp) - orc.logpost(xm)) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * scale + 1e-5, (idx, fd, g[idx])
+    argmax = np.unravel_index(np.argmax(tiny.top), tiny.top.shape)
+    tops = [np.unravel_index(k, tiny.top.shape) for k in rng.choice(tiny.top.size, 17, replace=False)]
+    tops = [t for t in tops if t != argmax][:16]
+    for t in tops:
+        vals = []
+        for sgn in (1.0, -1.0):
+            sc2 = copy.copy(tiny)
+            sc2.top = tiny.top.copy()
+            sc2.top[t] += sgn * h
+            o2 = oracle_mod.OracleProblem(sc2)
+            o2.set_voxel_model(n_z, gamma, tiny.truth)
+            o2._vox_ref[...] = orc._vox_ref   # the same linearisation point R0
+            vals.append(o2.logpost(x0))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[2][t]) <= 1e-6 * scale + 1e-5, (t, fd, g[2][t])
+
+
+def test_voxel_gradient_uniform_lift_sum_rule(oracle_mod):
+    """Flat layers crossed inside the box by one ray: lifting a surface
+    uniformly moves every smoothed interface by the same amount, and the
+    ray's length per level is dz / d_z, so the node gradients of the
+    opacity sum to (rho_l - rho_{l+1}) / d_z (the exact march's sum rule)
+    up to the midpoint sum of the sigmoid's derivative over the levels,
+    which is below 1e-6 for gamma = dz."""
+    R, C, X, Y = 6, 5, 100.0, 80.0
+    levels = [30.0, 45.0, 90.0]
+    dens = np.array([1.8, 0.0, 2.7])
+    free = np.stack([np.full((R, C), c) for c in levels[:2]])
+    d = unit([0.2, 0.1, 1.0])
+    q = np.array([40.0, 30.0, 0.0])
+    sc = make_scenario(3, R, C, X, Y, free, np.full((R, C), levels[2]), dens, q[None], d[None, None],
+                       exposure=np.array([[1e4]]), counts=np.array([[100]], np.int32), car_r=np.array([0.5, 0.5]))
+    orc = oracle_mod.OracleProblem(sc)
+    n_z = 45                              # dz = 2 m
+    orc.set_voxel_model(n_z, 2.0, free)   # at the reference, lambda-hat = lambda(R0)
+    lp, g = orc.grad(free)
+    _, gprior = orc.log_prior_grad(free)
+    _, O = orc.voxel_loglik(free, with_opacity=True)
+    lam0 = 1e4 * math.exp(-O[0] / 400.0)
+    dll_do = (100.0 / lam0 - 1.0) * (-lam0 / 400.0)
+    dOdH = (g - gprior) / dll_do
+    for l in range(2):
+        expect = (dens[l] - dens[l + 1]) / d[2]
+        assert dOdH[l].sum() == pytest.approx(expect, rel=1e-5), (l, dOdH[l].sum(), expect)
