@@ -94,6 +94,7 @@ def _load():
         "orc_quad_loglik": (D, [P, V, V]),
         "orc_heights_to_latent": (None, [P, V, V]),
         "orc_latent_logpost_grad": (D, [P, V, V]),
+        "orc_latent_r_logpost_grad": (D, [P, V, V]),
         "orc_nested_rhat": (None, [I, I, ct.c_size_t, V, V]),
         "orc_nuts_dense": (None, [ct.c_size_t, V, I, V, D, V, I, D, I64, U64, U64, V, V, V, V, V, V]),
         "orc_nuts_set_fault": (None, [I]),
@@ -321,17 +322,43 @@ class OracleProblem:
         return s.reshape(np.shape(states)), rr, lpa, acc, accr, marg
 
     def nuts(self, states, lp, eps, inv_mass=None, max_depth=8, max_dh=1000.0, n_warmup=0, n_steps=1,
-             target_accept=0.8, seed=0, step_offset=0, state_f32=False, latent=False):
+             target_accept=0.8, seed=0, step_offset=0, state_f32=False, latent=False, r=None):
         """NUTS on this posterior; states [n, S-1, R, C] (heights, or the latent CAR fields with
-        latent=True); eps [n]; inv_mass [n, S-1, R, C] or None."""
-        s = _f64(states).reshape(-1, self.M)
-        im = None if inv_mass is None else _f64(inv_mass).reshape(-1, self.M)
-        out = _nuts_call(ct.byref(self.prob), self.M, None, s, lp, eps, im, max_depth, max_dh, n_warmup, n_steps,
-                         target_accept, seed, step_offset, state_f32, latent)
-        out["x"] = out["x"].reshape(np.shape(states))
-        if im is not None:
-            out["inv_mass"] = out["inv_mass"].reshape(np.shape(states))
+        latent=True); eps [n]; inv_mass [n, S-1, R, C] or None.  With r [n, S-1] (latent only) the
+        chains also sample r: the state is (x, logit r), inv_mass is [n, (S-1) R C + S-1], and
+        out["r"] holds the final r."""
+        n = np.shape(states)[0]
+        if r is None:
+            s = _f64(states).reshape(-1, self.M)
+            im = None if inv_mass is None else _f64(inv_mass).reshape(-1, self.M)
+            out = _nuts_call(ct.byref(self.prob), self.M, None, s, lp, eps, im, max_depth, max_dh, n_warmup,
+                             n_steps, target_accept, seed, step_offset, state_f32, latent)
+            out["x"] = out["x"].reshape(np.shape(states))
+            if im is not None:
+                out["inv_mass"] = out["inv_mass"].reshape(np.shape(states))
+            return out
+        assert latent, "r is sampled on the latent parametrisation"
+        S1 = self.S - 1
+        ra = _f64(r).reshape(n, S1)
+        z = np.concatenate([_f64(states).reshape(n, self.M), np.log(ra / (1.0 - ra))], axis=1)
+        im = None if inv_mass is None else _f64(inv_mass).reshape(n, self.M + S1)
+        out = _nuts_call(ct.byref(self.prob), self.M + S1, None, z, lp, eps, im, max_depth, max_dh, n_warmup,
+                         n_steps, target_accept, seed, step_offset, state_f32, 2)
+        zf = out["x"]
+        out["x"] = zf[:, :self.M].reshape(np.shape(states))
+        out["r"] = 1.0 / (1.0 + np.exp(-zf[:, self.M:]))
         return out
+
+    def latent_r_logpost(self, x, r, with_grad=False):
+        """Log density of the latent vector (x, logit r) and optionally its
+        gradient (x part [S-1, R, C], logit-r part [S-1])."""
+        S1 = self.S - 1
+        z = np.concatenate([_f64(x).reshape(-1), np.log(_f64(r) / (1.0 - _f64(r)))])
+        g = np.empty(z.size) if with_grad else None
+        v = float(self.lib.orc_latent_r_logpost_grad(ct.byref(self.prob), _p(z), _p(g)))
+        if not with_grad:
+            return v
+        return v, g[:self.M].reshape(S1, self.R, self.C), g[self.M:].copy()
 
     def latent_to_heights(self, x):
         x = _f64(x).reshape(-1, self.M)
@@ -381,7 +408,7 @@ def _nuts_call(prob, n_dim, sd, x, lp, eps, inv_mass, max_depth, max_dh, n_warmu
     dv = np.zeros((n, total), np.int32)
     acc = np.zeros((n, total))
     marg = np.zeros(n)
-    lib.orc_nuts(prob, int(n_dim), _p(sd), int(bool(latent)), n, _p(x), _p(lpa), _p(ea), _p(im), int(max_depth),
+    lib.orc_nuts(prob, int(n_dim), _p(sd), int(latent), n, _p(x), _p(lpa), _p(ea), _p(im), int(max_depth),
                  float(max_dh),
                  int(n_warmup), int(n_steps), float(target_accept), int(seed), int(step_offset), int(bool(state_f32)),
                  _p(depth), _p(nl), _p(dv), _p(acc), _p(marg))

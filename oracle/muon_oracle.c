@@ -1202,7 +1202,8 @@ double orc_voxel_logpost_lik(const orc_problem *p, const double *free_h, double 
 /* Planted mistakes, for tests that show a pin can see them (0 = none):
  * bit 0 skips the U-turn checks of the blocks inside a subtree (only the
  * merges of whole subtrees are checked); bit 1 merges the proposal of a
- * subtree that turned inside instead of dropping it. */
+ * subtree that turned inside instead of dropping it; bit 2 drops the
+ * Jacobian of r = logistic(eta) from the latent density with r. */
 static int g_nuts_fault = 0;
 void orc_nuts_set_fault(int flags) { g_nuts_fault = flags; }
 
@@ -1431,6 +1432,13 @@ static double latent_target(const void *vctx, const double *x, double *grad) {
     return orc_latent_logpost_grad(c->p, x, grad);
 }
 
+double orc_latent_r_logpost_grad(const orc_problem *p, const double *z, double *gz);
+
+static double latent_r_target(const void *vctx, const double *z, double *grad) {
+    const cave_ctx *c = (const cave_ctx *)vctx;
+    return orc_latent_r_logpost_grad(c->p, z, grad);
+}
+
 /* A Gaussian test target N(0, diag(sd^2)) in M dimensions (for pins). */
 typedef struct { size_t M; const double *sd; } gauss_ctx;
 
@@ -1571,7 +1579,8 @@ void orc_nuts(const orc_problem *p, size_t n_dim, const double *gauss_sd, int la
               double *lp, double *eps, double *inv_mass, int max_depth, double max_dh, int64_t n_warmup,
               int64_t n_steps, double target_accept, uint64_t seed, uint64_t step_offset, int state_f32,
               int32_t *depth_out, int32_t *n_leap_out, int32_t *div_out, double *acc_out, double *margin_out) {
-    const size_t M = gauss_sd ? n_dim : (size_t)(p->S - 1) * p->R * p->C;
+    /* latent: 0 = heights, 1 = the CAR fields x, 2 = x and logit r (one r per free surface) */
+    const size_t M = gauss_sd ? n_dim : (size_t)(p->S - 1) * p->R * p->C + (latent == 2 ? p->S - 1 : 0);
     const size_t NS = gauss_sd ? n_dim : (size_t)p->S * p->R * p->C;
     if (max_depth > ORC_NUTS_MAX_DEPTH) max_depth = ORC_NUTS_MAX_DEPTH;
     const int64_t total = n_warmup + n_steps;
@@ -1585,7 +1594,8 @@ void orc_nuts(const orc_problem *p, size_t n_dim, const double *gauss_sd, int la
         int64_t wn = 0;
         cave_ctx cc = {p, gfull};
         gauss_ctx gc = {M, gauss_sd};
-        orc_target_fn tf = gauss_sd ? gauss_target : (latent ? latent_target : cave_target);
+        orc_target_fn tf = gauss_sd ? gauss_target
+                                    : (latent == 2 ? latent_r_target : (latent ? latent_target : cave_target));
         const void *ctx = gauss_sd ? (const void *)&gc : (const void *)&cc;
         double l = tf(ctx, x, g);
         if (isnan(lp[c])) lp[c] = l;
@@ -1712,6 +1722,97 @@ void orc_heights_to_latent(const orc_problem *p, const double *H, double *x) {
    Chain rule at each node, top layer first: with a_l = H_{l-1},
    dH_l/dx_l = (H_top - a_l) phi(w_l) / sqrt(Sigma11_l) and dH_l/da_l = 1 - u_l,
    D_l = dlogL/dH_l + (1 - u_{l+1}) D_{l+1} and dlogL/dx_l = D_l dH_l/dx_l. */
+/* d/dr of log det Q(r) and of Sigma11(r) on the R x C torus, from the
+   eigenvalues mu_km = 4 - 2 r c_km, c_km = cos(2 pi k / R) + cos(2 pi m / C):
+   d log det Q / dr = sum -2 c_km / mu_km, d Sigma11 / dr = sum 2 c_km / mu_km^2 / N. */
+static void car_consts_dr(int R, int C, double r, double *dlogdet, double *ds11) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < R; ++k)
+        for (int m = 0; m < C; ++m) {
+            const double c = cos(2.0 * M_PI * k / R) + cos(2.0 * M_PI * m / C);
+            const double mu = 4.0 - 2.0 * r * c;
+            a += -2.0 * c / mu;
+            b += 2.0 * c / (mu * mu);
+        }
+    *dlogdet = a;
+    *ds11 = b / ((double)R * C);
+}
+
+/*
+ * The sampler's latent vector with the hierarchical dependence (Sec. 2.2.1:
+ * r_l ~ Uniform(0, 1) a priori; Sec. 3.1: the sampler runs on a vector of
+ * all unknowns): z = (x_1 .. x_{S-1}, eta_1 .. eta_{S-1}), eta = logit r, so
+ * z has no boundaries.  Its log density is
+ *   log L(H(x, r)) + sum_l [ log det Q(r_l)/2 - x_l' Q(r_l) x_l / 2
+ *                            - (N/2) log 2 pi + log(r_l (1 - r_l)) ],
+ * the last term the Jacobian dr/deta of the flat prior; H(x, r) is the copula
+ * map with s_l = sqrt(Sigma11(r_l)).  Gradient in eta_l: r (1 - r) times
+ *   dlogL/dr_l + (d log det Q / dr)/2 + x_l' A x_l / 2   (Q = 4 I - r A),
+ * plus 1 - 2 r; dlogL/dr_l = sum_i D_l,i (b_i - a_l,i) phi(w) dw/dr with
+ * w = x / s, dw/dr = -w (dSigma11/dr) / (2 s^2) and D the total derivative
+ * of log L in H_l (through the layers above).  gz (optional) has the layout
+ * of z.
+ */
+double orc_latent_r_logpost_grad(const orc_problem *p, const double *z, double *gz) {
+    const int S1 = p->S - 1, R = p->R, C = p->C, N = R * C;
+    if (p->n_sub > 0) {   /* the gradient here: one ray per pixel */
+        if (gz) for (size_t i = 0; i < (size_t)S1 * N + S1; ++i) gz[i] = NAN;
+        return NAN;
+    }
+    const double *x = z, *eta = z + (size_t)S1 * N;
+    const size_t NS = (size_t)p->S * N;
+    double r[16], sl[16], ld[16], dld[16], ds11[16];
+    for (int l = 0; l < S1; ++l) {
+        r[l] = 1.0 / (1.0 + exp(-eta[l]));
+        double s11;
+        orc_car_consts(R, C, r[l], &ld[l], &s11);
+        sl[l] = sqrt(s11);
+        car_consts_dr(R, C, r[l], &dld[l], &ds11[l]);
+    }
+    double *H = calloc((size_t)S1 * N, sizeof(double)), *gH = calloc(NS, sizeof(double));
+    for (int l = 0; l < S1; ++l)
+        for (int i = 0; i < N; ++i) {
+            const double a = l ? H[(size_t)(l - 1) * N + i] : 0.0, b = p->top[i];
+            const double w = x[(size_t)l * N + i] / sl[l];
+            H[(size_t)l * N + i] = w <= 0.0 ? a + Phi(w) * (b - a) : b - Phi(-w) * (b - a);
+        }
+    double lp = loglik_grad_add_any(p, H, gH);
+    double dr[16];
+    for (int l = 0; l < S1; ++l) dr[l] = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double D = 0.0;
+        for (int l = S1 - 1; l >= 0; --l) {
+            const double a = l ? H[(size_t)(l - 1) * N + i] : 0.0, b = p->top[i];
+            const double w = x[(size_t)l * N + i] / sl[l];
+            D = gH[(size_t)l * N + i] + (l < S1 - 1 ? Phi(-x[(size_t)(l + 1) * N + i] / sl[l + 1]) * D : 0.0);
+            const double phi = exp(-0.5 * w * w) / sqrt(2.0 * M_PI);
+            if (gz) gz[(size_t)l * N + i] = D * (b - a) * phi / sl[l];
+            dr[l] += D * (b - a) * phi * (-w * ds11[l] / (2.0 * sl[l] * sl[l]));
+        }
+    }
+    for (int l = 0; l < S1; ++l) {
+        const double *xl = x + (size_t)l * N;
+        double quad = 0.0, xax = 0.0;
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < C; ++j) {
+                const int n = i * C + j;
+                const double nb = xl[i * C + (j + 1) % C] + xl[i * C + (j + C - 1) % C] +
+                                  xl[((i + 1) % R) * C + j] + xl[((i + R - 1) % R) * C + j];
+                const double qx = 4.0 * xl[n] - r[l] * nb;
+                quad += xl[n] * qx;
+                xax += xl[n] * nb;
+                if (gz) gz[(size_t)l * N + n] -= qx;
+            }
+        const int jac = !(g_nuts_fault & 4);   /* planted mistake (tests): drop the Jacobian */
+        lp += 0.5 * ld[l] - 0.5 * quad - 0.5 * N * log(2.0 * M_PI) + (jac ? log(r[l] * (1.0 - r[l])) : 0.0);
+        if (gz)
+            gz[(size_t)S1 * N + l] =
+                r[l] * (1.0 - r[l]) * (dr[l] + 0.5 * dld[l] + 0.5 * xax) + (jac ? 1.0 - 2.0 * r[l] : 0.0);
+    }
+    free(H); free(gH);
+    return lp;
+}
+
 double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx) {
     const int S1 = p->S - 1, N = p->R * p->C, R = p->R, C = p->C;
     if (p->n_sub > 0) {   /* the gradient here: one ray per pixel */
