@@ -63,7 +63,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # At 6 wavefronts per SIMD the march spills ~40 bytes per lane to scratch
 # once per wavefront; the dirty scratch lines written back at the end of the
 # kernel are most of WRITE_SIZE (about 1.7 bytes per ray).
-KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march.h", "march3.h", "march5.h"),
+KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march_common.h", "march3.h", "march5.h"),
                   "voxel64": ("device_common.h", "voxel.h")}
 MEASURED_TRAFFIC = {
     "grf_cave_64": dict(source_sha="9b722cd35d001b36", fetch_kib=30673.8, fetch_scale=262144 / 131093.4,

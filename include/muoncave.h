@@ -127,13 +127,18 @@ mc_status set_counts(mc_problem *p, const int32_t *counts);
  *   ref_heights[(S-1)*R*C]: host array, the free surfaces of H_ref (the top
  *   is the problem's); copied.
  * Needs geometry and sensors; load_geometry_grid and set_sensors switch the
- * model off again.  While it is on, logpost_batch and mcmc_run (random walk,
- * with or without sampled r) use it; logpost_grad_batch, MALA,
- * mcmc_run_multi, mc_time_march and mc_time_adjoint return
+ * model off again.  While it is on, logpost_batch, logpost_grad_batch,
+ * mcmc_run (random walk with or without sampled r, and MALA) and nuts_run
+ * use it; mcmc_run_multi, mc_time_march and mc_time_adjoint return
  * MC_ERR_UNSUPPORTED or MC_ERR_STATE.  The opacity output of logpost_batch
- * then holds O_p(R-hat).  Device memory: the ray-voxel lists (8 or 12 bytes
- * per piece) and, per call, R*C*n_z*round_up(n_chains, 64) smoothed
- * densities in the state precision.
+ * then holds O_p(R-hat).  Its gradient (the paper's reason for the sigmoid,
+ * Sec. 2.1.4): dLL/dH_l,n = sum_k B_(n,k) (rho_l - rho_{l+1}) s (1 - s) /
+ * (gamma (1 - s_0)), s = sigmoid((H_l,n - z_k) / gamma), s_0 the floor's, with
+ * B_v = sum_p (C_p / lambda-hat_p - 1) G_pv gathered over the rays that
+ * cross voxel v.  Device memory: the ray-voxel lists and their transpose
+ * (8 or 12 bytes per piece each) and, per call, R*C*n_z*round_up(n_chains,
+ * 64) smoothed densities in the state precision (plus n_rays of dLL/dO per
+ * chain for gradients).
  */
 mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *ref_heights);
 
@@ -180,6 +185,12 @@ mc_status logpost_batch(mc_problem *p, int n_chains, const void *heights, double
  *         rows of chains outside the support are zero.
  * The likelihood part uses the crossing form dO/dH_n = (rho_l - rho_{l+1})
  * sum over crossings of w_n / |d(z-h)/dt|; lp is piecewise smooth in H.
+ * float32: the march that precedes the adjoint records each crossing (cell,
+ * local coordinates, 1/|f'|) and dLL/dO of every ray, and the adjoint sums
+ * the node contributions from those records; chains whose record slots
+ * overflow (see mc_tuning.grad_slots) are re-walked instead, with the same
+ * result bit for bit.  Under set_voxel_model the gradient is the voxel
+ * model's (see there).
  */
 mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, double *logpost,
                              void *grad, void *stream);
@@ -226,31 +237,33 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
 
 /*
  * Launch shape of the ray-march kernel (performance only; results agree to
- * rounding).  march_variant: 1 = plain cell walk, 2 = band-limited walk
- * with per-lane crossing queues, 3 = surface-major band walks (queue unused),
- * 4 = lean band walks with branch-free inline crossing solves, 5 = lean band
- * walks whose crossing pieces are solved 64 at a time from a per-wave ring
- * (4 and 5 are float32 only; float64 handles run variant 3).  block: threads per block (256, 512 or
- * 1024; float64 handles use 256), queue: crossing-queue slots per lane (4 or
- * 8), rays_per_thread: rays each thread marches per launch (1..64),
- * top_in_lds: stage the fixed top surface in LDS when it fits (else it is
- * read from global memory).  Until mc_set_tuning is called the shape follows
- * the grid loaded last: float32 {4, 256, 4, 8, 0} below 48x48 nodes,
- * {4, 512, 4, 16, 0} up to 128x128, {4, 1024, 4, 16, 0} from 128x128 on;
- * float64 {3, 256, 4, 4, 1}.  A variant-2 shape whose queue does not fit
- * in LDS beside the surfaces runs as variant 3.  multi_blocks_per_cu (0..16,
- * read from problems[0] by mcmc_run_multi): 0 launches one block per
- * (problem, chain, ray tile) work item, k > 0 a persistent grid of k blocks
- * per compute unit that strides over the work table.  Setting a shape
- * this build does not provide returns MC_ERR_UNSUPPORTED.
+ * rounding).  march_variant: 3 = surface-major band walks (any precision;
+ * float64 handles always run it), 4 = lean band walks with branch-free
+ * inline crossing solves (float32).  Other values return
+ * MC_ERR_UNSUPPORTED.  block: threads per block (256, 512 or 1024; float64
+ * handles use 256), rays_per_thread: rays each thread marches per launch
+ * (1..64), top_in_lds: stage the fixed top surface in LDS when it fits (else
+ * it is read from global memory).  Until mc_set_tuning is called the shape
+ * follows the grid loaded last: float32 {4, 256, 8, 0} below 48x48 nodes,
+ * {4, 512, 16, 0} up to 128x128, {4, 1024, 16, 0} from 128x128 on; float64
+ * {3, 256, 4, 1}.  multi_blocks_per_cu (0..16, read from problems[0] by
+ * mcmc_run_multi): 0 launches one block per (problem, chain, ray tile) work
+ * item, k > 0 a persistent grid of k blocks per compute unit that strides
+ * over the work table.  Gradients (float32): the march that precedes the
+ * adjoint records every crossing, grad_slots records per thread and surface
+ * (0 = 2 x rays_per_thread; -1 = none, every chain's gradient then comes
+ * from re-walking its rays, as it does for a chain whose records overflow);
+ * adjoint_rows > 0 caps the node rows an adjoint block accumulates at once
+ * (0 = as many as fit the LDS).  Both change performance only.
  */
 typedef struct {
     int march_variant;
     int block;
-    int queue;
     int rays_per_thread;
     int top_in_lds;
     int multi_blocks_per_cu;
+    int grad_slots;
+    int adjoint_rows;
 } mc_tuning;
 
 mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t);
@@ -293,6 +306,8 @@ typedef struct {
     uint64_t step_offset;   /* Philox step of the first transition */
     int latent;             /* 1: the states are the latent CAR fields x (the paper's sampler
                                parametrisation, see latent_to_heights); 0: the heights */
+    double *r_state;        /* device [n][S-1] float64 in (0, 1), in/out, or NULL: sample every
+                               chain's CAR dependence r_l too (latent = 1 only; see nuts_run) */
 } mc_nuts_config;
 
 /*
@@ -305,8 +320,18 @@ typedef struct {
  *   accept_stat (f64, mean of min(1, w) over the leaves computed).
  * Device memory: about (6 + 5 (max_depth + 1)) * 8 + 9 * sizeof(state)
  * bytes per chain and free node, plus the gradient workspaces.  Errors:
- * MC_ERR_ARG for invalid sizes or pointers, MC_ERR_UNSUPPORTED while the
- * voxel model is set.
+ * MC_ERR_ARG for invalid sizes or pointers, MC_ERR_UNSUPPORTED while pixel
+ * quadrature is set.  Under set_voxel_model NUTS runs on the voxel model's
+ * gradient.
+ * Hierarchical r (Sec. 2.2.1, r_l ~ Uniform(0, 1); Sec. 3.1, the sampler's
+ * vector holds all unknowns): with cfg->r_state and latent = 1 each chain's
+ * state is z = (x, eta), eta_l = logit r_l, of log density
+ *   log L(H(x, r)) + sum_l [log det(Q(r_l))/2 - x_l' Q(r_l) x_l / 2
+ *                           - (N/2) log 2 pi + log(r_l (1 - r_l))],
+ * H(x, r) the copula map with Sigma11(r_l) (closed-form torus sums per
+ * chain).  inv_mass is then [n][(S-1) R C + S-1] (the fields, then eta),
+ * logpost holds that density, and r_state is updated.  Momentum normals are
+ * drawn over the S-1 extra coordinates as over the others (pair i/2).
  */
 mc_status nuts_run(mc_problem *p, const mc_nuts_config *cfg, int n_chains, void *heights, double *logpost,
                    double *step_size, double *inv_mass, int32_t *tree_depth, int32_t *n_leapfrog,
@@ -348,6 +373,9 @@ mc_status nested_rhat(mc_problem *p, int n_super, int n_within, const void *heig
  * cfgs[0].graph_steps steps are captured in one HIP graph.  A chain's
  * results equal those of mcmc_run on its problem alone with the same
  * launch shape (the same device code runs for it).
+ * Sampled r (Sec. 2.2.1): cfgs[i].r_state (with r_step, n_accept_r) as in
+ * mcmc_run, given for every problem or for none; log posteriors are then
+ * recomputed on entry at each chain's r.
  * Requirements: the same device, precision and n_surfaces for every problem,
  * kernel = 0, equal n_steps and graph_steps, distinct handles.  Errors are
  * reported on problems[0] (mc_last_error(problems[0])).
@@ -411,6 +439,8 @@ typedef struct {
     double step_size;
     uint64_t seed;
     int block, rays_per_thread;
+    double r_step;          /* > 0: every chain also samples its r_l (start: car_r), by the logit-scale
+                               random walk of this step as in mcmc_run; 0: r fixed at car_r */
 } mc_job_desc;
 
 enum { MC_JOB_QUEUED = 0, MC_JOB_RUNNING = 1, MC_JOB_DONE = 2, MC_JOB_FAILED = 3 };
@@ -423,6 +453,8 @@ typedef struct {
     double accept_rate;                 /* accepted / (n_chains * n_steps) */
     double map_logpost;
     size_t footprint;                   /* device bytes charged against the budget */
+    double r_mean[3];                   /* sampled r: mean over chains of each free surface's last r */
+    double r_accept_rate;               /* sampled r: accepted / (n_chains * (S-1) * n_steps) */
 } mc_job_info;
 
 typedef struct {

@@ -31,8 +31,9 @@ class MuonCaveError(RuntimeError):
 
 
 class Tuning(ct.Structure):
-    _fields_ = [("march_variant", ct.c_int), ("block", ct.c_int), ("queue", ct.c_int),
-                ("rays_per_thread", ct.c_int), ("top_in_lds", ct.c_int), ("multi_blocks_per_cu", ct.c_int)]
+    _fields_ = [("march_variant", ct.c_int), ("block", ct.c_int),
+                ("rays_per_thread", ct.c_int), ("top_in_lds", ct.c_int), ("multi_blocks_per_cu", ct.c_int),
+                ("grad_slots", ct.c_int), ("adjoint_rows", ct.c_int)]
 
 
 class RunConfig(ct.Structure):
@@ -45,7 +46,7 @@ class RunConfig(ct.Structure):
 class NutsConfig(ct.Structure):
     _fields_ = [("n_warmup", ct.c_int64), ("n_steps", ct.c_int64), ("max_depth", ct.c_int), ("adapt_mass", ct.c_int),
                 ("max_delta_h", ct.c_double), ("target_accept", ct.c_double), ("seed", ct.c_uint64),
-                ("step_offset", ct.c_uint64), ("latent", ct.c_int)]
+                ("step_offset", ct.c_uint64), ("latent", ct.c_int), ("r_state", ct.c_void_p)]
 
 
 class ServerConfig(ct.Structure):
@@ -62,13 +63,14 @@ class JobDesc(ct.Structure):
                 ("atten_len", ct.c_double), ("counts", ct.c_void_p),
                 ("n_chains", ct.c_int), ("init", ct.c_void_p), ("n_steps", ct.c_int64),
                 ("step_size", ct.c_double), ("seed", ct.c_uint64),
-                ("block", ct.c_int), ("rays_per_thread", ct.c_int)]
+                ("block", ct.c_int), ("rays_per_thread", ct.c_int), ("r_step", ct.c_double)]
 
 
 class JobInfo(ct.Structure):
     _fields_ = [("status", ct.c_int), ("map_chain", ct.c_int), ("steps_done", ct.c_int64),
                 ("t_submit", ct.c_double), ("t_admit", ct.c_double), ("t_done", ct.c_double),
-                ("accept_rate", ct.c_double), ("map_logpost", ct.c_double), ("footprint", ct.c_size_t)]
+                ("accept_rate", ct.c_double), ("map_logpost", ct.c_double), ("footprint", ct.c_size_t),
+                ("r_mean", ct.c_double * 3), ("r_accept_rate", ct.c_double)]
 
 
 class ServerStats(ct.Structure):
@@ -205,10 +207,10 @@ class Problem:
         return torch.float64 if self.prec == MC_F64 else torch.float32
 
     # -- launch shape -------------------------------------------------------
-    def set_tuning(self, march_variant=4, block=256, queue=4, rays_per_thread=16, top_in_lds=0,
-                   multi_blocks_per_cu=0):
-        t = Tuning(int(march_variant), int(block), int(queue), int(rays_per_thread), int(top_in_lds),
-                   int(multi_blocks_per_cu))
+    def set_tuning(self, march_variant=4, block=256, rays_per_thread=16, top_in_lds=0,
+                   multi_blocks_per_cu=0, grad_slots=0, adjoint_rows=0):
+        t = Tuning(int(march_variant), int(block), int(rays_per_thread), int(top_in_lds),
+                   int(multi_blocks_per_cu), int(grad_slots), int(adjoint_rows))
         self._check(self.lib.mc_set_tuning(self.h, ct.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -327,18 +329,25 @@ class Problem:
 
     def nuts_run(self, heights, logpost, step_size, n_steps, seed, n_warmup=0, max_depth=8, inv_mass=None,
                  adapt_mass=False, max_delta_h=1000.0, target_accept=0.8, step_offset=0, stats=True, latent=False,
-                 stream=None):
+                 r_state=None, stream=None):
         """NUTS (with optional warm-up adaptation) on the chains in place.  step_size [n] float64 and
         inv_mass [n, S-1, R, C] float64 (or None) are device tensors, updated by the warm-up.  With
-        stats, returns dict of per-transition tree_depth, n_leapfrog, diverged, accept_stat tensors."""
+        r_state [n, S-1] float64 (latent only) every chain also samples its r (inv_mass is then
+        [n, (S-1) R C + S-1]).  With stats, returns dict of per-transition tree_depth, n_leapfrog,
+        diverged, accept_stat tensors."""
         import torch
         n = int(heights.shape[0])
         self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
         self._check_tensor(logpost, (n,), torch.float64, "logpost")
         self._check_tensor(step_size, (n,), torch.float64, "step_size")
+        rp = None
+        if r_state is not None:
+            self._check_tensor(r_state, (n, self.S - 1), torch.float64, "r_state")
+            rp = r_state.data_ptr()
         im = None
         if inv_mass is not None:
-            self._check_tensor(inv_mass, self.heights_shape(n), torch.float64, "inv_mass")
+            shape = self.heights_shape(n) if r_state is None else (n, (self.S - 1) * (self.R * self.C + 1))
+            self._check_tensor(inv_mass, shape, torch.float64, "inv_mass")
             im = inv_mass.data_ptr()
         total = int(n_warmup) + int(n_steps)
         out = None
@@ -351,7 +360,7 @@ class Problem:
                        accept_stat=torch.zeros((n, total), dtype=torch.float64, device=dev))
             ptrs = [out[k].data_ptr() for k in ("tree_depth", "n_leapfrog", "diverged", "accept_stat")]
         cfg = NutsConfig(int(n_warmup), int(n_steps), int(max_depth), int(bool(adapt_mass)), float(max_delta_h),
-                         float(target_accept), int(seed), int(step_offset), int(bool(latent)))
+                         float(target_accept), int(seed), int(step_offset), int(bool(latent)), rp)
         self._check(self.lib.nuts_run(self.h, ct.byref(cfg), n, ct.c_void_p(heights.data_ptr()),
                                       ct.c_void_p(logpost.data_ptr()), ct.c_void_p(step_size.data_ptr()),
                                       im, *ptrs, _stream_handle(stream, self.device)))
@@ -417,12 +426,13 @@ class Problem:
 
 
 def mcmc_run_multi(problems, heights, logposts, n_accepts, n_steps, step_sizes, seeds, step_offsets=None,
-                   graph_steps=1, stream=None):
+                   graph_steps=1, r_states=None, r_step=0.0, n_accept_r=None, stream=None):
     """Random-walk Metropolis on several problems in shared launches.
 
     problems, heights, logposts, n_accepts, step_sizes and seeds are per-problem
     sequences (the tensors as for Problem.mcmc_run); n_steps and graph_steps are
-    common to all."""
+    common to all.  r_states (per problem [n, S-1] float64 tensors, with
+    r_step and optional n_accept_r [n, S-1] int64) samples r as in mcmc_run."""
     import torch
     n = len(problems)
     if not (len(heights) == len(logposts) == len(n_accepts) == len(step_sizes) == len(seeds) == n) or n == 0:
@@ -439,8 +449,15 @@ def mcmc_run_multi(problems, heights, logposts, n_accepts, n_steps, step_sizes, 
         pr._check_tensor(logposts[i], (c,), torch.float64, f"logposts[{i}]")
         pr._check_tensor(n_accepts[i], (c,), torch.int64, f"n_accepts[{i}]")
         hs[i] = pr.h
+        rp = ar = None
+        if r_states is not None and r_states[i] is not None:
+            pr._check_tensor(r_states[i], (c, pr.S - 1), torch.float64, f"r_states[{i}]")
+            rp = r_states[i].data_ptr()
+            if n_accept_r is not None and n_accept_r[i] is not None:
+                pr._check_tensor(n_accept_r[i], (c, pr.S - 1), torch.int64, f"n_accept_r[{i}]")
+                ar = n_accept_r[i].data_ptr()
         cfgs[i] = RunConfig(KERNEL_RW, int(n_steps), int(graph_steps), float(step_sizes[i]), None, int(seeds[i]),
-                            int(offs[i]), None, 0.0, None)
+                            int(offs[i]), rp, float(r_step), ar)
         nch[i] = c
         hp[i], lpp[i], ap[i] = heights[i].data_ptr(), logposts[i].data_ptr(), n_accepts[i].data_ptr()
     st = lib.mcmc_run_multi(n, hs, cfgs, nch, hp, lpp, ap, _stream_handle(stream, problems[0].device))
@@ -525,9 +542,10 @@ class Server:
             raise MuonCaveError(st, self.lib.mc_server_last_error(self.h).decode())
 
     def submit(self, sc, n_chains, n_steps, step_size, seed, init=None, counts=None, block=0,
-               rays_per_thread=0) -> int:
+               rays_per_thread=0, r_step=0.0) -> int:
         """Queue one job for scenario `sc`; every chain starts at `init`
-        ([S-1, R, C], default the scenario's truth).  Returns the job id."""
+        ([S-1, R, C], default the scenario's truth); r_step > 0 samples every
+        chain's r too (start: sc.car_r).  Returns the job id."""
         init = sc.truth if init is None else init
         c = sc.counts if counts is None else counts
         keep = dict(density=_host(sc.density), top=_host(sc.top), car_r=_host(sc.car_r),
@@ -540,7 +558,7 @@ class Server:
                     _hp(keep["density"]), _hp(keep["top"]), _hp(keep["car_r"]), n_s, n_pix,
                     _hp(keep["pos"]), _hp(keep["dirs"]), _hp(keep["expo"]), float(sc.atten_len), _hp(cnt),
                     int(n_chains), _hp(keep["init"]), int(n_steps), float(step_size), int(seed), int(block),
-                    int(rays_per_thread))
+                    int(rays_per_thread), float(r_step))
         jid = ct.c_int64()
         self._check(self.lib.mc_server_submit(self.h, ct.byref(d), ct.byref(jid)))
         self.shapes[jid.value] = (int(sc.n_surfaces) - 1, int(sc.n_rows), int(sc.n_cols))
@@ -555,6 +573,7 @@ class Server:
                                             _hp(mean) if arrays else None, _hp(sd) if arrays else None,
                                             _hp(mp) if arrays else None))
         out = {f: getattr(info, f) for f, _ in JobInfo._fields_}
+        out["r_mean"] = list(info.r_mean)
         if info.status == JOB_FAILED:
             out["error"] = self.lib.mc_server_last_error(self.h).decode()
         if arrays and info.status == JOB_DONE:

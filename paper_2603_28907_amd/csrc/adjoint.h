@@ -122,7 +122,7 @@ __device__ __forceinline__ void walk_surface_adjoint(const MarchParams<T> &P, co
                 const T t = t0 + tc[k];
                 // a crossing on the box lid z = max H_S is the kink of that max
                 // (the ray leaves the box there); it carries no derivative
-                if (dfma(t, dz, qz) >= P.ztop - P.margin) continue;
+                if (dfma(t, dz, qz) >= P.lid) continue;
                 const T s = dmin(dmax(dfma(dfma(t, dx, qx), P.ihx, -T(a)), T(0)), T(1));
                 const T w = dmin(dmax(dfma(dfma(t, dy, qy), P.ihy, -T(b)), T(0)), T(1));
                 const double g = scale / (double)fp[k];
@@ -234,59 +234,26 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T
 // float32 adjoint on the lean walk of k_march_lik4
 // ---------------------------------------------------------------------------
 
-// Crossings of a piece in the normalised variable s = tau / tau1 (the cases
-// and the root choice of piece_length): returns 0..2 crossings with their
-// s and |f'(tau)| = |B + 2 A s| / tau1.
-__device__ __forceinline__ int piece_crossings(float fe, float fx, float c2, float tau1, float *sc, float *fp) {
-    const bool be = fe < 0.f, bx = fx < 0.f;
-    const float A = c2 * tau1 * tau1;
-    const float B = (fx - fe) - A;
-    const float iA = __builtin_amdgcn_rcpf(A), it1 = __builtin_amdgcn_rcpf(tau1);
-    const float disc = fmaxf(B * B - 4.f * A * fe, 0.f);
-    const float sq = raw_sqrt(disc);
-    if (be != bx) {
-        const float q = -0.5f * (B + (B >= 0.f ? sq : -sq));
-        const float s1 = q * iA, s2 = fe * __builtin_amdgcn_rcpf(q);
-        const float d1 = fmaxf(fmaxf(-s1, s1 - 1.f), 0.f);
-        const float d2 = fmaxf(fmaxf(-s2, s2 - 1.f), 0.f);
-        const float sr = fminf(fmaxf(((d1 < d2) || (d2 != d2)) ? s1 : s2, 0.f), 1.f);
-        sc[0] = sr;
-        fp[0] = fabsf(B + 2.f * A * sr) * it1;
-        return 1;
-    }
-    const float sv = -0.5f * B * iA;
-    const float fv = fe + sv * (B + A * sv);
-    if ((A != 0.f) && (sv > 0.f) && (sv < 1.f) && ((fv < 0.f) != be)) {
-        const float half = 0.5f * sq * fabsf(iA);
-        const float sa = fmaxf(sv - half, 0.f), sb = fminf(sv + half, 1.f);
-        sc[0] = sa;
-        sc[1] = sb;
-        fp[0] = fabsf(B + 2.f * A * sa) * it1;
-        fp[1] = fabsf(B + 2.f * A * sb) * it1;
-        return 2;
-    }
-    return 0;
-}
-
-// float32 adjoint, per-node sums formed in LDS.  One block = one
-// (chain, ray tile, surface l, window of node rows): it stages surface l,
-// zeroes 64-bit fixed-point accumulators for the window's nodes, walks the
-// tile's rays through surface l (the walk and classification of
-// k_march_lik4), adds each crossing's four node contributions that fall in
-// the window with LDS integer atomics, and finally adds every accumulator to
-// the chain's gradient with one global atomic (a global atomic per crossing
-// and node would cost 12 per ray: the L2 atomic rate, not the walk, would
-// set the time).  Integer sums are order-independent, so the result is
-// bitwise reproducible.  The window keeps surface + accumulators inside the
-// LDS; with several windows each ray's walk is clipped to the stretch of x
-// over the cells that touch the window's node rows.
+// float32 adjoint by re-walking the rays (the chains whose crossing records
+// overflowed), per-node sums formed in LDS.  One block = one (chain, ray
+// tile, surface l, window of node rows): it stages surface l, zeroes 64-bit
+// fixed-point accumulators for the window's nodes, walks the tile's rays
+// through surface l (the walk and classification of k_march_lik4, started at
+// the band window or, with several windows, at the first cell whose node rows
+// can meet the window: the walk's node lines are integer indices, so either
+// start reproduces the forward walk's bits), adds each crossing's four node
+// contributions that fall in the window with LDS integer atomics, and finally
+// adds every accumulator to the chain's gradient with one global atomic.
+// Integer sums are order-independent, so the result is bitwise reproducible
+// and equals the record adjoint's.  Blocks of chains whose records are
+// complete (ovf[chain] == 0) exit at once.
 struct AdjointLdsShape {
     int n_windows, window_rows;
 };
 
 template <int S, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, RayConsts<float> K, const float *opacity,
-                                                       unsigned long long *gfix, AdjointLdsShape W_) {
+__global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, RayConsts<float> K, const float *gpbuf,
+                                                       const int *ovf, unsigned long long *gfix, AdjointLdsShape W_) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ float band[2];
     __shared__ float wred[2][BLOCK / kWave];
@@ -294,6 +261,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
     const int n_sub = P.n_tiles * S * W_.n_windows;
     int chain, sub;
     if (!xcd_chain_tile(n_sub, P.n_chains, chain, sub)) return;
+    if (!ovf[chain]) return;
     const int tile = sub / (S * W_.n_windows);
     const int rem = sub - tile * S * W_.n_windows;
     const int l = rem / W_.n_windows, win = rem - l * W_.n_windows;
@@ -337,9 +305,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
     const int r1 = min(r0 + P.rays_per_block, P.n_ray);
     for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
         const int sidx = ray / P.n_pix;
-        const double Od = (double)opacity[(size_t)chain * P.n_ray + ray];
-        const double gp = P.expo[ray] * exp(-Od * P.inv_L) * P.inv_L - P.c_over_L[ray];   // (lambda - C)/Lambda
-        const float scale = (float)(gp * (double)rho);
+        const float scale = gpbuf[(size_t)chain * P.n_ray + ray] * rho;   // (lambda - C)/Lambda (rho_l - rho_l+1)
         const float qx = P.sensor[3 * sidx], qy = P.sensor[3 * sidx + 1], qz = P.sensor[3 * sidx + 2];
         const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
         const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
@@ -361,9 +327,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
         }
         if (!(tl < th) || scale == 0.f) continue;
         const bool xpos = dx > 0.f, ypos = dy > 0.f;
-        Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, tl);
+        Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, tl);
         for (int it = 0; it < P.R + P.C; ++it) {
-            const Step st = walk_step(W, qz, dz, idx, idy, ox, oy, th);
+            const Step st = walk_step(W, qz, dz, ox, oy, th);
             const int off = W.off;
             const float h00 = Hl[off], h01 = Hl[off + 1], h10 = Hl[off + C], h11 = Hl[off + C + 1];
             const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));
@@ -382,12 +348,13 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
                 const float fx = end_value(pt, st.xkind, xpos, ypos, z1, sx, wx);
                 const float c2 = -(pt.dr1 - pt.dr0) * (dx * P.ihx) * (dy * P.ihy);
                 const float tau1 = t1 - t0;
-                float sc[2], fp[2];
-                const int nc = piece_crossings(fe, fx, c2, tau1, sc, fp);
-                for (int k = 0; k < nc; ++k) {
+                PieceCross pc;
+                (void)piece_length<true>(fe, fx, c2, tau1, &pc);
+                const float *fp = pc.fp;
+                for (int k = 0; k < pc.n; ++k) {
                     if (!(fp[k] > 0.f)) continue;   // tangency: a kink of lp, no derivative
-                    const float t = __builtin_fmaf(sc[k], tau1, t0);
-                    if (__builtin_fmaf(t, dz, qz) >= P.ztop - P.margin) continue;   // the box lid: a kink
+                    const float t = __builtin_fmaf(pc.s[k], tau1, t0);
+                    if (__builtin_fmaf(t, dz, qz) >= P.lid) continue;   // the box lid: a kink
                     const float s = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -W.af), 0.f), 1.f);
                     const float w = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -W.bf), 0.f), 1.f);
                     const float g = scale * __builtin_amdgcn_rcpf(fp[k]);
@@ -412,6 +379,69 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
         const unsigned long long v = acc[i];
         if (v) atomicAdd(G + i, v);
     }
+}
+
+// float32 adjoint from the crossing records of the gradient march (no walk).
+// One block = one (chain, surface l, window of node rows; one window while
+// the surface's 64-bit accumulators fit the LDS): it zeroes the window's
+// fixed-point accumulators in LDS, reads every record of (chain, l) over all
+// ray tiles, adds the contributions (rho_l - rho_{l+1}) g_p w_n / |f'| of
+// the nodes in the window with LDS integer atomics, and stores the window's
+// sums into the chain's gradient: the block owns those nodes, so no global
+// atomics and no zeroing beforehand.  A chain whose records overflowed gets
+// zeros here and its gradient from k_adjoint_lds.  fwd_block: the block
+// size of the gradient march (the width of a record row).
+template <int S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_adjoint_rec(MarchParams<float> P, CrossRecs X, int fwd_block,
+                                                       AdjointLdsShape W_, unsigned long long *gfix) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
+    int chain, sub;
+    if (!xcd_chain_tile(S * W_.n_windows, P.n_chains, chain, sub)) return;
+    const int l = sub / W_.n_windows, win = sub - l * W_.n_windows;
+    const int N = P.R * P.C, C = P.C, tid = threadIdx.x;
+    const int row0 = win * W_.window_rows;
+    const int rows = min(W_.window_rows, P.R - row0);
+    const int lo = row0 * C, hi = (row0 + rows) * C;   // node offsets of the window
+    for (int i = tid; i < rows * C; i += BLOCK) acc[i] = 0ull;
+    __syncthreads();
+    if (!X.ovf[chain]) {
+        const float rho = P.rho_diff[l];
+        const float *gpc = X.gp + (size_t)chain * P.n_ray;
+        for (int tile = 0; tile < P.n_tiles; ++tile) {
+            const size_t cb = (size_t)(chain * P.n_tiles + tile) * S + l;
+            const uint32_t *cnt = X.cnt + cb * fwd_block;
+            const uint4 *rec = X.rec + cb * (size_t)X.slots * fwd_block;
+            const int ray0 = tile * P.rays_per_block;
+            for (int j = tid; j < fwd_block; j += BLOCK) {
+                const int n = (int)cnt[j];
+                for (int k = 0; k < n; ++k) {
+                    const uint4 r = rec[(size_t)k * fwd_block + j];
+                    const int off = (int)(r.x & 0xFFFFu), ks = (int)((r.x >> 18) & 0x3Fu);
+                    if (off + C + 1 < lo || off >= hi) continue;   // the cell's node rows miss the window
+                    const float g = (gpc[ray0 + j + ks * fwd_block] * rho) * __uint_as_float(r.w);
+                    const float s = __uint_as_float(r.y), w = __uint_as_float(r.z);
+                    const float cv[4] = {g * (1.f - s) * (1.f - w), g * (1.f - s) * w, g * s * (1.f - w), g * s * w};
+                    const int no[4] = {off, off + 1, off + C, off + C + 1};
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        if (no[m] >= lo && no[m] < hi) {
+                            const float sv = fminf(fmaxf(cv[m] * 4294967296.0f, -9.0e18f), 9.0e18f);
+                            atomicAdd(acc + (no[m] - lo), (unsigned long long)(long long)__builtin_rintf(sv));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long *G = gfix + ((size_t)chain * S + l) * N + lo;
+    for (int i = tid; i < rows * C; i += BLOCK) G[i] = acc[i];
+}
+
+__global__ void k_fill_i32(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 __global__ void k_fill_u64(unsigned long long *p, size_t n) {

@@ -17,8 +17,6 @@
 #include <vector>
 
 #include "muoncave.h"
-#include "march.h"
-#include "march2.h"
 #include "march3.h"
 #include "march5.h"
 #include "adjoint.h"
@@ -34,7 +32,7 @@ using namespace mc;
 
 namespace {
 
-constexpr int kMarchBlock = 256;
+
 constexpr int kPriorBlock = 256;
 constexpr int kMaxNodes = 16384;   // n_rows * n_cols limit (prior workspace lives in LDS)
 
@@ -66,10 +64,10 @@ struct GraphKey {
 // of 128x128 nodes and more hold the free surfaces in 128 KB of LDS, one block
 // per compute unit, so they take 1024-thread blocks.
 static mc_tuning default_tuning(int prec, size_t n_nodes) {
-    if (prec == MC_F64) return mc_tuning{3, 256, 4, 4, 1, 0};
-    if (n_nodes >= 128 * 128) return mc_tuning{4, 1024, 4, 16, 0, 0};
-    if (n_nodes >= 48 * 48) return mc_tuning{4, 512, 4, 16, 0, 0};
-    return mc_tuning{4, 256, 4, 8, 0, 0};
+    if (prec == MC_F64) return mc_tuning{3, 256, 4, 1, 0, 0, 0};
+    if (n_nodes >= 128 * 128) return mc_tuning{4, 1024, 16, 0, 0, 0, 0};
+    if (n_nodes >= 48 * 48) return mc_tuning{4, 512, 16, 0, 0, 0, 0};
+    return mc_tuning{4, 256, 8, 0, 0, 0, 0};
 }
 
 struct mc_problem {
@@ -103,6 +101,9 @@ struct mc_problem {
     std::vector<double> vox_drho;   // [S] rho_l - rho_{l+1}
     int *d_vox_off = nullptr, *d_vox_idx = nullptr;
     void *d_vox_len = nullptr;   // [nnz] in prec
+    int *d_vox_toff = nullptr, *d_vox_tray = nullptr;   // the transpose: rays of each voxel
+    void *d_vox_tlen = nullptr;  // [nnz] in prec
+    DevBuf valpha;               // [n_pad/64][n_ray][64] dLL/dO of the voxel model (gradient)
     double *d_vox_lam0 = nullptr, *d_vox_o0 = nullptr, *d_vox_fsig = nullptr, *d_vox_inorm = nullptr;
     size_t vox_nnz = 0;
     DevBuf rhat;   // [R*C*n_z][n_pad] smoothed densities of the chains
@@ -115,8 +116,9 @@ struct mc_problem {
     DevBuf partials, prop, lptmp;
     DevBuf rstat;   // [2][n][S-1] sum w^2 and edge sums of the current states (r sampling)
     DevBuf obuf, gfix, gprior, gcur, gprop, lpprop;   // gradient and MALA workspaces
+    DevBuf xrec, xcnt, xovf, xgp;   // crossing records of the float32 gradient march
     uint64_t *d_step = nullptr;
-    mc_tuning tune = {2, 256, 4, 4, 1};
+    mc_tuning tune = {3, 256, 4, 1, 0, 0, 0};
     bool tune_user = false;   // launch shape set through mc_set_tuning (else chosen per grid)
     uint64_t gen = 1;   // bumped whenever device pointers or baked constants change
     // graph cache
@@ -185,8 +187,9 @@ void clear_voxel_model(mc_problem *p) {
     p->vox_nz = 0;
     p->vox_nnz = 0;
     free_ptr(p->d_vox_len);
+    free_ptr(p->d_vox_tlen);
     for (double **q : {&p->d_vox_lam0, &p->d_vox_o0, &p->d_vox_fsig, &p->d_vox_inorm}) free_ptr(*q);
-    for (int **q : {&p->d_vox_off, &p->d_vox_idx}) {
+    for (int **q : {&p->d_vox_off, &p->d_vox_idx, &p->d_vox_toff, &p->d_vox_tray}) {
         if (*q) (void)hipFree(*q);
         *q = nullptr;
     }
@@ -255,8 +258,7 @@ Tiling tiling(const mc_problem *p) {
         t.n_tiles = p->n_ray > 0 ? (p->n_ray + kVoxRaysPerTile - 1) / kVoxRaysPerTile : 0;
         return t;
     }
-    const int block = p->tune.march_variant == 1 ? kMarchBlock : p->tune.block;
-    t.rays_per_block = block * p->tune.rays_per_thread;
+    t.rays_per_block = p->tune.block * p->tune.rays_per_thread;
     t.n_tiles = p->n_ray > 0 ? (p->n_ray + t.rays_per_block - 1) / t.rays_per_block : 0;
     return t;
 }
@@ -272,15 +274,10 @@ int lik_tiles(const mc_problem *p) {
 // before the pixel kernel writes its).
 int partial_slots(const mc_problem *p) { return std::max(tiling(p).n_tiles, lik_tiles(p)); }
 
-size_t queue_bytes(const mc_problem *p) {
-    if (p->tune.march_variant != 2) return 0;
-    return (size_t)p->tune.queue * p->tune.block * (2 * elem_size(p) + 4);
-}
-
 bool top_in_lds(const mc_problem *p) {
     size_t N = (size_t)p->R * p->C;
     if (!p->tune.top_in_lds) return false;
-    return ((N * p->S * elem_size(p) + 15) & ~(size_t)15) + queue_bytes(p) + 4096 <= p->max_lds;
+    return ((N * p->S * elem_size(p) + 15) & ~(size_t)15) + 4096 <= p->max_lds;
 }
 
 template <typename T>
@@ -315,54 +312,20 @@ hipError_t launch_v3(int block, dim3 grid, size_t lds, hipStream_t st, const Mar
 }
 
 template <int S, bool TL, int B>
-hipError_t launch_v45_shape(int variant, dim3 grid, size_t lds, hipStream_t st, const MarchParams<float> &P,
-                            const RayConsts<float> &K) {
-    if (variant == 4) {
-        auto k = k_march_lik4<S, TL, B>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P, K);
-    } else {
-        auto k = k_march_lik5<S, TL, B>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P, K);
-    }
+hipError_t launch_v4_shape(dim3 grid, size_t lds, hipStream_t st, const MarchParams<float> &P,
+                           const RayConsts<float> &K) {
+    auto k = k_march_lik4<S, TL, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P, K);
     return hipGetLastError();
 }
 
 template <int S, bool TL>
-hipError_t launch_v45(int variant, int block, dim3 grid, size_t lds, hipStream_t st, const MarchParams<float> &P,
-                      const RayConsts<float> &K) {
-    if (block == 256) return launch_v45_shape<S, TL, 256>(variant, grid, lds, st, P, K);
-    if (block == 512) return launch_v45_shape<S, TL, 512>(variant, grid, lds, st, P, K);
-    return launch_v45_shape<S, TL, 1024>(variant, grid, lds, st, P, K);
-}
-
-// Instantiated (block, queue) shapes of the band-limited march.
-bool v2_shape_supported(int prec, int block, int queue) {
-    if (prec == MC_F64) return block == 256 && queue == 4;
-    return (block == 256 || block == 512 || block == 1024) && (queue == 4 || queue == 8);
-}
-
-template <typename T, int S, bool TL, int B, int QQ>
-hipError_t launch_v2_shape(dim3 grid, size_t lds, hipStream_t st, const MarchParams<T> &P) {
-    auto k = k_march_lik2<T, S, TL, B, QQ>;
-    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P);
-    return hipGetLastError();
-}
-
-template <typename T, int S, bool TL>
-hipError_t launch_v2(int block, int queue, dim3 grid, size_t lds, hipStream_t st, const MarchParams<T> &P) {
-    if constexpr (std::is_same<T, double>::value) {
-        return launch_v2_shape<T, S, TL, 256, 4>(grid, lds, st, P);
-    } else {
-        if (block == 256 && queue == 4) return launch_v2_shape<T, S, TL, 256, 4>(grid, lds, st, P);
-        if (block == 256 && queue == 8) return launch_v2_shape<T, S, TL, 256, 8>(grid, lds, st, P);
-        if (block == 512 && queue == 4) return launch_v2_shape<T, S, TL, 512, 4>(grid, lds, st, P);
-        if (block == 512 && queue == 8) return launch_v2_shape<T, S, TL, 512, 8>(grid, lds, st, P);
-        if (block == 1024 && queue == 4) return launch_v2_shape<T, S, TL, 1024, 4>(grid, lds, st, P);
-        return launch_v2_shape<T, S, TL, 1024, 8>(grid, lds, st, P);
-    }
+hipError_t launch_v4(int block, dim3 grid, size_t lds, hipStream_t st, const MarchParams<float> &P,
+                     const RayConsts<float> &K) {
+    if (block == 256) return launch_v4_shape<S, TL, 256>(grid, lds, st, P, K);
+    if (block == 512) return launch_v4_shape<S, TL, 512>(grid, lds, st, P, K);
+    return launch_v4_shape<S, TL, 1024>(grid, lds, st, P, K);
 }
 
 template <typename T>
@@ -386,6 +349,10 @@ MarchParams<T> march_params(const mc_problem *p, const T *heights, T *opacity, d
     double eps = sizeof(T) == 4 ? 1.1920929e-07 : 2.220446049250313e-16;
     double zscale = std::fabs(p->ztop) + std::fabs(p->top_min) + 1.0;
     P.margin = (T)(256.0 * eps * zscale);
+    // the lid band of the gradient: 16 float32 ulps below the lid (a crossing
+    // there is within the float32 rounding of the lid's kink); float64: the margin
+    P.lid = sizeof(T) == 4 ? (T)((float)p->ztop - 16.0f * (std::nextafter((float)p->ztop, 1e30f) - (float)p->ztop))
+                           : (T)(p->ztop - 256.0 * eps * zscale);
     P.top_min = (T)p->top_min;
     P.top_max = (T)p->top_max;
     for (int l = 0; l < kMaxSurfaces; ++l) {
@@ -415,68 +382,33 @@ mc_status launch_march(mc_problem *p, int n, const T *heights, T *opacity, doubl
     MarchParams<T> P = march_params<T>(p, heights, opacity, partials);
     P.only_nan = only_nan;
     P.n_chains = n;
-    // variants 3-5: XCD-aware 1-D grid (see xcd_chain_tile)
-    const dim3 grid_xcd((unsigned)P.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+    // XCD-aware 1-D grid (see xcd_chain_tile)
+    const dim3 grid((unsigned)P.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
     size_t N = (size_t)p->R * p->C;
     bool tl = top_in_lds(p);
     int variant = p->tune.march_variant;
-    if (variant >= 4 && sizeof(T) != 4) variant = 3;   // the lean walks are float32 only
-    if (variant >= 4) {
+    if (variant == 4 && sizeof(T) != 4) variant = 3;   // the lean walk is float32 only
+    if (variant == 4) {
         size_t lds = N * (tl ? S : S - 1) * sizeof(T);
         if (lds + 16384 > p->max_lds) {
             tl = false;
             lds = N * (S - 1) * sizeof(T);
         }
         if (lds + 16384 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-        const dim3 grid = grid_xcd;
         if constexpr (std::is_same<T, float>::value) {
             RayConsts<float> K = ray_consts<float>(p);
-            hipError_t e = tl ? launch_v45<S, true>(variant, p->tune.block, grid, lds, st, P, K)
-                              : launch_v45<S, false>(variant, p->tune.block, grid, lds, st, P, K);
+            hipError_t e = tl ? launch_v4<S, true>(p->tune.block, grid, lds, st, P, K)
+                              : launch_v4<S, false>(p->tune.block, grid, lds, st, P, K);
             HIP_TRY(p, e);
         }
         return MC_OK;
     }
-    if (variant == 2) {
-        // a queue that does not fit beside the surfaces: use the queue-free walk
-        size_t lds2 = ((N * (tl ? S : S - 1) * sizeof(T) + 15) & ~(size_t)15) + queue_bytes(p);
-        if (lds2 + 2048 > p->max_lds) {
-            variant = 3;
-            tl = N * S * sizeof(T) + 4096 <= p->max_lds && p->tune.top_in_lds;
-        }
-    }
-    if (variant == 3) {
-        size_t lds = N * (tl ? S : S - 1) * sizeof(T);
-        if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-        const dim3 grid = grid_xcd;
-        RayConsts<T> K = ray_consts<T>(p);
-        hipError_t e = tl ? launch_v3<T, S, true>(p->tune.block, grid, lds, st, P, K)
-                          : launch_v3<T, S, false>(p->tune.block, grid, lds, st, P, K);
-        HIP_TRY(p, e);
-        return MC_OK;
-    }
-    if (variant == 2) {
-        size_t lds = ((N * (tl ? S : S - 1) * sizeof(T) + 15) & ~(size_t)15) + queue_bytes(p);
-        if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-        dim3 grid(P.n_tiles, n);
-        hipError_t e = tl ? launch_v2<T, S, true>(p->tune.block, p->tune.queue, grid, lds, st, P)
-                          : launch_v2<T, S, false>(p->tune.block, p->tune.queue, grid, lds, st, P);
-        HIP_TRY(p, e);
-        return MC_OK;
-    }
     size_t lds = N * (tl ? S : S - 1) * sizeof(T);
     if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
-    dim3 grid(P.n_tiles, n), block(kMarchBlock);
-    if (tl) {
-        auto k = k_march_lik<T, S, true, kMarchBlock>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, st, P);
-    } else {
-        auto k = k_march_lik<T, S, false, kMarchBlock>;
-        if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, grid, block, lds, st, P);
-    }
-    HIP_TRY(p, hipGetLastError());
+    RayConsts<T> K = ray_consts<T>(p);
+    hipError_t e = tl ? launch_v3<T, S, true>(p->tune.block, grid, lds, st, P, K)
+                      : launch_v3<T, S, false>(p->tune.block, grid, lds, st, P, K);
+    HIP_TRY(p, e);
     return MC_OK;
 }
 
@@ -677,11 +609,82 @@ void launch_adjoint_shape(dim3 grid, size_t lds, const MarchParams<T> &M, const 
 
 template <int S, int B>
 void launch_adjoint_lds_shape(dim3 grid, size_t lds, const MarchParams<float> &M, const RayConsts<float> &K,
-                              const float *obuf, unsigned long long *gfix, AdjointLdsShape w, hipStream_t st) {
+                              const float *gp, const int *ovf, unsigned long long *gfix, AdjointLdsShape w,
+                              hipStream_t st) {
     auto k = k_adjoint_lds<S, B>;
     if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, K, obuf, gfix, w);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, K, gp, ovf, gfix, w);
 }
+
+template <int S, int B>
+void launch_adjoint_rec_shape(dim3 grid, size_t lds, const MarchParams<float> &M, const CrossRecs &X, int fwd_block,
+                              AdjointLdsShape w, unsigned long long *gfix, hipStream_t st) {
+    auto k = k_adjoint_rec<S, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, X, fwd_block, w, gfix);
+}
+
+// Crossing-record slots per thread and surface of the gradient march:
+// twice the rays a thread marches (the crossings of one surface per ray
+// are 1 on average at the benchmark shapes), or the tuning's grad_slots
+// (-1: none, so every chain takes the re-walk).
+int cross_slots(const mc_problem *p) {
+    if (p->tune.grad_slots < 0) return 0;
+    if (p->tune.grad_slots > 0) return p->tune.grad_slots;
+    return 2 * p->tune.rays_per_thread;
+}
+
+CrossRecs cross_recs(const mc_problem *p) {
+    CrossRecs X;
+    X.rec = (uint4 *)p->xrec.p;
+    X.cnt = (uint32_t *)p->xcnt.p;
+    X.ovf = (int *)p->xovf.p;
+    X.gp = (float *)p->xgp.p;
+    X.slots = cross_slots(p);
+    return X;
+}
+
+template <int S, bool TL, int B>
+void launch_march_rec_shape(dim3 grid, size_t lds, hipStream_t st, const MarchParams<float> &P,
+                            const RayConsts<float> &K, const CrossRecs &X) {
+    auto k = k_march_rec4<S, TL, B>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, P, K, X);
+}
+
+// The float32 gradient march: the forward march of n states with the
+// crossing records and dLL/dO of every ray (the partials feed the prior
+// kernel as usual).  Clears the overflow flags first.
+template <int S>
+mc_status launch_march_rec(mc_problem *p, int n, const float *heights, hipStream_t st) {
+    MarchParams<float> P = march_params<float>(p, heights, nullptr, (double *)p->partials.p);
+    P.n_chains = n;
+    const CrossRecs X = cross_recs(p);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X.ovf, n);
+    const dim3 grid((unsigned)P.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+    const size_t N = (size_t)p->R * p->C;
+    bool tl = top_in_lds(p);
+    size_t lds = N * (tl ? S : S - 1) * sizeof(float);
+    if (lds + 16384 > p->max_lds) {
+        tl = false;
+        lds = N * (S - 1) * sizeof(float);
+    }
+    if (lds + 16384 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+    const RayConsts<float> K = ray_consts<float>(p);
+    const int b = p->tune.block;
+    if (tl) {
+        if (b == 256) launch_march_rec_shape<S, true, 256>(grid, lds, st, P, K, X);
+        else if (b == 512) launch_march_rec_shape<S, true, 512>(grid, lds, st, P, K, X);
+        else launch_march_rec_shape<S, true, 1024>(grid, lds, st, P, K, X);
+    } else {
+        if (b == 256) launch_march_rec_shape<S, false, 256>(grid, lds, st, P, K, X);
+        else if (b == 512) launch_march_rec_shape<S, false, 512>(grid, lds, st, P, K, X);
+        else launch_march_rec_shape<S, false, 1024>(grid, lds, st, P, K, X);
+    }
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
 
 // The adjoint march of n states (forward opacities in p->obuf).  float32:
 // k_adjoint_lds with node-row windows sized so that one surface and the
@@ -694,22 +697,40 @@ mc_status launch_adjoint(mc_problem *p, int n, const T *heights, unsigned long l
     MarchParams<T> M = march_params<T>(p, heights, nullptr, (double *)p->partials.p);
     M.n_chains = n;
     RayConsts<T> K = ray_consts<T>(p);
-    if constexpr (std::is_same<T, float>::value) {   // float32: LDS sums
-        const size_t surf = (N * sizeof(float) + 15) & ~(size_t)15;
+    if constexpr (std::is_same<T, float>::value) {   // float32: the record adjoint, re-walks on overflow
         const size_t row_bytes = (size_t)p->C * sizeof(unsigned long long);
+        const CrossRecs X = cross_recs(p);
+        // the record adjoint: windows of node rows whose accumulators fit the LDS
+        {
+            const size_t budget = p->max_lds - 1024;
+            AdjointLdsShape w;
+            w.window_rows = (int)std::min<size_t>((size_t)p->R, budget / row_bytes);
+            if (p->tune.adjoint_rows > 0) w.window_rows = std::min(w.window_rows, p->tune.adjoint_rows);
+            w.n_windows = (p->R + w.window_rows - 1) / w.window_rows;
+            const size_t lds = (size_t)w.window_rows * row_bytes;
+            const dim3 grid((unsigned)(S * w.n_windows) * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+            const int fb = p->tune.block;
+            if (lds > 65536) launch_adjoint_rec_shape<S, 1024>(grid, lds, M, X, fb, w, gfix, st);
+            else if (lds > 16384) launch_adjoint_rec_shape<S, 512>(grid, lds, M, X, fb, w, gfix, st);
+            else launch_adjoint_rec_shape<S, 256>(grid, lds, M, X, fb, w, gfix, st);
+            HIP_TRY(p, hipGetLastError());
+        }
+        // the re-walk of chains whose records overflowed (other chains' blocks exit at once)
+        const size_t surf = (N * sizeof(float) + 15) & ~(size_t)15;
         if (surf + 4096 + row_bytes > p->max_lds)
             return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
         const size_t budget = p->max_lds - surf - 4096;
         AdjointLdsShape w;
         w.n_windows = (int)(((size_t)p->R * row_bytes + budget - 1) / budget);
         w.window_rows = (p->R + w.n_windows - 1) / w.n_windows;
+        if (p->tune.adjoint_rows > 0) w.window_rows = std::min(w.window_rows, p->tune.adjoint_rows);
         w.n_windows = (p->R + w.window_rows - 1) / w.window_rows;
         const size_t lds = surf + (size_t)w.window_rows * row_bytes;
         const dim3 grid((unsigned)(M.n_tiles * S * w.n_windows) * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
         // up to 64 KB of LDS: 512-thread blocks, so the LDS that limits blocks
         // per CU still leaves 6 wavefronts per SIMD (256 threads left 3)
-        if (lds > 65536) launch_adjoint_lds_shape<S, 1024>(grid, lds, M, K, (const float *)p->obuf.p, gfix, w, st);
-        else launch_adjoint_lds_shape<S, 512>(grid, lds, M, K, (const float *)p->obuf.p, gfix, w, st);
+        if (lds > 65536) launch_adjoint_lds_shape<S, 1024>(grid, lds, M, K, X.gp, X.ovf, gfix, w, st);
+        else launch_adjoint_lds_shape<S, 512>(grid, lds, M, K, X.gp, X.ovf, gfix, w, st);
         HIP_TRY(p, hipGetLastError());
         return MC_OK;
     } else {   // float64: the direct scatter
@@ -734,18 +755,46 @@ mc_status launch_adjoint(mc_problem *p, int n, const T *heights, unsigned long l
 // Log posterior and gradient of n states into lp and grad ([n][S][N] in T):
 // forward march with opacities, prior and its gradient, adjoint march,
 // combine.  Workspaces must be ensured by the caller (ensure_grad_ws).
+// The likelihood part of the gradient of n states into the fixed-point
+// accumulators gfix [n][S][R*C] (every entry written), and the partial sums
+// of the likelihood.  float32: the gradient march with crossing records and
+// the record adjoint; float64: the march with opacities, then the re-walking
+// scatter into zeroed accumulators.
+template <typename T, int S>
+mc_status lik_grad(mc_problem *p, int n, const T *heights, unsigned long long *gfix, hipStream_t st) {
+    mc_status s;
+    if (p->vox_nz > 0) {   // the smoothed voxel model: density, likelihood with dLL/dO, back-projection
+        VoxParams<T> V = vox_params<T>(p, n, heights, nullptr, (double *)p->partials.p, nullptr);
+        V.alpha = (T *)p->valpha.p;
+        V.t_off = p->d_vox_toff;
+        V.t_ray = p->d_vox_tray;
+        V.t_len = (const T *)p->d_vox_tlen;
+        V.gfix = gfix;
+        launch_vox_density<T, S>(V, st);
+        launch_vox_lik<T>(V, st);
+        hipLaunchKernelGGL((k_vox_grad<T, S>), dim3((unsigned)((V.N + 3) / 4), (unsigned)(V.n_pad / kVoxLanes)),
+                           dim3(256), 0, st, V);
+        HIP_TRY(p, hipGetLastError());
+        return MC_OK;
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        if ((s = launch_march_rec<S>(p, n, heights, st)) != MC_OK) return s;
+    } else {
+        const size_t tot = (size_t)S * p->R * p->C * n;
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
+        HIP_TRY(p, hipGetLastError());
+        if ((s = launch_march<T, S>(p, n, heights, (T *)p->obuf.p, (double *)p->partials.p, st)) != MC_OK) return s;
+    }
+    return launch_adjoint<T, S>(p, n, heights, gfix, st);
+}
+
 template <typename T, int S>
 mc_status grad_eval(mc_problem *p, int n, const T *heights, double *lp, T *grad, hipStream_t st) {
     const size_t N = (size_t)p->R * p->C, SN = (size_t)S * N;
     unsigned long long *gfix = (unsigned long long *)p->gfix.p;
     double *gprior = (double *)p->gprior.p;
     mc_status s;
-    if (p->n_ray > 0) {
-        const size_t tot = SN * n;
-        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
-        HIP_TRY(p, hipGetLastError());
-        if ((s = launch_march<T, S>(p, n, heights, (T *)p->obuf.p, (double *)p->partials.p, st)) != MC_OK) return s;
-    }
+    if (p->n_ray > 0 && (s = lik_grad<T, S>(p, n, heights, gfix, st)) != MC_OK) return s;
     PriorParams<T> P = prior_params<T>(p, heights, (const double *)p->partials.p);
     P.lp_out = lp;
     {
@@ -753,9 +802,6 @@ mc_status grad_eval(mc_problem *p, int n, const T *heights, double *lp, T *grad,
         if (N >= (size_t)kPriorLargeNodes) launch_prior_grad<T, S, kPriorBlockLarge>(n, lds, P, gprior, st);
         else launch_prior_grad<T, S, kPriorBlock>(n, lds, P, gprior, st);
         HIP_TRY(p, hipGetLastError());
-    }
-    if (p->n_ray > 0) {
-        if ((s = launch_adjoint<T, S>(p, n, heights, gfix, st)) != MC_OK) return s;
     }
     if (p->n_ray == 0) {
         const size_t tot = SN * n;
@@ -776,7 +822,18 @@ mc_status ensure_grad_ws(mc_problem *p, int n) {
     Tiling t = tiling(p);
     if (p->n_ray > 0) {
         if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
-        if ((s = ensure(p, p->obuf, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK) return s;
+        if (p->vox_nz > 0) {
+            if ((s = ensure(p, p->rhat, rhat_bytes(p, n))) != MC_OK) return s;
+            if ((s = ensure(p, p->valpha, sizeof(T) * (size_t)vox_n_pad(n) * p->n_ray)) != MC_OK) return s;
+        } else if constexpr (std::is_same<T, float>::value) {
+            const size_t rows = (size_t)n * t.n_tiles * S;   // (chain, tile, surface) record lists
+            if ((s = ensure(p, p->xrec, 16 * rows * (size_t)cross_slots(p) * p->tune.block)) != MC_OK) return s;
+            if ((s = ensure(p, p->xcnt, 4 * rows * p->tune.block)) != MC_OK) return s;
+            if ((s = ensure(p, p->xovf, sizeof(int) * (size_t)n)) != MC_OK) return s;
+            if ((s = ensure(p, p->xgp, sizeof(float) * (size_t)n * p->n_ray)) != MC_OK) return s;
+        } else {
+            if ((s = ensure(p, p->obuf, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK) return s;
+        }
     }
     if ((s = ensure(p, p->gfix, sizeof(unsigned long long) * SN * n)) != MC_OK) return s;
     if ((s = ensure(p, p->gprior, sizeof(double) * SN * n)) != MC_OK) return s;
@@ -1055,6 +1112,9 @@ struct MultiPlan {
     std::vector<const void *> H, lp, acc;
     std::vector<uint64_t> gens, seeds;
     std::vector<double> sigma;
+    std::vector<const void *> r, acc_r;   // sampled r: per-chain r and r acceptances (else null)
+    std::vector<double> r_step;
+    bool hier = false;
     int G = 0, device = 0;
     // device tables
     void *d_mp = nullptr, *d_rc = nullptr, *d_pp = nullptr, *d_pd = nullptr, *d_chain_items = nullptr;
@@ -1115,6 +1175,14 @@ mc_status build_multi_plan(MultiPlan *pl, const mc_run_config *cfgs) {
         pp[i].state = (T *)pl->H[i];
         pp[i].seed = cfgs[i].seed;
         pp[i].step_base = p->d_step;
+        if (cfgs[i].r_state) {
+            pp[i].r_chain = cfgs[i].r_state;
+            pp[i].sample_r = 1;
+            pp[i].r_step = cfgs[i].r_step;
+            pp[i].n_acc_r = cfgs[i].n_accept_r;
+            pp[i].stat_sw2 = (double *)p->rstat.p;
+            pp[i].stat_se = (double *)p->rstat.p + (size_t)pl->n[i] * (S - 1);
+        }
         pd[i].H = (const T *)pl->H[i];
         pd[i].prop = (T *)p->prop.p;
         pd[i].M = (S - 1) * p->R * p->C;
@@ -1286,14 +1354,14 @@ mc_status multi_step(MultiPlan *pl, int k, hipStream_t st) {
     const int2 *items = (const int2 *)pl->d_chain_items;
     const int nl = pl->n_chain_items_large, ns = pl->n_chain_items - nl;
     if (nl > 0) {
-        auto kp = k_prior_multi<T, S, kPriorBlockLarge>;
+        auto kp = pl->hier ? k_prior_multi<T, S, kPriorBlockLarge, true> : k_prior_multi<T, S, kPriorBlockLarge, false>;
         if (pl->prior_lds_large > 65536)
             (void)hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->prior_lds_large);
         hipLaunchKernelGGL(kp, dim3(nl), dim3(kPriorBlockLarge), pl->prior_lds_large, st,
                            (const PriorParams<T> *)pl->d_pp, items, k);
     }
     if (ns > 0) {
-        auto kp = k_prior_multi<T, S, kPriorBlock>;
+        auto kp = pl->hier ? k_prior_multi<T, S, kPriorBlock, true> : k_prior_multi<T, S, kPriorBlock, false>;
         if (pl->prior_lds > 65536)
             (void)hipFuncSetAttribute((const void *)kp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl->prior_lds);
         hipLaunchKernelGGL(kp, dim3(ns), dim3(kPriorBlock), pl->prior_lds, st, (const PriorParams<T> *)pl->d_pp,
@@ -1320,6 +1388,15 @@ mc_status mcmc_multi_impl(int np, mc_problem *const *ps, const mc_run_config *cf
         if ((s = ensure(p, p->prop, sizeof(T) * (size_t)n * M)) != MC_OK) return s;
         if ((s = ensure(p, p->lptmp, sizeof(double) * (size_t)n)) != MC_OK) return s;
         if (p->n_ray > 0 && (s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+        if (cfgs[i].r_state) {
+            // with r sampled: log posterior and w-statistics of every chain at its own r
+            // (always: the statistics feed the r updates)
+            if ((s = ensure(p, p->rstat, 2 * sizeof(double) * (size_t)n * (S - 1))) != MC_OK) return s;
+            if ((s = logpost_impl<T, S>(p, n, (const T *)heights[i], lps[i], nullptr, st, nullptr, cfgs[i].r_state,
+                                        (double *)p->rstat.p)) != MC_OK)
+                return s;
+            continue;
+        }
         if (!init_lp) continue;
         if ((s = logpost_impl<T, S>(p, n, (const T *)heights[i], (double *)p->lptmp.p, nullptr, st, lps[i])) != MC_OK)
             return s;
@@ -1334,7 +1411,8 @@ mc_status mcmc_multi_impl(int np, mc_problem *const *ps, const mc_run_config *cf
         for (int i = 0; same && i < np; ++i)
             same = q->ps[i] == ps[i] && q->n[i] == n_chains[i] && q->H[i] == heights[i] && q->lp[i] == lps[i] &&
                    q->acc[i] == accs[i] && q->gens[i] == ps[i]->gen && q->seeds[i] == cfgs[i].seed &&
-                   q->sigma[i] == cfgs[i].step_size;
+                   q->sigma[i] == cfgs[i].step_size && q->r[i] == cfgs[i].r_state &&
+                   q->acc_r[i] == cfgs[i].n_accept_r && q->r_step[i] == cfgs[i].r_step;
         if (same) {
             pl = q;
             break;
@@ -1353,7 +1431,11 @@ mc_status mcmc_multi_impl(int np, mc_problem *const *ps, const mc_run_config *cf
             pl->gens.push_back(ps[i]->gen);
             pl->seeds.push_back(cfgs[i].seed);
             pl->sigma.push_back(cfgs[i].step_size);
+            pl->r.push_back(cfgs[i].r_state);
+            pl->acc_r.push_back(cfgs[i].n_accept_r);
+            pl->r_step.push_back(cfgs[i].r_state ? cfgs[i].r_step : 0.0);
         }
+        pl->hier = cfgs[0].r_state != nullptr;
         if ((s = build_multi_plan<T, S>(pl, cfgs)) != MC_OK) {
             delete pl;
             return s;
@@ -1474,7 +1556,8 @@ void mc_destroy(mc_problem *p) {
     for (double **q : {&p->d_quad_w, &p->d_quad_tab, &p->d_quad_cnt}) free_ptr(*q);
     for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
     for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gprior, &p->gcur, &p->gprop,
-                      &p->lpprop, &p->rstat, &p->rhat, &p->nutsbuf})
+                      &p->lpprop, &p->rstat, &p->rhat, &p->nutsbuf, &p->xrec, &p->xcnt, &p->xovf, &p->xgp,
+                      &p->valpha})
         if (b->p) (void)hipFree(b->p);
     if (p->d_step) (void)hipFree(p->d_step);
     delete p;
@@ -1704,7 +1787,6 @@ mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, d
     if (n_chains == 0) return MC_OK;
     if (!heights || !logpost || !grad) return fail(p, MC_ERR_ARG, "NULL device pointer");
     if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
-    if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients follow the exact march; the voxel model is set");
     if (p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients take one ray per pixel; pixel quadrature is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
@@ -1724,7 +1806,6 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
     if (!(cfg->step_size >= 0) || !std::isfinite(cfg->step_size)) return fail(p, MC_ERR_ARG, "step_size invalid");
     if (cfg->kernel != 0 && cfg->kernel != 1) return fail(p, MC_ERR_ARG, "kernel %d", cfg->kernel);
     if (cfg->r_state && cfg->kernel != 0) return fail(p, MC_ERR_UNSUPPORTED, "r sampling runs with random-walk Metropolis");
-    if (cfg->kernel == 1 && p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA needs the exact march; the voxel model is set");
     if (cfg->kernel == 1 && p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA takes one ray per pixel; pixel quadrature is set");
     if (cfg->r_state && (!(cfg->r_step >= 0) || !std::isfinite(cfg->r_step))) return fail(p, MC_ERR_ARG, "r_step invalid");
     if (cfg->n_accept_r && !cfg->r_state) return fail(p, MC_ERR_ARG, "n_accept_r without r_state");
@@ -1759,6 +1840,7 @@ LatentParams<T> latent_params(const mc_problem *p, int n, const T *x, T *H, doub
         L.logdet[l] = p->logdet[l];
     }
     L.kconst = p->kconst;
+    L.xs = L.S1 * L.N;
     L.top64 = p->d_top64;
     L.x = x;
     L.H = H;
@@ -1774,22 +1856,58 @@ LatentParams<T> latent_params(const mc_problem *p, int n, const T *x, T *H, doub
 // [n][S][R][C] (the top row zero).
 template <typename T, int S>
 mc_status grad_eval_latent(mc_problem *p, int n, const T *x, double *lp, T *gx, hipStream_t st) {
-    const size_t N = (size_t)p->R * p->C, SN = (size_t)S * N;
+    const size_t N = (size_t)p->R * p->C;
     LatentParams<T> L = latent_params<T>(p, n, x, (T *)p->prop.p, lp, gx);
     hipLaunchKernelGGL(k_latent_to_heights<T>, dim3((unsigned)((N + 255) / 256), n), dim3(256), 0, st, L);
     HIP_TRY(p, hipGetLastError());
     mc_status s;
-    if (p->n_ray > 0) {
-        unsigned long long *gfix = (unsigned long long *)p->gfix.p;
-        const size_t tot = SN * n;
-        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
-        HIP_TRY(p, hipGetLastError());
-        if ((s = launch_march<T, S>(p, n, L.H, (T *)p->obuf.p, (double *)p->partials.p, st)) != MC_OK) return s;
-        if ((s = launch_adjoint<T, S>(p, n, L.H, gfix, st)) != MC_OK) return s;
-    }
+    if (p->n_ray > 0 && (s = lik_grad<T, S>(p, n, L.H, (unsigned long long *)p->gfix.p, st)) != MC_OK) return s;
     hipLaunchKernelGGL((k_latent_finish<T, 512>), dim3(n), dim3(512), 0, st, L);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
+}
+
+// The same with every chain's dependence parameters sampled: z [n][S1 N + S1]
+// holds the fields, then logit r (the paper's latent vector of all
+// unknowns); gz takes the logit-r gradient in the first S1 entries of the
+// top row.  rc: [n][S1][kRc] scratch for the per-chain constants of r.
+template <typename T, int S>
+mc_status grad_eval_latent_r(mc_problem *p, int n, const T *z, double *lp, T *gz, double *rc, hipStream_t st) {
+    const size_t N = (size_t)p->R * p->C;
+    LatentParams<T> L = latent_params<T>(p, n, z, (T *)p->prop.p, lp, gz);
+    L.xs = (S - 1) * (int)N + (S - 1);
+    L.rc = rc;
+    L.eig_g = p->d_eig_g;
+    L.eig_w = p->d_eig_w;
+    L.n_eig = p->n_eig;
+    hipLaunchKernelGGL((k_latent_r_consts<T, 256>), dim3(n), dim3(256), 0, st, L);
+    hipLaunchKernelGGL(k_latent_to_heights<T>, dim3((unsigned)((N + 255) / 256), n), dim3(256), 0, st, L);
+    HIP_TRY(p, hipGetLastError());
+    mc_status s;
+    if (p->n_ray > 0 && (s = lik_grad<T, S>(p, n, L.H, (unsigned long long *)p->gfix.p, st)) != MC_OK) return s;
+    hipLaunchKernelGGL((k_latent_finish<T, 512>), dim3(n), dim3(512), 0, st, L);
+    HIP_TRY(p, hipGetLastError());
+    return MC_OK;
+}
+
+// Packing of the sampler's state with r: z[c] = (x[c], logit r[c]) and back.
+template <typename T>
+__global__ void k_pack_latent_r(const T *x, const double *r, T *z, int M, int S1, int n) {
+    const size_t c = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) z[c * (M + S1) + i] = x[c * M + i];
+    else if (i < M + S1) {
+        const double rv = r[c * S1 + (i - M)];
+        z[c * (M + S1) + i] = (T)log(rv / (1.0 - rv));
+    }
+}
+
+template <typename T>
+__global__ void k_unpack_latent_r(const T *z, T *x, double *r, int M, int S1, int n) {
+    const size_t c = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) x[c * M + i] = z[c * (M + S1) + i];
+    else if (i < M + S1) r[c * S1 + (i - M)] = 1.0 / (1.0 + exp(-(double)z[c * (M + S1) + i]));
 }
 
 // ---------------------------------------------------------------------------
@@ -1882,18 +2000,36 @@ template <typename T, int S>
 mc_status nuts_impl(mc_problem *p, const mc_nuts_config *cfg, int n, T *heights, double *lp, double *eps,
                     double *inv_mass, int32_t *depth_out, int32_t *nleap_out, int32_t *div_out, double *acc_out,
                     hipStream_t st) {
-    const size_t N = (size_t)p->R * p->C, M = (size_t)(S - 1) * N, SN = (size_t)S * N;
+    const size_t N = (size_t)p->R * p->C, MH = (size_t)(S - 1) * N, SN = (size_t)S * N;
+    // with r sampled the state is z = (x, logit r): S - 1 more values per chain
+    const bool with_r = cfg->r_state != nullptr;
+    const size_t M = MH + (with_r ? S - 1 : 0);
     const int L = cfg->max_depth + 1;
     mc_status s;
     if ((s = ensure_grad_ws<T, S>(p, n)) != MC_OK) return s;
     if ((s = ensure(p, p->gcur, sizeof(T) * SN * n)) != MC_OK) return s;
-    if (cfg->latent && (s = ensure(p, p->prop, sizeof(T) * M * n)) != MC_OK) return s;
+    if (cfg->latent && (s = ensure(p, p->prop, sizeof(T) * MH * n)) != MC_OK) return s;
+    double *rc = nullptr;
+    if (with_r) {
+        if ((s = ensure(p, p->rstat, sizeof(double) * (size_t)n * (S - 1) * kRc)) != MC_OK) return s;
+        rc = (double *)p->rstat.p;
+    }
     auto target = [&](const T *xs, double *lps, T *gs) {
+        if (with_r) return grad_eval_latent_r<T, S>(p, n, xs, lps, gs, rc, st);
         return cfg->latent ? grad_eval_latent<T, S>(p, n, xs, lps, gs, st) : grad_eval<T, S>(p, n, xs, lps, gs, st);
     };
     const NutsLayout lay = nuts_layout(n, M, SN, L, sizeof(T));
-    if ((s = ensure(p, p->nutsbuf, lay.total)) != MC_OK) return s;
+    const size_t zoff = lay.total, ztotal = lay.total + (with_r ? ((n * M * sizeof(T) + 255) & ~(size_t)255) : 0);
+    if ((s = ensure(p, p->nutsbuf, ztotal)) != MC_OK) return s;
     char *base = (char *)p->nutsbuf.p;
+    T *const user_x = heights;
+    if (with_r) {
+        heights = (T *)(base + zoff);
+        const dim3 g((unsigned)((M + 255) / 256), (unsigned)n);
+        hipLaunchKernelGGL(k_pack_latent_r<T>, g, dim3(256), 0, st, (const T *)user_x, (const double *)cfg->r_state,
+                           heights, (int)MH, S - 1, n);
+        HIP_TRY(p, hipGetLastError());
+    }
     NutsParams<T> P;
     memset(&P, 0, sizeof(P));
     P.M = (int)M;
@@ -1972,6 +2108,12 @@ mc_status nuts_impl(mc_problem *p, const mc_nuts_config *cfg, int n, T *heights,
     }
     hipLaunchKernelGGL(k_nuts_eps_out, dim3((n + 255) / 256), dim3(256), 0, st, (const NutsChain *)P.ch, eps, n);
     HIP_TRY(p, hipGetLastError());
+    if (with_r) {
+        const dim3 g((unsigned)((M + 255) / 256), (unsigned)n);
+        hipLaunchKernelGGL(k_unpack_latent_r<T>, g, dim3(256), 0, st, (const T *)heights, user_x, cfg->r_state,
+                           (int)MH, S - 1, n);
+        HIP_TRY(p, hipGetLastError());
+    }
     return MC_OK;
 }
 
@@ -2003,9 +2145,10 @@ mc_status nuts_run(mc_problem *p, const mc_nuts_config *cfg, int n_chains, void 
     if (!(cfg->max_delta_h > 0) || !std::isfinite(cfg->max_delta_h)) return fail(p, MC_ERR_ARG, "max_delta_h invalid");
     if (!(cfg->target_accept > 0 && cfg->target_accept < 1)) return fail(p, MC_ERR_ARG, "target_accept not in (0, 1)");
     if (cfg->adapt_mass && !inv_mass) return fail(p, MC_ERR_ARG, "adapt_mass needs inv_mass");
+    if (cfg->r_state && !cfg->latent)
+        return fail(p, MC_ERR_ARG, "r_state is sampled on the latent parametrisation (latent = 1)");
     if (cfg->step_offset + (uint64_t)(cfg->n_warmup + cfg->n_steps) >= (1ULL << 48))
         return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
-    if (p->vox_nz > 0) return fail(p, MC_ERR_UNSUPPORTED, "NUTS needs the exact march's gradient; the voxel model is set");
     if (p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "NUTS takes one ray per pixel; pixel quadrature is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
@@ -2096,7 +2239,11 @@ mc_status mcmc_run_multi(int n_problems, mc_problem *const *problems, const mc_r
         for (int j = 0; j < i; ++j)
             if (problems[j] == p) return fail(e, MC_ERR_ARG, "problem %d repeats problem %d", i, j);
         if (cfgs[i].kernel != 0) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi runs random-walk Metropolis");
-        if (cfgs[i].r_state) return fail(e, MC_ERR_UNSUPPORTED, "mcmc_run_multi samples with fixed r");
+        if ((cfgs[i].r_state != nullptr) != (cfgs[0].r_state != nullptr))
+            return fail(e, MC_ERR_ARG, "r_state must be given for every problem or for none");
+        if (cfgs[i].r_state && (!(cfgs[i].r_step >= 0) || !std::isfinite(cfgs[i].r_step)))
+            return fail(e, MC_ERR_ARG, "r_step invalid");
+        if (cfgs[i].n_accept_r && !cfgs[i].r_state) return fail(e, MC_ERR_ARG, "n_accept_r without r_state");
         if (p->vox_nz > 0 || p->quad_nsub > 0)
             return fail(e, MC_ERR_UNSUPPORTED, "problem %d: mcmc_run_multi runs the exact march with one ray per pixel", i);
         if (cfgs[i].n_steps != cfgs[0].n_steps || cfgs[i].graph_steps != cfgs[0].graph_steps)
@@ -2242,6 +2389,31 @@ mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *re
         HIP_TRY(p, hipMemcpy(q, vi.data(), sizeof(int) * vi.size(), hipMemcpyHostToDevice));
         if ((s = upload_prec(p, p->d_vox_len, vl)) != MC_OK) return s;
     }
+    {
+        // the transpose (voxel -> rays crossing it, in ray order) for the gradient's gather
+        const size_t V = (size_t)p->R * p->C * n_z;
+        std::vector<int> toff(V + 1, 0), tray(vi.size());
+        std::vector<double> tlen(vi.size());
+        for (int v : vi) ++toff[(size_t)v + 1];
+        for (size_t v = 0; v < V; ++v) toff[v + 1] += toff[v];
+        std::vector<int> fill(toff.begin(), toff.end() - 1);
+        for (int r = 0; r < p->n_ray; ++r)
+            for (int e = off[r]; e < off[r + 1]; ++e) {
+                const int at = fill[vi[e]]++;
+                tray[at] = r;
+                tlen[at] = vl[e];
+            }
+        HIP_TRY(p, hipMalloc(&q, sizeof(int) * toff.size()));
+        p->d_vox_toff = (int *)q;
+        HIP_TRY(p, hipMemcpy(q, toff.data(), sizeof(int) * toff.size(), hipMemcpyHostToDevice));
+        if (!vi.empty()) {
+            q = nullptr;
+            HIP_TRY(p, hipMalloc(&q, sizeof(int) * tray.size()));
+            p->d_vox_tray = (int *)q;
+            HIP_TRY(p, hipMemcpy(q, tray.data(), sizeof(int) * tray.size(), hipMemcpyHostToDevice));
+            if ((s = upload_prec(p, p->d_vox_tlen, tlen)) != MC_OK) return s;
+        }
+    }
     for (auto pr : {std::make_pair(&p->d_vox_lam0, &lam0), std::make_pair(&p->d_vox_o0, &o0),
                     std::make_pair(&p->d_vox_fsig, &fsig), std::make_pair(&p->d_vox_inorm, &inorm)}) {
         void *d = nullptr;
@@ -2346,19 +2518,19 @@ mc_status mc_time_voxel(mc_problem *p, int n_chains, const void *heights, int it
 
 mc_status mc_set_tuning(mc_problem *p, const mc_tuning *t) {
     if (!p || !t) return MC_ERR_ARG;
-    if (t->march_variant < 1 || t->march_variant > 5) return fail(p, MC_ERR_ARG, "march_variant %d", t->march_variant);
-    if (t->march_variant >= 3 && !(t->block == 256 || (p->prec == MC_F32 && (t->block == 512 || t->block == 1024))))
+    if (t->march_variant != 3 && t->march_variant != 4)
+        return fail(p, MC_ERR_UNSUPPORTED, "march_variant %d is not built (3 and 4 are)", t->march_variant);
+    if (!(t->block == 256 || (p->prec == MC_F32 && (t->block == 512 || t->block == 1024))))
         return fail(p, MC_ERR_UNSUPPORTED, "block %d not built for this precision", t->block);
     if (t->rays_per_thread < 1 || t->rays_per_thread > 64) return fail(p, MC_ERR_ARG, "rays_per_thread %d", t->rays_per_thread);
     if (t->multi_blocks_per_cu < 0 || t->multi_blocks_per_cu > 16)
         return fail(p, MC_ERR_ARG, "multi_blocks_per_cu %d", t->multi_blocks_per_cu);
-    if (t->march_variant == 2 && !v2_shape_supported(p->prec, t->block, t->queue))
-        return fail(p, MC_ERR_UNSUPPORTED, "block %d / queue %d not built for this precision", t->block, t->queue);
+    if (t->grad_slots < -1 || t->grad_slots > 1024) return fail(p, MC_ERR_ARG, "grad_slots %d", t->grad_slots);
+    if (t->adjoint_rows < 0) return fail(p, MC_ERR_ARG, "adjoint_rows %d", t->adjoint_rows);
     DeviceGuard g(p->device);
     drop_graph(p);
     p->tune = *t;
     p->tune_user = true;
-    if (p->tune.march_variant == 1) p->tune.block = kMarchBlock;
     return MC_OK;
 }
 

@@ -1,8 +1,8 @@
-// march3.h -- surface-major band walks: the production ray march.
+// march3.h -- surface-major band walks (any precision; the float64 march).
 //
-// Same quantity as march.h and march2.h (exact below-lengths L_l of every
-// surface, paper Sec. 2.1.1 opacity of the layered density).  Each thread
-// marches its ray through one surface at a time:
+// Exact below-lengths L_l of every surface (paper Sec. 2.1.1 opacity of the
+// layered density).  Each thread marches its ray through one surface at a
+// time:
 //
 //   for each surface l:
 //     [t_lo, t_hi] = the t-range where z(t) lies in the band of surface l
@@ -17,12 +17,13 @@
 // solve runs inline.  Per-ray constants (reciprocal directions, box exit,
 // the DDA offsets) are precomputed on the host, chain independent.
 //
-// Crossing decisions use the boundary formulas of march.h: the end values of
-// a cell piece come from the lerp along the shared cell edge, so adjacent
-// cells see identical bits and a crossing is never dropped or double counted.
+// Crossing decisions use the boundary formulas of march_common.h: the end
+// values of a cell piece come from the lerp along the shared cell edge, so
+// adjacent cells see identical bits and a crossing is never dropped or double
+// counted.
 #pragma once
 
-#include "march.h"
+#include "march_common.h"
 
 namespace mc {
 
@@ -37,8 +38,11 @@ struct RayConsts {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
-// cell_below_length with reciprocal-based arithmetic (float: the hardware
-// reciprocal, 1 ulp; double: exact division).
+// Below-length of one cell piece [0, tau1] given the end values fe, fx of
+// f = z - h and the curvature c2 of f along the ray: one crossing when the
+// end signs differ (stable quadratic root), two around an interior vertex of
+// the opposite sign, else none.  Reciprocal-based arithmetic (float: the
+// hardware reciprocal, 1 ulp; double: exact division).
 template <typename T>
 __device__ __forceinline__ T cell_below_length_fast(T fe, T fx, T c2, T tau1) {
     const bool be = fe < T(0), bx = fx < T(0);

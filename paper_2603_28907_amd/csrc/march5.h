@@ -1,6 +1,6 @@
 // march5.h -- lean surface-major band walks (float32).
 //
-// Same quantity and the same boundary-value rule as march.h / march3.h (exact
+// Same quantity and the same boundary-value rule as march3.h (exact
 // below-lengths of every surface, paper Sec. 2.1.1), with the per-cell work
 // cut down for CDNA wavefronts:
 //
@@ -8,19 +8,12 @@
 //    remaining cells to the grid edge): no integer multiplies in the loop;
 //  * a piece's two end values share the row and column lerps of its patch and
 //    are formed with selects, without branches; they are bit-identical to the
-//    shared-edge formulas of march.h, so adjacent cells agree on every sign;
+//    shared-edge formulas of march_common.h, so adjacent cells agree on every
+//    sign;
 //  * the in-cell quadratic is solved without branches (hardware reciprocal and
 //    square root, 1 ulp each).
 //
-// Two ways of running the ambiguous pieces:
-//  k_march_lik4 -- solve in the lane that met the piece (v3's structure);
-//  k_march_lik5 -- append the piece to a per-wave compacted ring in LDS and
-//                  solve 64 pieces at a time, one per lane, so the solver runs
-//                  with every lane busy.  A solved length is added to its
-//                  owner's 32-bit fixed-point accumulator (2^-20 m per unit)
-//                  with an LDS integer atomic: integer addition is
-//                  associative, so the result does not depend on which lane
-//                  solved what, and repeat runs are bitwise identical.
+// Each lane solves the ambiguous pieces of its own ray inline (k_march_lik4).
 #pragma once
 
 #include "march3.h"
@@ -29,13 +22,24 @@ namespace mc {
 
 __device__ __forceinline__ float raw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Crossings of one piece in the normalised variable s = tau / tau1, with
+// |f'(tau)| at each (for the crossing records of the gradient march).
+struct PieceCross {
+    int n;
+    float s[2], fp[2];
+};
+
 // Branch-free below-length of a piece of length tau1 with end values fe, fx
-// and curvature c2 of f = z - h (the cases of cell_below_length).  Solved in
-// the normalised variable s = tau / tau1 on [0, 1]:
+// and curvature c2 of f = z - h (the cases of cell_below_length_fast).
+// Solved in the normalised variable s = tau / tau1 on [0, 1]:
 //   f(s) = fe + B s + A s^2,  A = c2 tau1^2,  B = fx - fe - A,
 // which needs two hardware reciprocals and one square root.  The stable root
-// fe / q also covers A = 0 (q = -B there: the straight-line crossing).
-__device__ __forceinline__ float piece_length(float fe, float fx, float c2, float tau1) {
+// fe / q also covers A = 0 (q = -B there: the straight-line crossing).  With
+// REC the crossings are reported too: the one root when the end signs
+// differ, else the two roots around an interior vertex of the opposite sign;
+// |f'| = |B + 2 A s| / tau1.
+template <bool REC = false>
+__device__ __forceinline__ float piece_length(float fe, float fx, float c2, float tau1, PieceCross *pc = nullptr) {
     const bool be = fe < 0.f, bx = fx < 0.f;
     const float A = c2 * tau1 * tau1;
     const float B = (fx - fe) - A;
@@ -58,6 +62,15 @@ __device__ __forceinline__ float piece_length(float fe, float fx, float c2, floa
     const float inner = fmaxf(fminf(sv + half, 1.f) - fmaxf(sv - half, 0.f), 0.f) * tau1;
     const float none = be ? tau1 : 0.f;
     const float twol = be ? tau1 - inner : inner;
+    if constexpr (REC) {
+        const float it1 = __builtin_amdgcn_rcpf(tau1);
+        const float sa = fmaxf(sv - half, 0.f), sb = fminf(sv + half, 1.f);
+        pc->n = (be != bx) ? 1 : (two ? 2 : 0);
+        pc->s[0] = (be != bx) ? sr : sa;
+        pc->s[1] = sb;
+        pc->fp[0] = fabsf(B + 2.f * A * pc->s[0]) * it1;
+        pc->fp[1] = fabsf(B + 2.f * A * sb) * it1;
+    }
     return (be != bx) ? one : (two ? twol : none);
 }
 
@@ -95,9 +108,10 @@ __device__ __forceinline__ float end_value(const Patch &p, int kind, bool xrow1,
 
 // Below-length of one piece [t0, t1] of cell (af, bf) (cell origin indices
 // as floats) of a surface patch.
+template <bool REC = false>
 __device__ __forceinline__ float solve_cell_piece(const Patch &p, float af, float bf, float ihx, float ihy, float qx,
                                                   float qy, float qz, float dx, float dy, float dz, float t0,
-                                                  float t1, int ekind, int xkind) {
+                                                  float t1, int ekind, int xkind, PieceCross *pc = nullptr) {
     const bool xpos = dx > 0.f, ypos = dy > 0.f;
     const float z0 = __builtin_fmaf(t0, dz, qz), z1 = __builtin_fmaf(t1, dz, qz);
     const float se = __builtin_fmaf(__builtin_fmaf(t0, dx, qx), ihx, -af);
@@ -108,12 +122,16 @@ __device__ __forceinline__ float solve_cell_piece(const Patch &p, float af, floa
     const float fe = end_value(p, ekind, !xpos, !ypos, z0, se, we);
     const float fx = end_value(p, xkind, xpos, ypos, z1, sx, wx);
     const float c2 = -(p.dr1 - p.dr0) * (dx * ihx) * (dy * ihy);
-    return piece_length(fe, fx, c2, t1 - t0);
+    return piece_length<REC>(fe, fx, c2, t1 - t0, pc);
 }
 
-// Cell walk state shared by the two kernels.
+// Cell walk state (also used by the adjoint).  The next node lines are
+// kept as integer-valued indices, so the parameter where the ray meets one,
+// t = line * (h / d) + o, depends only on the line: a walk started at any cell
+// of a ray reproduces the bits of the walk that reached that cell.
 struct Walk {
-    float xn, yn, dxn, dyn;   // next node-line coordinates and their steps
+    float xl, yl;             // indices of the next x and y node lines
+    float tx, ty;             // h_x / d_x, h_y / d_y: parameter step per line
     float af, bf;             // cell origin indices as floats
     int off, offx, offy;      // element offset of node (a, b) in the surface and its steps
     int remx, remy;           // cells left before the grid edge along x / y
@@ -122,7 +140,7 @@ struct Walk {
 };
 
 __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx, float qy, float qz, float dx,
-                                          float dy, float dz, float tl) {
+                                          float dy, float dz, float idx, float idy, float tl) {
     const int R = P.R, C = P.C;
     const bool xpos = dx > 0.f, ypos = dy > 0.f;
     const float x0 = __builtin_fmaf(tl, dx, qx), y0 = __builtin_fmaf(tl, dy, qy);
@@ -130,10 +148,10 @@ __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx,
     a = a < 0 ? 0 : (a > R - 2 ? R - 2 : a);
     b = b < 0 ? 0 : (b > C - 2 ? C - 2 : b);
     Walk W;
-    W.xn = (float)(xpos ? a + 1 : a) * P.hx;
-    W.yn = (float)(ypos ? b + 1 : b) * P.hy;
-    W.dxn = xpos ? P.hx : -P.hx;
-    W.dyn = ypos ? P.hy : -P.hy;
+    W.xl = (float)(xpos ? a + 1 : a);
+    W.yl = (float)(ypos ? b + 1 : b);
+    W.tx = P.hx * idx;
+    W.ty = P.hy * idy;
     W.af = (float)a;
     W.bf = (float)b;
     W.off = a * C + b;
@@ -147,18 +165,17 @@ __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx,
     return W;
 }
 
-// One step of a walk: the piece [t0, t1] of the current cell.  Returns
-// whether the walk continues; fills the piece and its classification.
+// One step of a walk: the piece [t0, t1] of the current cell and its
+// classification; `edge` says whether the walk continues.
 struct Step {
     float t1, z1;
     int xkind;
     bool edge, stepx;
 };
 
-__device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, float idx, float idy, float ox,
-                                          float oy, float th) {
+__device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, float ox, float oy, float th) {
     Step s;
-    const float tnx = __builtin_fmaf(W.xn, idx, ox), tny = __builtin_fmaf(W.yn, idy, oy);
+    const float tnx = __builtin_fmaf(W.xl, W.tx, ox), tny = __builtin_fmaf(W.yl, W.ty, oy);
     s.stepx = tnx <= tny;
     const float tn = s.stepx ? tnx : tny;
     const bool room = s.stepx ? (W.remx > 0) : (W.remy > 0);
@@ -173,10 +190,11 @@ __device__ __forceinline__ void walk_advance(Walk &W, const Step &s) {
     // value selects (a branch here makes the compiler select between field
     // addresses and keep the walk state in scratch memory)
     const bool sx = s.stepx;
-    W.xn = sx ? W.xn + W.dxn : W.xn;
-    W.yn = sx ? W.yn : W.yn + W.dyn;
-    W.af = sx ? W.af + (W.dxn > 0.f ? 1.f : -1.f) : W.af;
-    W.bf = sx ? W.bf : W.bf + (W.dyn > 0.f ? 1.f : -1.f);
+    const float gx = W.tx > 0.f ? 1.f : -1.f, gy = W.ty > 0.f ? 1.f : -1.f;
+    W.xl = sx ? W.xl + gx : W.xl;
+    W.yl = sx ? W.yl : W.yl + gy;
+    W.af = sx ? W.af + gx : W.af;
+    W.bf = sx ? W.bf : W.bf + gy;
     W.off += sx ? W.offx : W.offy;
     W.remx = sx ? W.remx - 1 : W.remx;
     W.remy = sx ? W.remy : W.remy - 1;
@@ -186,7 +204,7 @@ __device__ __forceinline__ void walk_advance(Walk &W, const Step &s) {
 }
 
 // Stage the chain's free surfaces (and the top if TOP_LDS) and reduce the
-// per-surface bands; common prologue of the lean kernels.
+// per-surface bands; prologue of the lean march and its adjoint.
 template <int S, bool TOP_LDS, int BLOCK>
 __device__ __forceinline__ void stage_surfaces(const MarchParams<float> &P, float *sh, float *band, int chain) {
     const int tid = threadIdx.x, N = P.R * P.C;
@@ -236,11 +254,33 @@ __device__ __forceinline__ void stage_surfaces(const MarchParams<float> &P, floa
 }
 
 // ---------------------------------------------------------------------------
+// Crossing records (the gradient march)
+// ---------------------------------------------------------------------------
+// The march that precedes the adjoint records every crossing it solves: per
+// (chain, ray tile, surface l) a list per thread, laid out [slot][thread] so
+// that a wavefront's lanes write and later read neighbouring records.  One
+// record (16 bytes) holds the cell offset a C + b (16 bits), l (2 bits) and
+// the slot k of the ray among the thread's rays (ray = tile start + thread +
+// k BLOCK; 6 bits), the local coordinates (s, w) of the crossing in the cell
+// and 1/|f'| there.  The adjoint then needs no walk: every node
+// contribution of the crossing form is (rho_l - rho_{l+1}) g_p w_n / |f'|,
+// with g_p = dLL/dO_p, which the march also writes per ray.  A thread whose
+// slots of a surface run out sets the chain's overflow flag; the adjoint
+// re-walks such chains.
+struct CrossRecs {
+    uint4 *rec;        // [n_chains][n_tiles][S][slots][BLOCK]
+    uint32_t *cnt;     // [n_chains][n_tiles][S][BLOCK] records kept per thread
+    int *ovf;          // [n_chains] 1 when some thread's slots ran out (else untouched)
+    float *gp;         // [n_chains][n_ray] dLL/dO_p = (lambda_p - C_p) / Lambda
+    int slots;         // records per thread and surface
+};
+
+// ---------------------------------------------------------------------------
 // v4: inline solves
 // ---------------------------------------------------------------------------
-template <int S, bool TOP_LDS, int BLOCK>
+template <int S, bool TOP_LDS, int BLOCK, bool REC = false>
 __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const RayConsts<float> &K, int chain,
-                                             int tile, float *sh) {
+                                             int tile, float *sh, const CrossRecs &X = CrossRecs{}) {
     __shared__ double red[16];
     __shared__ float band[2 * kMaxSurfaces];
     const int tid = threadIdx.x;
@@ -250,7 +290,12 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     double acc = 0.0;
     const int r0 = tile * P.rays_per_block;
     const int r1 = min(r0 + P.rays_per_block, P.n_ray);
-    for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
+    int nrec[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) nrec[l] = 0;
+    const size_t rbase = (size_t)(chain * P.n_tiles + tile) * S * (size_t)X.slots * BLOCK + tid;
+    int kslot = 0;
+    for (int ray = r0 + tid; ray < r1; ray += BLOCK, ++kslot) {
         const int s = ray / P.n_pix;
         const float qx = P.sensor[3 * s], qy = P.sensor[3 * s + 1], qz = P.sensor[3 * s + 2];
         const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
@@ -264,9 +309,9 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
             const float th = fminf(fmaxf((band[kMaxSurfaces + l] - qz) * idz, 0.f), Texit);
             float L = tl;
             if (tl < th) {
-                Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, tl);
+                Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, tl);
                 for (int it = 0; it < P.R + P.C; ++it) {
-                    const Step st = walk_step(W, qz, dz, idx, idy, ox, oy, th);
+                    const Step st = walk_step(W, qz, dz, ox, oy, th);
                     const float h00 = Hl[W.off], h01 = Hl[W.off + 1], h10 = Hl[W.off + C], h11 = Hl[W.off + C + 1];
                     const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));
                     const float hmax = fmaxf(fmaxf(h00, h01), fmaxf(h10, h11));
@@ -274,8 +319,31 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                         L += st.t1 - W.t0;
                     } else if (!(W.z0 > hmax + P.margin) && st.t1 > W.t0) {
                         const Patch pt = make_patch(h00, h01, h10, h11);
-                        L += solve_cell_piece(pt, W.af, W.bf, P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0, st.t1,
-                                              W.ekind, st.xkind);
+                        if constexpr (REC) {
+                            PieceCross pc;
+                            L += solve_cell_piece<true>(pt, W.af, W.bf, P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0,
+                                                        st.t1, W.ekind, st.xkind, &pc);
+                            const float tau1 = st.t1 - W.t0;
+                            for (int k = 0; k < pc.n; ++k) {
+                                const float fp = pc.fp[k];
+                                if (!(fp > 0.f)) continue;   // tangency: a kink of lp, no derivative
+                                const float t = __builtin_fmaf(pc.s[k], tau1, W.t0);
+                                if (__builtin_fmaf(t, dz, qz) >= P.lid) continue;   // the box lid: a kink
+                                const float sc =
+                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -W.af), 0.f), 1.f);
+                                const float wc =
+                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -W.bf), 0.f), 1.f);
+                                if (nrec[l] < X.slots)
+                                    X.rec[rbase + ((size_t)l * X.slots + nrec[l]) * BLOCK] =
+                                        make_uint4((uint32_t)W.off | ((uint32_t)l << 16) | ((uint32_t)kslot << 18),
+                                                   __float_as_uint(sc), __float_as_uint(wc),
+                                                   __float_as_uint(__builtin_amdgcn_rcpf(fp)));
+                                ++nrec[l];
+                            }
+                        } else {
+                            L += solve_cell_piece(pt, W.af, W.bf, P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0, st.t1,
+                                                  W.ekind, st.xkind);
+                        }
                     }
                     if (!st.edge) break;
                     walk_advance(W, st);
@@ -285,7 +353,18 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
         }
         if (P.opacity) P.opacity[(size_t)chain * P.n_ray + ray] = O;
         const double Od = (double)O;
-        acc += -P.c_over_L[ray] * Od - P.expo[ray] * exp(-Od * P.inv_L);
+        const double lam = P.expo[ray] * exp(-Od * P.inv_L);
+        acc += -P.c_over_L[ray] * Od - lam;
+        if constexpr (REC) X.gp[(size_t)chain * P.n_ray + ray] = (float)(lam * P.inv_L - P.c_over_L[ray]);
+    }
+    if constexpr (REC) {
+        bool over = false;
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            X.cnt[((size_t)(chain * P.n_tiles + tile) * S + l) * BLOCK + tid] = (uint32_t)min(nrec[l], X.slots);
+            over |= nrec[l] > X.slots;
+        }
+        if (over) X.ovf[chain] = 1;
     }
     const double tot = block_sum<BLOCK>(acc, red);
     if (tid == 0) P.partials[(size_t)chain * P.n_tiles + tile] = tot;
@@ -293,162 +372,30 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
 
 // At least 6 wavefronts per SIMD: the walk is latency-bound, and 6 resident
 // waves beat 5 even with a few registers spilled (512-thread blocks keep the
-// LDS from capping residency below 6 on 64x64 grids).
-constexpr int kMarchWavesPerSimd = 6;
+// LDS from capping residency below 6 on 64x64 grids).  1024-thread blocks
+// serve grids whose surfaces take most of the LDS (one block, 4 wavefronts
+// per SIMD): there the register budget of 4 wavefronts costs no residency.
+template <int BLOCK>
+constexpr int march_waves_per_simd() { return BLOCK >= 1024 ? 4 : 6; }
 
 template <int S, bool TOP_LDS, int BLOCK>
-__global__ __launch_bounds__(BLOCK, kMarchWavesPerSimd) void k_march_lik4(MarchParams<float> P, RayConsts<float> K) {
+__global__ __launch_bounds__(BLOCK, march_waves_per_simd<BLOCK>()) void k_march_lik4(MarchParams<float> P,
+                                                                                    RayConsts<float> K) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int chain, tile;
     if (!xcd_chain_tile(P.n_tiles, P.n_chains, chain, tile)) return;
     march_block4<S, TOP_LDS, BLOCK>(P, K, chain, tile, reinterpret_cast<float *>(smem_raw));
 }
 
-// ---------------------------------------------------------------------------
-// v5: compacted per-wave solve ring
-// ---------------------------------------------------------------------------
-constexpr int kRing = 128;                 // ring slots per wave (>= 2 x 64)
-constexpr float kFixScale = 1048576.f;     // 2^20 fixed-point units per metre
-constexpr float kFixInv = 1.f / 1048576.f;
-
-// LDS layout per wave: ring of (t0, t1, packed) and S x 64 accumulators.
-struct WaveRing {
-    float *t0, *t1;
-    uint32_t *pk;
-    uint32_t *acc;   // [S][64]
-};
-
-// packed: a (8) | b << 8 | ekind << 16 | xkind << 18 | l << 20 | owner lane << 24
-template <int S, bool TOP_LDS>
-__device__ __forceinline__ void ring_solve(const MarchParams<float> &P, const float *sh, const WaveRing &rg,
-                                           int head, int n, float qx, float qy, float qz, float dx, float dy,
-                                           float dz) {
-    const int lane = threadIdx.x % kWave;
-    const int slot = (head + lane) & (kRing - 1);
-    const float t0 = rg.t0[slot], t1 = rg.t1[slot];
-    const uint32_t pk = rg.pk[slot];
-    const int owner = (int)(pk >> 24);
-    // the owner's ray (every lane takes part in the shuffles)
-    const float oqx = __shfl(qx, owner, kWave), oqy = __shfl(qy, owner, kWave), oqz = __shfl(qz, owner, kWave);
-    const float odx = __shfl(dx, owner, kWave), ody = __shfl(dy, owner, kWave), odz = __shfl(dz, owner, kWave);
-    if (lane < n) {
-        const int a = pk & 0xFF, b = (pk >> 8) & 0xFF, ek = (pk >> 16) & 3, xk = (pk >> 18) & 3;
-        const int l = (pk >> 20) & 0xF;
-        const int C = P.C, N = P.R * C;
-        const float *Hl = (TOP_LDS || l < S - 1) ? sh + l * N : P.top;
-        const int off = a * C + b;
-        const Patch pt = make_patch(Hl[off], Hl[off + 1], Hl[off + C], Hl[off + C + 1]);
-        const float len = solve_cell_piece(pt, (float)a, (float)b, P.ihx, P.ihy, oqx, oqy, oqz, odx, ody, odz, t0, t1,
-                                           ek, xk);
-        const uint32_t fix = (uint32_t)(fminf(len, 4000.f) * kFixScale + 0.5f);
-        atomicAdd(&rg.acc[l * kWave + owner], fix);
-    }
-}
-
+// The gradient march: the same walk, plus the crossing records and dLL/dO
+// of every ray.
 template <int S, bool TOP_LDS, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_march_lik5(MarchParams<float> P, RayConsts<float> K) {
+__global__ __launch_bounds__(BLOCK, march_waves_per_simd<BLOCK>()) void k_march_rec4(MarchParams<float> P,
+                                                                                    RayConsts<float> K, CrossRecs X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float *sh = reinterpret_cast<float *>(smem_raw);
-    __shared__ double red[16];
-    __shared__ float band[2 * kMaxSurfaces];
-    constexpr int NW = BLOCK / kWave;
-    __shared__ float ring_t0[NW][kRing], ring_t1[NW][kRing];
-    __shared__ uint32_t ring_pk[NW][kRing];
-    __shared__ uint32_t ring_acc[NW][S * kWave];
-    const int tid = threadIdx.x;
     int chain, tile;
     if (!xcd_chain_tile(P.n_tiles, P.n_chains, chain, tile)) return;
-    if (P.only_nan && !(P.only_nan[chain] != P.only_nan[chain])) return;
-    stage_surfaces<S, TOP_LDS, BLOCK>(P, sh, band, chain);
-    const int wid = tid / kWave, lane = tid % kWave;
-    WaveRing rg{ring_t0[wid], ring_t1[wid], ring_pk[wid], ring_acc[wid]};
-#pragma unroll
-    for (int l = 0; l < S; ++l) rg.acc[l * kWave + lane] = 0u;
-    const int N = P.R * P.C, C = P.C;
-    double acc = 0.0;
-    const int r0 = tile * P.rays_per_block;
-    const int r1 = min(r0 + P.rays_per_block, P.n_ray);
-    // every lane of the wave loops over the same number of ray slots
-    const int n_slots = (P.rays_per_block + BLOCK - 1) / BLOCK;
-    int head = 0, count = 0;   // wave-uniform ring state
-    for (int k = 0; k < n_slots; ++k) {
-        const int ray = r0 + k * BLOCK + tid;
-        const bool live = ray < r1;
-        const int rr = live ? ray : r0;
-        const int s = rr / P.n_pix;
-        const float qx = P.sensor[3 * s], qy = P.sensor[3 * s + 1], qz = P.sensor[3 * s + 2];
-        const float dx = P.dx[rr], dy = P.dy[rr], dz = P.dz[rr];
-        const float idx = K.idx[rr], idy = K.idy[rr], idz = K.idz[rr];
-        const float ox = K.ox[rr], oy = K.oy[rr], Texit = K.texit[rr];
-        float L[S];
-#pragma unroll
-        for (int l = 0; l < S; ++l) {
-            const float *Hl = (l < S - 1 || TOP_LDS) ? sh + l * N : P.top;
-            const float tl = fminf(fmaxf((band[l] - qz) * idz, 0.f), Texit);
-            const float th = fminf(fmaxf((band[kMaxSurfaces + l] - qz) * idz, 0.f), Texit);
-            float Ll = tl;
-            bool done = !(tl < th) || !live;
-            Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, tl);
-            for (int it = 0; it < P.R + P.C && __any(!done); ++it) {
-                bool amb = false;
-                Step st;
-                if (!done) {
-                    st = walk_step(W, qz, dz, idx, idy, ox, oy, th);
-                    const float h00 = Hl[W.off], h01 = Hl[W.off + 1], h10 = Hl[W.off + C], h11 = Hl[W.off + C + 1];
-                    const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));
-                    const float hmax = fmaxf(fmaxf(h00, h01), fmaxf(h10, h11));
-                    if (st.z1 < hmin - P.margin) Ll += st.t1 - W.t0;
-                    else amb = !(W.z0 > hmax + P.margin) && st.t1 > W.t0;
-                }
-                // append the ambiguous pieces of this step to the wave's ring
-                const uint64_t mask = __ballot(amb);
-                if (amb) {
-                    const int pos = (head + count + (int)__builtin_amdgcn_mbcnt_hi(
-                                                           (uint32_t)(mask >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))) &
-                                    (kRing - 1);
-                    rg.t0[pos] = W.t0;
-                    rg.t1[pos] = st.t1;
-                    rg.pk[pos] = (uint32_t)(int)W.af | ((uint32_t)(int)W.bf << 8) | ((uint32_t)W.ekind << 16) |
-                                 ((uint32_t)st.xkind << 18) | ((uint32_t)l << 20) | ((uint32_t)lane << 24);
-                }
-                count += __popcll(mask);
-                if (count >= kWave) {
-                    ring_solve<S, TOP_LDS>(P, sh, rg, head, kWave, qx, qy, qz, dx, dy, dz);
-                    head = (head + kWave) & (kRing - 1);
-                    count -= kWave;
-                }
-                if (!done) {
-                    if (!st.edge) done = true;
-                    else walk_advance(W, st);
-                }
-            }
-            L[l] = Ll;
-        }
-        // drain what is left for this ray, then fold the accumulators in
-        if (count > 0) {
-            ring_solve<S, TOP_LDS>(P, sh, rg, head, count, qx, qy, qz, dx, dy, dz);
-            head = (head + count) & (kRing - 1);
-            count = 0;
-        }
-        // the other lanes' LDS atomics on this lane's accumulators are done
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        float O = 0.f;
-#pragma unroll
-        for (int l = 0; l < S; ++l) {
-            const uint32_t fx = rg.acc[l * kWave + lane];
-            rg.acc[l * kWave + lane] = 0u;
-            O += P.rho_diff[l] * (L[l] + (float)fx * kFixInv);
-        }
-        if (live) {
-            if (P.opacity) P.opacity[(size_t)chain * P.n_ray + ray] = O;
-            const double Od = (double)O;
-            acc += -P.c_over_L[ray] * Od - P.expo[ray] * exp(-Od * P.inv_L);
-        }
-    }
-    const double tot = block_sum<BLOCK>(acc, red);
-    if (tid == 0) P.partials[(size_t)chain * P.n_tiles + tile] = tot;
+    march_block4<S, TOP_LDS, BLOCK, true>(P, K, chain, tile, reinterpret_cast<float *>(smem_raw), X);
 }
 
 }  // namespace mc

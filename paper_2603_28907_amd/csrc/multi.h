@@ -38,7 +38,7 @@ struct ProposeDesc {
 // PERSIST = false is the one-item-per-block form (grid = number of items):
 // without the loop the descriptor stays in scalar registers.
 template <int S, bool TOP_LDS, int BLOCK, bool PERSIST>
-__global__ __launch_bounds__(BLOCK, PERSIST ? 1 : kMarchWavesPerSimd) void k_march_multi4(const MarchParams<float> *Ps, const RayConsts<float> *Ks,
+__global__ __launch_bounds__(BLOCK, PERSIST ? 1 : march_waves_per_simd<BLOCK>()) void k_march_multi4(const MarchParams<float> *Ps, const RayConsts<float> *Ks,
                                                         const int4 *items, int n_items) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     if (!PERSIST) {
@@ -77,11 +77,11 @@ __global__ __launch_bounds__(BLOCK) void k_march_multi3(const MarchParams<T> *Ps
     }
 }
 
-template <typename T, int S, int BLOCK>
+template <typename T, int S, int BLOCK, bool HIER>
 __global__ __launch_bounds__(BLOCK, 4) void k_prior_multi(const PriorParams<T> *Ps, const int2 *items, int step_k) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int2 it = items[blockIdx.x];
-    prior_block<T, S, BLOCK>(Ps[it.x], it.y, reinterpret_cast<T *>(smem_raw), step_k);
+    prior_block<T, S, BLOCK, HIER>(Ps[it.x], it.y, reinterpret_cast<T *>(smem_raw), step_k);
 }
 
 // One block per (problem, chain): the pairs of normals of that chain.

@@ -35,6 +35,7 @@ struct ServerJob {
     std::vector<int32_t> counts;
     int64_t n_steps = 0;
     uint64_t seed = 0;
+    double r_step = 0;   // > 0: every chain samples its r (logit-scale random walk of this step)
     size_t footprint = 0;
     // progress
     int status = MC_JOB_QUEUED;
@@ -43,11 +44,11 @@ struct ServerJob {
     // device state while resident
     mc_problem *p = nullptr;
     void *H = nullptr;
-    double *lp = nullptr, *dsum = nullptr;
-    int64_t *acc = nullptr;
+    double *lp = nullptr, *dsum = nullptr, *r = nullptr;
+    int64_t *acc = nullptr, *acc_r = nullptr;
     // summary
-    std::vector<double> mean, sd, map_state;
-    double accept_rate = 0, map_lp = 0;
+    std::vector<double> mean, sd, map_state, r_mean;
+    double accept_rate = 0, map_lp = 0, r_accept_rate = 0;
     int map_chain = 0;
     std::string err;
 };
@@ -73,6 +74,7 @@ size_t job_footprint(const ServerJob &j, int prec) {
     b += round_up((size_t)j.n_s * 3 * sz);                   // sensors
     b += 9 * round_up(nr * sz) + 2 * round_up(nr * 8);       // directions, ray constants, exposure, count terms
     b += round_up((3 * M + 4) * 8);                          // summary / start state
+    if (j.r_step > 0) b += 4 * round_up((size_t)j.n * (j.S - 1) * 8);   // r, r acceptances, w-statistics
     return b + (64u << 10);
 }
 
@@ -117,12 +119,14 @@ mc_status server_fail(mc_server *s, mc_status code, const char *fmt, ...) {
 void release_device(ServerJob *j) {
     if (j->p) mc_destroy(j->p);
     j->p = nullptr;
-    for (void *q : {j->H, (void *)j->lp, (void *)j->dsum, (void *)j->acc})
+    for (void *q : {j->H, (void *)j->lp, (void *)j->dsum, (void *)j->acc, (void *)j->r, (void *)j->acc_r})
         if (q) (void)hipFree(q);
     j->H = nullptr;
     j->lp = nullptr;
     j->dsum = nullptr;
     j->acc = nullptr;
+    j->r = nullptr;
+    j->acc_r = nullptr;
 }
 
 // Handle, uploads, chain start and initial log posterior of an admitted job
@@ -164,6 +168,22 @@ mc_status setup_job(mc_server *s, ServerJob *j) {
         j->err = "upload of the start state failed";
         return MC_ERR_DEVICE;
     }
+    if (j->r_step > 0) {
+        // every chain starts at the job's r
+        const size_t nr = (size_t)j->n * (j->S - 1);
+        std::vector<double> r0(nr);
+        for (size_t i = 0; i < nr; ++i) r0[i] = j->car_r[i % (j->S - 1)];
+        if (hipMalloc((void **)&j->r, 8 * nr) != hipSuccess || hipMalloc((void **)&j->acc_r, 8 * nr) != hipSuccess) {
+            j->err = "device allocation failed";
+            return MC_ERR_NOMEM;
+        }
+        if (hipMemcpy(j->r, r0.data(), 8 * nr, hipMemcpyHostToDevice) != hipSuccess) {
+            j->err = "upload of the r start failed";
+            return MC_ERR_DEVICE;
+        }
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s->st,
+                           (unsigned long long *)j->acc_r, nr);
+    }
     const size_t tot = (size_t)j->n * M;
     const unsigned gb = (unsigned)std::min<size_t>((tot + 255) / 256, 65535);
     if (s->cfg.precision == MC_F64)
@@ -194,6 +214,11 @@ mc_status run_group(mc_server *s, const std::vector<ServerJob *> &group, int k) 
         ServerJob *j = group[i];
         ps[i] = j->p;
         cfgs[i] = mc_run_config{0, k, k, j->step, nullptr, j->seed, (uint64_t)j->steps_done};
+        if (j->r_step > 0) {
+            cfgs[i].r_state = j->r;
+            cfgs[i].r_step = j->r_step;
+            cfgs[i].n_accept_r = j->acc_r;
+        }
         nch[i] = j->n;
         hs[i] = j->H;
         lps[i] = j->lp;
@@ -205,10 +230,13 @@ mc_status run_group(mc_server *s, const std::vector<ServerJob *> &group, int k) 
 }
 
 mc_status run_round(mc_server *s, const std::vector<ServerJob *> &res, int k) {
-    for (int S = 2; S <= kMaxSurfaces; ++S) {
+    // one group per surface count and per kind of r (fixed or sampled)
+    for (int gi = 0; gi < 2 * (kMaxSurfaces - 1); ++gi) {
+        const int S = 2 + gi / 2;
+        const bool hier = gi % 2 == 1;
         std::vector<ServerJob *> group;
         for (ServerJob *j : res)
-            if (j->S == S) group.push_back(j);
+            if (j->S == S && (j->r_step > 0) == hier) group.push_back(j);
         if (group.empty()) continue;
         mc_status r;
         if (s->cfg.precision == MC_F64) {
@@ -316,12 +344,20 @@ void scheduler(mc_server *s) {
                     (j->steps_done >= j->n_steps ? finished : keep).push_back(j);
                 }
                 for (ServerJob *j : finished) enqueue_summary(s, j);
-                std::vector<std::vector<double>> host(finished.size());
+                std::vector<std::vector<double>> host(finished.size()), hr(finished.size());
+                std::vector<std::vector<int64_t>> hacc(finished.size());
                 for (size_t i = 0; i < finished.size(); ++i) {
                     ServerJob *j = finished[i];
                     const size_t M = (size_t)(j->S - 1) * j->R * j->C;
                     host[i].resize(3 * M + 3);
                     (void)hipMemcpyAsync(host[i].data(), j->dsum, 8 * (3 * M + 3), hipMemcpyDeviceToHost, s->st);
+                    if (j->r) {
+                        hr[i].resize((size_t)j->n * (j->S - 1));
+                        hacc[i].resize(hr[i].size());
+                        (void)hipMemcpyAsync(hr[i].data(), j->r, 8 * hr[i].size(), hipMemcpyDeviceToHost, s->st);
+                        (void)hipMemcpyAsync(hacc[i].data(), j->acc_r, 8 * hacc[i].size(), hipMemcpyDeviceToHost,
+                                             s->st);
+                    }
                 }
                 se = hipStreamSynchronize(s->st);
                 for (size_t i = 0; i < finished.size(); ++i) {
@@ -339,6 +375,18 @@ void scheduler(mc_server *s) {
                     j->map_lp = host[i][3 * M];
                     j->map_chain = (int)host[i][3 * M + 1];
                     j->accept_rate = host[i][3 * M + 2] / ((double)j->n * (double)j->n_steps);
+                    if (!hr[i].empty()) {
+                        // mean r of every free surface over the chains' last states, in chain order
+                        const int S1 = j->S - 1;
+                        j->r_mean.assign(S1, 0.0);
+                        double na = 0.0;
+                        for (int c = 0; c < j->n; ++c)
+                            for (int l = 0; l < S1; ++l) {
+                                j->r_mean[l] += hr[i][(size_t)c * S1 + l] / j->n;
+                                na += (double)hacc[i][(size_t)c * S1 + l];
+                            }
+                        j->r_accept_rate = na / ((double)j->n * S1 * (double)j->n_steps);
+                    }
                     j->status = MC_JOB_DONE;
                     j->t_done = s->now();
                     s->stats.done += 1;
@@ -435,6 +483,7 @@ mc_status mc_server_submit(mc_server *s, const mc_job_desc *d, int64_t *job_id) 
     if (d->n_chains <= 0 || d->n_chains > 65535) return server_fail(s, MC_ERR_ARG, "n_chains %d", d->n_chains);
     if (d->n_steps < 1 || d->n_steps >= (1LL << 47)) return server_fail(s, MC_ERR_ARG, "n_steps");
     if (!(d->step_size >= 0) || !std::isfinite(d->step_size)) return server_fail(s, MC_ERR_ARG, "step_size");
+    if (!(d->r_step >= 0) || !std::isfinite(d->r_step)) return server_fail(s, MC_ERR_ARG, "r_step");
     if (!d->density || !d->top || !d->car_r || !d->init) return server_fail(s, MC_ERR_ARG, "NULL array");
     const size_t nr = (size_t)d->n_sensors * d->n_pix, N = (size_t)R * C;
     if (nr > 0 && (!d->sensor_pos || !d->dirs || !d->exposure || !d->counts))
@@ -464,6 +513,7 @@ mc_status mc_server_submit(mc_server *s, const mc_job_desc *d, int64_t *job_id) 
     j->seed = d->seed;
     j->block = d->block;
     j->rpt = d->rays_per_thread;
+    j->r_step = d->r_step;
     j->footprint = job_footprint(*j, s->cfg.precision);
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->stop) {
@@ -501,6 +551,8 @@ mc_status mc_server_poll(mc_server *s, int64_t job_id, mc_job_info *info, double
     info->accept_rate = j->accept_rate;
     info->map_logpost = j->map_lp;
     info->footprint = j->footprint;
+    for (int l = 0; l < 3; ++l) info->r_mean[l] = l < (int)j->r_mean.size() ? j->r_mean[l] : 0.0;
+    info->r_accept_rate = j->r_accept_rate;
     if (j->status == MC_JOB_DONE) {
         if (mean) std::copy(j->mean.begin(), j->mean.end(), mean);
         if (sd) std::copy(j->sd.begin(), j->sd.end(), sd);

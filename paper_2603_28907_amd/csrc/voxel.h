@@ -51,6 +51,12 @@ struct VoxParams {
     double *partials;            // [n][n_tiles] per-chain, per-tile sums of C log(lambda) - lambda
     T *opacity;                  // optional [n][n_ray]: O_p(R-hat)
     const double *only_nan;      // optional [n]: chains whose value is not NaN are skipped
+    // gradient (optional)
+    T *alpha;                    // [n_pad/64][n_ray][64]: dLL/dO_p = (C_p / lambda-hat_p - 1)(-lambda_p(R0) / Lambda)
+    const int *t_off;            // [N*n_z + 1] CSR offsets of the voxels' ray lists (the transpose of G's pattern)
+    const int *t_ray;            // [nnz] ray index
+    const T *t_len;              // [nnz] length of that ray inside the voxel
+    unsigned long long *gfix;    // [n][S][N] fixed-point gradient of the likelihood (every entry written)
 };
 
 // sigma = 1 / (1 + exp(x)), x = (z - H) / gamma
@@ -134,6 +140,9 @@ __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> 
         const double l0 = P.lam0[p];
         const double lam = l0 - (o - P.o0[p]) * (l0 * P.inv_atten);
         tsum += lam > 0.0 ? P.cnt[p] * log(lam) - lam : -__builtin_huge_val();
+        if (P.alpha)
+            P.alpha[((size_t)group * P.n_ray + p) * kVoxLanes + lane] =
+                lam > 0.0 ? (T)((P.cnt[p] / lam - 1.0) * (-l0 * P.inv_atten)) : T(0);
     }
     red[wave][lane] = tsum;
     __syncthreads();
@@ -142,6 +151,54 @@ __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> 
 #pragma unroll
         for (int w = 1; w < kVoxWaves; ++w) s += red[w][lane];
         P.partials[(size_t)c * P.n_tiles + tile] = s;
+    }
+}
+
+// Gradient of the linearised likelihood with respect to every height.
+// dLL/dRhat_v = sum_p alpha_p L_pv (a gather over voxel v's ray list, the
+// transpose of G's pattern), and Rhat of voxel (n, k) depends on column n
+// alone: dRhat/dH_l,n = (rho_l - rho_{l+1}) sigma_l (1 - sigma_l) /
+// (gamma (1 - sigma_0)).  One wavefront per (column, 64-chain group), lane =
+// chain: it walks the column's levels, gathers each level's sum (one 64-chain
+// row of alpha per list entry) and adds it into the S height derivatives,
+// then writes them in the 2^-32 fixed point of the march's adjoint.  Sums run
+// in a fixed order: the result is deterministic.
+template <typename T, int S>
+__global__ __launch_bounds__(256) void k_vox_grad(VoxParams<T> P) {
+    const int lane = threadIdx.x & (kVoxLanes - 1);
+    const int col = blockIdx.x * 4 + threadIdx.x / kVoxLanes;
+    const int group = blockIdx.y;
+    if (col >= P.N) return;
+    const int c = group * kVoxLanes + lane;
+    const bool live = c < P.n_chains;
+    T h[S];
+#pragma unroll
+    for (int l = 0; l < S - 1; ++l) h[l] = live ? P.heights[(size_t)c * P.M + (size_t)l * P.N + col] : T(0);
+    h[S - 1] = P.top[col];
+    double g[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) g[l] = 0.0;
+    const T ig = (T)P.inv_gamma, dz = (T)P.dz;
+    const T *arow = P.alpha + (size_t)group * P.n_ray * kVoxLanes + lane;
+    for (int k = 0; k < P.n_z; ++k) {
+        const int v = col * P.n_z + k;
+        const int beg = P.t_off[v], end = P.t_off[v + 1];
+        if (beg == end) continue;
+        double B = 0.0;
+        for (int e = beg; e < end; ++e) B += (double)arow[(size_t)P.t_ray[e] * kVoxLanes] * (double)P.t_len[e];
+        const T z = ((T)k + T(0.5)) * dz;
+        const double bn = B * P.inv_gamma * P.inv_norm[k];
+#pragma unroll
+        for (int l = 0; l < S; ++l) {
+            const double sg = (double)vox_sigma((z - h[l]) * ig);
+            g[l] += bn * P.drho[l] * (sg * (1.0 - sg));
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        const double sv = fmin(fmax(g[l] * 4294967296.0, -9.0e18), 9.0e18);
+        P.gfix[((size_t)c * S + l) * P.N + col] = (unsigned long long)(long long)__builtin_rint(sv);
     }
 }
 

@@ -1,18 +1,20 @@
 """GPU parity of the hand-written adjoint (gradient of the log posterior with
 respect to every surface height) and of the MALA sampler that uses it.
 
-Tolerances: float64, relative 1e-9 in the L2 norm per chain.  float32 on
-the small cave, relative 1e-4 in the L2 norm per chain and
-|dg| <= 1e-4 max|g| + 1e-6 on 99% of the coordinates; float32 at paper scale
-(128x128), relative 1e-3 per chain and 99.9% of coordinates within
-1e-3 max|g|: a crossing contributes w_n/|f'|, and float32 rounding of the end
-values moves a grazing crossing (small |f'|) or one near a cell vertex by
-enough to shift part of its weight between nodes."""
+Tolerances: float64, relative 1e-9 in the L2 norm per chain.  float32:
+every coordinate within its own conditioning bound (tests.gpu_common.
+f32_gradient_tolerance: a crossing contributes w_n/|f'|, so float32 rounding
+of z - h moves it by eps_z/|f'| and its weight by about eps_z/f'^2; pairs
+near tangency may vanish; dLL/dO carries the ray's measured opacity error),
+with no coordinate exempt, and relative 1e-4 (small cave) or 1e-3 (128x128)
+in the L2 norm per chain.  Central differences of float64 log posteriors
+(h = 1e-3 m, 64 seeded coordinates, kinks of the piecewise-smooth lp
+detected and skipped) on the small cave and on the 128x128 geometry."""
 import numpy as np
 import pytest
 
 from paper_2603_28907_amd import inputs
-from tests.gpu_common import require_gpu, rounded_states, say, to_dev
+from tests.gpu_common import f32_gradient_tolerance, require_gpu, rounded_states, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -39,6 +41,31 @@ def gpu_grad(torch, sc, states, precision):
     return lp.cpu().numpy(), g.double().cpu().numpy(), prob
 
 
+def gpu_opacities(torch, prob, states):
+    """The float32 forward opacities of `states` (the ones the gradient uses:
+    the march is the same kernel, and a chain's results do not depend on the
+    batch)."""
+    H = to_dev(states, torch.float32)
+    O = torch.empty((states.shape[0], prob.n_rays), dtype=torch.float32, device="cuda:0")
+    prob.logpost_batch(H, opacity=O)
+    torch.cuda.synchronize()
+    return O.double().cpu().numpy()
+
+
+def check_f32_gradient(orc, state, g_gpu, g_ref, O_gpu, label):
+    """Every coordinate within its conditioning bound."""
+    _, gpr = orc.log_prior_grad(state)
+    dO = O_gpu - orc.opacity(state)
+    tol = f32_gradient_tolerance(orc, state, dO, gpr)
+    err = np.abs(g_gpu - g_ref)
+    ratio = err / tol
+    k = np.unravel_index(np.argmax(ratio), ratio.shape)
+    say(f"{label}: worst error / bound {ratio[k]:.3f} at node {k} (error {err[k]:.3g}, bound {tol[k]:.3g}); "
+        f"median bound / max|g| {np.median(tol) / np.abs(g_ref).max():.2e}")
+    assert np.all(err <= tol), (label, k, g_gpu[k], g_ref[k], tol[k])
+    return tol
+
+
 def test_prior_gradient_without_sensors(torch_mod, oracle_mod):
     from tests.helpers import make_scenario
     sc = inputs.tiny_bumps(seed=3)
@@ -58,7 +85,7 @@ def test_prior_gradient_without_sensors(torch_mod, oracle_mod):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_gradient_matches_oracle(torch_mod, oracle_mod, tiny, precision):
     states = np.concatenate([tiny.truth[None], inputs.init_states(tiny, 3, seed=2)])
-    lp, g, _ = gpu_grad(torch_mod, tiny, states, precision)
+    lp, g, prob = gpu_grad(torch_mod, tiny, states, precision)
     st = rounded_states(states, precision)
     orc = oracle_mod.OracleProblem(tiny)
     lpo, go = orc.grad_batch(st)
@@ -76,8 +103,8 @@ def test_gradient_matches_oracle(torch_mod, oracle_mod, tiny, precision):
             assert lp[c] == pytest.approx(lpo[c], rel=1e-11, abs=1e-6)
         else:
             assert rel < 1e-4
-            bad = np.abs(g[c] - go[c]) > 1e-4 * np.abs(go[c]).max() + 1e-6
-            assert bad.mean() < 0.01, bad.sum()
+            O = gpu_opacities(torch_mod, prob, st[c:c + 1])[0]
+            check_f32_gradient(orc, st[c], g[c], go[c], O, f"grad f32 chain {c}")
 
 
 def test_gradient_finite_differences_on_gpu(torch_mod, tiny):
@@ -118,11 +145,13 @@ def test_gradient_paper_scale_128(torch_mod, oracle_mod):
     sc.counts = oracle_mod.make_counts(sc, seed=11)
     states = inputs.init_states(sc, 512, seed=12)
     say("gradient at 128x128 x 512 chains")
-    lp, g, _ = gpu_grad(torch_mod, sc, states, "f32")
+    lp, g, prob = gpu_grad(torch_mod, sc, states, "f32")
     assert np.all(np.isfinite(lp)) and np.all(np.isfinite(g))
     st = rounded_states(states, "f32")
     orc = oracle_mod.OracleProblem(sc)
-    for c in (0, 511):
+    O = gpu_opacities(torch_mod, prob, st[[0, 511]])
+    tol0 = None
+    for k_c, c in enumerate((0, 511)):
         lpo, go = orc.grad(st[c])
         rel = np.linalg.norm(g[c] - go) / np.linalg.norm(go)
         say(f"128x128 chain {c}: relative L2 error {rel:.2e}")
@@ -132,7 +161,23 @@ def test_gradient_paper_scale_128(torch_mod, oracle_mod):
             say(f"  surface {l}: rel {np.linalg.norm(g[c, l] - go[l]) / np.linalg.norm(go[l]):.2e}, worst node {k} "
                 f"gpu {g[c, l][k]:.6g} oracle {go[l][k]:.6g}")
         assert rel < 1e-3
-        assert np.mean(np.abs(g[c] - go) > 1e-3 * np.abs(go).max()) < 1e-3
+        tol = check_f32_gradient(orc, st[c], g[c], go, O[k_c], f"128x128 chain {c}")
+        if c == 0:
+            tol0, scale = tol, np.abs(go).max()
+    # central differences of the oracle's float64 log posterior (h = 1e-3 m)
+    # on 64 seeded coordinates of all three surfaces, against the GPU's
+    # float32 gradient of chain 0
+    from tests.helpers import central_differences, is_kink
+    fd = central_differences(oracle_mod, sc, st[0], 64, 1e-3, seed=13)
+    kinks = 0
+    for (l, i, j, fwd, bwd, cd) in fd:
+        t_fd = 1e-4 * scale + 1e-3
+        if is_kink(fwd, bwd, t_fd):
+            kinks += 1
+            continue
+        assert abs(cd - g[0, l, i, j]) <= t_fd + tol0[l, i, j], (l, i, j, cd, g[0, l, i, j])
+    say(f"128x128 finite differences: {len(fd) - kinks} coordinates compared, {kinks} kinks")
+    assert kinks <= 8
 
 
 def test_gradient_repeat_bitwise_and_out_of_support(torch_mod, tiny):
@@ -178,3 +223,40 @@ def test_mala_f64_matches_oracle(torch_mod, oracle_mod, tiny):
     assert np.array_equal(acc.cpu().numpy(), acco)
     np.testing.assert_allclose(H.cpu().numpy(), Ho, rtol=1e-12, atol=1e-10)
     np.testing.assert_allclose(lp.cpu().numpy(), lpo, rtol=1e-11, atol=1e-6)
+
+
+def test_adjoint_paths_agree_bitwise(torch_mod, oracle_mod):
+    """float32: the record adjoint (one window of node rows, or several) and
+    the re-walk of the rays (every chain, with one or several windows; or
+    only the chains whose record slots overflow) give the same gradient bit
+    for bit: they add the same fixed-point contributions, computed from the
+    same walk.  The gradient also meets the oracle within its conditioning
+    bound."""
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    sc = inputs.grf_cave(seed=14, n_grid=32, n_sensors=4, pix_side=32)
+    sc.counts = oracle_mod.make_counts(sc, seed=15)
+    states = inputs.init_states(sc, 24, seed=16)
+    prob = Problem.from_scenario(sc, precision="f32")
+    base = prob.get_tuning()
+    H = to_dev(states, torch.float32)
+    lp0, g0 = prob.logpost_grad_batch(H)
+    torch.cuda.synchronize()
+    variants = [dict(adjoint_rows=5), dict(adjoint_rows=1), dict(grad_slots=-1), dict(grad_slots=-1, adjoint_rows=7),
+                dict(grad_slots=1), dict(grad_slots=6), dict(grad_slots=9), dict(grad_slots=12, adjoint_rows=3)]
+    for v in variants:
+        t = dict(base)
+        t.update(v)
+        prob.set_tuning(**t)
+        lp, g = prob.logpost_grad_batch(H)
+        torch.cuda.synchronize()
+        say(f"adjoint variant {v}: bitwise {torch.equal(g, g0)}")
+        assert torch.equal(lp, lp0) and torch.equal(g, g0), v
+    prob.set_tuning(**base)
+    st = rounded_states(states, "f32")
+    orc = oracle_mod.OracleProblem(sc)
+    O = gpu_opacities(torch, prob, st[:2])
+    gn = g0.double().cpu().numpy()
+    for c in range(2):
+        _, go = orc.grad(st[c])
+        check_f32_gradient(orc, st[c], gn[c], go, O[c], f"32x32 chain {c}")

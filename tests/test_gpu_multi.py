@@ -152,3 +152,42 @@ def test_autotune_per_class(torch_mod, oracle_mod, tmp_path):
     autotune._memo.clear()
     again = autotune.tune_batch(probs, H, cache_path=cache, iters=2)
     assert again == res
+
+
+@pytest.mark.parametrize("precision,ids", [("f32", [0, 2, 3, 5]), ("f64", [1, 4])])
+def test_multi_with_sampled_r_equals_single(torch_mod, oracle_mod, precision, ids):
+    """Every chain's r sampled too (logit-scale Metropolis-within-Gibbs after
+    each H decision): each problem in the shared launches gives the states,
+    r values, log posteriors and acceptance counts of mcmc_run on its own,
+    bit for bit, across a resumed second call."""
+    from paper_2603_28907_amd.binding import Problem, mcmc_run_multi
+    torch = torch_mod
+    batch = _batch(oracle_mod, ids)
+    probs = [Problem.from_scenario(sc, precision=precision) for sc, _, _, _ in batch]
+    dt = probs[0].torch_dtype
+    H, lp, acc = _states(torch, batch, dt)
+    H1, lp1, acc1 = _clone(H), _clone(lp), _clone(acc)
+    rng = np.random.default_rng(9)
+    r = [to_dev(rng.uniform(0.3, 0.95, size=(n, sc.n_surfaces - 1)), torch.float64) for sc, n, _, _ in batch]
+    ar = [torch.zeros((n, sc.n_surfaces - 1), dtype=torch.int64, device="cuda:0") for sc, n, _, _ in batch]
+    r1, ar1 = _clone(r), _clone(ar)
+    tau, G = 0.4, 4
+    for k, (pr, (sc, n, sig, seed)) in enumerate(zip(probs, batch)):
+        pr.mcmc_run(H1[k], lp1[k], acc1[k], 8, sig, seed, graph_steps=G, r_state=r1[k], r_step=tau,
+                    n_accept_r=ar1[k])
+        pr.mcmc_run(H1[k], lp1[k], acc1[k], 5, sig, seed, step_offset=8, graph_steps=G, r_state=r1[k], r_step=tau,
+                    n_accept_r=ar1[k])
+    sig, seeds = [b[2] for b in batch], [b[3] for b in batch]
+    mcmc_run_multi(probs, H, lp, acc, 8, sig, seeds, graph_steps=G, r_states=r, r_step=tau, n_accept_r=ar)
+    mcmc_run_multi(probs, H, lp, acc, 5, sig, seeds, step_offsets=[8] * len(probs), graph_steps=G, r_states=r,
+                   r_step=tau, n_accept_r=ar)
+    torch.cuda.synchronize()
+    moved = 0
+    for k in range(len(probs)):
+        assert torch.equal(H[k], H1[k]) and torch.equal(lp[k], lp1[k]) and torch.equal(acc[k], acc1[k]), k
+        assert torch.equal(r[k], r1[k]) and torch.equal(ar[k], ar1[k]), k
+        moved += int(ar[k].sum())
+    say("r accepted", moved)
+    assert moved > 0
+    with pytest.raises(Exception, match="every problem or for none"):
+        mcmc_run_multi(probs, H, lp, acc, 2, sig, seeds, r_states=[r[0]] + [None] * (len(probs) - 1), r_step=tau)

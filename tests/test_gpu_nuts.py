@@ -154,9 +154,18 @@ def test_nuts_errors(torch_mod, tiny):
         prob.nuts_run(H, lp, e, 1, 1, target_accept=1.5)
     with pytest.raises(MuonCaveError, match="inv_mass"):
         prob.nuts_run(H, lp, e, 1, 1, n_warmup=5, adapt_mass=True)
-    prob.set_voxel_model(10, 1.0, tiny.truth)
-    with pytest.raises(MuonCaveError, match="voxel"):
+    prob.set_pixel_quadrature(*_one_subray_quadrature(tiny))
+    prob.set_counts(tiny.counts)   # one sub-ray per pixel: the same counts
+    with pytest.raises(MuonCaveError, match="quadrature"):
         prob.nuts_run(H, lp, e, 1, 1)
+
+
+def _one_subray_quadrature(sc):
+    """Pixel quadrature with one sub-ray per pixel (n_sub, weights, log
+    intensity table, o_max): enough to switch the gradient paths off."""
+    w = np.asarray(sc.exposure, np.float64).reshape(-1)
+    tab = -np.linspace(0.0, 2000.0, 64) / sc.atten_len
+    return 1, w, tab, 2000.0
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -252,3 +261,46 @@ def test_nuts_shapes_depths_and_prior_only(torch_mod, oracle_mod, S, n_sensors, 
     assert len(ok) >= 2, "near-ties in most chains; choose another seed"
     assert o["depth"].max() <= max_depth and o["n_leap"].max() <= 2 ** max_depth - 1
     compare(g, o, ok, rtol_x=1e-8, rtol_acc=1e-6, rtol_lp=1e-10)
+
+
+def test_nuts_with_sampled_r_matches_oracle(torch_mod, oracle_mod, tiny):
+    """The paper's latent vector of all unknowns: the CAR fields and every
+    free surface's r (as logit r) sampled jointly.  float64 trees, fields, r
+    and log densities equal the oracle's; a warm-up that adapts the mass of
+    all S-1 extra coordinates too runs and stays finite in float32."""
+    torch = torch_mod
+    from paper_2603_28907_amd.binding import Problem
+    n = 4
+    orc = oracle_mod.OracleProblem(tiny)
+    x0 = orc.heights_to_latent(inputs.init_states(tiny, n, seed=2))
+    r0 = np.array([[0.8, 0.95], [0.9, 0.6], [0.99, 0.7], [0.5, 0.9]])
+    eps = np.full(n, 0.01)
+    o = orc.nuts(x0, np.full(n, np.nan), eps, max_depth=5, n_steps=4, seed=61, latent=True, r=r0)
+    say("nuts with r: depths", o["depth"].tolist(), "margins", o["margin"], "r", o["r"].tolist())
+    ok = [c for c in range(n) if o["margin"][c] > 1e-7]
+    assert len(ok) >= 3 and o["n_leap"].sum() > 40
+    prob = Problem.from_scenario(tiny, precision="f64")
+    X = to_dev(x0, torch.float64)
+    lp = to_dev(np.full(n, np.nan), torch.float64)
+    e = to_dev(eps, torch.float64)
+    r = to_dev(r0, torch.float64)
+    st = prob.nuts_run(X, lp, e, 4, 61, max_depth=5, latent=True, r_state=r)
+    torch.cuda.synchronize()
+    for c in ok:
+        assert np.array_equal(st["tree_depth"].cpu().numpy()[c], o["depth"][c]), c
+        assert np.array_equal(st["n_leapfrog"].cpu().numpy()[c], o["n_leap"][c]), c
+        np.testing.assert_allclose(X.cpu().numpy()[c], o["x"][c], rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(r.cpu().numpy()[c], o["r"][c], rtol=1e-9, atol=1e-12)
+        assert lp.cpu().numpy()[c] == pytest.approx(o["lp"][c], rel=1e-10, abs=1e-6)
+    assert np.any(np.abs(r.cpu().numpy() - r0) > 1e-3)
+    # float32 with warm-up and mass adaptation over all coordinates
+    p32 = Problem.from_scenario(tiny, precision="f32")
+    X32 = to_dev(x0, torch.float32)
+    lp32 = to_dev(np.full(n, np.nan), torch.float64)
+    r32 = to_dev(r0, torch.float64)
+    im = torch.ones((n, 2 * (tiny.n_rows * tiny.n_cols + 1)), dtype=torch.float64, device="cuda:0")
+    p32.nuts_run(X32, lp32, to_dev(eps, torch.float64), 5, 62, n_warmup=30, max_depth=5, inv_mass=im,
+                 adapt_mass=True, latent=True, r_state=r32)
+    torch.cuda.synchronize()
+    assert torch.isfinite(lp32).all() and torch.isfinite(X32).all()
+    assert torch.all((r32 > 0) & (r32 < 1))

@@ -213,3 +213,50 @@ def test_release_before_done_is_refused(torch_mod, oracle_mod):
     assert srv.poll(j, arrays=False)["status"] == JOB_DONE
     srv.release(j)
     srv.close()
+
+
+def test_job_with_sampled_r_alone_mix_and_plain(torch_mod, oracle_mod):
+    """A served job whose chains sample r too (r_step > 0): the same bits alone,
+    in a mix with fixed-r jobs and another r job, and as the plain sampler
+    mcmc_run with r_state started at the job's r."""
+    from paper_2603_28907_amd.binding import JOB_DONE, Problem, Server
+    torch = torch_mod
+    jobs = _jobs(oracle_mod, [0, 2, 3, 4])
+    x_sc, x_n, x_seed = jobs[2]
+    steps, sigma, tau = 60, 0.005, 0.4
+    srv = Server(precision="f32", max_jobs=1, steps_per_round=20)
+    jx = srv.submit(x_sc, x_n, steps, sigma, x_seed, r_step=tau)
+    srv.wait_idle(120)
+    alone = srv.poll(jx)
+    srv.close()
+    assert alone["status"] == JOB_DONE
+    srv = Server(precision="f32", max_jobs=8, steps_per_round=20)
+    others = [srv.submit(jobs[0][0], jobs[0][1], 80, sigma, jobs[0][2]),
+              srv.submit(jobs[1][0], jobs[1][1], 40, sigma, jobs[1][2], r_step=0.3)]
+    jx2 = srv.submit(x_sc, x_n, steps, sigma, x_seed, r_step=tau)
+    others.append(srv.submit(jobs[3][0], jobs[3][1], 60, sigma, jobs[3][2]))
+    srv.wait_idle(120)
+    mixed = srv.poll(jx2)
+    assert all(srv.poll(j, arrays=False)["status"] == JOB_DONE for j in others)
+    srv.close()
+    _same(alone, mixed)
+    assert alone["r_mean"] == mixed["r_mean"] and alone["r_accept_rate"] == mixed["r_accept_rate"]
+    # the plain sampler with r
+    prob = Problem.from_scenario(x_sc, precision="f32")
+    H = to_dev(np.broadcast_to(x_sc.truth, (x_n,) + x_sc.truth.shape), torch.float32)
+    lp = to_dev(np.full(x_n, np.nan), torch.float64)
+    acc = to_dev(np.zeros(x_n, np.int64), torch.int64)
+    S1 = x_sc.n_surfaces - 1
+    r = to_dev(np.broadcast_to(x_sc.car_r, (x_n, S1)), torch.float64)
+    ar = torch.zeros((x_n, S1), dtype=torch.int64, device="cuda:0")
+    prob.mcmc_run(H, lp, acc, steps, sigma, x_seed, graph_steps=20, r_state=r, r_step=tau, n_accept_r=ar)
+    torch.cuda.synchronize()
+    Hh, lph = H.double().cpu().numpy(), lp.cpu().numpy()
+    best = int(np.argmax(lph))
+    assert alone["map_chain"] == best and alone["map_logpost"] == lph[best]
+    assert np.array_equal(alone["map_state"], Hh[best])
+    rh = r.cpu().numpy()
+    want = [float(v) for v in sum(rh[c] / x_n for c in range(x_n))]
+    np.testing.assert_allclose(alone["r_mean"][:S1], want, rtol=1e-14)
+    assert alone["r_accept_rate"] == ar.sum().item() / (x_n * S1 * steps)
+    assert 0.0 < alone["r_accept_rate"] < 1.0

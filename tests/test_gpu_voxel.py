@@ -179,7 +179,7 @@ def test_graph_eager_repeat_bitwise_and_switching_back(torch_mod, oracle_mod, ti
 
 
 def test_voxel_model_errors(torch_mod, tiny):
-    from paper_2603_28907_amd.binding import KERNEL_MALA, MuonCaveError, Problem, mcmc_run_multi, time_march
+    from paper_2603_28907_amd.binding import MuonCaveError, Problem, mcmc_run_multi, time_march
     torch = torch_mod
     prob = Problem.from_scenario(tiny, precision="f32")
     with pytest.raises(MuonCaveError, match="n_z"):
@@ -191,11 +191,6 @@ def test_voxel_model_errors(torch_mod, tiny):
     H = to_dev(inputs.init_states(tiny, n, seed=1), torch.float32)
     lp = to_dev(np.full(n, np.nan), torch.float64)
     acc = to_dev(np.zeros(n, np.int64), torch.int64)
-    g = torch.empty((n, 3, tiny.n_rows, tiny.n_cols), dtype=torch.float32, device="cuda:0")
-    with pytest.raises(MuonCaveError, match="exact march"):
-        prob.logpost_grad_batch(H, lp, g)
-    with pytest.raises(MuonCaveError, match="MALA"):
-        prob.mcmc_run(H, lp, acc, 2, 0.01, 1, kernel=KERNEL_MALA)
     with pytest.raises(MuonCaveError, match="exact march"):
         mcmc_run_multi([prob], [H], [lp], [acc], 2, [0.01], [1])
     with pytest.raises(MuonCaveError, match="mc_time_voxel"):
@@ -249,3 +244,112 @@ def test_close_after_graph_capture_with_voxel_model(torch_mod, tiny):
         torch.cuda.synchronize()
         prob.close()
     assert np.all(np.isfinite(lp.cpu().numpy()))
+
+
+# ---------------------------------------------------------------------------
+# The voxel model's gradient (the reason the paper smooths the density)
+# ---------------------------------------------------------------------------
+
+VOX_NZ, VOX_GAMMA = 25, 2.0
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_voxel_gradient_matches_oracle(torch_mod, oracle_mod, tiny, precision):
+    """logpost_grad_batch under the voxel model: the back-projection of
+    dLL/dO through G's transposed pattern and the sigmoid derivatives, against
+    the oracle's chain rule.  float64: relative 1e-9 (L2 per chain); float32:
+    relative 1e-4 and every coordinate within 1e-4 max|g|."""
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    states = np.concatenate([tiny.truth[None], inputs.init_states(tiny, 3, seed=4, jitter=1.0)])
+    prob = Problem.from_scenario(tiny, precision=precision)
+    prob.set_voxel_model(VOX_NZ, VOX_GAMMA, tiny.truth)
+    dt = torch.float64 if precision == "f64" else torch.float32
+    lp, g = prob.logpost_grad_batch(to_dev(states, dt))
+    torch.cuda.synchronize()
+    lp, g = lp.cpu().numpy(), g.double().cpu().numpy()
+    orc = oracle_vox(oracle_mod, tiny, VOX_NZ, VOX_GAMMA, tiny.truth)
+    st = rounded_states(states, precision)
+    for c in range(states.shape[0]):
+        lpo, go = orc.grad(st[c])
+        rel = np.linalg.norm(g[c] - go) / np.linalg.norm(go)
+        worst = np.abs(g[c] - go).max() / np.abs(go).max()
+        say(f"voxel grad {precision} chain {c}: relative L2 {rel:.2e}, worst coordinate / max|g| {worst:.2e}")
+        assert np.abs(go[2]).max() > 0.0
+        if precision == "f64":
+            assert rel < 1e-9
+            assert lp[c] == pytest.approx(lpo, rel=1e-11, abs=1e-6)
+        else:
+            assert rel < 1e-4 and worst < 1e-4
+
+
+def test_voxel_gradient_zero_where_counts_nonpositive(torch_mod, oracle_mod, tiny):
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    sc = inputs.tiny_bumps(seed=0)
+    sc.atten_len = 5.0
+    sc.counts = tiny.counts
+    prob = Problem.from_scenario(sc, precision="f64")
+    prob.set_voxel_model(30, 1.0, tiny.truth)
+    low = tiny.truth.copy()
+    low[1] = low[0] + 0.5
+    lp, g = prob.logpost_grad_batch(to_dev(np.stack([tiny.truth, low]), torch.float64))
+    torch.cuda.synchronize()
+    assert np.isfinite(lp[0].item()) and lp[1].item() == -np.inf
+    assert torch.all(g[1] == 0.0) and torch.any(g[0] != 0.0)
+
+
+def test_voxel_mala_f64_matches_oracle(torch_mod, oracle_mod, tiny):
+    from paper_2603_28907_amd.binding import KERNEL_MALA, Problem
+    torch = torch_mod
+    states = inputs.init_states(tiny, 4, seed=6)
+    n_steps, eps, seed = 20, 0.2, 33
+    orc = oracle_vox(oracle_mod, tiny, VOX_NZ, VOX_GAMMA, tiny.truth)
+    Ho, lpo, acco, marg = orc.mcmc_mala(states, np.full(4, np.nan), np.zeros(4, np.int64), n_steps, 0, eps, seed,
+                                        want_margins=True)
+    say("voxel mala acceptances", acco, "min margin", np.nanmin(marg))
+    assert np.nanmin(marg) > 1e-6, "a near-tie decision; choose another seed"
+    assert 0 < acco.sum() < 4 * n_steps
+    prob = Problem.from_scenario(tiny, precision="f64")
+    prob.set_voxel_model(VOX_NZ, VOX_GAMMA, tiny.truth)
+    H = to_dev(states, torch.float64)
+    lp = to_dev(np.full(4, np.nan), torch.float64)
+    acc = to_dev(np.zeros(4, np.int64), torch.int64)
+    prob.mcmc_run(H, lp, acc, n_steps, eps, seed, kernel=KERNEL_MALA, graph_steps=5)
+    torch.cuda.synchronize()
+    assert np.array_equal(acc.cpu().numpy(), acco)
+    np.testing.assert_allclose(H.cpu().numpy(), Ho, rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(lp.cpu().numpy(), lpo, rtol=1e-11, atol=1e-6)
+
+
+@pytest.mark.parametrize("latent", [0, 1])
+def test_voxel_nuts_f64_matches_oracle(torch_mod, oracle_mod, tiny, latent):
+    """NUTS on the voxel model (heights, or the latent CAR fields as the
+    paper's sampler runs): f64 trees equal the oracle's."""
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    n = 4
+    states = inputs.init_states(tiny, n, seed=7)
+    orc = oracle_vox(oracle_mod, tiny, VOX_NZ, VOX_GAMMA, tiny.truth)
+    prob = Problem.from_scenario(tiny, precision="f64")
+    prob.set_voxel_model(VOX_NZ, VOX_GAMMA, tiny.truth)
+    if latent:
+        x = orc.heights_to_latent(states)
+        eps = np.full(n, 0.01)
+    else:
+        x = states
+        eps = np.array([0.01, 0.02, 0.015, 0.01])
+    H = to_dev(x, torch.float64)
+    lp = to_dev(np.full(n, np.nan), torch.float64)
+    e = to_dev(eps, torch.float64)
+    st = prob.nuts_run(H, lp, e, n_steps=4, seed=51, max_depth=5, latent=latent)
+    torch.cuda.synchronize()
+    o = orc.nuts(x, np.full(n, np.nan), eps, max_depth=5, n_steps=4, seed=51, latent=bool(latent))
+    say("voxel nuts depths", o["depth"].tolist(), "margins", o["margin"])
+    ok = [c for c in range(n) if o["margin"][c] > 1e-7]
+    assert len(ok) >= 3
+    assert o["n_leap"].sum() > 20
+    for c in ok:
+        assert np.array_equal(st["tree_depth"].cpu().numpy()[c], o["depth"][c])
+        assert np.array_equal(st["n_leapfrog"].cpu().numpy()[c], o["n_leap"][c])
+        np.testing.assert_allclose(H.cpu().numpy()[c], o["x"][c], rtol=1e-9, atol=1e-9)
