@@ -179,6 +179,25 @@ mc_status logpost_batch(mc_problem *p, int n_chains, const void *heights, double
                         void *opacity, void *stream);
 
 /*
+ * logpost_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results as logpost_batch, with no
+ * hipMalloc, hipFree or other allocating call.  Its workspace (the float64
+ * partial sums of the likelihood per chain and ray tile) is a fixed 1 MiB
+ * array per device, resolved by mc_create: n_chains x n_tiles must be at
+ * most 131072, with n_tiles = ceil(n_sensors*n_pix / (block x
+ * rays_per_thread)) of the handle's launch shape (mc_get_tuning); larger
+ * requests return MC_ERR_ARG.  Exact march with one ray per pixel only:
+ * while set_voxel_model or set_pixel_quadrature is on it returns
+ * MC_ERR_UNSUPPORTED.  Every call on one device shares that array and
+ * nothing in it needs to start at zero; calls that overlap in time on one
+ * device (other streams, other handles, other host threads) race on it and
+ * must be serialised by the caller.
+ */
+mc_status logpost_batch_noalloc(mc_problem *p, int n_chains, const void *heights, double *logpost,
+                                void *opacity, void *stream);
+
+/*
  * Log posterior and its gradient with respect to every surface height,
  * including the fixed top surface.
  *   grad: device, [n_chains][S][n_rows][n_cols] in the handle's precision;

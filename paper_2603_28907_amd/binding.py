@@ -109,6 +109,7 @@ def load_library(path: Optional[str] = None):
         "set_sensors": (I, [V, I, V, I, V, V, D]),
         "set_counts": (I, [V, V]),
         "logpost_batch": (I, [V, I, V, V, V, V]),
+        "logpost_batch_noalloc": (I, [V, I, V, V, V, V]),
         "logpost_grad_batch": (I, [V, I, V, V, V, V]),
         "mcmc_run": (I, [V, P(RunConfig), I, V, V, V, V]),
         "mc_debug_philox": (I, [I, ct.c_uint64, ct.c_uint32, ct.c_uint64, ct.c_uint32, ct.c_uint32, I, V, V]),
@@ -151,7 +152,7 @@ EXPORTED_SYMBOLS = ("mc_create", "mc_destroy", "mc_last_error", "load_geometry_g
                     "mc_server_poll", "mc_server_release", "mc_server_wait_idle", "mc_server_get_stats",
                     "mc_measure_valu_rate", "mc_time_adjoint", "set_voxel_model", "mc_time_voxel", "mc_voxel_info",
                     "nuts_run", "nested_rhat", "latent_to_heights", "heights_to_latent",
-                    "set_pixel_quadrature")
+                    "set_pixel_quadrature", "logpost_batch_noalloc")
 
 
 def _host(a, dtype=np.float64):
@@ -310,6 +311,22 @@ class Problem:
                                            ct.c_void_p(logpost.data_ptr()),
                                            ct.c_void_p(opacity.data_ptr()) if opacity is not None else None,
                                            _stream_handle(stream, self.device)))
+        return logpost
+
+    def logpost_batch_noalloc(self, heights, logpost, opacity=None, stream=None):
+        """logpost_batch through the allocation-free entry point: the caller
+        passes every output (the library's workspace is a fixed per-device
+        array)."""
+        n = int(heights.shape[0])
+        import torch
+        self._check_tensor(heights, self.heights_shape(n), self.torch_dtype, "heights")
+        self._check_tensor(logpost, (n,), torch.float64, "logpost")
+        if opacity is not None:
+            self._check_tensor(opacity, (n, self.n_rays), self.torch_dtype, "opacity")
+        self._check(self.lib.logpost_batch_noalloc(self.h, n, ct.c_void_p(heights.data_ptr()),
+                                                   ct.c_void_p(logpost.data_ptr()),
+                                                   ct.c_void_p(opacity.data_ptr()) if opacity is not None else None,
+                                                   _stream_handle(stream, self.device)))
         return logpost
 
     def logpost_grad_batch(self, heights, logpost=None, grad=None, stream=None):

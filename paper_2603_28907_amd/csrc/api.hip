@@ -30,8 +30,18 @@
 
 using namespace mc;
 
+// Workspace of logpost_batch_noalloc: the per-(chain, ray tile) partial sums
+// of the likelihood, [n_chains][n_tiles] float64.  Every device the library
+// runs on holds its own copy until the process ends.  Host code never uses
+// this name as an address: mc_create resolves the device address once per
+// device with hipGetSymbolAddress and keeps it in g_scratch_ptr.
+constexpr size_t kScratchDoubles = 131072;   // 1 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace {
 
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;   // device -> address of its `scratch`
 
 constexpr int kPriorBlock = 256;
 constexpr int kMaxNodes = 16384;   // n_rows * n_cols limit (prior workspace lives in LDS)
@@ -588,6 +598,29 @@ mc_status logpost_dispatch(mc_problem *p, int n, const void *heights, double *lp
         case 2: return logpost_impl<T, 2>(p, n, (const T *)heights, lp, (T *)opacity, st);
         case 3: return logpost_impl<T, 3>(p, n, (const T *)heights, lp, (T *)opacity, st);
         case 4: return logpost_impl<T, 4>(p, n, (const T *)heights, lp, (T *)opacity, st);
+    }
+    return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
+}
+
+// logpost_batch on the exact march with the likelihood partials in the
+// device's `scratch` array (ws): the same kernels, no workspace allocation.
+template <typename T, int S>
+mc_status logpost_noalloc_impl(mc_problem *p, int n, const T *heights, double *lp, T *opacity, hipStream_t st,
+                               double *ws) {
+    mc_status s;
+    if (p->n_ray > 0 && (s = launch_march<T, S>(p, n, heights, opacity, ws, st)) != MC_OK) return s;
+    PriorParams<T> P = prior_params<T>(p, heights, ws);
+    P.lp_out = lp;
+    return launch_prior<T, S>(p, n, P, st);
+}
+
+template <typename T>
+mc_status logpost_noalloc_dispatch(mc_problem *p, int n, const void *heights, double *lp, void *opacity,
+                                   hipStream_t st, double *ws) {
+    switch (p->S) {
+        case 2: return logpost_noalloc_impl<T, 2>(p, n, (const T *)heights, lp, (T *)opacity, st, ws);
+        case 3: return logpost_noalloc_impl<T, 3>(p, n, (const T *)heights, lp, (T *)opacity, st, ws);
+        case 4: return logpost_noalloc_impl<T, 4>(p, n, (const T *)heights, lp, (T *)opacity, st, ws);
     }
     return fail(p, MC_ERR_UNSUPPORTED, "n_surfaces %d", p->S);
 }
@@ -1514,6 +1547,19 @@ mc_status mc_create(int hip_device, int precision, mc_problem **out) {
     p->prec = precision;
     p->tune = default_tuning(precision, 64 * 64);
     DeviceGuard g(hip_device);
+    {
+        // once per device, with that device current
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr.count(hip_device)) {
+            double *ptr = nullptr;
+            hipError_t se = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+            if (se != hipSuccess || !ptr) {
+                delete p;
+                return fail(nullptr, MC_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(se));
+            }
+            g_scratch_ptr[hip_device] = ptr;
+        }
+    }
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, hip_device) == hipSuccess && lds > 0)
         p->max_lds = (size_t)lds;
@@ -1763,6 +1809,35 @@ mc_status set_counts(mc_problem *p, const int32_t *counts) {
     p->kconst_vox = (double)KV;
     p->have_counts = true;
     return MC_OK;
+}
+
+mc_status logpost_batch_noalloc(mc_problem *p, int n_chains, const void *heights, double *logpost, void *opacity,
+                                void *stream) {
+    mc_status s = check_ready(p);
+    if (s != MC_OK) return s;
+    if (n_chains < 0) return fail(p, MC_ERR_ARG, "n_chains < 0");
+    if (n_chains == 0) return MC_OK;
+    if (!heights || !logpost) return fail(p, MC_ERR_ARG, "NULL device pointer");
+    if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
+    if (p->vox_nz > 0 || p->quad_nsub > 0)
+        return fail(p, MC_ERR_UNSUPPORTED, "logpost_batch_noalloc runs the exact march with one ray per pixel only");
+    const size_t need = p->n_ray > 0 ? (size_t)n_chains * (size_t)tiling(p).n_tiles : 0;
+    if (need > kScratchDoubles)
+        return fail(p, MC_ERR_ARG,
+                    "logpost_batch_noalloc: %d chains x %d ray tiles = %zu partial sums exceed its fixed workspace "
+                    "of %zu (fewer chains per call, or more rays per thread)",
+                    n_chains, tiling(p).n_tiles, need, kScratchDoubles);
+    double *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        auto it = g_scratch_ptr.find(p->device);
+        if (it != g_scratch_ptr.end()) ws = it->second;
+    }
+    if (!ws) return fail(p, MC_ERR_STATE, "no workspace address for device %d", p->device);
+    DeviceGuard g(p->device);
+    hipStream_t st = (hipStream_t)stream;
+    return p->prec == MC_F64 ? logpost_noalloc_dispatch<double>(p, n_chains, heights, logpost, opacity, st, ws)
+                             : logpost_noalloc_dispatch<float>(p, n_chains, heights, logpost, opacity, st, ws);
 }
 
 mc_status logpost_batch(mc_problem *p, int n_chains, const void *heights, double *logpost, void *opacity,
