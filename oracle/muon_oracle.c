@@ -541,10 +541,13 @@ void orc_logpost_batch(const orc_problem *p, int n_chains, const double *free_al
 double orc_loglik_grad_add(const orc_problem *p, const double *free_h, double *grad);
 
 static double voxel_loglik_grad_add(const orc_problem *p, const double *surf, double *grad);
+static double quad_loglik_grad_add(const orc_problem *p, const double *free_h, double *grad);
 
 /* Log-likelihood and its gradient (added to grad [S][R][C]) under the
-   problem's forward model: the exact march, or the smoothed voxel model. */
+   problem's forward model: the exact march (one ray per pixel, or the
+   solid-angle quadrature over sub-rays), or the smoothed voxel model. */
 static double loglik_grad_add_any(const orc_problem *p, const double *free_h, double *grad) {
+    if (p->n_z == 0 && p->n_sub > 0) return quad_loglik_grad_add(p, free_h, grad);
     if (p->n_z == 0) return orc_loglik_grad_add(p, free_h, grad);
     if (p->n_s * p->n_pix == 0) return 0.0;
     double *surf = stack_surfaces(p, free_h);
@@ -555,10 +558,6 @@ static double loglik_grad_add_any(const orc_problem *p, const double *free_h, do
 
 double orc_grad(const orc_problem *p, const double *free_h, double *grad) {
     size_t NS = (size_t)p->S * p->R * p->C;
-    if (p->n_sub > 0) {   /* the gradient here: one ray per pixel */
-        for (size_t i = 0; i < NS; ++i) grad[i] = NAN;
-        return NAN;
-    }
     memset(grad, 0, sizeof(double) * NS);
     double lpr = orc_log_prior_grad(p, free_h, grad);
     if (lpr == -INFINITY) { memset(grad, 0, sizeof(double) * NS); return -INFINITY; }
@@ -1755,10 +1754,6 @@ static void car_consts_dr(int R, int C, double r, double *dlogdet, double *ds11)
  */
 double orc_latent_r_logpost_grad(const orc_problem *p, const double *z, double *gz) {
     const int S1 = p->S - 1, R = p->R, C = p->C, N = R * C;
-    if (p->n_sub > 0) {   /* the gradient here: one ray per pixel */
-        if (gz) for (size_t i = 0; i < (size_t)S1 * N + S1; ++i) gz[i] = NAN;
-        return NAN;
-    }
     const double *x = z, *eta = z + (size_t)S1 * N;
     const size_t NS = (size_t)p->S * N;
     double r[16], sl[16], ld[16], dld[16], ds11[16];
@@ -1815,10 +1810,6 @@ double orc_latent_r_logpost_grad(const orc_problem *p, const double *z, double *
 
 double orc_latent_logpost_grad(const orc_problem *p, const double *x, double *gx) {
     const int S1 = p->S - 1, N = p->R * p->C, R = p->R, C = p->C;
-    if (p->n_sub > 0) {   /* the gradient here: one ray per pixel */
-        if (gx) for (size_t i = 0; i < (size_t)S1 * N; ++i) gx[i] = NAN;
-        return NAN;
-    }
     const size_t M = (size_t)S1 * N, NS = (size_t)p->S * N;
     double *H = malloc(sizeof(double) * M), *gH = calloc(NS, sizeof(double));
     double sl[16], ld[16];
@@ -1885,6 +1876,45 @@ double orc_log_intensity(const orc_problem *p, double O) {
 
 /* Poisson log-likelihood of the per-pixel counts; lam (optional) receives
    lambda_p of every pixel.  O: opacities of the sub-rays. */
+/* d log I / dO on the segment of the table that orc_log_intensity uses. */
+static double log_intensity_slope(const orc_problem *p, double O) {
+    const double dO = p->tab_omax / (p->n_tab - 1);
+    int j = (int)floor(O / dO);
+    if (j < 0) j = 0;
+    if (j > p->n_tab - 2) j = p->n_tab - 2;
+    return (p->tab_logI[j + 1] - p->tab_logI[j]) / dO;
+}
+
+/* Gradient of the solid-angle pixel likelihood (eq. expected_counts as a
+   quadrature): lambda_p = sum_q w_q I(O_q), so sub-ray q of pixel p carries
+   dLL/dO_q = (C_p / lambda_p - 1) w_q I(O_q) dlogI/dO(O_q), and its crossings
+   scatter that through the crossing form as a single ray does.  grad
+   [S][R][C] is added to; returns LL. */
+static double quad_loglik_grad_add(const orc_problem *p, const double *free_h, double *grad) {
+    const int nr = p->n_s * p->n_pix, npx = nr / p->n_sub;
+    if (nr == 0) return 0.0;
+    double *surf = stack_surfaces(p, free_h);
+    double *O = (double *)malloc(sizeof(double) * nr), *lam = (double *)malloc(sizeof(double) * npx);
+    const double ztop = top_max(p);
+    double L[16];
+    for (int ray = 0; ray < nr; ++ray) {
+        const int s = ray / p->n_pix;
+        O[ray] = march_ray(p, surf, p->pos + 3 * s, p->dirs + 3 * (size_t)ray, ztop, L, NULL, 0.0, NULL);
+    }
+    const double ll = orc_quad_loglik(p, O, lam);
+    for (int ray = 0; ray < nr; ++ray) {
+        const int s = ray / p->n_pix, px = ray / p->n_sub;
+        const double c = (double)p->counts[px];
+        const double g = (c / lam[px] - 1.0) * p->sub_w[ray] * exp(orc_log_intensity(p, O[ray])) *
+                         log_intensity_slope(p, O[ray]);
+        march_ray(p, surf, p->pos + 3 * s, p->dirs + 3 * (size_t)ray, ztop, L, grad, g, NULL);
+    }
+    free(surf);
+    free(O);
+    free(lam);
+    return ll;
+}
+
 double orc_quad_loglik(const orc_problem *p, const double *O, double *lam) {
     const int nr = p->n_s * p->n_pix, npx = nr / p->n_sub;
     double ll = 0.0;
