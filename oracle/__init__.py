@@ -69,6 +69,7 @@ def _load():
         "orc_logpost_batch": (None, [P, I, V, V]),
         "orc_grad": (D, [P, V, V]),
         "orc_grad_batch": (None, [P, I, V, V, V]),
+        "orc_max_threads": (I, []),
         "orc_ndtri_lower": (D, [D]),
         "orc_car_consts": (None, [I, I, D, V, V]),
         "orc_philox4x32_10": (None, [V, V, V]),
@@ -81,7 +82,7 @@ def _load():
         "orc_mcmc_mala": (None, [P, I, V, V, V, I64, U64, D, V, U64, I, V]),
         "orc_march_one": (D, [P, V, V, V, V, ct.POINTER(_Stats)]),
         "orc_ray_stats": (None, [P, V, V, V, V]),
-        "orc_grad_conditioning": (None, [P, V, D, D, D, D, V, D, V]),
+        "orc_grad_conditioning": (None, [P, V, D, D, D, D, V, D, V, V, V]),
         "orc_sigmoid": (D, [D, D]),
         "orc_voxel_weights": (None, [P, V, I, D, V]),
         "orc_voxel_density": (None, [P, V, I, D, V]),
@@ -281,16 +282,26 @@ class OracleProblem:
         self.lib.orc_ray_stats(ct.byref(self.prob), _p(self._free(free)), _p(cr), _p(mf), _p(ce))
         return dict(crossings=cr, min_fprime=mf, cells=ce)
 
-    def grad_conditioning(self, free, eps_z, eps_rel, eps_w=0.0, lid_band=0.0, dO=None, o_rel=1e-5):
+    def grad_conditioning(self, free, eps_z, eps_rel, eps_w=0.0, lid_band=0.0, dO=None, o_rel=1e-5, g=None,
+                          g_err=None):
         """Per-node bound [S, R, C] on how far an evaluation of the likelihood
         gradient that rounds z - h by eps_z, each contribution by eps_rel and
         each bilinear weight by eps_w, drops crossings within lid_band of the
         box lid, with opacity errors dO per ray (or the bound o_rel |O| + ...),
-        can move (see orc_grad_conditioning)."""
+        can move (see orc_grad_conditioning).  g, g_err [n_rays]: dL/dO of each
+        ray and its error, given in place of the one-ray model's."""
         out = np.empty((self.S, self.R, self.C))
         d = None if dO is None else _f64(dO)
+        if (g is None) != (g_err is None):
+            raise ValueError("g and g_err go together")
+        gr = None if g is None else _f64(g)
+        ge = None if g_err is None else _f64(g_err)
+        for a in (gr, ge):
+            if a is not None and a.size != self.n_rays:
+                raise ValueError("g and g_err take one value per ray")
         self.lib.orc_grad_conditioning(ct.byref(self.prob), _p(self._free(free)), float(eps_z), float(eps_rel),
-                                       float(eps_w), float(lid_band), _p(d), float(o_rel), _p(out))
+                                       float(eps_w), float(lid_band), _p(d), float(o_rel), _p(gr), _p(ge),
+                                       _p(out))
         return out
 
     def mcmc_rw(self, states, lp, n_accept, n_steps, step_offset, sigma, seed,
@@ -499,6 +510,11 @@ def normal_pair(seed, chain, step, tag, j) -> np.ndarray:
     out = np.empty(2)
     _load().orc_normal_pair(int(seed), int(chain), int(step), int(tag), int(j), _p(out))
     return out
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's batch calls use."""
+    return int(_load().orc_max_threads())
 
 
 def make_counts(sc, seed: int, mode: str = "poisson") -> np.ndarray:

@@ -33,6 +33,7 @@
  *    Its density in H-space is written out by change of variables.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -589,6 +590,9 @@ double orc_loglik_grad_add(const orc_problem *p, const double *free_h, double *g
     return ll;
 }
 
+/* OpenMP threads a batch call uses (for reporting host timings). */
+int orc_max_threads(void) { return omp_get_max_threads(); }
+
 void orc_grad_batch(const orc_problem *p, int n_chains, const double *free_all, double *lp, double *grad_all) {
     size_t M = (size_t)(p->S - 1) * p->R * p->C, NS = (size_t)p->S * p->R * p->C;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -884,9 +888,12 @@ double orc_march_one(const orc_problem *p, const double *free_h, const double q[
    lid_band of the box lid dropped), with dL/dO of each ray from its opacity and
    its error lambda |dO| / Lambda^2 from the opacity error dO of the ray:
    dO_ray[ray] when given, else o_rel |O| + rho_max n_cross eps_z / min|f'|
-   + 1e-6. */
+   + 1e-6.  With g_ray (and g_err) given, |g_ray[ray]| and g_err[ray] take the
+   place of that one-ray dL/dO and its error (the solid-angle pixel model,
+   whose dL/dO of a sub-ray also depends on the pixel's other sub-rays). */
 void orc_grad_conditioning(const orc_problem *p, const double *free_h, double eps_z, double eps_rel, double eps_w,
-                           double lid_band, const double *dO_ray, double o_rel, double *out) {
+                           double lid_band, const double *dO_ray, double o_rel, const double *g_ray,
+                           const double *g_err, double *out) {
     double *surf = stack_surfaces(p, free_h);
     double ztop = top_max(p), L[16], rho_max = 0.0;
     for (int l = 0; l < p->S; ++l) rho_max = fmax(rho_max, fabs(p->density[l]));
@@ -907,8 +914,8 @@ void orc_grad_conditioning(const orc_problem *p, const double *free_h, double ep
             memset(&st2, 0, sizeof(st2));
             st2.min_fprime = INFINITY;
             st2.gcond = out;
-            st2.cond_g = fabs(lam - (double)p->counts[ray]) / p->atten;
-            st2.cond_gerr = lam * dO / (p->atten * p->atten);
+            st2.cond_g = g_ray ? fabs(g_ray[ray]) : fabs(lam - (double)p->counts[ray]) / p->atten;
+            st2.cond_gerr = g_ray ? g_err[ray] : lam * dO / (p->atten * p->atten);
             st2.eps_z = eps_z;
             st2.eps_rel = eps_rel;
             st2.eps_w = eps_w;

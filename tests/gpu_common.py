@@ -50,7 +50,7 @@ def opacity_tolerance(O_ref, crossings, min_fprime, precision, rho_max=2.7, ztop
     return rel * np.abs(O_ref) + rho_max * crossings * eps_z / mf + (1e-6 if precision == "f32" else 1e-12)
 
 
-def f32_gradient_tolerance(orc, state, dO, g_prior):
+def f32_gradient_tolerance(orc, state, dO, g_prior, g=None, g_err=None):
     """Per-node tolerance of a float32 gradient: the oracle's conditioning
     report over every crossing (root shift eps_z/|f'| moving the bilinear
     weights and 1/|f'|; the weights' own rounding, 2^-22 (max(R, C) - 1) in
@@ -59,9 +59,27 @@ def f32_gradient_tolerance(orc, state, dO, g_prior):
     of the box lid, which the GPU takes for the lid's kink; 4e-6 relative
     rounding per contribution; the error of dLL/dO from the measured opacity
     error dO of each ray), plus the float32 prior workspace (1e-5 of the
-    prior gradient) and 1e-6 absolute."""
+    prior gradient) and 1e-6 absolute.  g, g_err: each ray's dLL/dO and its
+    error where the one-ray model's do not apply (solid-angle pixels)."""
     ztop = float(np.max(orc._top))
     eps_w = 2.0 ** -22 * (max(orc.R, orc.C) - 1)
     lid = 16.0 * float(np.spacing(np.float32(ztop)))
-    cond = orc.grad_conditioning(state, f32_eps_z(ztop), 4e-6, eps_w=eps_w, lid_band=lid, dO=dO)
+    cond = orc.grad_conditioning(state, f32_eps_z(ztop), 4e-6, eps_w=eps_w, lid_band=lid, dO=dO, g=g,
+                                 g_err=g_err)
     return cond + 1e-5 * np.abs(g_prior) + 1e-6
+
+
+def f64_gradient_tolerance(orc, state, dO, g_prior, g=None, g_err=None):
+    """Per-node tolerance of a float64 gradient: the same conditioning report
+    at float64 rounding (3 ulps of z - h at the box height, 2^-50 (max(R, C)
+    - 1) on the bilinear weights, 1e-13 relative per contribution, the
+    float64 lid band of 256 eps (|z_top| + |min top| + 1)), with the measured
+    float64 opacity error of each ray, plus 1e-10 of the prior gradient and
+    64 roundings of the 2^-32 fixed point in which the likelihood gradient
+    is summed (2^-33 each)."""
+    ztop = float(np.max(orc._top))
+    eps_z = 3.0 * float(np.spacing(ztop))
+    eps_w = 2.0 ** -50 * (max(orc.R, orc.C) - 1)
+    lid = 256.0 * 2.0 ** -52 * (abs(ztop) + abs(float(np.min(orc._top))) + 1.0)
+    cond = orc.grad_conditioning(state, eps_z, 1e-13, eps_w=eps_w, lid_band=lid, dO=dO, g=g, g_err=g_err)
+    return cond + 1e-10 * np.abs(g_prior) + 64 * 2.0 ** -33
