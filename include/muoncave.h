@@ -153,11 +153,14 @@ mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *re
  * log I tabulated at n_table uniform opacity nodes over [0, o_max] (linear
  * interpolation in log I; beyond o_max the last segment continues).  After
  * this call set_counts takes one count per pixel (n_rays / n_sub values) and
- * must be called again; logpost_batch and random-walk mcmc_run use the
- * quadrature, and the opacity output holds the sub-rays' opacities.  Gradient
- * paths, NUTS, mcmc_run_multi and the voxel model are refused while it is
- * set.  n_sub = 0 switches back to one ray per pixel (counts must be set
- * again); set_sensors and load_geometry_grid switch it off.
+ * must be called again; logpost_batch, logpost_grad_batch, mcmc_run (random
+ * walk and MALA) and nuts_run use the quadrature, and the opacity output
+ * holds the sub-rays' opacities.  The gradient gives each sub-ray
+ *   dLL/dO_q = (C_p / lambda_p - 1) weights[q] I(O_q) dlog I/dO(O_q)
+ * (the slope of O_q's table segment) and sums its crossings as for one ray
+ * per pixel.  mcmc_run_multi, the server and the voxel model are refused
+ * while it is set.  n_sub = 0 switches back to one ray per pixel (counts
+ * must be set again); set_sensors and load_geometry_grid switch it off.
  */
 mc_status set_pixel_quadrature(mc_problem *p, int n_sub, const double *weights, int n_table, double o_max,
                                const double *log_intensity);
@@ -209,7 +212,7 @@ mc_status logpost_batch_noalloc(mc_problem *p, int n_chains, const void *heights
  * the node contributions from those records; chains whose record slots
  * overflow (see mc_tuning.grad_slots) are re-walked instead, with the same
  * result bit for bit.  Under set_voxel_model the gradient is the voxel
- * model's (see there).
+ * model's, under set_pixel_quadrature the solid-angle pixels' (see there).
  */
 mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, double *logpost,
                              void *grad, void *stream);
@@ -339,9 +342,8 @@ typedef struct {
  *   accept_stat (f64, mean of min(1, w) over the leaves computed).
  * Device memory: about (6 + 5 (max_depth + 1)) * 8 + 9 * sizeof(state)
  * bytes per chain and free node, plus the gradient workspaces.  Errors:
- * MC_ERR_ARG for invalid sizes or pointers, MC_ERR_UNSUPPORTED while pixel
- * quadrature is set.  Under set_voxel_model NUTS runs on the voxel model's
- * gradient.
+ * MC_ERR_ARG for invalid sizes or pointers.  Under set_voxel_model or
+ * set_pixel_quadrature NUTS runs on that model's gradient.
  * Hierarchical r (Sec. 2.2.1, r_l ~ Uniform(0, 1); Sec. 3.1, the sampler's
  * vector holds all unknowns): with cfg->r_state and latent = 1 each chain's
  * state is z = (x, eta), eta_l = logit r_l, of log density

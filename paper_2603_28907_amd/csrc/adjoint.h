@@ -149,11 +149,11 @@ __device__ __forceinline__ void walk_surface_adjoint(const MarchParams<T> &P, co
 }
 
 // One block = one chain x one tile of rays (XCD-aware 1-D grid, as the
-// forward march); g_p from the forward opacities.
+// forward march); g_p from the forward opacities, or given (gpbuf).
 // gfix: [n_chains][S][R*C] fixed-point accumulators (zeroed beforehand).
 template <typename T, int S, bool TOP_LDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T> K, const T *opacity,
-                                                   unsigned long long *gfix) {
+                                                   unsigned long long *gfix, const T *gpbuf) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sh = reinterpret_cast<T *>(smem_raw);
     __shared__ T band[2 * kMaxSurfaces];
@@ -211,9 +211,13 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T
     const int r1 = min(r0 + P.rays_per_block, P.n_ray);
     for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
         const int s = ray / P.n_pix;
-        const double Od = (double)opacity[(size_t)chain * P.n_ray + ray];
-        const double lam = P.expo[ray] * exp(-Od * P.inv_L);
-        const double gp = lam * P.inv_L - P.c_over_L[ray];   // dLL/dO = (lambda - C)/Lambda
+        double gp;
+        if (gpbuf) {   // dLL/dO given (solid-angle pixels)
+            gp = (double)gpbuf[(size_t)chain * P.n_ray + ray];
+        } else {
+            const double Od = (double)opacity[(size_t)chain * P.n_ray + ray];
+            gp = P.expo[ray] * exp(-Od * P.inv_L) * P.inv_L - P.c_over_L[ray];   // dLL/dO = (lambda - C)/Lambda
+        }
         const T qx = P.sensor[3 * s], qy = P.sensor[3 * s + 1], qz = P.sensor[3 * s + 2];
         const T dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
         const T idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
@@ -449,25 +453,38 @@ __global__ void k_fill_u64(unsigned long long *p, size_t n) {
     if (i < n) p[i] = 0ull;
 }
 
-// Log prior and its gradient per chain (one block per chain), plus the
-// fixed-order sum of the likelihood partials.  gprior: [n][S][N] float64.
+// Log posterior and its gradient per chain (one block per chain): the log
+// prior with its gradient, the fixed-order sum of the likelihood partials,
+// and the likelihood gradient gfix ([n][S][N] in 2^-32 fixed point, or null
+// without sensors) added in.  grad: [n][S][N], every entry written; rows of
+// chains whose log posterior is -inf are zero.
+//
+// Node n of layer l gets its own prior term's derivative, then (one layer
+// later) the derivative of layer l+1's term through that layer's lower
+// bound; the top node gets every layer's term.  Each thread owns the same
+// nodes in every layer and accumulates in grad itself, in a fixed order.
 template <typename T, int S, int BLOCK>
-__global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, double *gprior) {
+__global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, const unsigned long long *gfix,
+                                                         T *grad) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *w = reinterpret_cast<double *>(smem_raw);   // [N]
     __shared__ double red[16];
     __shared__ int ired[16];
+    __shared__ int zero_rows;
     const int c = blockIdx.x, tid = threadIdx.x;
     const int R = P.R, C = P.C, N = R * C;
     const T *H = P.heights + (size_t)c * (S - 1) * N;
-    double *gp = gprior + (size_t)c * S * N;
-    for (int i = tid; i < S * N; i += BLOCK) gp[i] = 0.0;
-    __syncthreads();
+    T *g = grad + (size_t)c * S * N;
+    const unsigned long long *gf = gfix ? gfix + (size_t)c * S * N : nullptr;
+    auto lik = [&](int k) -> double { return gf ? (double)(long long)gf[k] * kGradFixInv : 0.0; };
     double lp = 0.0;
     int ok = 1;
-#pragma unroll
+    // loops kept rolled: the Phi^-1 call is out of line, and an unrolled body
+    // keeps more values live across it (spilled around every call)
+#pragma unroll 1
     for (int l = 0; l < S - 1; ++l) {
         double sw2 = 0.0, sld = 0.0;
+#pragma unroll 1
         for (int n = tid; n < N; n += BLOCK) {
             const double h = (double)H[l * N + n];
             const double a = l ? (double)H[(l - 1) * N + n] : 0.0;
@@ -484,26 +501,30 @@ __global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, doubl
         __syncthreads();
         double se = 0.0;
         const double r = P.r[l], s11 = P.s11[l];
+#pragma unroll 1
         for (int n = tid; n < N; n += BLOCK) {
             const int i = n / C, j = n - i * C;
             const double wi = w[n];
             const double wr = w[i * C + (j + 1 == C ? 0 : j + 1)], wl = w[i * C + (j == 0 ? C - 1 : j - 1)];
             const double wd = w[(i + 1 == R ? 0 : i + 1) * C + j], wu = w[(i == 0 ? R - 1 : i - 1) * C + j];
             se += (wi - wr) * (wi - wr) + (wi - wd) * (wi - wd);
-            // gradient of this layer's term (this thread owns node n in every layer)
             const double h = (double)H[l * N + n];
             const double a = l ? (double)H[(l - 1) * N + n] : 0.0;
             const double b = P.top64[n];
-            const double d = b - a;
-            const double u = (h - a) / d, v = (b - h) / d;
+            const double d = b - a, id = 1.0 / d;
+            const double u = (h - a) * id, v = (b - h) * id;
+            double own = 0.0, below = 0.0, top = 0.0;
             if ((d > 0.0) && (u > 0.0) && (v > 0.0)) {
                 const double G = -s11 * (4.0 * (1.0 - r) * wi + r * (4.0 * wi - (wr + wl + wd + wu))) + wi;
                 const double phi = exp(-0.5 * wi * wi) * 0.39894228040143267793994605993438;
-                const double gu = G / phi;
-                gp[l * N + n] += gu / d;
-                if (l) gp[(l - 1) * N + n] += -gu * v / d + 1.0 / d;
-                gp[(S - 1) * N + n] += -gu * u / d - 1.0 / d;
+                own = G / phi * id;   // dlp/du / d
+                below = id - own * v;
+                top = -own * u - id;
             }
+            g[l * N + n] = (T)(lik(l * N + n) + own);
+            if (l) g[(l - 1) * N + n] = (T)((double)g[(l - 1) * N + n] + below);
+            const int kt = (S - 1) * N + n;
+            g[kt] = (T)((l ? (double)g[kt] : lik(kt)) + top);
         }
         const double SW2 = block_sum<BLOCK>(sw2, red);
         const double SLD = block_sum<BLOCK>(sld, red);
@@ -518,20 +539,13 @@ __global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, doubl
             for (int t = 0; t < P.n_tiles; ++t) ll += pp[t];
             ll += P.kconst;
         }
-        P.lp_out[c] = ok ? lp + ll : -__builtin_huge_val();
+        const double v = ok ? lp + ll : -__builtin_huge_val();
+        P.lp_out[c] = v;
+        zero_rows = v == -__builtin_huge_val();
     }
-}
-
-// grad = likelihood (fixed point) + prior; zero rows where lp = -inf.
-template <typename T>
-__global__ void k_grad_combine(const unsigned long long *gfix, const double *gprior, const double *lp, T *grad,
-                               int SN, int n) {
-    const int c = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= SN || c >= n) return;
-    const size_t k = (size_t)c * SN + i;
-    const double v = (double)(long long)gfix[k] * kGradFixInv + gprior[k];
-    grad[k] = (lp[c] == -__builtin_huge_val()) ? T(0) : (T)v;
+    __syncthreads();
+    if (zero_rows)
+        for (int k = tid; k < S * N; k += BLOCK) g[k] = T(0);
 }
 
 // MALA proposal: prop = H + (eps^2/2) m g + eps sqrt(m) z, z from tag 2.

@@ -125,7 +125,7 @@ struct mc_problem {
     // workspaces (grow only)
     DevBuf partials, prop, lptmp;
     DevBuf rstat;   // [2][n][S-1] sum w^2 and edge sums of the current states (r sampling)
-    DevBuf obuf, gfix, gprior, gcur, gprop, lpprop;   // gradient and MALA workspaces
+    DevBuf obuf, gfix, gcur, gprop, lpprop;   // gradient and MALA workspaces
     DevBuf xrec, xcnt, xovf, xgp;   // crossing records of the float32 gradient march
     uint64_t *d_step = nullptr;
     mc_tuning tune = {3, 256, 4, 1, 0, 0, 0};
@@ -626,18 +626,19 @@ mc_status logpost_noalloc_dispatch(mc_problem *p, int n, const void *heights, do
 }
 
 template <typename T, int S, int B>
-void launch_prior_grad(int n, size_t lds, const PriorParams<T> &P, double *gprior, hipStream_t st) {
+void launch_prior_grad(int n, size_t lds, const PriorParams<T> &P, const unsigned long long *gfix, T *grad,
+                       hipStream_t st) {
     auto k = k_prior_grad<T, S, B>;
     if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(n), dim3(B), lds, st, P, gprior);
+    hipLaunchKernelGGL(k, dim3(n), dim3(B), lds, st, P, gfix, grad);
 }
 
 template <typename T, int S, bool TL, int B>
 void launch_adjoint_shape(dim3 grid, size_t lds, const MarchParams<T> &M, const RayConsts<T> &K, const T *obuf,
-                          unsigned long long *gfix, hipStream_t st) {
+                          unsigned long long *gfix, const T *gpbuf, hipStream_t st) {
     auto k = k_adjoint<T, S, TL, B>;
     if (lds > 65536) (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, K, obuf, gfix);
+    hipLaunchKernelGGL(k, grid, dim3(B), lds, st, M, K, obuf, gfix, gpbuf);
 }
 
 template <int S, int B>
@@ -689,8 +690,8 @@ void launch_march_rec_shape(dim3 grid, size_t lds, hipStream_t st, const MarchPa
 // crossing records and dLL/dO of every ray (the partials feed the prior
 // kernel as usual).  Clears the overflow flags first.
 template <int S>
-mc_status launch_march_rec(mc_problem *p, int n, const float *heights, hipStream_t st) {
-    MarchParams<float> P = march_params<float>(p, heights, nullptr, (double *)p->partials.p);
+mc_status launch_march_rec(mc_problem *p, int n, const float *heights, hipStream_t st, float *opacity = nullptr) {
+    MarchParams<float> P = march_params<float>(p, heights, opacity, (double *)p->partials.p);
     P.n_chains = n;
     const CrossRecs X = cross_recs(p);
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X.ovf, n);
@@ -772,13 +773,14 @@ mc_status launch_adjoint(mc_problem *p, int n, const T *heights, unsigned long l
         if (lds + 2048 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
         const dim3 grid((unsigned)M.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
         const T *ob = (const T *)p->obuf.p;
+        const T *gpb = p->quad_nsub > 0 ? (const T *)p->xgp.p : nullptr;   // dLL/dO of the sub-rays
         const bool big = lds > 65536;
         if (tl) {
-            if (big) launch_adjoint_shape<T, S, true, 1024>(grid, lds, M, K, ob, gfix, st);
-            else launch_adjoint_shape<T, S, true, 256>(grid, lds, M, K, ob, gfix, st);
+            if (big) launch_adjoint_shape<T, S, true, 1024>(grid, lds, M, K, ob, gfix, gpb, st);
+            else launch_adjoint_shape<T, S, true, 256>(grid, lds, M, K, ob, gfix, gpb, st);
         } else {
-            if (big) launch_adjoint_shape<T, S, false, 1024>(grid, lds, M, K, ob, gfix, st);
-            else launch_adjoint_shape<T, S, false, 256>(grid, lds, M, K, ob, gfix, st);
+            if (big) launch_adjoint_shape<T, S, false, 1024>(grid, lds, M, K, ob, gfix, gpb, st);
+            else launch_adjoint_shape<T, S, false, 256>(grid, lds, M, K, ob, gfix, gpb, st);
         }
         HIP_TRY(p, hipGetLastError());
         return MC_OK;
@@ -810,40 +812,40 @@ mc_status lik_grad(mc_problem *p, int n, const T *heights, unsigned long long *g
         HIP_TRY(p, hipGetLastError());
         return MC_OK;
     }
+    const bool quad = p->quad_nsub > 0;
     if constexpr (std::is_same<T, float>::value) {
-        if ((s = launch_march_rec<S>(p, n, heights, st)) != MC_OK) return s;
+        if ((s = launch_march_rec<S>(p, n, heights, st, quad ? (float *)p->obuf.p : nullptr)) != MC_OK) return s;
     } else {
         const size_t tot = (size_t)S * p->R * p->C * n;
         hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
         HIP_TRY(p, hipGetLastError());
         if ((s = launch_march<T, S>(p, n, heights, (T *)p->obuf.p, (double *)p->partials.p, st)) != MC_OK) return s;
     }
+    if (quad) {
+        // solid-angle pixels: the pixel likelihood from the sub-ray opacities, and
+        // each sub-ray's dLL/dO in place of the march's one-ray value
+        const int tiles = lik_tiles(p);
+        hipLaunchKernelGGL(k_quad_lik<T>, dim3(tiles, n), dim3(256), 0, st, (const T *)p->obuf.p, p->n_ray,
+                           p->quad_npx, p->quad_nsub, (const double *)p->d_quad_w, (const double *)p->d_quad_tab,
+                           p->quad_ntab, (p->quad_ntab - 1) / p->quad_omax, (const double *)p->d_quad_cnt,
+                           (double *)p->partials.p, tiles, (const double *)nullptr, (T *)p->xgp.p);
+        HIP_TRY(p, hipGetLastError());
+    }
     return launch_adjoint<T, S>(p, n, heights, gfix, st);
 }
 
 template <typename T, int S>
 mc_status grad_eval(mc_problem *p, int n, const T *heights, double *lp, T *grad, hipStream_t st) {
-    const size_t N = (size_t)p->R * p->C, SN = (size_t)S * N;
+    const size_t N = (size_t)p->R * p->C;
     unsigned long long *gfix = (unsigned long long *)p->gfix.p;
-    double *gprior = (double *)p->gprior.p;
     mc_status s;
     if (p->n_ray > 0 && (s = lik_grad<T, S>(p, n, heights, gfix, st)) != MC_OK) return s;
     PriorParams<T> P = prior_params<T>(p, heights, (const double *)p->partials.p);
     P.lp_out = lp;
-    {
-        size_t lds = sizeof(double) * N;
-        if (N >= (size_t)kPriorLargeNodes) launch_prior_grad<T, S, kPriorBlockLarge>(n, lds, P, gprior, st);
-        else launch_prior_grad<T, S, kPriorBlock>(n, lds, P, gprior, st);
-        HIP_TRY(p, hipGetLastError());
-    }
-    if (p->n_ray == 0) {
-        const size_t tot = SN * n;
-        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
-        HIP_TRY(p, hipGetLastError());
-    }
-    dim3 cg((unsigned)((SN + 255) / 256), n);
-    hipLaunchKernelGGL(k_grad_combine<T>, cg, dim3(256), 0, st, (const unsigned long long *)gfix,
-                       (const double *)gprior, (const double *)lp, grad, (int)SN, n);
+    const unsigned long long *gl = p->n_ray > 0 ? gfix : nullptr;
+    const size_t lds = sizeof(double) * N;
+    if (N >= (size_t)kPriorLargeNodes) launch_prior_grad<T, S, kPriorBlockLarge>(n, lds, P, gl, grad, st);
+    else launch_prior_grad<T, S, kPriorBlock>(n, lds, P, gl, grad, st);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
 }
@@ -854,7 +856,11 @@ mc_status ensure_grad_ws(mc_problem *p, int n) {
     mc_status s;
     Tiling t = tiling(p);
     if (p->n_ray > 0) {
-        if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * t.n_tiles)) != MC_OK) return s;
+        if ((s = ensure(p, p->partials, sizeof(double) * (size_t)n * partial_slots(p))) != MC_OK) return s;
+        if (p->quad_nsub > 0) {   // sub-ray opacities and dLL/dO (also in float64)
+            if ((s = ensure(p, p->obuf, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK) return s;
+            if ((s = ensure(p, p->xgp, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK) return s;
+        }
         if (p->vox_nz > 0) {
             if ((s = ensure(p, p->rhat, rhat_bytes(p, n))) != MC_OK) return s;
             if ((s = ensure(p, p->valpha, sizeof(T) * (size_t)vox_n_pad(n) * p->n_ray)) != MC_OK) return s;
@@ -868,8 +874,7 @@ mc_status ensure_grad_ws(mc_problem *p, int n) {
             if ((s = ensure(p, p->obuf, sizeof(T) * (size_t)n * p->n_ray)) != MC_OK) return s;
         }
     }
-    if ((s = ensure(p, p->gfix, sizeof(unsigned long long) * SN * n)) != MC_OK) return s;
-    if ((s = ensure(p, p->gprior, sizeof(double) * SN * n)) != MC_OK) return s;
+    if (p->n_ray > 0 && (s = ensure(p, p->gfix, sizeof(unsigned long long) * SN * n)) != MC_OK) return s;
     return MC_OK;
 }
 
@@ -1601,7 +1606,7 @@ void mc_destroy(mc_problem *p) {
     clear_voxel_model(p);
     for (double **q : {&p->d_quad_w, &p->d_quad_tab, &p->d_quad_cnt}) free_ptr(*q);
     for (int k = 0; k < 6; ++k) free_ptr(p->d_rc[k]);
-    for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gprior, &p->gcur, &p->gprop,
+    for (DevBuf *b : {&p->partials, &p->prop, &p->lptmp, &p->obuf, &p->gfix, &p->gcur, &p->gprop,
                       &p->lpprop, &p->rstat, &p->rhat, &p->nutsbuf, &p->xrec, &p->xcnt, &p->xovf, &p->xgp,
                       &p->valpha})
         if (b->p) (void)hipFree(b->p);
@@ -1862,7 +1867,6 @@ mc_status logpost_grad_batch(mc_problem *p, int n_chains, const void *heights, d
     if (n_chains == 0) return MC_OK;
     if (!heights || !logpost || !grad) return fail(p, MC_ERR_ARG, "NULL device pointer");
     if (n_chains > 65535) return fail(p, MC_ERR_ARG, "n_chains > 65535");
-    if (p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "gradients take one ray per pixel; pixel quadrature is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64 ? logpost_grad_dispatch<double>(p, n_chains, heights, logpost, grad, st)
@@ -1881,7 +1885,6 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
     if (!(cfg->step_size >= 0) || !std::isfinite(cfg->step_size)) return fail(p, MC_ERR_ARG, "step_size invalid");
     if (cfg->kernel != 0 && cfg->kernel != 1) return fail(p, MC_ERR_ARG, "kernel %d", cfg->kernel);
     if (cfg->r_state && cfg->kernel != 0) return fail(p, MC_ERR_UNSUPPORTED, "r sampling runs with random-walk Metropolis");
-    if (cfg->kernel == 1 && p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "MALA takes one ray per pixel; pixel quadrature is set");
     if (cfg->r_state && (!(cfg->r_step >= 0) || !std::isfinite(cfg->r_step))) return fail(p, MC_ERR_ARG, "r_step invalid");
     if (cfg->n_accept_r && !cfg->r_state) return fail(p, MC_ERR_ARG, "n_accept_r without r_state");
     if (cfg->step_offset + (uint64_t)cfg->n_steps >= (1ULL << 48)) return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
@@ -2224,7 +2227,6 @@ mc_status nuts_run(mc_problem *p, const mc_nuts_config *cfg, int n_chains, void 
         return fail(p, MC_ERR_ARG, "r_state is sampled on the latent parametrisation (latent = 1)");
     if (cfg->step_offset + (uint64_t)(cfg->n_warmup + cfg->n_steps) >= (1ULL << 48))
         return fail(p, MC_ERR_ARG, "step counter exceeds 48 bits");
-    if (p->quad_nsub > 0) return fail(p, MC_ERR_UNSUPPORTED, "NUTS takes one ray per pixel; pixel quadrature is set");
     DeviceGuard g(p->device);
     hipStream_t st = (hipStream_t)stream;
     return p->prec == MC_F64

@@ -154,18 +154,9 @@ def test_nuts_errors(torch_mod, tiny):
         prob.nuts_run(H, lp, e, 1, 1, target_accept=1.5)
     with pytest.raises(MuonCaveError, match="inv_mass"):
         prob.nuts_run(H, lp, e, 1, 1, n_warmup=5, adapt_mass=True)
-    prob.set_pixel_quadrature(*_one_subray_quadrature(tiny))
-    prob.set_counts(tiny.counts)   # one sub-ray per pixel: the same counts
-    with pytest.raises(MuonCaveError, match="quadrature"):
-        prob.nuts_run(H, lp, e, 1, 1)
-
-
-def _one_subray_quadrature(sc):
-    """Pixel quadrature with one sub-ray per pixel (n_sub, weights, log
-    intensity table, o_max): enough to switch the gradient paths off."""
-    w = np.asarray(sc.exposure, np.float64).reshape(-1)
-    tab = -np.linspace(0.0, 2000.0, 64) / sc.atten_len
-    return 1, w, tab, 2000.0
+    r = to_dev(np.full((n, 2), 0.5), torch.float64)
+    with pytest.raises(MuonCaveError, match="latent"):
+        prob.nuts_run(H, lp, e, 1, 1, r_state=r)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
