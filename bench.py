@@ -60,19 +60,47 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # (FETCH_SIZE reads 131089 KiB for 262144 KiB moved: scale 2.0; WRITE_SIZE
 # reads exactly: scale 1.0).  Valid only for the kernel sources they were
 # taken on: the entry is dropped when the hash of those sources changes.
-# At 6 wavefronts per SIMD the march spills ~40 bytes per lane to scratch
-# once per wavefront; the dirty scratch lines written back at the end of the
-# kernel are most of WRITE_SIZE (about 1.7 bytes per ray).
+# At 6 wavefronts per SIMD the march spills 32 bytes per lane to scratch
+# (around the ray loop, not inside the walk); the dirty scratch lines written
+# back are most of WRITE_SIZE.
 KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march_common.h", "march3.h", "march5.h"),
                   "voxel64": ("device_common.h", "voxel.h")}
 MEASURED_TRAFFIC = {
-    "grf_cave_64": dict(source_sha="9b722cd35d001b36", fetch_kib=30673.8, fetch_scale=262144 / 131093.4,
-                        write_kib=56985.9, write_scale=1.0),
+    "grf_cave_64": dict(source_sha="cf13820ebd89508f", fetch_kib=30713.0, fetch_scale=262144 / 131093.2,
+                        write_kib=56968.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
     "voxel64": dict(source_sha="344071297b08c061", fetch_kib=2449389.3, fetch_scale=262144 / 131092.25,
                     write_kib=70379.2, write_scale=1.0),
 }
+
+
+# Executed-instruction counters of one 1024-chain march launch (rocprofv3
+# --pmc SQ_WAVES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU
+# SQ_BUSY_CU_CYCLES SQ_INSTS_SALU GRBM_GUI_ACTIVE GRBM_COUNT with the kernel
+# trace, same run; same source hash rule as the traffic).  GRBM_GUI_ACTIVE is
+# summed over the 8 XCDs.  The FMA probe of the same run reads exactly its
+# known instruction count (32768 waves x 2^16 x 8 = 1.718e10) at 0.967
+# instructions per CU-clock, the full-lane issue limit.
+MEASURED_VALU = {
+    "grf_cave_64": dict(source_sha="cf13820ebd89508f", valu_insts=1.086e9, thread_cycles_valu=3.303e10,
+                        active_inst_valu=1.107e9, grbm_gui_active_per_xcd=2.876e6, cus=256),
+}
+
+
+def measured_valu(name, rays_per_launch):
+    """Issue rate and executed active-lane operations of the march launch
+    from the stored counters (None when the kernel sources changed)."""
+    m = MEASURED_VALU.get(name)
+    if m is None or m["source_sha"] != kernel_source_sha(name):
+        return None
+    clocks = m["grbm_gui_active_per_xcd"]
+    lane_ops = m["thread_cycles_valu"]   # active lanes summed over the VALU instructions
+    return {"valu_insts_per_cu_clock": m["valu_insts"] / (m["cus"] * clocks),
+            "lane_utilisation": m["thread_cycles_valu"] / (64.0 * m["active_inst_valu"]),
+            "executed_lane_ops_per_ray": lane_ops / rays_per_launch,
+            "executed_lane_ops_frac": lane_ops / (m["cus"] * 64.0 * clocks),
+            "source_sha": m["source_sha"]}
 
 
 def kernel_source_sha(name):
@@ -106,6 +134,14 @@ def ops_per_ray(name):
     return OPS_RAY + c["cells"] * (OPS_CELL_BASE + c["S"] * OPS_TEST) + c["crossings"] * OPS_CROSS
 
 
+def survey_ops_per_ray(name):
+    """The plainer count cells x (10 S + 6): a cell step and one bound test
+    per surface, nothing for the crossings' root solves or the float64
+    Poisson term."""
+    c = WORKLOAD_COUNTS[name]
+    return c["cells"] * (10.0 * c["S"] + 6.0)
+
+
 def adjoint_ops_per_ray(name):
     c = WORKLOAD_COUNTS[name]
     return OPS_RAY + c["cells"] * (OPS_CELL_BASE + c["S"] * OPS_TEST) + c["crossings"] * OPS_CROSS_ADJ
@@ -132,26 +168,72 @@ def gpu_counts(sc, torch):
     return inputs.draw_counts(lam, 11).reshape(sc.n_sensors, sc.n_pix)
 
 
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it) or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(name, budget_s=10.0):
-    """FP64 oracle (plain C, OpenMP over chains) on a bounded sample of the
-    same workload: batches of chains, one log-posterior evaluation each."""
+    """FP64 oracle (plain C, OpenMP over chains) on bounded samples: the
+    headline workload (batches of chains, one log-posterior evaluation each,
+    about budget_s), the tiny cave in full (4 chains x 1000 random-walk
+    steps) and the 128x128 gradient (batches of chains, one log posterior and
+    gradient each, about budget_s / 2).  Counts come from the oracle's own
+    forward model (the GPU legs draw theirs from the library's); the timing
+    does not depend on their values."""
     import oracle
     from paper_2603_28907_amd import inputs
+    threads = oracle.max_threads()
     sc, n_chains, w = make_workload(name)
     sc.counts = oracle.make_counts(sc, seed=w["counts_seed"])
     orc = oracle.OracleProblem(sc)
     states = inputs.init_states(sc, 256, seed=w["init_seed"])
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
     done, t0 = 0, time.perf_counter()
-    batch = max(cores, 8)
+    batch = max(threads, 8)
     while done < states.shape[0] and time.perf_counter() - t0 < budget_s:
         orc.logpost_batch(states[done:done + batch])
         done += batch
     dt = time.perf_counter() - t0
-    return {"value": done * sc.n_rays / dt, "unit": "ray-evals/s", "cores": cores, "kind": "oracle",
-            "logpost_evals_per_s": done / dt,
-            "sample": f"{done} chains x 1 log-posterior evaluation ({sc.n_rays} rays each) of the "
-                      f"{name} workload, FP64"}
+    out = {"value": done * sc.n_rays / dt, "unit": "ray-evals/s", "cores": threads, "kind": "oracle",
+           "logpost_evals_per_s": done / dt,
+           "sample": f"{done} chains x 1 log-posterior evaluation ({sc.n_rays} rays each) of the "
+                     f"{name} workload, FP64, {threads} OpenMP threads",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    # the tiny cave in full
+    tiny = inputs.tiny_bumps(seed=0)
+    tiny.counts = oracle.make_counts(tiny, seed=1)
+    ot = oracle.OracleProblem(tiny)
+    st0 = inputs.init_states(tiny, 4, seed=2)
+    t0 = time.perf_counter()
+    _, _, acc, _ = ot.mcmc_rw(st0, np.full(4, np.nan), np.zeros(4, np.int64), 1000, 0, 0.05, 3)
+    dt = time.perf_counter() - t0
+    out["tiny_full"] = {"seconds": dt, "ray_evals_per_s": 4 * 1000 * tiny.n_rays / dt,
+                        "logpost_evals_per_s": 4000 / dt, "accept_rate": float(acc.sum()) / 4000,
+                        "threads": min(threads, 4),
+                        "sample": f"tiny cave ({tiny.n_rays} rays, 16x16 nodes), 4 chains x 1000 random-walk "
+                                  f"steps (sigma 0.05 m), FP64: the whole run"}
+    # the 128x128 gradient
+    sg = inputs.grf_cave(seed=10, n_grid=128)
+    sg.counts = oracle.make_counts(sg, seed=11)
+    og = oracle.OracleProblem(sg)
+    sgs = inputs.init_states(sg, 64, seed=12)
+    done, t0 = 0, time.perf_counter()
+    while done < sgs.shape[0] and time.perf_counter() - t0 < budget_s / 2:
+        og.grad_batch(sgs[done:done + threads])
+        done += threads
+    dt = time.perf_counter() - t0
+    out["grad128"] = {"gradient_evals_per_s": done / dt, "ray_evals_per_s": done * sg.n_rays / dt,
+                      "threads": threads,
+                      "sample": f"{done} chains x 1 log posterior + gradient of the 128x128 geometry "
+                                f"({sg.n_rays} rays), FP64"}
+    return out
 
 
 def build_hetero(n_problems, torch, precision="f32"):
@@ -215,14 +297,32 @@ def bench_hetero(args, torch):
     dt_plain_tuned = time.perf_counter() - t0
     off += k_plain
     G = max(1, min(args.graph_steps, args.steps))
-    mcmc_run_multi(probs, H, lp, acc, args.warmup, sigma, seeds, step_offsets=[off] * n_prob,
-                   graph_steps=min(G, max(args.warmup, 1)))
-    torch.cuda.synchronize()
-    off += args.warmup
-    t0 = time.perf_counter()
-    mcmc_run_multi(probs, H, lp, acc, args.steps, sigma, seeds, step_offsets=[off] * n_prob, graph_steps=G)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+
+    def batched(blocks_per_cu):
+        """Warm-up and timed steps of the batched form: one launch per grid
+        class per step (blocks_per_cu = 0), or the persistent grid of
+        blocks_per_cu blocks per CU over each class's work table."""
+        nonlocal off
+        t = probs[0].get_tuning()
+        t["multi_blocks_per_cu"] = blocks_per_cu
+        probs[0].set_tuning(**t)
+        mcmc_run_multi(probs, H, lp, acc, args.warmup, sigma, seeds, step_offsets=[off] * n_prob,
+                       graph_steps=min(G, max(args.warmup, 1)))
+        torch.cuda.synchronize()
+        off += args.warmup
+        t0 = time.perf_counter()
+        mcmc_run_multi(probs, H, lp, acc, args.steps, sigma, seeds, step_offsets=[off] * n_prob, graph_steps=G)
+        torch.cuda.synchronize()
+        off += args.steps
+        return time.perf_counter() - t0
+
+    forms = {}
+    for k in (0, 1, 2):
+        forms[k] = batched(k)
+        print(f"[bench] batched, blocks per CU {k}: {forms[k] / args.steps * 1e3:.2f} ms/step", file=sys.stderr,
+              flush=True)
+    best = min(forms, key=forms.get)
+    dt = forms[best]
     print("[bench] timed region done", file=sys.stderr, flush=True)
     for x in lp:
         assert torch.isfinite(x).all(), "non-finite log posterior"
@@ -245,6 +345,9 @@ def bench_hetero(args, torch):
                         "ms_per_step": dt_plain_tuned / k_plain * 1e3, "steps": k_plain,
                         "kind": "per-problem mcmc_run, graph_steps=1, autotuned launch shapes"},
         "speedup_vs_plain": value / plain_value,
+        "batched_form": "one launch per grid class" if best == 0 else f"persistent grid, {best} blocks per CU",
+        "batched_forms_ms_per_step": {("per_class" if k == 0 else f"persistent_{k}_per_cu"): v / args.steps * 1e3
+                                      for k, v in forms.items()},
         "autotune": {"seconds": dt_tune, "classes": {k: {f: v[f] for f in ("block", "rays_per_thread")}
                                                      for k, v in tuned.items()}},
     }
@@ -573,7 +676,15 @@ def bench_serve(args, torch):
     and by the plain one-job-at-a-time loop (max_jobs = 1)."""
     from paper_2603_28907_amd import inputs
     from paper_2603_28907_amd.binding import JOB_DONE, Server
-    arrivals = inputs.poisson_arrivals(args.rate, args.duration, seed=40)
+    if getattr(args, "n_jobs", 0) > 0:   # the first n_jobs arrivals of the stream
+        horizon = 2.0 * args.n_jobs / args.rate + 10.0
+        arrivals = inputs.poisson_arrivals(args.rate, horizon, seed=40)
+        while len(arrivals) < args.n_jobs:
+            horizon *= 2.0
+            arrivals = inputs.poisson_arrivals(args.rate, horizon, seed=40)
+        arrivals = arrivals[:args.n_jobs]
+    else:
+        arrivals = inputs.poisson_arrivals(args.rate, args.duration, seed=40)
     n_jobs = len(arrivals)
     t0 = time.perf_counter()
     jobs = []
@@ -627,12 +738,13 @@ def bench_serve(args, torch):
         "metric": METRIC, "value": batched["ray_evals_per_s"], "unit": "ray-evals/s", "n_gpus": 1,
         "steps": args.job_steps, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"serve: Poisson arrivals at {args.rate} jobs/s for {args.duration} s "
-                               f"({n_jobs} jobs, seed 40), job sizes as the hetero workload, "
+        "config": {"workload": f"serve: Poisson arrivals at {args.rate} jobs/s, the first {n_jobs} jobs "
+                               f"(seed 40, {arrivals[-1]:.1f} s of arrivals), job sizes as the hetero workload, "
                                f"{args.job_steps} steps per chain, rounds of {args.graph_steps} steps, "
                                f"up to {args.max_jobs} resident jobs",
                    "jobs": n_jobs, "rate_per_s": args.rate},
         "p50_s": batched["p50_s"], "p99_s": batched["p99_s"],
+        "queue_p99_s": batched["queue_p99_s"], "service_p99_s": batched["service_p99_s"],
         "logpost_evals_per_s": batched["logpost_evals_per_s"],
         "offered_load": offered,
         "batched": batched, "plain": plain,
@@ -652,6 +764,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=5, help="steps of the plain per-problem sampler")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="serve: seconds of arrivals")
+    ap.add_argument("--n-jobs", type=int, default=0,
+                    help="serve: take the first n arrivals of the stream instead of --duration seconds")
     ap.add_argument("--job-steps", type=int, default=2000, help="serve: steps per chain per job")
     ap.add_argument("--max-jobs", type=int, default=64, help="serve: resident jobs at once")
     ap.add_argument("--mala-eps", type=float, default=0.004, help="grad128: MALA step size (m)")
@@ -733,6 +847,8 @@ def main():
     tune = prob.get_tuning()
     opr = ops_per_ray(args.workload)
     achieved = opr * n_chains * sc.n_rays / (ms_march * 1e-3) / 1e12
+    sopr = survey_ops_per_ray(args.workload)
+    sach = sopr * n_chains * sc.n_rays / (ms_march * 1e-3) / 1e12
     measured_f32 = binding.measure_valu_rate(0, "f32") / 1e12
     measured_f64 = binding.measure_valu_rate(0, "f64") / 1e12
     out = {
@@ -759,7 +875,9 @@ def main():
                      "traffic_unit": "bytes per launch", "algorithmic_bytes": algorithmic_bytes(sc, n_chains, tune["block"] * tune["rays_per_thread"]),
                      "kernel": "k_march_lik4", "launch_shape": tune, "ms_per_launch": ms_march,
                      "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays,
-                     "measured_fma_rate": {"f32": measured_f32, "f64": measured_f64, "unit": "Tlane-op/s"}},
+                     "ops_per_ray_cell_count": sopr, "frac_cell_count": sach / VALU_PEAK_TOPS,
+                     "measured_fma_rate": {"f32": measured_f32, "f64": measured_f64, "unit": "Tlane-op/s"},
+                     "counters": measured_valu(args.workload, n_chains * sc.n_rays)},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -783,18 +901,20 @@ def run_extras(args, torch):
                                       no_cpu_baseline=True)),
         ("nuts64", bench_nuts, dict(steps=2, nuts_warmup=10, nuts_eps=0.0005, nuts_jitter=0.3, nuts_heights=False,
                                     march_iters=3)),
-        ("serve_20_per_s", bench_serve, dict(rate=20.0, duration=1.0, job_steps=2000, max_jobs=8, graph_steps=50,
+        ("serve_20_per_s", bench_serve, dict(rate=20.0, n_jobs=100, job_steps=2000, max_jobs=8, graph_steps=50,
                                              no_plain=True)),
     ]
     keep = {
-        "hetero_256": ("value", "ms_per_step", "logpost_evals_per_s", "speedup_vs_plain"),
+        "hetero_256": ("value", "ms_per_step", "logpost_evals_per_s", "speedup_vs_plain", "batched_form",
+                       "batched_forms_ms_per_step"),
         "grad128": ("value", "ms_per_step", "logpost_evals_per_s", "accept_rate", "gradient_evals_per_s"),
         "hier_r_64": ("value", "ms_per_step", "fixed_r_ms_per_step", "overhead_vs_fixed_r", "accept_rate",
                       "r_accept_rate", "r_mean"),
         "voxel64": ("value", "ms_per_step", "logpost_evals_per_s", "accept_rate", "kernels"),
         "nuts64": ("value", "ms_per_step", "leapfrog_steps_per_s", "useful_fraction", "mean_tree_depth",
                    "divergent_fraction", "mean_accept_stat", "nested_rhat_max"),
-        "serve_20_per_s": ("value", "p50_s", "p99_s", "logpost_evals_per_s", "offered_load"),
+        "serve_20_per_s": ("value", "p50_s", "p99_s", "queue_p99_s", "service_p99_s", "logpost_evals_per_s",
+                           "offered_load"),
     }
     for name, fn, over in jobs:
         a = copy.copy(args)

@@ -344,10 +344,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
                 const Patch pt = make_patch(h00, h01, h10, h11);
                 const float t0 = W.t0, t1 = st.t1;
                 const float z0 = W.z0, z1 = st.z1;
-                const float se = __builtin_fmaf(__builtin_fmaf(t0, dx, qx), P.ihx, -W.af);
-                const float we = __builtin_fmaf(__builtin_fmaf(t0, dy, qy), P.ihy, -W.bf);
-                const float sx = __builtin_fmaf(__builtin_fmaf(t1, dx, qx), P.ihx, -W.af);
-                const float wx = __builtin_fmaf(__builtin_fmaf(t1, dy, qy), P.ihy, -W.bf);
+                const float se = __builtin_fmaf(__builtin_fmaf(t0, dx, qx), P.ihx, -walk_af(W));
+                const float we = __builtin_fmaf(__builtin_fmaf(t0, dy, qy), P.ihy, -walk_bf(W));
+                const float sx = __builtin_fmaf(__builtin_fmaf(t1, dx, qx), P.ihx, -walk_af(W));
+                const float wx = __builtin_fmaf(__builtin_fmaf(t1, dy, qy), P.ihy, -walk_bf(W));
                 const float fe = end_value(pt, W.ekind, !xpos, !ypos, z0, se, we);
                 const float fx = end_value(pt, st.xkind, xpos, ypos, z1, sx, wx);
                 const float c2 = -(pt.dr1 - pt.dr0) * (dx * P.ihx) * (dy * P.ihy);
@@ -359,8 +359,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
                     if (!(fp[k] > 0.f)) continue;   // tangency: a kink of lp, no derivative
                     const float t = __builtin_fmaf(pc.s[k], tau1, t0);
                     if (__builtin_fmaf(t, dz, qz) >= P.lid) continue;   // the box lid: a kink
-                    const float s = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -W.af), 0.f), 1.f);
-                    const float w = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -W.bf), 0.f), 1.f);
+                    const float s = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -walk_af(W)), 0.f), 1.f);
+                    const float w = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -walk_bf(W)), 0.f), 1.f);
                     const float g = scale * __builtin_amdgcn_rcpf(fp[k]);
                     const float cv[4] = {g * (1.f - s) * (1.f - w), g * (1.f - s) * w, g * s * (1.f - w), g * s * w};
                     const int no[4] = {off, off + 1, off + C, off + C + 1};
@@ -587,14 +587,15 @@ __global__ __launch_bounds__(BLOCK) void k_mala_finalize(T *H, const T *prop, T 
     const T *gc = g_cur + (size_t)c * SN;
     const T *gq = g_prop + (size_t)c * SN;
     double fwd = 0.0, bwd = 0.0;
-    const double e2 = eps * eps;
+    const double e2 = eps * eps, k1 = 0.5 / e2;
     for (int n = tid; n < M; n += BLOCK) {
         const double m = inv_mass ? inv_mass[n] : 1.0;
+        const double k = inv_mass ? k1 / m : k1;   // 1 / (2 eps^2 m)
         const double h = (double)Hc[n], q = (double)Pc[n];
         const double df = q - h - 0.5 * e2 * m * (double)gc[n];
         const double db = h - q - 0.5 * e2 * m * (double)gq[n];
-        fwd -= df * df / (2.0 * e2 * m);
-        bwd -= db * db / (2.0 * e2 * m);
+        fwd -= df * df * k;
+        bwd -= db * db * k;
     }
     const double F = block_sum<BLOCK>(fwd, red);
     const double B = block_sum<BLOCK>(bwd, red);

@@ -911,8 +911,10 @@ mc_status mala_step(mc_problem *p, int n, T *heights, double *lp, int64_t *acc, 
     HIP_TRY(p, hipGetLastError());
     mc_status s;
     if ((s = grad_eval<T, S>(p, n, prop, lpp, gprop, st)) != MC_OK) return s;
-    auto kfin = k_mala_finalize<T, kPriorBlock>;
-    hipLaunchKernelGGL(kfin, dim3(n), dim3(kPriorBlock), 0, st, heights,
+    // one block per chain; large grids take 1024 threads (more loads in flight per chain)
+    const bool big = (size_t)M >= (size_t)kPriorLargeNodes;
+    auto kfin = big ? k_mala_finalize<T, kPriorBlockLarge> : k_mala_finalize<T, kPriorBlock>;
+    hipLaunchKernelGGL(kfin, dim3(n), dim3(big ? kPriorBlockLarge : kPriorBlock), 0, st, heights,
                        (const T *)prop, gcur, (const T *)gprop, lp, (const double *)lpp, acc, cfg->inv_mass, M, SN,
                        cfg->step_size, cfg->seed, (const uint64_t *)p->d_step, k);
     HIP_TRY(p, hipGetLastError());

@@ -132,12 +132,17 @@ __device__ __forceinline__ float solve_cell_piece(const Patch &p, float af, floa
 struct Walk {
     float xl, yl;             // indices of the next x and y node lines
     float tx, ty;             // h_x / d_x, h_y / d_y: parameter step per line
-    float af, bf;             // cell origin indices as floats
+    float xe, ye;             // the grid's last node line in the walk's x and y directions
+    float ax, ay;             // 1 when the walk moves to +x (+y), else 0
     int off, offx, offy;      // element offset of node (a, b) in the surface and its steps
-    int remx, remy;           // cells left before the grid edge along x / y
     float t0, z0;
     int ekind;
 };
+
+// Cell origin indices (a, b) as floats: the next node line minus the
+// direction offset (exact small integers).
+__device__ __forceinline__ float walk_af(const Walk &W) { return W.xl - W.ax; }
+__device__ __forceinline__ float walk_bf(const Walk &W) { return W.yl - W.ay; }
 
 __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx, float qy, float qz, float dx,
                                           float dy, float dz, float idx, float idy, float tl) {
@@ -152,13 +157,15 @@ __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx,
     W.yl = (float)(ypos ? b + 1 : b);
     W.tx = P.hx * idx;
     W.ty = P.hy * idy;
-    W.af = (float)a;
-    W.bf = (float)b;
+    // a step along +x is allowed while a < R - 2, i.e. xl < R - 1; along -x
+    // while a > 0, i.e. xl > 0: the walk stops at the line xe (ye)
+    W.xe = xpos ? (float)(R - 1) : 0.f;
+    W.ye = ypos ? (float)(C - 1) : 0.f;
+    W.ax = xpos ? 1.f : 0.f;
+    W.ay = ypos ? 1.f : 0.f;
     W.off = a * C + b;
     W.offx = xpos ? C : -C;
     W.offy = ypos ? 1 : -1;
-    W.remx = xpos ? R - 2 - a : a;
-    W.remy = ypos ? C - 2 - b : b;
     W.t0 = tl;
     W.z0 = __builtin_fmaf(tl, dz, qz);
     W.ekind = kPoint;
@@ -178,7 +185,8 @@ __device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, flo
     const float tnx = __builtin_fmaf(W.xl, W.tx, ox), tny = __builtin_fmaf(W.yl, W.ty, oy);
     s.stepx = tnx <= tny;
     const float tn = s.stepx ? tnx : tny;
-    const bool room = s.stepx ? (W.remx > 0) : (W.remy > 0);
+    const float line = s.stepx ? W.xl : W.yl, last = s.stepx ? W.xe : W.ye;
+    const bool room = line != last;
     s.edge = (tn < th) && room;
     s.t1 = fmaxf(fminf(tn, th), W.t0);
     s.z1 = __builtin_fmaf(s.t1, dz, qz);
@@ -190,14 +198,10 @@ __device__ __forceinline__ void walk_advance(Walk &W, const Step &s) {
     // value selects (a branch here makes the compiler select between field
     // addresses and keep the walk state in scratch memory)
     const bool sx = s.stepx;
-    const float gx = W.tx > 0.f ? 1.f : -1.f, gy = W.ty > 0.f ? 1.f : -1.f;
+    const float gx = 2.f * W.ax - 1.f, gy = 2.f * W.ay - 1.f;
     W.xl = sx ? W.xl + gx : W.xl;
     W.yl = sx ? W.yl : W.yl + gy;
-    W.af = sx ? W.af + gx : W.af;
-    W.bf = sx ? W.bf : W.bf + gy;
     W.off += sx ? W.offx : W.offy;
-    W.remx = sx ? W.remx - 1 : W.remx;
-    W.remy = sx ? W.remy : W.remy - 1;
     W.ekind = sx ? kXEdge : kYEdge;
     W.t0 = s.t1;
     W.z0 = s.z1;
@@ -321,7 +325,7 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                         const Patch pt = make_patch(h00, h01, h10, h11);
                         if constexpr (REC) {
                             PieceCross pc;
-                            L += solve_cell_piece<true>(pt, W.af, W.bf, P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0,
+                            L += solve_cell_piece<true>(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0,
                                                         st.t1, W.ekind, st.xkind, &pc);
                             const float tau1 = st.t1 - W.t0;
                             for (int k = 0; k < pc.n; ++k) {
@@ -330,9 +334,9 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                                 const float t = __builtin_fmaf(pc.s[k], tau1, W.t0);
                                 if (__builtin_fmaf(t, dz, qz) >= P.lid) continue;   // the box lid: a kink
                                 const float sc =
-                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -W.af), 0.f), 1.f);
+                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -walk_af(W)), 0.f), 1.f);
                                 const float wc =
-                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -W.bf), 0.f), 1.f);
+                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -walk_bf(W)), 0.f), 1.f);
                                 if (nrec[l] < X.slots)
                                     X.rec[rbase + ((size_t)l * X.slots + nrec[l]) * BLOCK] =
                                         make_uint4((uint32_t)W.off | ((uint32_t)l << 16) | ((uint32_t)kslot << 18),
@@ -341,7 +345,7 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                                 ++nrec[l];
                             }
                         } else {
-                            L += solve_cell_piece(pt, W.af, W.bf, P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0, st.t1,
+                            L += solve_cell_piece(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0, st.t1,
                                                   W.ekind, st.xkind);
                         }
                     }
