@@ -44,10 +44,6 @@ METRIC = ("ray-opacity evals/s + log-posterior evals/s (chains) at 1 GPU; p50/p9
 OPS_CELL_BASE, OPS_TEST, OPS_CROSS, OPS_RAY = 8.0, 9.0, 45.0, 80.0
 WORKLOAD_COUNTS = {"grf_cave_64": dict(cells=18.93, crossings=2.94, S=3),
                    "grf_cave_128": dict(cells=37.24, crossings=2.92, S=3)}
-# The adjoint re-walks every ray and, per crossing, adds the four bilinear
-# weights times g_p / |f'| converted to fixed point: 32 more lane-operations
-# per crossing (its four 64-bit atomics are memory operations, not counted).
-OPS_CROSS_ADJ = OPS_CROSS + 32.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed VALU lane-op
 # per lane per clock; wave64 instructions issue over 4 clocks)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -64,14 +60,18 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # (around the ray loop, not inside the walk); the dirty scratch lines written
 # back are most of WRITE_SIZE.
 KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march_common.h", "march3.h", "march5.h"),
-                  "voxel64": ("device_common.h", "voxel.h")}
+                  "voxel64": ("device_common.h", "voxel.h"),
+                  "grad128_adjoint": ("device_common.h", "march_common.h", "march5.h", "adjoint.h")}
 MEASURED_TRAFFIC = {
-    "grf_cave_64": dict(source_sha="cf13820ebd89508f", fetch_kib=30713.0, fetch_scale=262144 / 131093.2,
-                        write_kib=56968.0, write_scale=1.0),
+    "grf_cave_64": dict(source_sha="bd001bbde1f07850", fetch_kib=30722.0, fetch_scale=262144 / 131093.2,
+                        write_kib=56943.7, write_scale=1.0),
+    # k_adjoint_rec on the 128x128 gradient workload (512 chains)
+    "grad128_adjoint": dict(source_sha="be90c1431fd55972", fetch_kib=429639.2, fetch_scale=262144 / 131088.8,
+                            write_kib=196608.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
-    "voxel64": dict(source_sha="344071297b08c061", fetch_kib=2449389.3, fetch_scale=262144 / 131092.25,
-                    write_kib=70379.2, write_scale=1.0),
+    "voxel64": dict(source_sha="a54470c4ae3bcfc7", fetch_kib=2433874.6, fetch_scale=262144 / 131093.7,
+                    write_kib=63535.4, write_scale=1.0),
 }
 
 
@@ -83,8 +83,8 @@ MEASURED_TRAFFIC = {
 # known instruction count (32768 waves x 2^16 x 8 = 1.718e10) at 0.967
 # instructions per CU-clock, the full-lane issue limit.
 MEASURED_VALU = {
-    "grf_cave_64": dict(source_sha="cf13820ebd89508f", valu_insts=1.086e9, thread_cycles_valu=3.303e10,
-                        active_inst_valu=1.107e9, grbm_gui_active_per_xcd=2.876e6, cus=256),
+    "grf_cave_64": dict(source_sha="bd001bbde1f07850", valu_insts=1.046e9, thread_cycles_valu=3.149e10,
+                        active_inst_valu=1.066e9, grbm_gui_active_per_xcd=2.788e6, cus=256),
 }
 
 
@@ -142,9 +142,17 @@ def survey_ops_per_ray(name):
     return c["cells"] * (10.0 * c["S"] + 6.0)
 
 
-def adjoint_ops_per_ray(name):
+def adjoint_bytes(name, sc, n_chains, block, rays_per_thread):
+    """Bytes one launch of the record adjoint must move at least: every
+    crossing record once (16 B; the oracle's crossings per ray), the record
+    counts of every (chain, tile, surface, thread), dLL/dO of every ray
+    (4 B), and the 64-bit fixed-point gradient of every node written once."""
     c = WORKLOAD_COUNTS[name]
-    return OPS_RAY + c["cells"] * (OPS_CELL_BASE + c["S"] * OPS_TEST) + c["crossings"] * OPS_CROSS_ADJ
+    rays = n_chains * sc.n_rays
+    tiles = -(-sc.n_rays // (block * rays_per_thread))
+    N = sc.n_rows * sc.n_cols
+    return (rays * c["crossings"] * 16 + n_chains * tiles * sc.n_surfaces * block * 4 + rays * 4
+            + n_chains * sc.n_surfaces * N * 8)
 
 
 def make_workload(name):
@@ -260,6 +268,14 @@ def bench_hetero(args, torch):
     from paper_2603_28907_amd import autotune
     from paper_2603_28907_amd.binding import mcmc_run_multi
     n_prob = args.problems
+
+    def gap():
+        """With --phase-gaps: 300 ms of idle GPU between phases, so that a
+        kernel trace splits them."""
+        if getattr(args, "phase_gaps", False):
+            torch.cuda.synchronize()
+            time.sleep(0.3)
+
     t0 = time.perf_counter()
     probs, H, lp, acc = build_hetero(n_prob, torch)
     sigma = [0.005] * n_prob
@@ -272,6 +288,7 @@ def bench_hetero(args, torch):
     for i, p in enumerate(probs):
         p.mcmc_run(H[i], lp[i], acc[i], 1, sigma[i], seeds[i], step_offset=0, graph_steps=1)
     torch.cuda.synchronize()
+    gap()
     k_plain = max(1, args.plain_steps)
     t0 = time.perf_counter()
     for i, p in enumerate(probs):
@@ -279,6 +296,7 @@ def bench_hetero(args, torch):
     torch.cuda.synchronize()
     dt_plain = time.perf_counter() - t0
     print(f"[bench] plain sampler: {dt_plain / k_plain * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    gap()
     # autotuned shapes per grid class
     t0 = time.perf_counter()
     tuned = autotune.tune_batch(probs, H)
@@ -310,11 +328,14 @@ def bench_hetero(args, torch):
                        graph_steps=min(G, max(args.warmup, 1)))
         torch.cuda.synchronize()
         off += args.warmup
+        gap()
         t0 = time.perf_counter()
         mcmc_run_multi(probs, H, lp, acc, args.steps, sigma, seeds, step_offsets=[off] * n_prob, graph_steps=G)
         torch.cuda.synchronize()
         off += args.steps
-        return time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        gap()
+        return dt
 
     forms = {}
     for k in (0, 1, 2):
@@ -356,7 +377,7 @@ def bench_hetero(args, torch):
 def bench_grad(args, torch):
     """Gradient-driven sampling on the 128x128 geometry: full log-posterior +
     gradient evaluations (forward march, adjoint march, prior gradient) and
-    MALA steps on 512 chains; roofline of the adjoint kernel."""
+    MALA steps on 512 chains; HBM roofline of the record adjoint."""
     from paper_2603_28907_amd import binding, inputs
     from paper_2603_28907_amd.binding import KERNEL_MALA, Problem
     sc = inputs.grf_cave(seed=10, n_grid=128)
@@ -389,8 +410,9 @@ def bench_grad(args, torch):
     assert torch.isfinite(lpm).all(), "non-finite log posterior"
     ms_adj = binding.time_adjoint(prob, H, iters=args.march_iters)
     ms_fwd = binding.time_march(prob, H, iters=args.march_iters)
-    opr = adjoint_ops_per_ray("grf_cave_128")
-    achieved = opr * n_chains * sc.n_rays / (ms_adj * 1e-3) / 1e12
+    t = prob.get_tuning()
+    abytes = adjoint_bytes("grf_cave_128", sc, n_chains, t["block"], t["rays_per_thread"])
+    achieved = abytes / (ms_adj * 1e-3) / 1e9
     return {
         "metric": METRIC, "value": n_chains * sc.n_rays * args.steps / dt, "unit": "ray-evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
@@ -403,9 +425,10 @@ def bench_grad(args, torch):
         "accept_rate": float((acc - a0).double().mean().item()) / args.steps,
         "gradient_evals_per_s": n_chains / dt_grad, "ms_per_gradient_eval": dt_grad * 1e3,
         "forward_ms_per_launch": ms_fwd,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_adjoint_lds",
-                     "ms_per_launch": ms_adj, "ops_per_ray": opr, "rays_per_launch": n_chains * sc.n_rays},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("grad128_adjoint"),
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes": abytes, "kernel": "k_adjoint_rec",
+                     "ms_per_launch": ms_adj, "rays_per_launch": n_chains * sc.n_rays},
     }
 
 
@@ -578,8 +601,9 @@ def bench_nuts(args, torch):
         H = prob.latent_to_heights(H)
     rhat = prob.nested_rhat(H, n_super, n_within)
     ms_adj = binding.time_adjoint(prob, H, iters=args.march_iters)
-    opr = adjoint_ops_per_ray("grf_cave_64")
-    achieved = opr * n * sc.n_rays / (ms_adj * 1e-3) / 1e12
+    t = prob.get_tuning()
+    abytes = adjoint_bytes("grf_cave_64", sc, n, t["block"], t["rays_per_thread"])
+    achieved = abytes / (ms_adj * 1e-3) / 1e9
     return {
         "metric": METRIC, "value": leaps * sc.n_rays / dt, "unit": "ray-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.nuts_warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
@@ -597,9 +621,9 @@ def bench_nuts(args, torch):
         "mean_accept_stat": float(st["accept_stat"].mean().item()),
         "step_size_median": float(eps.median().item()),
         "nested_rhat_max": float(rhat.max().item()), "warmup_s": t_warm,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TVALUop/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "k_adjoint_lds",
-                     "ms_per_launch": ms_adj, "ops_per_ray": opr, "rays_per_launch": n * sc.n_rays},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": abytes,
+                     "kernel": "k_adjoint_rec", "ms_per_launch": ms_adj, "rays_per_launch": n * sc.n_rays},
     }
 
 
@@ -705,6 +729,10 @@ def bench_serve(args, torch):
             if delay > 0:
                 time.sleep(delay)
             ids.append(srv.submit(sc, n, args.job_steps, 0.005, 7000 + k))
+            if (k + 1) % max(1, n_jobs // 20) == 0:
+                st = srv.stats()
+                print(f"[bench] max_jobs {max_jobs}: {k + 1}/{n_jobs} jobs submitted, {st['done']} done",
+                      file=sys.stderr, flush=True)
         done = 0
         while True:
             st = srv.stats()
@@ -762,6 +790,8 @@ def main():
     ap.add_argument("--march-iters", type=int, default=20)
     ap.add_argument("--problems", type=int, default=256, help="problems in the hetero workload")
     ap.add_argument("--plain-steps", type=int, default=5, help="steps of the plain per-problem sampler")
+    ap.add_argument("--phase-gaps", action="store_true",
+                    help="hetero: 300 ms of idle GPU between phases (for splitting a kernel trace)")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="serve: seconds of arrivals")
     ap.add_argument("--n-jobs", type=int, default=0,

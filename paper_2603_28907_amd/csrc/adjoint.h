@@ -314,6 +314,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
         const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
         const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
         const float ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
+        const float kxy = -(dx * P.ihx) * (dy * P.ihy);   // the march's curvature factor
         float tl = fminf(fmaxf((band[0] - qz) * idz, 0.f), Texit);
         float th = fminf(fmaxf((band[1] - qz) * idz, 0.f), Texit);
         if (W_.n_windows > 1) {
@@ -350,12 +351,14 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
                 const float wx = __builtin_fmaf(__builtin_fmaf(t1, dy, qy), P.ihy, -walk_bf(W));
                 const float fe = end_value(pt, W.ekind, !xpos, !ypos, z0, se, we);
                 const float fx = end_value(pt, st.xkind, xpos, ypos, z1, sx, wx);
-                const float c2 = -(pt.dr1 - pt.dr0) * (dx * P.ihx) * (dy * P.ihy);
+                const float c2 = (pt.dr1 - pt.dr0) * kxy;
                 const float tau1 = t1 - t0;
                 PieceCross pc;
                 (void)piece_length<true>(fe, fx, c2, tau1, &pc);
                 const float *fp = pc.fp;
-                for (int k = 0; k < pc.n; ++k) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {   // at most two crossings; unrolled to keep them in registers
+                    if (k >= pc.n) break;
                     if (!(fp[k] > 0.f)) continue;   // tangency: a kink of lp, no derivative
                     const float t = __builtin_fmaf(pc.s[k], tau1, t0);
                     if (__builtin_fmaf(t, dz, qz) >= P.lid) continue;   // the box lid: a kink

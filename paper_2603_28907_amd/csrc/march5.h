@@ -107,13 +107,15 @@ __device__ __forceinline__ float end_value(const Patch &p, int kind, bool xrow1,
 }
 
 // Below-length of one piece [t0, t1] of cell (af, bf) (cell origin indices
-// as floats) of a surface patch.
+// as floats) of a surface patch; z0, z1: the ray's heights at t0, t1 (the
+// walk's own values); kxy = -(d_x / h_x)(d_y / h_y), the ray's factor of the
+// patch curvature.
 template <bool REC = false>
 __device__ __forceinline__ float solve_cell_piece(const Patch &p, float af, float bf, float ihx, float ihy, float qx,
-                                                  float qy, float qz, float dx, float dy, float dz, float t0,
-                                                  float t1, int ekind, int xkind, PieceCross *pc = nullptr) {
+                                                  float qy, float dx, float dy, float kxy, float t0, float t1,
+                                                  float z0, float z1, int ekind, int xkind,
+                                                  PieceCross *pc = nullptr) {
     const bool xpos = dx > 0.f, ypos = dy > 0.f;
-    const float z0 = __builtin_fmaf(t0, dz, qz), z1 = __builtin_fmaf(t1, dz, qz);
     const float se = __builtin_fmaf(__builtin_fmaf(t0, dx, qx), ihx, -af);
     const float we = __builtin_fmaf(__builtin_fmaf(t0, dy, qy), ihy, -bf);
     const float sx = __builtin_fmaf(__builtin_fmaf(t1, dx, qx), ihx, -af);
@@ -121,7 +123,7 @@ __device__ __forceinline__ float solve_cell_piece(const Patch &p, float af, floa
     // entry edge: row a+1 when moving -x, column b+1 when moving -y; exit: the opposite
     const float fe = end_value(p, ekind, !xpos, !ypos, z0, se, we);
     const float fx = end_value(p, xkind, xpos, ypos, z1, sx, wx);
-    const float c2 = -(p.dr1 - p.dr0) * (dx * ihx) * (dy * ihy);
+    const float c2 = (p.dr1 - p.dr0) * kxy;
     return piece_length<REC>(fe, fx, c2, t1 - t0, pc);
 }
 
@@ -188,7 +190,9 @@ __device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, flo
     const float line = s.stepx ? W.xl : W.yl, last = s.stepx ? W.xe : W.ye;
     const bool room = line != last;
     s.edge = (tn < th) && room;
-    s.t1 = fmaxf(fminf(tn, th), W.t0);
+    // max(min(tn, th), t0) as one median: t0 <= th along the walk, and tn is
+    // finite or +inf (an axis-parallel ray has step 0 and offset +inf)
+    s.t1 = __builtin_amdgcn_fmed3f(tn, th, W.t0);
     s.z1 = __builtin_fmaf(s.t1, dz, qz);
     s.xkind = s.edge ? (s.stepx ? kXEdge : kYEdge) : kPoint;
     return s;
@@ -294,10 +298,16 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     double acc = 0.0;
     const int r0 = tile * P.rays_per_block;
     const int r1 = min(r0 + P.rays_per_block, P.n_ray);
-    int nrec[S];
+    // records kept per surface by this thread: counters in LDS, not
+    // registers (the gradient march is tight on registers at 6 waves per SIMD)
+    __shared__ int nrec_s[REC ? S : 1][REC ? BLOCK : 1];
+    if constexpr (REC) {
 #pragma unroll
-    for (int l = 0; l < S; ++l) nrec[l] = 0;
-    const size_t rbase = (size_t)(chain * P.n_tiles + tile) * S * (size_t)X.slots * BLOCK + tid;
+        for (int l = 0; l < S; ++l) nrec_s[l][tid] = 0;
+    }
+    // this block's record lists (a block-uniform base) and this thread's
+    // offset inside them: a 32-bit index, no per-lane 64-bit pointer to keep
+    uint4 *const recb = X.rec + (size_t)(chain * P.n_tiles + tile) * S * (size_t)X.slots * BLOCK;
     int kslot = 0;
     for (int ray = r0 + tid; ray < r1; ray += BLOCK, ++kslot) {
         const int s = ray / P.n_pix;
@@ -305,6 +315,7 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
         const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
         const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
         const float ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
+        const float kxy = -(dx * P.ihx) * (dy * P.ihy);
         float O = 0.f;
 #pragma unroll
         for (int l = 0; l < S; ++l) {
@@ -325,10 +336,15 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                         const Patch pt = make_patch(h00, h01, h10, h11);
                         if constexpr (REC) {
                             PieceCross pc;
-                            L += solve_cell_piece<true>(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0,
-                                                        st.t1, W.ekind, st.xkind, &pc);
+                            L += solve_cell_piece<true>(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, dx, dy, kxy,
+                                                        W.t0, st.t1, W.z0, st.z1, W.ekind, st.xkind, &pc);
                             const float tau1 = st.t1 - W.t0;
-                            for (int k = 0; k < pc.n; ++k) {
+                            // at most two crossings: unrolled, so the crossing
+                            // data stay in registers (an indexed array would
+                            // live in scratch memory)
+#pragma unroll
+                            for (int k = 0; k < 2; ++k) {
+                                if (k >= pc.n) break;
                                 const float fp = pc.fp[k];
                                 if (!(fp > 0.f)) continue;   // tangency: a kink of lp, no derivative
                                 const float t = __builtin_fmaf(pc.s[k], tau1, W.t0);
@@ -337,16 +353,17 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                                     fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -walk_af(W)), 0.f), 1.f);
                                 const float wc =
                                     fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -walk_bf(W)), 0.f), 1.f);
-                                if (nrec[l] < X.slots)
-                                    X.rec[rbase + ((size_t)l * X.slots + nrec[l]) * BLOCK] =
+                                const int nr = nrec_s[l][tid];
+                                if (nr < X.slots)
+                                    recb[(unsigned)((l * X.slots + nr) * BLOCK + tid)] =
                                         make_uint4((uint32_t)W.off | ((uint32_t)l << 16) | ((uint32_t)kslot << 18),
                                                    __float_as_uint(sc), __float_as_uint(wc),
                                                    __float_as_uint(__builtin_amdgcn_rcpf(fp)));
-                                ++nrec[l];
+                                nrec_s[l][tid] = nr + 1;
                             }
                         } else {
-                            L += solve_cell_piece(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, qz, dx, dy, dz, W.t0, st.t1,
-                                                  W.ekind, st.xkind);
+                            L += solve_cell_piece(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, dx, dy, kxy, W.t0,
+                                                  st.t1, W.z0, st.z1, W.ekind, st.xkind);
                         }
                     }
                     if (!st.edge) break;
@@ -365,8 +382,9 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
         bool over = false;
 #pragma unroll
         for (int l = 0; l < S; ++l) {
-            X.cnt[((size_t)(chain * P.n_tiles + tile) * S + l) * BLOCK + tid] = (uint32_t)min(nrec[l], X.slots);
-            over |= nrec[l] > X.slots;
+            const int nr = nrec_s[l][tid];
+            X.cnt[((size_t)(chain * P.n_tiles + tile) * S + l) * BLOCK + tid] = (uint32_t)min(nr, X.slots);
+            over |= nr > X.slots;
         }
         if (over) X.ovf[chain] = 1;
     }
