@@ -63,10 +63,10 @@ KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march_common.h", "march3.h
                   "voxel64": ("device_common.h", "voxel.h"),
                   "grad128_adjoint": ("device_common.h", "march_common.h", "march5.h", "adjoint.h")}
 MEASURED_TRAFFIC = {
-    "grf_cave_64": dict(source_sha="bd001bbde1f07850", fetch_kib=30722.0, fetch_scale=262144 / 131093.2,
-                        write_kib=56943.7, write_scale=1.0),
+    "grf_cave_64": dict(source_sha="d7477b7a2404e879", fetch_kib=30733.2, fetch_scale=262144 / 131093.9,
+                        write_kib=56947.0, write_scale=1.0),
     # k_adjoint_rec on the 128x128 gradient workload (512 chains)
-    "grad128_adjoint": dict(source_sha="be90c1431fd55972", fetch_kib=429639.2, fetch_scale=262144 / 131088.8,
+    "grad128_adjoint": dict(source_sha="1a3ab50f289ea46e", fetch_kib=429639.0, fetch_scale=262144 / 131093.9,
                             write_kib=196608.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
@@ -83,8 +83,8 @@ MEASURED_TRAFFIC = {
 # known instruction count (32768 waves x 2^16 x 8 = 1.718e10) at 0.967
 # instructions per CU-clock, the full-lane issue limit.
 MEASURED_VALU = {
-    "grf_cave_64": dict(source_sha="bd001bbde1f07850", valu_insts=1.046e9, thread_cycles_valu=3.149e10,
-                        active_inst_valu=1.066e9, grbm_gui_active_per_xcd=2.788e6, cus=256),
+    "grf_cave_64": dict(source_sha="d7477b7a2404e879", valu_insts=1.046e9, thread_cycles_valu=3.149e10,
+                        active_inst_valu=1.066e9, grbm_gui_active_per_xcd=2.793e6, cus=256),
 }
 
 

@@ -697,15 +697,17 @@ mc_status launch_march_rec(mc_problem *p, int n, const float *heights, hipStream
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X.ovf, n);
     const dim3 grid((unsigned)P.n_tiles * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
     const size_t N = (size_t)p->R * p->C;
+    const int b = p->tune.block;
+    // static LDS: the march's reductions (< 16 KiB) and the record indices (S x block)
+    const size_t fixed = 16384 + (size_t)S * b * sizeof(unsigned);
     bool tl = top_in_lds(p);
     size_t lds = N * (tl ? S : S - 1) * sizeof(float);
-    if (lds + 16384 > p->max_lds) {
+    if (lds + fixed > p->max_lds) {
         tl = false;
         lds = N * (S - 1) * sizeof(float);
     }
-    if (lds + 16384 > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
+    if (lds + fixed > p->max_lds) return fail(p, MC_ERR_UNSUPPORTED, "grid %dx%d too large for LDS", p->R, p->C);
     const RayConsts<float> K = ray_consts<float>(p);
-    const int b = p->tune.block;
     if (tl) {
         if (b == 256) launch_march_rec_shape<S, true, 256>(grid, lds, st, P, K, X);
         else if (b == 512) launch_march_rec_shape<S, true, 512>(grid, lds, st, P, K, X);

@@ -298,18 +298,18 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     double acc = 0.0;
     const int r0 = tile * P.rays_per_block;
     const int r1 = min(r0 + P.rays_per_block, P.n_ray);
-    // records kept per surface by this thread: counters in LDS, not
-    // registers (the gradient march is tight on registers at 6 waves per SIMD)
-    __shared__ int nrec_s[REC ? S : 1][REC ? BLOCK : 1];
+    // the index of this thread's next record of each surface, in LDS rather
+    // than registers (the gradient march is tight on registers at 6 waves per
+    // SIMD): record k of surface l goes to (l slots + k) BLOCK + thread
+    __shared__ unsigned rec_next[REC ? S : 1][REC ? BLOCK : 1];
     if constexpr (REC) {
 #pragma unroll
-        for (int l = 0; l < S; ++l) nrec_s[l][tid] = 0;
+        for (int l = 0; l < S; ++l) rec_next[l][tid] = (unsigned)(l * X.slots * BLOCK + tid);
     }
     // this block's record lists (a block-uniform base) and this thread's
     // offset inside them: a 32-bit index, no per-lane 64-bit pointer to keep
     uint4 *const recb = X.rec + (size_t)(chain * P.n_tiles + tile) * S * (size_t)X.slots * BLOCK;
-    int kslot = 0;
-    for (int ray = r0 + tid; ray < r1; ray += BLOCK, ++kslot) {
+    for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
         const int s = ray / P.n_pix;
         const float qx = P.sensor[3 * s], qy = P.sensor[3 * s + 1], qz = P.sensor[3 * s + 2];
         const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
@@ -353,13 +353,17 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                                     fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -walk_af(W)), 0.f), 1.f);
                                 const float wc =
                                     fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -walk_bf(W)), 0.f), 1.f);
-                                const int nr = nrec_s[l][tid];
-                                if (nr < X.slots)
-                                    recb[(unsigned)((l * X.slots + nr) * BLOCK + tid)] =
-                                        make_uint4((uint32_t)W.off | ((uint32_t)l << 16) | ((uint32_t)kslot << 18),
+                                // the thread and its ray slot follow from the ray index
+                                // (ray = r0 + tid + kslot BLOCK): nothing more to keep live
+                                const unsigned rr = (unsigned)(ray - r0);
+                                const unsigned lane_t = rr % BLOCK, kslot = rr / BLOCK;
+                                const unsigned ri = rec_next[l][lane_t];
+                                if (ri < (unsigned)((l + 1) * X.slots * BLOCK))
+                                    recb[ri] =
+                                        make_uint4((uint32_t)W.off | ((uint32_t)l << 16) | (kslot << 18),
                                                    __float_as_uint(sc), __float_as_uint(wc),
                                                    __float_as_uint(__builtin_amdgcn_rcpf(fp)));
-                                nrec_s[l][tid] = nr + 1;
+                                rec_next[l][lane_t] = ri + BLOCK;
                             }
                         } else {
                             L += solve_cell_piece(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, dx, dy, kxy, W.t0,
@@ -382,7 +386,7 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
         bool over = false;
 #pragma unroll
         for (int l = 0; l < S; ++l) {
-            const int nr = nrec_s[l][tid];
+            const int nr = (int)((rec_next[l][tid] - (unsigned)(l * X.slots * BLOCK + tid)) / BLOCK);
             X.cnt[((size_t)(chain * P.n_tiles + tile) * S + l) * BLOCK + tid] = (uint32_t)min(nr, X.slots);
             over |= nr > X.slots;
         }
