@@ -761,7 +761,8 @@ def bench_serve(args, torch):
     batched = serve(args.max_jobs)
     print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
     plain = serve(1) if not args.no_plain else None
-    offered = args.rate * (work_chain_steps / n_jobs) / batched["logpost_evals_per_s"]
+    # offered load: arrival rate x GPU-busy seconds per job of the batched run
+    offered = args.rate * batched["busy_s"] / n_jobs
     return {
         "metric": METRIC, "value": batched["ray_evals_per_s"], "unit": "ray-evals/s", "n_gpus": 1,
         "steps": args.job_steps, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -931,7 +932,7 @@ def run_extras(args, torch):
                                       no_cpu_baseline=True)),
         ("nuts64", bench_nuts, dict(steps=2, nuts_warmup=10, nuts_eps=0.0005, nuts_jitter=0.3, nuts_heights=False,
                                     march_iters=3)),
-        ("serve_20_per_s", bench_serve, dict(rate=20.0, n_jobs=100, job_steps=2000, max_jobs=8, graph_steps=50,
+        ("serve_20_per_s", bench_serve, dict(rate=20.0, n_jobs=100, job_steps=2000, max_jobs=16, graph_steps=50,
                                              no_plain=True)),
     ]
     keep = {
