@@ -332,10 +332,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
         }
         if (!(tl < th) || scale == 0.f) continue;
         const bool xpos = dx > 0.f, ypos = dy > 0.f;
-        Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, tl);
-        for (int it = 0; it < P.R + P.C; ++it) {
-            const Step st = walk_step(W, qz, dz, ox, oy, th);
-            const int off = W.off;
+        Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, ox, oy, tl);
+        for (;;) {   // at most R + C - 2 steps, as in the march
+            const Step st = walk_step(W, qz, dz, th);
+            const int off = (int)(W.off >> 2);
             const float h00 = Hl[off], h01 = Hl[off + 1], h10 = Hl[off + C], h11 = Hl[off + C + 1];
             const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));
             const float hmax = fmaxf(fmaxf(h00, h01), fmaxf(h10, h11));

@@ -33,21 +33,23 @@ struct PieceCross {
 // and curvature c2 of f = z - h (the cases of cell_below_length_fast).
 // Solved in the normalised variable s = tau / tau1 on [0, 1]:
 //   f(s) = fe + B s + A s^2,  A = c2 tau1^2,  B = fx - fe - A,
-// which needs two hardware reciprocals and one square root.  The stable root
-// fe / q also covers A = 0 (q = -B there: the straight-line crossing).  With
-// REC the crossings are reported too: the one root when the end signs
-// differ, else the two roots around an interior vertex of the opposite sign;
-// |f'| = |B + 2 A s| / tau1.
+// which needs two hardware reciprocals and one square root.  With
+// hB = -B / 2 the roots are (hB -+ sqrt(hB^2 - A fe)) / A and the vertex is
+// sv = hB / A with f(sv) = fe - hB sv.  The stable root fe / q also covers
+// A = 0 (q = -B there: the straight-line crossing).  With REC the crossings
+// are reported too: the one root when the end signs differ, else the two
+// roots around an interior vertex of the opposite sign; |f'| = |B + 2 A s| / tau1.
 template <bool REC = false>
 __device__ __forceinline__ float piece_length(float fe, float fx, float c2, float tau1, PieceCross *pc = nullptr) {
     const bool be = fe < 0.f, bx = fx < 0.f;
     const float A = c2 * tau1 * tau1;
     const float B = (fx - fe) - A;
+    const float hB = -0.5f * B;
     const float iA = __builtin_amdgcn_rcpf(A);
-    const float disc = fmaxf(B * B - 4.f * A * fe, 0.f);
-    const float sq = raw_sqrt(disc);
+    // half the square root of the discriminant B^2 - 4 A fe
+    const float sq = raw_sqrt(fmaxf(__builtin_fmaf(hB, hB, -(A * fe)), 0.f));
     // one crossing: the stable pair of roots, keep the one nearest [0, 1]
-    const float q = -0.5f * (B + (B >= 0.f ? sq : -sq));
+    const float q = hB + (hB <= 0.f ? -sq : sq);
     const float s1 = q * iA, s2 = fe * __builtin_amdgcn_rcpf(q);
     const float d1 = fmaxf(fmaxf(-s1, s1 - 1.f), 0.f);
     const float d2 = fmaxf(fmaxf(-s2, s2 - 1.f), 0.f);
@@ -55,16 +57,16 @@ __device__ __forceinline__ float piece_length(float fe, float fx, float c2, floa
     const float r = sr * tau1;
     const float one = be ? r : tau1 - r;
     // same signs: two crossings around an interior vertex of the opposite sign
-    const float sv = -0.5f * B * iA;
-    const float fv = fe + sv * (B + A * sv);
+    const float sv = hB * iA;
+    const float fv = __builtin_fmaf(-sv, hB, fe);
     const bool two = (A != 0.f) && (sv > 0.f) && (sv < 1.f) && ((fv < 0.f) != be);
-    const float half = 0.5f * sq * fabsf(iA);
-    const float inner = fmaxf(fminf(sv + half, 1.f) - fmaxf(sv - half, 0.f), 0.f) * tau1;
+    const float aiA = fabsf(iA);
+    const float sa = fmaxf(__builtin_fmaf(-aiA, sq, sv), 0.f), sb = fminf(__builtin_fmaf(aiA, sq, sv), 1.f);
+    const float inner = fmaxf(sb - sa, 0.f) * tau1;
     const float none = be ? tau1 : 0.f;
     const float twol = be ? tau1 - inner : inner;
     if constexpr (REC) {
         const float it1 = __builtin_amdgcn_rcpf(tau1);
-        const float sa = fmaxf(sv - half, 0.f), sb = fminf(sv + half, 1.f);
         pc->n = (be != bx) ? 1 : (two ? 2 : 0);
         pc->s[0] = (be != bx) ? sr : sa;
         pc->s[1] = sb;
@@ -127,27 +129,29 @@ __device__ __forceinline__ float solve_cell_piece(const Patch &p, float af, floa
     return piece_length<REC>(fe, fx, c2, t1 - t0, pc);
 }
 
-// Cell walk state (also used by the adjoint).  The next node lines are
-// kept as integer-valued indices, so the parameter where the ray meets one,
-// t = line * (h / d) + o, depends only on the line: a walk started at any cell
-// of a ray reproduces the bits of the walk that reached that cell.
+// Cell walk state (also used by the adjoint).  The cell indices are kept
+// as integer-valued floats, so the parameter where the ray leaves a cell
+// across an x (y) node line, t = a t_x + o_x, depends only on the cell: a
+// walk started at any cell of a ray reproduces the bits of the walk that
+// reached that cell.
 struct Walk {
-    float xl, yl;             // indices of the next x and y node lines
-    float tx, ty;             // h_x / d_x, h_y / d_y: parameter step per line
-    float xe, ye;             // the grid's last node line in the walk's x and y directions
-    float ax, ay;             // 1 when the walk moves to +x (+y), else 0
-    int off, offx, offy;      // element offset of node (a, b) in the surface and its steps
+    float af, bf;             // cell origin indices (a, b) as floats (exact small integers)
+    float tx, ty;             // h_x / d_x, h_y / d_y: parameter step per cell
+    float ox, oy;             // parameter of the exit line of cell index 0 in the walk's direction
+    float xe, ye;             // the last cell index in the walk's x and y directions
+    float gx, gy;             // the index step along x and y (+1 or -1)
+    unsigned off, offx, offy; // byte offset of node (a, b) in the surface and its steps (mod 2^32)
     float t0, z0;
     int ekind;
 };
 
-// Cell origin indices (a, b) as floats: the next node line minus the
-// direction offset (exact small integers).
-__device__ __forceinline__ float walk_af(const Walk &W) { return W.xl - W.ax; }
-__device__ __forceinline__ float walk_bf(const Walk &W) { return W.yl - W.ay; }
+__device__ __forceinline__ float walk_af(const Walk &W) { return W.af; }
+__device__ __forceinline__ float walk_bf(const Walk &W) { return W.bf; }
 
+// ox, oy: the ray's parameter at the node lines x = 0 and y = 0 (+inf for a
+// ray parallel to that axis, whose step tx or ty is then 0).
 __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx, float qy, float qz, float dx,
-                                          float dy, float dz, float idx, float idy, float tl) {
+                                          float dy, float dz, float idx, float idy, float ox, float oy, float tl) {
     const int R = P.R, C = P.C;
     const bool xpos = dx > 0.f, ypos = dy > 0.f;
     const float x0 = __builtin_fmaf(tl, dx, qx), y0 = __builtin_fmaf(tl, dy, qy);
@@ -155,19 +159,21 @@ __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx,
     a = a < 0 ? 0 : (a > R - 2 ? R - 2 : a);
     b = b < 0 ? 0 : (b > C - 2 ? C - 2 : b);
     Walk W;
-    W.xl = (float)(xpos ? a + 1 : a);
-    W.yl = (float)(ypos ? b + 1 : b);
+    W.af = (float)a;
+    W.bf = (float)b;
     W.tx = P.hx * idx;
     W.ty = P.hy * idy;
-    // a step along +x is allowed while a < R - 2, i.e. xl < R - 1; along -x
-    // while a > 0, i.e. xl > 0: the walk stops at the line xe (ye)
-    W.xe = xpos ? (float)(R - 1) : 0.f;
-    W.ye = ypos ? (float)(C - 1) : 0.f;
-    W.ax = xpos ? 1.f : 0.f;
-    W.ay = ypos ? 1.f : 0.f;
-    W.off = a * C + b;
-    W.offx = xpos ? C : -C;
-    W.offy = ypos ? 1 : -1;
+    // the exit line of cell a is a + 1 along +x and a along -x
+    W.ox = xpos ? ox + W.tx : ox;
+    W.oy = ypos ? oy + W.ty : oy;
+    // a step along +x is allowed while a < R - 2, along -x while a > 0
+    W.xe = xpos ? (float)(R - 2) : 0.f;
+    W.ye = ypos ? (float)(C - 2) : 0.f;
+    W.gx = xpos ? 1.f : -1.f;
+    W.gy = ypos ? 1.f : -1.f;
+    W.off = (unsigned)(a * C + b) * 4u;
+    W.offx = xpos ? 4u * (unsigned)C : 0u - 4u * (unsigned)C;
+    W.offy = ypos ? 4u : 0u - 4u;
     W.t0 = tl;
     W.z0 = __builtin_fmaf(tl, dz, qz);
     W.ekind = kPoint;
@@ -182,13 +188,19 @@ struct Step {
     bool edge, stepx;
 };
 
-__device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, float ox, float oy, float th) {
+// Height of the node `boff` bytes past H (the walk keeps byte offsets: the
+// address of a node is one add, with no scaling or base constant per cell).
+__device__ __forceinline__ float node_at(const float *H, unsigned boff) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(H) + boff);
+}
+
+__device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, float th) {
     Step s;
-    const float tnx = __builtin_fmaf(W.xl, W.tx, ox), tny = __builtin_fmaf(W.yl, W.ty, oy);
+    const float tnx = __builtin_fmaf(W.af, W.tx, W.ox), tny = __builtin_fmaf(W.bf, W.ty, W.oy);
     s.stepx = tnx <= tny;
     const float tn = s.stepx ? tnx : tny;
-    const float line = s.stepx ? W.xl : W.yl, last = s.stepx ? W.xe : W.ye;
-    const bool room = line != last;
+    const float cell = s.stepx ? W.af : W.bf, last = s.stepx ? W.xe : W.ye;
+    const bool room = cell != last;
     s.edge = (tn < th) && room;
     // max(min(tn, th), t0) as one median: t0 <= th along the walk, and tn is
     // finite or +inf (an axis-parallel ray has step 0 and offset +inf)
@@ -202,9 +214,8 @@ __device__ __forceinline__ void walk_advance(Walk &W, const Step &s) {
     // value selects (a branch here makes the compiler select between field
     // addresses and keep the walk state in scratch memory)
     const bool sx = s.stepx;
-    const float gx = 2.f * W.ax - 1.f, gy = 2.f * W.ay - 1.f;
-    W.xl = sx ? W.xl + gx : W.xl;
-    W.yl = sx ? W.yl : W.yl + gy;
+    W.af = sx ? W.af + W.gx : W.af;
+    W.bf = sx ? W.bf : W.bf + W.gy;
     W.off += sx ? W.offx : W.offy;
     W.ekind = sx ? kXEdge : kYEdge;
     W.t0 = s.t1;
@@ -294,7 +305,8 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     const int tid = threadIdx.x;
     if (P.only_nan && !(P.only_nan[chain] != P.only_nan[chain])) return;
     stage_surfaces<S, TOP_LDS, BLOCK>(P, sh, band, chain);
-    const int N = P.R * P.C, C = P.C;
+    const int N = P.R * P.C;
+    const unsigned C4 = 4u * (unsigned)P.C;
     double acc = 0.0;
     const int r0 = tile * P.rays_per_block;
     const int r1 = min(r0 + P.rays_per_block, P.n_ray);
@@ -324,10 +336,16 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
             const float th = fminf(fmaxf((band[kMaxSurfaces + l] - qz) * idz, 0.f), Texit);
             float L = tl;
             if (tl < th) {
-                Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, tl);
-                for (int it = 0; it < P.R + P.C; ++it) {
-                    const Step st = walk_step(W, qz, dz, ox, oy, th);
-                    const float h00 = Hl[W.off], h01 = Hl[W.off + 1], h10 = Hl[W.off + C], h11 = Hl[W.off + C + 1];
+                Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, ox, oy, tl);
+                // no step counter: every step moves one node line by one
+                // towards the grid's last line in its direction and the walk
+                // ends when the chosen line is that last one (or the next
+                // line parameter is not below th, NaN included), so it takes
+                // at most R + C - 2 steps
+                for (;;) {
+                    const Step st = walk_step(W, qz, dz, th);
+                    const float h00 = node_at(Hl, W.off), h01 = node_at(Hl, W.off + 4u);
+                    const float h10 = node_at(Hl, W.off + C4), h11 = node_at(Hl, W.off + C4 + 4u);
                     const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));
                     const float hmax = fmaxf(fmaxf(h00, h01), fmaxf(h10, h11));
                     if (st.z1 < hmin - P.margin) {
@@ -360,7 +378,7 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                                 const unsigned ri = rec_next[l][lane_t];
                                 if (ri < (unsigned)((l + 1) * X.slots * BLOCK))
                                     recb[ri] =
-                                        make_uint4((uint32_t)W.off | ((uint32_t)l << 16) | (kslot << 18),
+                                        make_uint4((W.off >> 2) | ((uint32_t)l << 16) | (kslot << 18),
                                                    __float_as_uint(sc), __float_as_uint(wc),
                                                    __float_as_uint(__builtin_amdgcn_rcpf(fp)));
                                 rec_next[l][lane_t] = ri + BLOCK;
