@@ -310,11 +310,14 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
     for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
         const int sidx = ray / P.n_pix;
         const float scale = gpbuf[(size_t)chain * P.n_ray + ray] * rho;   // (lambda - C)/Lambda (rho_l - rho_l+1)
-        const float qx = P.sensor[3 * sidx], qy = P.sensor[3 * sidx + 1], qz = P.sensor[3 * sidx + 2];
-        const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
+        const float qx = P.sensor[3 * sidx], qz = P.sensor[3 * sidx + 2];
+        const float dx = P.dx[ray], dz = P.dz[ray];
+        // the ray in cell units, as in the march
+        const float qxi = qx * P.ihx, qyi = P.sensor[3 * sidx + 1] * P.ihy;
+        const float dxi = dx * P.ihx, dyi = P.dy[ray] * P.ihy;
         const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
         const float ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
-        const float kxy = -(dx * P.ihx) * (dy * P.ihy);   // the march's curvature factor
+        const float kxy = -dxi * dyi;   // the march's curvature factor
         float tl = fminf(fmaxf((band[0] - qz) * idz, 0.f), Texit);
         float th = fminf(fmaxf((band[1] - qz) * idz, 0.f), Texit);
         if (W_.n_windows > 1) {
@@ -331,8 +334,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
             }
         }
         if (!(tl < th) || scale == 0.f) continue;
-        const bool xpos = dx > 0.f, ypos = dy > 0.f;
-        Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, ox, oy, tl);
+        Walk W = walk_init(P, qxi, qyi, qz, dxi, dyi, dz, idx, idy, ox, oy, tl);
         for (;;) {   // at most R + C - 2 steps, as in the march
             const Step st = walk_step(W, qz, dz, th);
             const int off = (int)(W.off >> 2);
@@ -342,19 +344,11 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
             // the cell's node rows a, a+1 must meet the window
             if (off + C + 1 >= lo && off < hi && !(st.z1 < hmin - P.margin) && !(W.z0 > hmax + P.margin) &&
                 st.t1 > W.t0) {
-                const Patch pt = make_patch(h00, h01, h10, h11);
-                const float t0 = W.t0, t1 = st.t1;
-                const float z0 = W.z0, z1 = st.z1;
-                const float se = __builtin_fmaf(__builtin_fmaf(t0, dx, qx), P.ihx, -walk_af(W));
-                const float we = __builtin_fmaf(__builtin_fmaf(t0, dy, qy), P.ihy, -walk_bf(W));
-                const float sx = __builtin_fmaf(__builtin_fmaf(t1, dx, qx), P.ihx, -walk_af(W));
-                const float wx = __builtin_fmaf(__builtin_fmaf(t1, dy, qy), P.ihy, -walk_bf(W));
-                const float fe = end_value(pt, W.ekind, !xpos, !ypos, z0, se, we);
-                const float fx = end_value(pt, st.xkind, xpos, ypos, z1, sx, wx);
-                const float c2 = (pt.dr1 - pt.dr0) * kxy;
-                const float tau1 = t1 - t0;
+                const float t0 = W.t0, tau1 = st.t1 - W.t0;
+                const float qxa = qxi - walk_af(W), qyb = qyi - walk_bf(W);
                 PieceCross pc;
-                (void)piece_length<true>(fe, fx, c2, tau1, &pc);
+                (void)solve_cell_piece<true>(h00, h01, h10, h11, qxa, qyb, dxi, dyi, kxy, W.t0, st.t1, W.z0, st.z1,
+                                             W.enx, W.eny, st.edge && st.stepx, st.edge && !st.stepx, &pc);
                 const float *fp = pc.fp;
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {   // at most two crossings; unrolled to keep them in registers
@@ -362,8 +356,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
                     if (!(fp[k] > 0.f)) continue;   // tangency: a kink of lp, no derivative
                     const float t = __builtin_fmaf(pc.s[k], tau1, t0);
                     if (__builtin_fmaf(t, dz, qz) >= P.lid) continue;   // the box lid: a kink
-                    const float s = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -walk_af(W)), 0.f), 1.f);
-                    const float w = fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -walk_bf(W)), 0.f), 1.f);
+                    const float s = fminf(fmaxf(__builtin_fmaf(t, dxi, qxa), 0.f), 1.f);
+                    const float w = fminf(fmaxf(__builtin_fmaf(t, dyi, qyb), 0.f), 1.f);
                     const float g = scale * __builtin_amdgcn_rcpf(fp[k]);
                     const float cv[4] = {g * (1.f - s) * (1.f - w), g * (1.f - s) * w, g * s * (1.f - w), g * s * w};
                     const int no[4] = {off, off + 1, off + C, off + C + 1};

@@ -4,12 +4,12 @@
 // below-lengths of every surface, paper Sec. 2.1.1), with the per-cell work
 // cut down for CDNA wavefronts:
 //
-//  * cell bookkeeping is incremental (node-line coordinates, LDS byte offset,
-//    remaining cells to the grid edge): no integer multiplies in the loop;
-//  * a piece's two end values share the row and column lerps of its patch and
-//    are formed with selects, without branches; they are bit-identical to the
-//    shared-edge formulas of march_common.h, so adjacent cells agree on every
-//    sign;
+//  * cell bookkeeping is incremental (cell indices as floats, byte offsets of
+//    the nodes): no integer multiplies in the loop, no step counter;
+//  * a piece's end values are bilinear values from lerps with exact end
+//    points, with the coordinate across a node line set to exactly 0 or 1, so
+//    two cells that share an edge compute the same bits there and agree on
+//    every sign;
 //  * the in-cell quadratic is solved without branches (hardware reciprocal and
 //    square root, 1 ulp each).
 //
@@ -76,56 +76,42 @@ __device__ __forceinline__ float piece_length(float fe, float fx, float c2, floa
     return (be != bx) ? one : (two ? twol : none);
 }
 
-// f = z - h at a piece end.  kind: 0 point, 1 x-edge, 2 y-edge; `xrow1`
-// (`ycol1`) selects the node row a+1 (column b+1) for an x-edge (y-edge).
-// Row lerps r0 (row a) and r1 (row a+1) run along w; column lerps c0, c1
-// along s; a point uses the bilinear value lerp(r0, r1, s).
-struct Patch {
-    float h00, h01, h10, h11, dr0, dr1, dc0, dc1;
-};
-
-__device__ __forceinline__ Patch make_patch(float h00, float h01, float h10, float h11) {
-    Patch p;
-    p.h00 = h00;
-    p.h01 = h01;
-    p.h10 = h10;
-    p.h11 = h11;
-    p.dr0 = h01 - h00;
-    p.dr1 = h11 - h10;
-    p.dc0 = h10 - h00;
-    p.dc1 = h11 - h01;
-    return p;
+// Bilinear height of a cell at local coordinates (s, w) in [0, 1]^2 from
+// lerps with exact end points: lerp(u, v, t) = t v + (u - t u) gives u at
+// t = 0 and v at t = 1 exactly.  A piece end on a node line takes that
+// coordinate exactly (0 or 1), so there the value is the plain lerp along the
+// shared edge, and the two cells that share the edge compute the same bits
+// (adjacent cells agree on every sign).
+__device__ __forceinline__ float lerp_exact(float u, float v, float t) {
+    return __builtin_fmaf(t, v, __builtin_fmaf(-t, u, u));
 }
 
-__device__ __forceinline__ float end_value(const Patch &p, int kind, bool xrow1, bool ycol1, float z, float s,
-                                           float w) {
-    const float r0 = __builtin_fmaf(w, p.dr0, p.h00), r1 = __builtin_fmaf(w, p.dr1, p.h10);
-    const float c0 = __builtin_fmaf(s, p.dc0, p.h00), c1 = __builtin_fmaf(s, p.dc1, p.h01);
-    const float hx = xrow1 ? r1 : r0;
-    const float hy = ycol1 ? c1 : c0;
-    const float hp = __builtin_fmaf(s, r1 - r0, r0);
-    const float h = kind == kXEdge ? hx : (kind == kYEdge ? hy : hp);
-    return z - h;
+__device__ __forceinline__ float cell_height(float h00, float h01, float h10, float h11, float s, float w) {
+    return lerp_exact(lerp_exact(h00, h01, w), lerp_exact(h10, h11, w), s);
 }
 
-// Below-length of one piece [t0, t1] of cell (af, bf) (cell origin indices
-// as floats) of a surface patch; z0, z1: the ray's heights at t0, t1 (the
-// walk's own values); kxy = -(d_x / h_x)(d_y / h_y), the ray's factor of the
-// patch curvature.
+// Below-length of one piece [t0, t1] of a cell with corner heights h00 (node
+// (a, b)), h01 (a, b+1), h10 (a+1, b), h11 (a+1, b+1).  The ray in cell
+// units: x / h_x = t dxi + qxi, so the local coordinate is s = t dxi + qxa
+// with qxa = qxi - a (w likewise with qyb = qyi - b).  z0, z1: the ray's
+// heights at t0, t1 (the walk's own values); enx (eny): the piece starts on
+// an x (y) node line, xedge (yedge): it ends on one; kxy = -dxi dyi, the
+// ray's factor of the patch curvature.
 template <bool REC = false>
-__device__ __forceinline__ float solve_cell_piece(const Patch &p, float af, float bf, float ihx, float ihy, float qx,
-                                                  float qy, float dx, float dy, float kxy, float t0, float t1,
-                                                  float z0, float z1, int ekind, int xkind,
+__device__ __forceinline__ float solve_cell_piece(float h00, float h01, float h10, float h11, float qxa, float qyb,
+                                                  float dxi, float dyi, float kxy, float t0, float t1, float z0,
+                                                  float z1, bool enx, bool eny, bool xedge, bool yedge,
                                                   PieceCross *pc = nullptr) {
-    const bool xpos = dx > 0.f, ypos = dy > 0.f;
-    const float se = __builtin_fmaf(__builtin_fmaf(t0, dx, qx), ihx, -af);
-    const float we = __builtin_fmaf(__builtin_fmaf(t0, dy, qy), ihy, -bf);
-    const float sx = __builtin_fmaf(__builtin_fmaf(t1, dx, qx), ihx, -af);
-    const float wx = __builtin_fmaf(__builtin_fmaf(t1, dy, qy), ihy, -bf);
-    // entry edge: row a+1 when moving -x, column b+1 when moving -y; exit: the opposite
-    const float fe = end_value(p, ekind, !xpos, !ypos, z0, se, we);
-    const float fx = end_value(p, xkind, xpos, ypos, z1, sx, wx);
-    const float c2 = (p.dr1 - p.dr0) * kxy;
+    const bool xpos = dxi > 0.f, ypos = dyi > 0.f;
+    // a walk along +x enters a cell on its row a (s = 0) and leaves on row
+    // a + 1 (s = 1); along -x the other way round (w, y likewise)
+    const float se = enx ? (xpos ? 0.f : 1.f) : __builtin_fmaf(t0, dxi, qxa);
+    const float we = eny ? (ypos ? 0.f : 1.f) : __builtin_fmaf(t0, dyi, qyb);
+    const float sx = xedge ? (xpos ? 1.f : 0.f) : __builtin_fmaf(t1, dxi, qxa);
+    const float wx = yedge ? (ypos ? 1.f : 0.f) : __builtin_fmaf(t1, dyi, qyb);
+    const float fe = z0 - cell_height(h00, h01, h10, h11, se, we);
+    const float fx = z1 - cell_height(h00, h01, h10, h11, sx, wx);
+    const float c2 = ((h11 - h10) - (h01 - h00)) * kxy;
     return piece_length<REC>(fe, fx, c2, t1 - t0, pc);
 }
 
@@ -142,20 +128,20 @@ struct Walk {
     float gx, gy;             // the index step along x and y (+1 or -1)
     unsigned off, offx, offy; // byte offset of node (a, b) in the surface and its steps (mod 2^32)
     float t0, z0;
-    int ekind;
+    bool enx, eny;            // the current piece starts on an x (y) node line
 };
 
 __device__ __forceinline__ float walk_af(const Walk &W) { return W.af; }
 __device__ __forceinline__ float walk_bf(const Walk &W) { return W.bf; }
 
+// The ray in cell units: x / h_x = t dxi + qxi, y / h_y = t dyi + qyi.
 // ox, oy: the ray's parameter at the node lines x = 0 and y = 0 (+inf for a
 // ray parallel to that axis, whose step tx or ty is then 0).
-__device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx, float qy, float qz, float dx,
-                                          float dy, float dz, float idx, float idy, float ox, float oy, float tl) {
+__device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qxi, float qyi, float qz, float dxi,
+                                          float dyi, float dz, float idx, float idy, float ox, float oy, float tl) {
     const int R = P.R, C = P.C;
-    const bool xpos = dx > 0.f, ypos = dy > 0.f;
-    const float x0 = __builtin_fmaf(tl, dx, qx), y0 = __builtin_fmaf(tl, dy, qy);
-    int a = (int)floorf(x0 * P.ihx), b = (int)floorf(y0 * P.ihy);
+    const bool xpos = dxi > 0.f, ypos = dyi > 0.f;
+    int a = (int)floorf(__builtin_fmaf(tl, dxi, qxi)), b = (int)floorf(__builtin_fmaf(tl, dyi, qyi));
     a = a < 0 ? 0 : (a > R - 2 ? R - 2 : a);
     b = b < 0 ? 0 : (b > C - 2 ? C - 2 : b);
     Walk W;
@@ -176,7 +162,7 @@ __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx,
     W.offy = ypos ? 4u : 0u - 4u;
     W.t0 = tl;
     W.z0 = __builtin_fmaf(tl, dz, qz);
-    W.ekind = kPoint;
+    W.enx = W.eny = false;
     return W;
 }
 
@@ -184,7 +170,6 @@ __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qx,
 // classification; `edge` says whether the walk continues.
 struct Step {
     float t1, z1;
-    int xkind;
     bool edge, stepx;
 };
 
@@ -206,7 +191,6 @@ __device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, flo
     // finite or +inf (an axis-parallel ray has step 0 and offset +inf)
     s.t1 = __builtin_amdgcn_fmed3f(tn, th, W.t0);
     s.z1 = __builtin_fmaf(s.t1, dz, qz);
-    s.xkind = s.edge ? (s.stepx ? kXEdge : kYEdge) : kPoint;
     return s;
 }
 
@@ -217,7 +201,8 @@ __device__ __forceinline__ void walk_advance(Walk &W, const Step &s) {
     W.af = sx ? W.af + W.gx : W.af;
     W.bf = sx ? W.bf : W.bf + W.gy;
     W.off += sx ? W.offx : W.offy;
-    W.ekind = sx ? kXEdge : kYEdge;
+    W.enx = sx;
+    W.eny = !sx;
     W.t0 = s.t1;
     W.z0 = s.z1;
 }
@@ -323,11 +308,13 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     uint4 *const recb = X.rec + (size_t)(chain * P.n_tiles + tile) * S * (size_t)X.slots * BLOCK;
     for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
         const int s = ray / P.n_pix;
-        const float qx = P.sensor[3 * s], qy = P.sensor[3 * s + 1], qz = P.sensor[3 * s + 2];
-        const float dx = P.dx[ray], dy = P.dy[ray], dz = P.dz[ray];
+        const float qz = P.sensor[3 * s + 2], dz = P.dz[ray];
+        // the ray in cell units
+        const float qxi = P.sensor[3 * s] * P.ihx, qyi = P.sensor[3 * s + 1] * P.ihy;
+        const float dxi = P.dx[ray] * P.ihx, dyi = P.dy[ray] * P.ihy;
         const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
         const float ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
-        const float kxy = -(dx * P.ihx) * (dy * P.ihy);
+        const float kxy = -dxi * dyi;
         float O = 0.f;
 #pragma unroll
         for (int l = 0; l < S; ++l) {
@@ -336,7 +323,7 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
             const float th = fminf(fmaxf((band[kMaxSurfaces + l] - qz) * idz, 0.f), Texit);
             float L = tl;
             if (tl < th) {
-                Walk W = walk_init(P, qx, qy, qz, dx, dy, dz, idx, idy, ox, oy, tl);
+                Walk W = walk_init(P, qxi, qyi, qz, dxi, dyi, dz, idx, idy, ox, oy, tl);
                 // no step counter: every step moves one node line by one
                 // towards the grid's last line in its direction and the walk
                 // ends when the chosen line is that last one (or the next
@@ -351,11 +338,12 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                     if (st.z1 < hmin - P.margin) {
                         L += st.t1 - W.t0;
                     } else if (!(W.z0 > hmax + P.margin) && st.t1 > W.t0) {
-                        const Patch pt = make_patch(h00, h01, h10, h11);
+                        const float qxa = qxi - walk_af(W), qyb = qyi - walk_bf(W);
+                        const bool xedge = st.edge && st.stepx, yedge = st.edge && !st.stepx;
                         if constexpr (REC) {
                             PieceCross pc;
-                            L += solve_cell_piece<true>(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, dx, dy, kxy,
-                                                        W.t0, st.t1, W.z0, st.z1, W.ekind, st.xkind, &pc);
+                            L += solve_cell_piece<true>(h00, h01, h10, h11, qxa, qyb, dxi, dyi, kxy, W.t0, st.t1, W.z0,
+                                                        st.z1, W.enx, W.eny, xedge, yedge, &pc);
                             const float tau1 = st.t1 - W.t0;
                             // at most two crossings: unrolled, so the crossing
                             // data stay in registers (an indexed array would
@@ -367,10 +355,8 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                                 if (!(fp > 0.f)) continue;   // tangency: a kink of lp, no derivative
                                 const float t = __builtin_fmaf(pc.s[k], tau1, W.t0);
                                 if (__builtin_fmaf(t, dz, qz) >= P.lid) continue;   // the box lid: a kink
-                                const float sc =
-                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dx, qx), P.ihx, -walk_af(W)), 0.f), 1.f);
-                                const float wc =
-                                    fminf(fmaxf(__builtin_fmaf(__builtin_fmaf(t, dy, qy), P.ihy, -walk_bf(W)), 0.f), 1.f);
+                                const float sc = fminf(fmaxf(__builtin_fmaf(t, dxi, qxa), 0.f), 1.f);
+                                const float wc = fminf(fmaxf(__builtin_fmaf(t, dyi, qyb), 0.f), 1.f);
                                 // the thread and its ray slot follow from the ray index
                                 // (ray = r0 + tid + kslot BLOCK): nothing more to keep live
                                 const unsigned rr = (unsigned)(ray - r0);
@@ -384,8 +370,8 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
                                 rec_next[l][lane_t] = ri + BLOCK;
                             }
                         } else {
-                            L += solve_cell_piece(pt, walk_af(W), walk_bf(W), P.ihx, P.ihy, qx, qy, dx, dy, kxy, W.t0,
-                                                  st.t1, W.z0, st.z1, W.ekind, st.xkind);
+                            L += solve_cell_piece(h00, h01, h10, h11, qxa, qyb, dxi, dyi, kxy, W.t0, st.t1, W.z0,
+                                                  st.z1, W.enx, W.eny, xedge, yedge);
                         }
                     }
                     if (!st.edge) break;
