@@ -56,17 +56,15 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # (FETCH_SIZE reads 131089 KiB for 262144 KiB moved: scale 2.0; WRITE_SIZE
 # reads exactly: scale 1.0).  Valid only for the kernel sources they were
 # taken on: the entry is dropped when the hash of those sources changes.
-# At 6 wavefronts per SIMD the march spills 32 bytes per lane to scratch
-# (around the ray loop, not inside the walk); the dirty scratch lines written
-# back are most of WRITE_SIZE.
+# The march keeps nothing in scratch: its WRITE_SIZE is the partial sums.
 KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march_common.h", "march3.h", "march5.h"),
                   "voxel64": ("device_common.h", "voxel.h"),
                   "grad128_adjoint": ("device_common.h", "march_common.h", "march5.h", "adjoint.h")}
 MEASURED_TRAFFIC = {
-    "grf_cave_64": dict(source_sha="d7477b7a2404e879", fetch_kib=30733.2, fetch_scale=262144 / 131093.9,
-                        write_kib=56947.0, write_scale=1.0),
+    "grf_cave_64": dict(source_sha="4cf98bfab8e32aec", fetch_kib=23165.0, fetch_scale=262144 / 131088.5,
+                        write_kib=32.0, write_scale=1.0),
     # k_adjoint_rec on the 128x128 gradient workload (512 chains)
-    "grad128_adjoint": dict(source_sha="1a3ab50f289ea46e", fetch_kib=429639.0, fetch_scale=262144 / 131093.9,
+    "grad128_adjoint": dict(source_sha="97428600c1bb92f1", fetch_kib=429636.5, fetch_scale=262144 / 131093.2,
                             write_kib=196608.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
@@ -80,11 +78,11 @@ MEASURED_TRAFFIC = {
 # SQ_BUSY_CU_CYCLES SQ_INSTS_SALU GRBM_GUI_ACTIVE GRBM_COUNT with the kernel
 # trace, same run; same source hash rule as the traffic).  GRBM_GUI_ACTIVE is
 # summed over the 8 XCDs.  The FMA probe of the same run reads exactly its
-# known instruction count (32768 waves x 2^16 x 8 = 1.718e10) at 0.967
+# known instruction count (32768 waves x 2^16 x 8 = 1.718e10) at 0.969
 # instructions per CU-clock, the full-lane issue limit.
 MEASURED_VALU = {
-    "grf_cave_64": dict(source_sha="d7477b7a2404e879", valu_insts=1.046e9, thread_cycles_valu=3.149e10,
-                        active_inst_valu=1.066e9, grbm_gui_active_per_xcd=2.793e6, cus=256),
+    "grf_cave_64": dict(source_sha="4cf98bfab8e32aec", valu_insts=8.782e8, thread_cycles_valu=2.805e10,
+                        active_inst_valu=8.988e8, grbm_gui_active_per_xcd=2.415e6, cus=256),
 }
 
 

@@ -334,9 +334,9 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
             }
         }
         if (!(tl < th) || scale == 0.f) continue;
-        Walk W = walk_init(P, qxi, qyi, qz, dxi, dyi, dz, idx, idy, ox, oy, tl);
-        for (;;) {   // at most R + C - 2 steps, as in the march
-            const Step st = walk_step(W, qz, dz, th);
+        Walk W = walk_init(P, qxi, qyi, qz, dxi, dyi, dz, idx, idy, ox, oy, tl, th);
+        for (;;) {   // at most R + C - 4 steps, as in the march
+            const Step st = walk_step(W, qz, dz);
             const int off = (int)(W.off >> 2);
             const float h00 = Hl[off], h01 = Hl[off + 1], h10 = Hl[off + C], h11 = Hl[off + C + 1];
             const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));

@@ -124,7 +124,7 @@ struct Walk {
     float af, bf;             // cell origin indices (a, b) as floats (exact small integers)
     float tx, ty;             // h_x / d_x, h_y / d_y: parameter step per cell
     float ox, oy;             // parameter of the exit line of cell index 0 in the walk's direction
-    float xe, ye;             // the last cell index in the walk's x and y directions
+    float th;                 // end of the walk: the band end, or the grid edge if that comes first
     float gx, gy;             // the index step along x and y (+1 or -1)
     unsigned off, offx, offy; // byte offset of node (a, b) in the surface and its steps (mod 2^32)
     float t0, z0;
@@ -138,7 +138,8 @@ __device__ __forceinline__ float walk_bf(const Walk &W) { return W.bf; }
 // ox, oy: the ray's parameter at the node lines x = 0 and y = 0 (+inf for a
 // ray parallel to that axis, whose step tx or ty is then 0).
 __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qxi, float qyi, float qz, float dxi,
-                                          float dyi, float dz, float idx, float idy, float ox, float oy, float tl) {
+                                          float dyi, float dz, float idx, float idy, float ox, float oy, float tl,
+                                          float th) {
     const int R = P.R, C = P.C;
     const bool xpos = dxi > 0.f, ypos = dyi > 0.f;
     int a = (int)floorf(__builtin_fmaf(tl, dxi, qxi)), b = (int)floorf(__builtin_fmaf(tl, dyi, qyi));
@@ -152,9 +153,14 @@ __device__ __forceinline__ Walk walk_init(const MarchParams<float> &P, float qxi
     // the exit line of cell a is a + 1 along +x and a along -x
     W.ox = xpos ? ox + W.tx : ox;
     W.oy = ypos ? oy + W.ty : oy;
-    // a step along +x is allowed while a < R - 2, along -x while a > 0
-    W.xe = xpos ? (float)(R - 2) : 0.f;
-    W.ye = ypos ? (float)(C - 2) : 0.f;
+    // the last cells in the walk's directions are xe = R - 2 or 0 (ye = C - 2
+    // or 0), whose exit lines are the grid edge: th is clipped to their
+    // parameters.  A step along x needs t(af) < th <= t(xe), so af != xe (equal
+    // indices give equal bits): a and b move one by one toward xe and ye and
+    // never past them, every cell of the walk is inside the grid, and the walk
+    // takes at most R + C - 4 steps
+    const float xe = xpos ? (float)(R - 2) : 0.f, ye = ypos ? (float)(C - 2) : 0.f;
+    W.th = fminf(th, fminf(__builtin_fmaf(xe, W.tx, W.ox), __builtin_fmaf(ye, W.ty, W.oy)));
     W.gx = xpos ? 1.f : -1.f;
     W.gy = ypos ? 1.f : -1.f;
     W.off = (unsigned)(a * C + b) * 4u;
@@ -173,23 +179,39 @@ struct Step {
     bool edge, stepx;
 };
 
+// Minimum (maximum) of four corner heights in two instructions.  Written in
+// assembly because the compiler canonicalizes the loaded operands of a
+// two-operand min or max first (two more instructions per cell); the heights
+// are finite, for which canonicalizing changes nothing.
+__device__ __forceinline__ float min4(float a, float b, float c, float d) {
+    float m, r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(m) : "v"(c), "v"(d));
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(m));
+    return r;
+}
+
+__device__ __forceinline__ float max4(float a, float b, float c, float d) {
+    float m, r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(m) : "v"(c), "v"(d));
+    asm("v_max3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(m));
+    return r;
+}
+
 // Height of the node `boff` bytes past H (the walk keeps byte offsets: the
 // address of a node is one add, with no scaling or base constant per cell).
 __device__ __forceinline__ float node_at(const float *H, unsigned boff) {
     return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(H) + boff);
 }
 
-__device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz, float th) {
+__device__ __forceinline__ Step walk_step(const Walk &W, float qz, float dz) {
     Step s;
     const float tnx = __builtin_fmaf(W.af, W.tx, W.ox), tny = __builtin_fmaf(W.bf, W.ty, W.oy);
     s.stepx = tnx <= tny;
     const float tn = s.stepx ? tnx : tny;
-    const float cell = s.stepx ? W.af : W.bf, last = s.stepx ? W.xe : W.ye;
-    const bool room = cell != last;
-    s.edge = (tn < th) && room;
+    s.edge = tn < W.th;
     // max(min(tn, th), t0) as one median: t0 <= th along the walk, and tn is
     // finite or +inf (an axis-parallel ray has step 0 and offset +inf)
-    s.t1 = __builtin_amdgcn_fmed3f(tn, th, W.t0);
+    s.t1 = __builtin_amdgcn_fmed3f(tn, W.th, W.t0);
     s.z1 = __builtin_fmaf(s.t1, dz, qz);
     return s;
 }
@@ -323,18 +345,13 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
             const float th = fminf(fmaxf((band[kMaxSurfaces + l] - qz) * idz, 0.f), Texit);
             float L = tl;
             if (tl < th) {
-                Walk W = walk_init(P, qxi, qyi, qz, dxi, dyi, dz, idx, idy, ox, oy, tl);
-                // no step counter: every step moves one node line by one
-                // towards the grid's last line in its direction and the walk
-                // ends when the chosen line is that last one (or the next
-                // line parameter is not below th, NaN included), so it takes
-                // at most R + C - 2 steps
+                Walk W = walk_init(P, qxi, qyi, qz, dxi, dyi, dz, idx, idy, ox, oy, tl, th);
+                // no step counter: the walk ends within R + C - 4 steps (walk_init)
                 for (;;) {
-                    const Step st = walk_step(W, qz, dz, th);
+                    const Step st = walk_step(W, qz, dz);
                     const float h00 = node_at(Hl, W.off), h01 = node_at(Hl, W.off + 4u);
                     const float h10 = node_at(Hl, W.off + C4), h11 = node_at(Hl, W.off + C4 + 4u);
-                    const float hmin = fminf(fminf(h00, h01), fminf(h10, h11));
-                    const float hmax = fmaxf(fmaxf(h00, h01), fmaxf(h10, h11));
+                    const float hmin = min4(h00, h01, h10, h11), hmax = max4(h00, h01, h10, h11);
                     if (st.z1 < hmin - P.margin) {
                         L += st.t1 - W.t0;
                     } else if (!(W.z0 > hmax + P.margin) && st.t1 > W.t0) {
