@@ -64,8 +64,8 @@ MEASURED_TRAFFIC = {
     "grf_cave_64": dict(source_sha="4cf98bfab8e32aec", fetch_kib=23165.0, fetch_scale=262144 / 131088.5,
                         write_kib=32.0, write_scale=1.0),
     # k_adjoint_rec on the 128x128 gradient workload (512 chains)
-    "grad128_adjoint": dict(source_sha="97428600c1bb92f1", fetch_kib=429636.5, fetch_scale=262144 / 131093.2,
-                            write_kib=196608.0, write_scale=1.0),
+    "grad128_adjoint": dict(source_sha="97428600c1bb92f1", shape=(1024, 16), fetch_kib=429636.5,
+                            fetch_scale=262144 / 131093.2, write_kib=196608.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
     "voxel64": dict(source_sha="a54470c4ae3bcfc7", fetch_kib=2433874.6, fetch_scale=262144 / 131093.7,
@@ -110,9 +110,13 @@ def kernel_source_sha(name):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name):
+def measured_traffic(name, shape=None):
+    """Stored HBM bytes per launch (None when the kernel sources, or the
+    launch shape (block, rays per thread) where one is stored, differ)."""
     m = MEASURED_TRAFFIC.get(name)
     if m is None or m["source_sha"] != kernel_source_sha(name):
+        return None
+    if shape is not None and "shape" in m and tuple(m["shape"]) != tuple(shape):
         return None
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024
 
@@ -376,7 +380,7 @@ def bench_grad(args, torch):
     """Gradient-driven sampling on the 128x128 geometry: full log-posterior +
     gradient evaluations (forward march, adjoint march, prior gradient) and
     MALA steps on 512 chains; HBM roofline of the record adjoint."""
-    from paper_2603_28907_amd import binding, inputs
+    from paper_2603_28907_amd import autotune, binding, inputs
     from paper_2603_28907_amd.binding import KERNEL_MALA, Problem
     sc = inputs.grf_cave(seed=10, n_grid=128)
     n_chains, eps = 512, args.mala_eps
@@ -385,6 +389,9 @@ def bench_grad(args, torch):
     H = torch.as_tensor(inputs.init_states(sc, n_chains, seed=12), dtype=torch.float32, device="cuda:0")
     lp = torch.empty(n_chains, dtype=torch.float64, device="cuda:0")
     g = torch.empty((n_chains, 3, 128, 128), dtype=torch.float32, device="cuda:0")
+    tuned = autotune.tune_gradient(prob, H)   # launch shape of the gradient for these chains
+    print(f"[bench] gradient launch shape {tuned['tuning']['block']}x{tuned['tuning']['rays_per_thread']}",
+          file=sys.stderr, flush=True)
     prob.logpost_grad_batch(H, lp, g)
     torch.cuda.synchronize()
     k = max(1, args.steps // 10)
@@ -423,8 +430,10 @@ def bench_grad(args, torch):
         "accept_rate": float((acc - a0).double().mean().item()) / args.steps,
         "gradient_evals_per_s": n_chains / dt_grad, "ms_per_gradient_eval": dt_grad * 1e3,
         "forward_ms_per_launch": ms_fwd,
+        "launch_shape": {"block": t["block"], "rays_per_thread": t["rays_per_thread"], "autotuned": True},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("grad128_adjoint"),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("grad128_adjoint", (t["block"], t["rays_per_thread"])),
                      "traffic_unit": "bytes per launch", "algorithmic_bytes": abytes, "kernel": "k_adjoint_rec",
                      "ms_per_launch": ms_adj, "rays_per_launch": n_chains * sc.n_rays},
     }
@@ -566,7 +575,7 @@ def bench_nuts(args, torch):
     their initial states, a short warm-up (dual averaging and windowed
     diagonal mass), then timed transitions; nested R-hat of the final states.
     Roofline of the adjoint march, the dominant kernel of each leapfrog step."""
-    from paper_2603_28907_amd import binding, inputs
+    from paper_2603_28907_amd import autotune, binding, inputs
     from paper_2603_28907_amd.binding import Problem
     sc, _, w = make_workload("grf_cave_64")
     sc.counts = gpu_counts(sc, torch)
@@ -575,6 +584,9 @@ def bench_nuts(args, torch):
     n = n_super * n_within
     starts = inputs.init_states(sc, n_super, seed=w["init_seed"], jitter=args.nuts_jitter)
     H = torch.as_tensor(np.repeat(starts, n_within, axis=0), dtype=torch.float32, device="cuda:0").contiguous()
+    tuned = autotune.tune_gradient(prob, H)   # launch shape of the gradient for these chains
+    print(f"[bench] gradient launch shape {tuned['tuning']['block']}x{tuned['tuning']['rays_per_thread']}: "
+          f"{tuned['ms']:.3f} ms per evaluation", file=sys.stderr, flush=True)
     latent = not args.nuts_heights
     if latent:   # the paper's parametrisation: the CAR fields behind the heights
         H = prob.heights_to_latent(H)
@@ -619,6 +631,7 @@ def bench_nuts(args, torch):
         "mean_accept_stat": float(st["accept_stat"].mean().item()),
         "step_size_median": float(eps.median().item()),
         "nested_rhat_max": float(rhat.max().item()), "warmup_s": t_warm,
+        "launch_shape": {"block": t["block"], "rays_per_thread": t["rays_per_thread"], "autotuned": True},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": abytes,
                      "kernel": "k_adjoint_rec", "ms_per_launch": ms_adj, "rays_per_launch": n * sc.n_rays},

@@ -1,8 +1,9 @@
-"""Launch-shape autotuner for the ray-march kernel.
+"""Launch-shape autotuner for the ray-march kernel and the gradient.
 
 For one problem the tuner times the march kernel (HIP events on the given
 stream, through mc_time_march) over a small grid of launch shapes and keeps
-the fastest.  For a heterogeneous batch it tunes one representative problem
+the fastest; tune_gradient does the same for the log posterior + gradient
+evaluation.  For a heterogeneous batch it tunes one representative problem
 per grid class -- (surfaces, rows, cols, precision) -- and applies the winner
 to every problem of that class, so mcmc_run_multi then groups the class into
 one launch of that shape.  Results are cached in memory and, when a path is
@@ -21,6 +22,10 @@ from typing import Dict, Iterable, Optional, Sequence
 F32_SHAPES = [dict(march_variant=4, block=b, rays_per_thread=r, top_in_lds=0)
               for b in (256, 512, 1024) for r in (2, 4, 8, 16)]
 F64_SHAPES = [dict(march_variant=3, block=256, rays_per_thread=r, top_in_lds=1) for r in (1, 2, 4, 8)]
+# the gradient (march with crossing records, record adjoint): 512- and
+# 1024-thread blocks (256-thread blocks lose to both on every grid measured)
+GRAD_SHAPES = [dict(march_variant=4, block=b, rays_per_thread=r, top_in_lds=0)
+               for b in (512, 1024) for r in (4, 8, 16)]
 
 _memo: Dict[str, dict] = {}
 
@@ -56,6 +61,51 @@ def tune_problem(problem, heights, shapes: Optional[Sequence[dict]] = None, iter
         except MuonCaveError:
             continue
         trials.append((t, ms))
+    if not trials:
+        problem.set_tuning(**base)
+        return {"tuning": base, "ms": float("nan"), "trials": []}
+    best, ms = min(trials, key=lambda x: x[1])
+    problem.set_tuning(**best)
+    return {"tuning": best, "ms": ms, "trials": trials}
+
+
+def tune_gradient(problem, heights, shapes: Optional[Sequence[dict]] = None, iters: int = 5,
+                  stream=None) -> dict:
+    """Time the log posterior + gradient evaluation (logpost_grad_batch: the
+    gradient march, the adjoint and the prior gradient) on `heights` for every
+    shape, with HIP events on the stream, and leave the fastest set on the
+    problem.  The best shape depends on the chain count as well as the grid
+    (few chains leave too few blocks for the GPU at many rays per thread), so
+    the caller tunes with the chains it will run.  Float32 problems only; a
+    float64 problem keeps its shape.  Returns {"tuning":..., "ms":...,
+    "trials": [(shape, ms), ...]}."""
+    import torch
+    from .binding import MuonCaveError
+    base = problem.get_tuning()
+    if problem.n_rays == 0 or problem.precision != "f32":
+        return {"tuning": base, "ms": float("nan"), "trials": []}
+    if shapes is None:
+        shapes = GRAD_SHAPES
+    n = int(heights.shape[0])
+    lp = torch.empty(n, dtype=torch.float64, device=heights.device)
+    g = torch.empty((n, problem.S, problem.R, problem.C), dtype=torch.float32, device=heights.device)
+    s = stream if stream is not None else torch.cuda.current_stream(heights.device)
+    trials = []
+    for sh in shapes:
+        t = dict(base)
+        t.update(sh)
+        try:
+            problem.set_tuning(**t)
+            problem.logpost_grad_batch(heights, lp, g, stream=s)   # code load, workspaces
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(iters):
+                problem.logpost_grad_batch(heights, lp, g, stream=s)
+            e1.record(s)
+            e1.synchronize()
+        except MuonCaveError:
+            continue
+        trials.append((t, e0.elapsed_time(e1) / iters))
     if not trials:
         problem.set_tuning(**base)
         return {"tuning": base, "ms": float("nan"), "trials": []}

@@ -285,3 +285,30 @@ def test_gradient_equal_across_launch_shapes(torch_mod, oracle_mod):
             ref = g.clone()
         say(f"gradient at block {block} x {rpt}: bitwise {torch.equal(g, ref)}")
         assert torch.equal(g, ref), (block, rpt)
+
+
+@pytest.mark.gpu
+def test_gradient_autotune_keeps_the_gradient(torch_mod, oracle_mod):
+    """The gradient tuner times every candidate shape, leaves the fastest one
+    set, and the gradient at that shape equals the one at the default shape
+    bit for bit (launch shape changes performance only)."""
+    from paper_2603_28907_amd import autotune
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    sc = inputs.grf_cave(seed=14, n_grid=32, n_sensors=4, pix_side=32)
+    sc.counts = oracle_mod.make_counts(sc, seed=15)
+    prob = Problem.from_scenario(sc, precision="f32")
+    H = to_dev(inputs.init_states(sc, 24, seed=17), torch.float32)
+    _, g0 = prob.logpost_grad_batch(H)
+    torch.cuda.synchronize()
+    res = autotune.tune_gradient(prob, H, iters=2)
+    shapes = [(t["block"], t["rays_per_thread"]) for t, _ in res["trials"]]
+    say(f"trials {[(b, r, round(ms, 4)) for (b, r), (_, ms) in zip(shapes, res['trials'])]}")
+    assert len(res["trials"]) == len(autotune.GRAD_SHAPES)
+    assert all(ms > 0 for _, ms in res["trials"])
+    best = min(res["trials"], key=lambda x: x[1])[0]
+    t = prob.get_tuning()
+    assert (t["block"], t["rays_per_thread"]) == (best["block"], best["rays_per_thread"])
+    _, g1 = prob.logpost_grad_batch(H)
+    torch.cuda.synchronize()
+    assert torch.equal(g0, g1)
