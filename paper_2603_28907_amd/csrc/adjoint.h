@@ -239,18 +239,20 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(MarchParams<T> P, RayConsts<T
 // ---------------------------------------------------------------------------
 
 // float32 adjoint by re-walking the rays (the chains whose crossing records
-// overflowed), per-node sums formed in LDS.  One block = one (chain, ray
-// tile, surface l, window of node rows): it stages surface l, zeroes 64-bit
-// fixed-point accumulators for the window's nodes, walks the tile's rays
-// through surface l (the walk and classification of k_march_lik4, started at
-// the band window or, with several windows, at the first cell whose node rows
-// can meet the window: the walk's node lines are integer indices, so either
-// start reproduces the forward walk's bits), adds each crossing's four node
-// contributions that fall in the window with LDS integer atomics, and finally
-// adds every accumulator to the chain's gradient with one global atomic.
-// Integer sums are order-independent, so the result is bitwise reproducible
-// and equals the record adjoint's.  Blocks of chains whose records are
-// complete (ovf[chain] == 0) exit at once.
+// overflowed), per-node sums formed in LDS.  One block = one (chain, surface
+// l, window of node rows): it stages surface l, zeroes 64-bit fixed-point
+// accumulators for the window's nodes, walks every ray of the chain through
+// surface l (the walk and classification of k_march_lik4, started at the
+// band window or, with several windows, at the first cell whose node rows can
+// meet the window: the walk's cell indices are integers, so either start
+// reproduces the forward walk's bits), adds each crossing's four node
+// contributions that fall in the window with LDS integer atomics, and stores
+// the window into the chain's gradient (the block owns those nodes; the
+// record adjoint wrote zeros there for this chain).  Integer sums are
+// order-independent, so the result is bitwise reproducible and equals the
+// record adjoint's.  Blocks of chains whose records are complete
+// (ovf[chain] == 0) exit at once: the grid has no per-tile blocks, so the
+// launch costs little when no chain overflowed.
 struct AdjointLdsShape {
     int n_windows, window_rows;
 };
@@ -262,13 +264,10 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
     __shared__ float band[2];
     __shared__ float wred[2][BLOCK / kWave];
     const int tid = threadIdx.x;
-    const int n_sub = P.n_tiles * S * W_.n_windows;
     int chain, sub;
-    if (!xcd_chain_tile(n_sub, P.n_chains, chain, sub)) return;
+    if (!xcd_chain_tile(S * W_.n_windows, P.n_chains, chain, sub)) return;
     if (!ovf[chain]) return;
-    const int tile = sub / (S * W_.n_windows);
-    const int rem = sub - tile * S * W_.n_windows;
-    const int l = rem / W_.n_windows, win = rem - l * W_.n_windows;
+    const int l = sub / W_.n_windows, win = sub - l * W_.n_windows;
     const int N = P.R * P.C, C = P.C;
     const int row0 = win * W_.window_rows;
     const int rows = min(W_.window_rows, P.R - row0);
@@ -305,9 +304,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
     }
     const float rho = P.rho_diff[l];
     const int lo = row0 * C, hi = (row0 + rows) * C;   // node offsets of the window
-    const int r0 = tile * P.rays_per_block;
-    const int r1 = min(r0 + P.rays_per_block, P.n_ray);
-    for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
+    for (int ray = tid; ray < P.n_ray; ray += BLOCK) {
         const int sidx = ray / P.n_pix;
         const float scale = gpbuf[(size_t)chain * P.n_ray + ray] * rho;   // (lambda - C)/Lambda (rho_l - rho_l+1)
         const float qx = P.sensor[3 * sidx], qz = P.sensor[3 * sidx + 2];
@@ -376,10 +373,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
     }
     __syncthreads();
     unsigned long long *G = gfix + ((size_t)chain * S + l) * N + lo;
-    for (int i = tid; i < rows * C; i += BLOCK) {
-        const unsigned long long v = acc[i];
-        if (v) atomicAdd(G + i, v);
-    }
+    for (int i = tid; i < rows * C; i += BLOCK) G[i] = acc[i];
 }
 
 // float32 adjoint from the crossing records of the gradient march (no walk).
@@ -416,19 +410,33 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_rec(MarchParams<float> P, Cro
             const int ray0 = tile * P.rays_per_block;
             for (int j = tid; j < fwd_block; j += BLOCK) {
                 const int n = (int)cnt[j];
-                for (int k = 0; k < n; ++k) {
-                    const uint4 r = rec[(size_t)k * fwd_block + j];
-                    const int off = (int)(r.x & 0xFFFFu), ks = (int)((r.x >> 18) & 0x3Fu);
-                    if (off + C + 1 < lo || off >= hi) continue;   // the cell's node rows miss the window
-                    const float g = (gpc[ray0 + j + ks * fwd_block] * rho) * __uint_as_float(r.w);
-                    const float s = __uint_as_float(r.y), w = __uint_as_float(r.z);
-                    const float cv[4] = {g * (1.f - s) * (1.f - w), g * (1.f - s) * w, g * s * (1.f - w), g * s * w};
-                    const int no[4] = {off, off + 1, off + C, off + C + 1};
+                // four records at a time: their loads, then the dLL/dO gathers
+                // they name, are all in flight before the first is used
+                for (int k0 = 0; k0 < n; k0 += 4) {
+                    uint4 r[4];
+                    float gv[4];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        if (no[m] >= lo && no[m] < hi) {
-                            const float sv = fminf(fmaxf(cv[m] * 4294967296.0f, -9.0e18f), 9.0e18f);
-                            atomicAdd(acc + (no[m] - lo), (unsigned long long)(long long)__builtin_rintf(sv));
+                    for (int u = 0; u < 4; ++u)
+                        if (k0 + u < n) r[u] = rec[(size_t)(k0 + u) * fwd_block + j];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (k0 + u < n) gv[u] = gpc[ray0 + j + (int)((r[u].x >> 18) & 0x3Fu) * fwd_block];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (k0 + u >= n) break;
+                        const int off = (int)(r[u].x & 0xFFFFu);
+                        if (off + C + 1 < lo || off >= hi) continue;   // the cell's node rows miss the window
+                        const float g = (gv[u] * rho) * __uint_as_float(r[u].w);
+                        const float s = __uint_as_float(r[u].y), w = __uint_as_float(r[u].z);
+                        const float cv[4] = {g * (1.f - s) * (1.f - w), g * (1.f - s) * w, g * s * (1.f - w),
+                                             g * s * w};
+                        const int no[4] = {off, off + 1, off + C, off + C + 1};
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            if (no[m] >= lo && no[m] < hi) {
+                                const float sv = fminf(fmaxf(cv[m] * 4294967296.0f, -9.0e18f), 9.0e18f);
+                                atomicAdd(acc + (no[m] - lo), (unsigned long long)(long long)__builtin_rintf(sv));
+                            }
                         }
                     }
                 }

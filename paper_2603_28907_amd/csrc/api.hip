@@ -762,7 +762,7 @@ mc_status launch_adjoint(mc_problem *p, int n, const T *heights, unsigned long l
         if (p->tune.adjoint_rows > 0) w.window_rows = std::min(w.window_rows, p->tune.adjoint_rows);
         w.n_windows = (p->R + w.window_rows - 1) / w.window_rows;
         const size_t lds = surf + (size_t)w.window_rows * row_bytes;
-        const dim3 grid((unsigned)(M.n_tiles * S * w.n_windows) * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
+        const dim3 grid((unsigned)(S * w.n_windows) * (unsigned)((n + kXcds - 1) / kXcds * kXcds));
         // up to 64 KB of LDS: 512-thread blocks, so the LDS that limits blocks
         // per CU still leaves 6 wavefronts per SIMD (256 threads left 3)
         if (lds > 65536) launch_adjoint_lds_shape<S, 1024>(grid, lds, M, K, X.gp, X.ovf, gfix, w, st);
