@@ -386,6 +386,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_lds(MarchParams<float> P, Ray
 // atomics and no zeroing beforehand.  A chain whose records overflowed gets
 // zeros here and its gradient from k_adjoint_lds.  fwd_block: the block
 // size of the gradient march (the width of a record row).
+constexpr int kRecBatch = 8;   // records per thread in flight in the record adjoint
+
 template <int S, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_adjoint_rec(MarchParams<float> P, CrossRecs X, int fwd_block,
                                                        AdjointLdsShape W_, unsigned long long *gfix) {
@@ -410,19 +412,19 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint_rec(MarchParams<float> P, Cro
             const int ray0 = tile * P.rays_per_block;
             for (int j = tid; j < fwd_block; j += BLOCK) {
                 const int n = (int)cnt[j];
-                // four records at a time: their loads, then the dLL/dO gathers
-                // they name, are all in flight before the first is used
-                for (int k0 = 0; k0 < n; k0 += 4) {
-                    uint4 r[4];
-                    float gv[4];
+                // kRecBatch records at a time: their loads, then the dLL/dO
+                // gathers they name, are all in flight before the first is used
+                for (int k0 = 0; k0 < n; k0 += kRecBatch) {
+                    uint4 r[kRecBatch];
+                    float gv[kRecBatch];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < kRecBatch; ++u)
                         if (k0 + u < n) r[u] = rec[(size_t)(k0 + u) * fwd_block + j];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < kRecBatch; ++u)
                         if (k0 + u < n) gv[u] = gpc[ray0 + j + (int)((r[u].x >> 18) & 0x3Fu) * fwd_block];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < kRecBatch; ++u) {
                         if (k0 + u >= n) break;
                         const int off = (int)(r[u].x & 0xFFFFu);
                         if (off + C + 1 < lo || off >= hi) continue;   // the cell's node rows miss the window
