@@ -273,7 +273,7 @@ mc_status mcmc_run(mc_problem *p, const mc_run_config *cfg, int n_chains, void *
  * item, k > 0 a persistent grid of k blocks per compute unit that strides
  * over the work table.  Gradients (float32): the march that precedes the
  * adjoint records every crossing, grad_slots records per thread and surface
- * (0 = 2 x rays_per_thread; -1 = none, every chain's gradient then comes
+ * (0 = 2 x rays_per_thread + 16; -1 = none, every chain's gradient then comes
  * from re-walking its rays, as it does for a chain whose records overflow);
  * adjoint_rows > 0 caps the node rows an adjoint block accumulates at once
  * (0 = as many as fit the LDS).  Both change performance only.

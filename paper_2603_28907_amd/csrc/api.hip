@@ -659,13 +659,17 @@ void launch_adjoint_rec_shape(dim3 grid, size_t lds, const MarchParams<float> &M
 }
 
 // Crossing-record slots per thread and surface of the gradient march:
-// twice the rays a thread marches (the crossings of one surface per ray
-// are 1 on average at the benchmark shapes), or the tuning's grad_slots
-// (-1: none, so every chain takes the re-walk).
+// twice the rays a thread marches plus 16 (the crossings of one surface per
+// ray are 1 on average at the benchmark shapes, and a thread's count varies
+// by a few times its square root; with 2 x rays only, one thread list in a
+// few hundred overflowed at 8 rays per thread, sending its chain to the
+// re-walk nearly every call), or the tuning's grad_slots (-1: none, so every
+// chain takes the re-walk).  Slots cost memory, not traffic: only written
+// records are read.
 int cross_slots(const mc_problem *p) {
     if (p->tune.grad_slots < 0) return 0;
     if (p->tune.grad_slots > 0) return p->tune.grad_slots;
-    return 2 * p->tune.rays_per_thread;
+    return 2 * p->tune.rays_per_thread + 16;
 }
 
 CrossRecs cross_recs(const mc_problem *p) {
