@@ -486,6 +486,9 @@ __global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, const
     auto lik = [&](int k) -> double { return gf ? (double)(long long)gf[k] * kGradFixInv : 0.0; };
     double lp = 0.0;
     int ok = 1;
+    // node (i, j) of n = tid + k BLOCK, stepped without a division per node
+    const int bi = BLOCK / C, bj = BLOCK - bi * C;
+    const int i0 = tid / C, j0 = tid - i0 * C;
     // loops kept rolled: the Phi^-1 call is out of line, and an unrolled body
     // keeps more values live across it (spilled around every call)
 #pragma unroll 1
@@ -496,21 +499,27 @@ __global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, const
             const double h = (double)H[l * N + n];
             const double a = l ? (double)H[(l - 1) * N + n] : 0.0;
             const double b = P.top64[n];
-            const double d = b - a;
-            const double u = (h - a) / d, v = (b - h) / d;
+            const double d = b - a, id = 1.0 / d;
+            const double u = (h - a) * id, v = (b - h) * id;
             const bool good = (d > 0.0) && (u > 0.0) && (v > 0.0);
             ok &= good ? 1 : 0;
             const double wi = good ? probit_uv(u, v) : 0.0;
             w[n] = wi;
             sw2 += wi * wi;
-            sld += good ? log(d) : 0.0;
+            // log(b - a) of the first surface is log(top): summed once on the host
+            if (l) sld += good ? log(d) : 0.0;
         }
+        if (l == 0) sld = tid == 0 ? P.sum_log_top : 0.0;
         __syncthreads();
         double se = 0.0;
         const double r = P.r[l], s11 = P.s11[l];
+        int i = i0, j = j0;
 #pragma unroll 1
-        for (int n = tid; n < N; n += BLOCK) {
-            const int i = n / C, j = n - i * C;
+        for (int n = tid; n < N; n += BLOCK, i += bi, j += bj) {
+            if (j >= C) {
+                j -= C;
+                ++i;
+            }
             const double wi = w[n];
             const double wr = w[i * C + (j + 1 == C ? 0 : j + 1)], wl = w[i * C + (j == 0 ? C - 1 : j - 1)];
             const double wd = w[(i + 1 == R ? 0 : i + 1) * C + j], wu = w[(i == 0 ? R - 1 : i - 1) * C + j];
@@ -523,8 +532,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_prior_grad(PriorParams<T> P, const
             double own = 0.0, below = 0.0, top = 0.0;
             if ((d > 0.0) && (u > 0.0) && (v > 0.0)) {
                 const double G = -s11 * (4.0 * (1.0 - r) * wi + r * (4.0 * wi - (wr + wl + wd + wu))) + wi;
-                const double phi = exp(-0.5 * wi * wi) * 0.39894228040143267793994605993438;
-                own = G / phi * id;   // dlp/du / d
+                // 1 / phi(w) = sqrt(2 pi) exp(w^2 / 2): a product instead of a
+                // division; single precision suffices for a float32 gradient
+                double iphi;
+                if constexpr (sizeof(T) == 4)
+                    iphi = (double)expf((float)(0.5 * wi * wi));
+                else
+                    iphi = exp(0.5 * wi * wi);
+                own = G * iphi * 2.5066282746310002416 * id;   // dlp/du / d
                 below = id - own * v;
                 top = -own * u - id;
             }
