@@ -64,8 +64,8 @@ MEASURED_TRAFFIC = {
     "grf_cave_64": dict(source_sha="4cf98bfab8e32aec", fetch_kib=23165.0, fetch_scale=262144 / 131088.5,
                         write_kib=32.0, write_scale=1.0),
     # k_adjoint_rec on the 128x128 gradient workload (512 chains)
-    "grad128_adjoint": dict(source_sha="97428600c1bb92f1", shape=(1024, 16), fetch_kib=429636.5,
-                            fetch_scale=262144 / 131093.2, write_kib=196608.0, write_scale=1.0),
+    "grad128_adjoint": dict(source_sha="851b6bc27f91b87b", shape=(1024, 16), fetch_kib=431272.0,
+                            fetch_scale=262144 / 131093.3, write_kib=196608.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
     "voxel64": dict(source_sha="a54470c4ae3bcfc7", fetch_kib=2433874.6, fetch_scale=262144 / 131093.7,
