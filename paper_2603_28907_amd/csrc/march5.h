@@ -22,6 +22,31 @@ namespace mc {
 
 __device__ __forceinline__ float raw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// e^x in float64 for the per-pixel Poisson term (x = -O / Lambda), written
+// out: x = k ln2 + r with k = rint(x / ln2) and r = x - k ln2 by Cody and
+// Waite's two-part ln 2 (the high part has trailing zero bits, so k times it
+// is exact for |k| < 2^21), |r| <= ln2 / 2; e^r by its Taylor series to
+// degree 13 (truncation below 1e-17 relative); 2^k by ldexp.  The series
+// coefficients 1/n! come from constant memory with scalar loads, so they sit
+// in scalar registers (as constants of the ray loop the compiler would keep
+// them, and a copy of each per use, in vector registers).
+__constant__ double kExpTaylor[12] = {
+    1.6059043836821614599e-10, 2.0876756987868098979e-09, 2.5052108385441718775e-08, 2.7557319223985890653e-07,
+    2.7557319223985890653e-06, 2.4801587301587301587e-05, 1.9841269841269841270e-04, 1.3888888888888888889e-03,
+    8.3333333333333333333e-03, 4.1666666666666666667e-02, 1.6666666666666666667e-01, 0.5};   // 1/n!, n = 13..2
+
+__device__ __forceinline__ double exp_f64(double x) {
+    const double k = fmin(fmax(rint(x * 1.4426950408889634074), -1100.0), 1100.0);
+    double r = __builtin_fma(-k, 6.93147180369123816490e-01, x);
+    r = __builtin_fma(-k, 1.90821492927058770002e-10, r);
+    double p = kExpTaylor[0];
+#pragma unroll
+    for (int i = 1; i < 12; ++i) p = __builtin_fma(p, r, kExpTaylor[i]);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
 // Crossings of one piece in the normalised variable s = tau / tau1, with
 // |f'(tau)| at each (for the crossing records of the gradient march).
 struct PieceCross {
@@ -328,14 +353,22 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     // this block's record lists (a block-uniform base) and this thread's
     // offset inside them: a 32-bit index, no per-lane 64-bit pointer to keep
     uint4 *const recb = X.rec + (size_t)(chain * P.n_tiles + tile) * S * (size_t)X.slots * BLOCK;
+    // sensor s and pixel p of the thread's ray, stepped with the ray (no
+    // division per ray)
+    int s = 0, pix = 0;
+    if (r0 + tid < r1) {
+        s = (r0 + tid) / P.n_pix;
+        pix = r0 + tid - s * P.n_pix;
+    }
     for (int ray = r0 + tid; ray < r1; ray += BLOCK) {
-        const int s = ray / P.n_pix;
-        const float qz = P.sensor[3 * s + 2], dz = P.dz[ray];
+        // per-ray tables through 32-bit byte offsets (one address add each)
+        const unsigned b4 = 4u * (unsigned)ray;
+        const float qz = P.sensor[3 * s + 2], dz = node_at(P.dz, b4);
         // the ray in cell units
         const float qxi = P.sensor[3 * s] * P.ihx, qyi = P.sensor[3 * s + 1] * P.ihy;
-        const float dxi = P.dx[ray] * P.ihx, dyi = P.dy[ray] * P.ihy;
-        const float idx = K.idx[ray], idy = K.idy[ray], idz = K.idz[ray];
-        const float ox = K.ox[ray], oy = K.oy[ray], Texit = K.texit[ray];
+        const float dxi = node_at(P.dx, b4) * P.ihx, dyi = node_at(P.dy, b4) * P.ihy;
+        const float idx = node_at(K.idx, b4), idy = node_at(K.idy, b4), idz = node_at(K.idz, b4);
+        const float ox = node_at(K.ox, b4), oy = node_at(K.oy, b4), Texit = node_at(K.texit, b4);
         const float kxy = -dxi * dyi;
         float O = 0.f;
 #pragma unroll
@@ -399,9 +432,14 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
         }
         if (P.opacity) P.opacity[(size_t)chain * P.n_ray + ray] = O;
         const double Od = (double)O;
-        const double lam = P.expo[ray] * exp(-Od * P.inv_L);
+        const double lam = P.expo[ray] * exp_f64(-Od * P.inv_L);
         acc += -P.c_over_L[ray] * Od - lam;
         if constexpr (REC) X.gp[(size_t)chain * P.n_ray + ray] = (float)(lam * P.inv_L - P.c_over_L[ray]);
+        pix += BLOCK;
+        while (pix >= P.n_pix) {
+            pix -= P.n_pix;
+            ++s;
+        }
     }
     if constexpr (REC) {
         bool over = false;
@@ -417,13 +455,16 @@ __device__ __forceinline__ void march_block4(const MarchParams<float> &P, const 
     if (tid == 0) P.partials[(size_t)chain * P.n_tiles + tile] = tot;
 }
 
-// At least 6 wavefronts per SIMD: the walk is latency-bound, and 6 resident
-// waves beat 5 even with a few registers spilled (512-thread blocks keep the
-// LDS from capping residency below 6 on 64x64 grids).  1024-thread blocks
-// serve grids whose surfaces take most of the LDS (one block, 4 wavefronts
-// per SIMD): there the register budget of 4 wavefronts costs no residency.
+// Register budget of the march: 8 wavefronts per SIMD (64 VGPRs, which the
+// forward march fits without scratch; 512-thread blocks keep the LDS from
+// capping residency below that on 64x64 grids).  The gradient march keeps 6
+// (80 VGPRs): its record code spills at 64.  1024-thread blocks serve grids
+// whose surfaces take most of the LDS (one block, 4 wavefronts per SIMD):
+// there the register budget of 4 wavefronts costs no residency.
 template <int BLOCK>
-constexpr int march_waves_per_simd() { return BLOCK >= 1024 ? 4 : 6; }
+constexpr int march_waves_per_simd() { return BLOCK >= 1024 ? 4 : 8; }
+template <int BLOCK>
+constexpr int march_rec_waves_per_simd() { return BLOCK >= 1024 ? 4 : 6; }
 
 template <int S, bool TOP_LDS, int BLOCK>
 __global__ __launch_bounds__(BLOCK, march_waves_per_simd<BLOCK>()) void k_march_lik4(MarchParams<float> P,
@@ -437,7 +478,7 @@ __global__ __launch_bounds__(BLOCK, march_waves_per_simd<BLOCK>()) void k_march_
 // The gradient march: the same walk, plus the crossing records and dLL/dO
 // of every ray.
 template <int S, bool TOP_LDS, int BLOCK>
-__global__ __launch_bounds__(BLOCK, march_waves_per_simd<BLOCK>()) void k_march_rec4(MarchParams<float> P,
+__global__ __launch_bounds__(BLOCK, march_rec_waves_per_simd<BLOCK>()) void k_march_rec4(MarchParams<float> P,
                                                                                     RayConsts<float> K, CrossRecs X) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     int chain, tile;
