@@ -61,11 +61,11 @@ KERNEL_SOURCES = {"grf_cave_64": ("device_common.h", "march_common.h", "march3.h
                   "voxel64": ("device_common.h", "voxel.h"),
                   "grad128_adjoint": ("device_common.h", "march_common.h", "march5.h", "adjoint.h")}
 MEASURED_TRAFFIC = {
-    "grf_cave_64": dict(source_sha="4cf98bfab8e32aec", fetch_kib=23165.0, fetch_scale=262144 / 131088.5,
+    "grf_cave_64": dict(source_sha="0b8b340510832dff", fetch_kib=23174.0, fetch_scale=262144 / 131093.3,
                         write_kib=32.0, write_scale=1.0),
     # k_adjoint_rec on the 128x128 gradient workload (512 chains)
-    "grad128_adjoint": dict(source_sha="851b6bc27f91b87b", shape=(1024, 16), fetch_kib=431272.0,
-                            fetch_scale=262144 / 131093.3, write_kib=196608.0, write_scale=1.0),
+    "grad128_adjoint": dict(source_sha="a98a85b4ce252dfa", shape=(1024, 16), fetch_kib=431173.5,
+                            fetch_scale=262144 / 131088.5, write_kib=196608.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
     "voxel64": dict(source_sha="a54470c4ae3bcfc7", fetch_kib=2433874.6, fetch_scale=262144 / 131093.7,
@@ -81,8 +81,8 @@ MEASURED_TRAFFIC = {
 # known instruction count (32768 waves x 2^16 x 8 = 1.718e10) at 0.969
 # instructions per CU-clock, the full-lane issue limit.
 MEASURED_VALU = {
-    "grf_cave_64": dict(source_sha="4cf98bfab8e32aec", valu_insts=8.782e8, thread_cycles_valu=2.805e10,
-                        active_inst_valu=8.988e8, grbm_gui_active_per_xcd=2.415e6, cus=256),
+    "grf_cave_64": dict(source_sha="0b8b340510832dff", valu_insts=8.934e8, thread_cycles_valu=2.695e10,
+                        active_inst_valu=9.140e8, grbm_gui_active_per_xcd=2.3925e6, cus=256),
 }
 
 
