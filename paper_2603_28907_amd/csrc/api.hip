@@ -2468,11 +2468,18 @@ mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *re
     p->d_vox_off = (int *)q;
     HIP_TRY(p, hipMemcpy(q, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice));
     if (!vi.empty()) {
+        // kVoxPad padding entries (voxel 0, length 0) past the end: the
+        // likelihood kernel reads its lists in whole batches, one ahead
+        const size_t nnz = vi.size();
+        vi.resize(nnz + kVoxPad, 0);
+        vl.resize(nnz + kVoxPad, 0.0);
         q = nullptr;
         HIP_TRY(p, hipMalloc(&q, sizeof(int) * vi.size()));
         p->d_vox_idx = (int *)q;
         HIP_TRY(p, hipMemcpy(q, vi.data(), sizeof(int) * vi.size(), hipMemcpyHostToDevice));
         if ((s = upload_prec(p, p->d_vox_len, vl)) != MC_OK) return s;
+        vi.resize(nnz);
+        vl.resize(nnz);
     }
     {
         // the transpose (voxel -> rays crossing it, in ray order) for the gradient's gather

@@ -23,6 +23,12 @@ constexpr int kVoxLanes = 64;          // chains per wavefront
 constexpr int kVoxWaves = 4;           // wavefronts per block
 constexpr int kVoxRaysPerWave = 4;     // rays one wavefront walks in turn
 constexpr int kVoxRaysPerTile = kVoxWaves * kVoxRaysPerWave;
+// ray-voxel pieces whose density rows one wavefront has in flight at once;
+// the voxel and length lists carry kVoxPad padding entries past their end
+// (voxel 0, length 0), so a batch, and the prefetch of the next batch's
+// voxel indices, may read past the ray's last piece
+constexpr int kVoxBatch = 16;
+constexpr int kVoxPad = 2 * kVoxBatch;
 // float32 sigmoids whose argument exceeds this in magnitude are taken as
 // exactly 0 or 1: the neglected part, below exp(-30) = 9.4e-14, is far
 // under the float32 rounding of the density.
@@ -58,6 +64,13 @@ struct VoxParams {
     const T *t_len;              // [nnz] length of that ray inside the voxel
     unsigned long long *gfix;    // [n][S][N] fixed-point gradient of the likelihood (every entry written)
 };
+
+// A wavefront-uniform read of a list that no kernel of the launch writes,
+// through the scalar unit (constant address space).
+template <typename T>
+__device__ __forceinline__ T vox_uniform(const T *a, int i) {
+    return ((const __attribute__((address_space(4))) T *)a)[i];
+}
 
 // sigma = 1 / (1 + exp(x)), x = (z - H) / gamma
 __device__ __forceinline__ double vox_sigma(double x) { return 1.0 / (1.0 + exp(x)); }
@@ -119,30 +132,51 @@ __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kVoxLanes);
     const int c = group * kVoxLanes + lane;
     const bool live = c < P.n_chains && !(P.only_nan && !(P.only_nan[c] != P.only_nan[c]));
-    const T *grp = P.rhat + (size_t)group * P.N * P.n_z * kVoxLanes + lane;
-    auto row_at = [&](int v) -> T { return grp[(size_t)v * kVoxLanes]; };
+    // the group's rows; a row's 64 values sit at a uniform address plus lane * sizeof(T)
+    const T *grp = P.rhat + (size_t)group * P.N * P.n_z * kVoxLanes;
+    const unsigned ul = (unsigned)lane;
+    auto row_at = [&](int v) -> T { return (grp + (size_t)(unsigned)v * kVoxLanes)[ul]; };
     double tsum = 0.0;
     const int p0 = tile * kVoxRaysPerTile + wave * kVoxRaysPerWave;
     const int p1 = min(p0 + kVoxRaysPerWave, P.n_ray);
     for (int p = p0; p < p1; ++p) {
-        const int beg = P.ray_off[p], end = P.ray_off[p + 1];
+        const int beg = vox_uniform(P.ray_off, p), end = vox_uniform(P.ray_off, p + 1);
         double o = 0.0;
-        int e = beg;
-        for (; e + 8 <= end; e += 8) {
-            T v[8];
+        // kVoxBatch rows in flight; the last batch of a ray reads padding or
+        // the next ray's voxels for its missing pieces and adds nothing of
+        // them.  The next batch's voxel indices are loaded while the rows are
+        // in flight.
+        int vx[kVoxBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = row_at(P.vox[e + u]);
+        for (int u = 0; u < kVoxBatch; ++u) vx[u] = vox_uniform(P.vox, beg + u);
+        for (int e = beg; e < end; e += kVoxBatch) {
+            T v[kVoxBatch], w[kVoxBatch];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) o += (double)(P.len[e + u] * v[u]);
+            for (int u = 0; u < kVoxBatch; ++u) v[u] = row_at(vx[u]);
+#pragma unroll
+            for (int u = 0; u < kVoxBatch; ++u) w[u] = vox_uniform(P.len, e + u);
+#pragma unroll
+            for (int u = 0; u < kVoxBatch; ++u) {
+                vx[u] = vox_uniform(P.vox, e + kVoxBatch + u);
+                // keeps the load here, ahead of the sums, instead of sunk to the loop's end
+                asm volatile("" ::"s"(vx[u]));
+            }
+            if (e + kVoxBatch <= end) {
+#pragma unroll
+                for (int u = 0; u < kVoxBatch; ++u) o += (double)(w[u] * v[u]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < kVoxBatch; ++u)
+                    if (e + u < end) o += (double)(w[u] * v[u]);
+            }
         }
-        for (; e < end; ++e) o += (double)(P.len[e] * row_at(P.vox[e]));
         if (P.opacity && live) P.opacity[(size_t)c * P.n_ray + p] = (T)o;
-        const double l0 = P.lam0[p];
-        const double lam = l0 - (o - P.o0[p]) * (l0 * P.inv_atten);
-        tsum += lam > 0.0 ? P.cnt[p] * log(lam) - lam : -__builtin_huge_val();
+        const double l0 = vox_uniform(P.lam0, p), cp = vox_uniform(P.cnt, p);
+        const double lam = l0 - (o - vox_uniform(P.o0, p)) * (l0 * P.inv_atten);
+        tsum += lam > 0.0 ? cp * log(lam) - lam : -__builtin_huge_val();
         if (P.alpha)
             P.alpha[((size_t)group * P.n_ray + p) * kVoxLanes + lane] =
-                lam > 0.0 ? (T)((P.cnt[p] / lam - 1.0) * (-l0 * P.inv_atten)) : T(0);
+                lam > 0.0 ? (T)((cp / lam - 1.0) * (-l0 * P.inv_atten)) : T(0);
     }
     red[wave][lane] = tsum;
     __syncthreads();
