@@ -522,6 +522,18 @@ def bench_voxel(args, torch):
     print("[bench] timed region done", file=sys.stderr, flush=True)
     assert torch.isfinite(lp).all(), "non-finite log posterior"
     ms_dens, ms_lik = binding.time_voxel(prob, H, iters=args.march_iters)
+    # log posterior + gradient under the voxel model (density, likelihood with
+    # dLL/dO, back-projection, prior gradient), the evaluation MALA and NUTS make
+    g = torch.empty((n_chains, sc.n_surfaces, sc.n_rows, sc.n_cols), dtype=torch.float32, device="cuda:0")
+    lpg = torch.empty(n_chains, dtype=torch.float64, device="cuda:0")
+    prob.logpost_grad_batch(H, lpg, g)
+    torch.cuda.synchronize()
+    kg = max(2, args.march_iters)
+    t0 = time.perf_counter()
+    for _ in range(kg):
+        prob.logpost_grad_batch(H, lpg, g)
+    torch.cuda.synchronize()
+    ms_grad = (time.perf_counter() - t0) / kg * 1e3
     n_pad = (n_chains + 63) // 64 * 64
     n_vox = sc.n_rows * sc.n_cols * n_z
     rhat_bytes = n_vox * n_pad * 4
@@ -552,6 +564,7 @@ def bench_voxel(args, torch):
                     "k_vox_lik": {"ms_per_launch": ms_lik, "algorithmic_bytes": lik_bytes, "GB_per_s": lik_gbs,
                                   "frac_hbm": lik_gbs / HBM_PEAK_GBS,
                                   "gathered_bytes": n_pieces * n_pad * 4}},
+        "gradient_ms_per_eval": ms_grad, "gradient_evals_per_s": n_chains / (ms_grad * 1e-3),
     }
     if not args.no_cpu_baseline:
         import oracle

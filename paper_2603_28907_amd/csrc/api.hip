@@ -112,6 +112,8 @@ struct mc_problem {
     int *d_vox_off = nullptr, *d_vox_idx = nullptr;
     void *d_vox_len = nullptr;   // [nnz] in prec
     int *d_vox_toff = nullptr, *d_vox_tray = nullptr;   // the transpose: rays of each voxel
+    int *d_vox_items = nullptr;  // [vox_n_items][4] gradient work items over the transposed lists
+    int vox_n_items = 0;
     void *d_vox_tlen = nullptr;  // [nnz] in prec
     DevBuf valpha;               // [n_pad/64][n_ray][64] dLL/dO of the voxel model (gradient)
     double *d_vox_lam0 = nullptr, *d_vox_o0 = nullptr, *d_vox_fsig = nullptr, *d_vox_inorm = nullptr;
@@ -199,7 +201,8 @@ void clear_voxel_model(mc_problem *p) {
     free_ptr(p->d_vox_len);
     free_ptr(p->d_vox_tlen);
     for (double **q : {&p->d_vox_lam0, &p->d_vox_o0, &p->d_vox_fsig, &p->d_vox_inorm}) free_ptr(*q);
-    for (int **q : {&p->d_vox_off, &p->d_vox_idx, &p->d_vox_toff, &p->d_vox_tray}) {
+    p->vox_n_items = 0;
+    for (int **q : {&p->d_vox_off, &p->d_vox_idx, &p->d_vox_toff, &p->d_vox_tray, &p->d_vox_items}) {
         if (*q) (void)hipFree(*q);
         *q = nullptr;
     }
@@ -810,12 +813,22 @@ mc_status lik_grad(mc_problem *p, int n, const T *heights, unsigned long long *g
         V.t_off = p->d_vox_toff;
         V.t_ray = p->d_vox_tray;
         V.t_len = (const T *)p->d_vox_tlen;
+        V.items = p->d_vox_items;
+        V.n_items = p->vox_n_items;
         V.gfix = gfix;
         launch_vox_density<T, S>(V, st);
         launch_vox_lik<T>(V, st);
-        hipLaunchKernelGGL((k_vox_grad<T, S>), dim3((unsigned)((V.N + 3) / 4), (unsigned)(V.n_pad / kVoxLanes)),
-                           dim3(256), 0, st, V);
+        const size_t tot = (size_t)S * V.N * n;   // the items add into zeroed accumulators
+        hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, gfix, tot);
         HIP_TRY(p, hipGetLastError());
+        if (V.n_items > 0) {
+            const int n_ib = (V.n_items + 3) / 4;
+            const int upx = (n_ib + kVoxGradUnit * kXcds - 1) / (kVoxGradUnit * kXcds);
+            hipLaunchKernelGGL((k_vox_grad<T, S>),
+                               dim3((unsigned)(kXcds * upx * kVoxGradUnit * (V.n_pad / kVoxLanes))), dim3(256), 0, st,
+                               V);
+            HIP_TRY(p, hipGetLastError());
+        }
         return MC_OK;
     }
     const bool quad = p->quad_nsub > 0;
@@ -2498,7 +2511,29 @@ mc_status set_voxel_model(mc_problem *p, int n_z, double gamma, const double *re
         HIP_TRY(p, hipMalloc(&q, sizeof(int) * toff.size()));
         p->d_vox_toff = (int *)q;
         HIP_TRY(p, hipMemcpy(q, toff.data(), sizeof(int) * toff.size(), hipMemcpyHostToDevice));
+        // the gradient's work items: each column's entries cut into pieces of
+        // at most kVoxItemEntries, with the level of each piece's first entry
+        std::vector<int> items;
+        for (int c = 0; c < p->R * p->C; ++c) {
+            const size_t vb = (size_t)c * n_z;
+            const int e0 = toff[vb], e1 = toff[vb + n_z];
+            int k = 0;
+            for (int e = e0; e < e1; e += kVoxItemEntries) {
+                while (toff[vb + k + 1] <= e) ++k;
+                items.insert(items.end(), {c, k, e, std::min(e + kVoxItemEntries, e1)});
+            }
+        }
+        if (!items.empty()) {
+            q = nullptr;
+            HIP_TRY(p, hipMalloc(&q, sizeof(int) * items.size()));
+            p->d_vox_items = (int *)q;
+            HIP_TRY(p, hipMemcpy(q, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice));
+            p->vox_n_items = (int)(items.size() / 4);
+        }
         if (!vi.empty()) {
+            // kVoxPad padding entries (ray 0, length 0): the gradient reads whole batches
+            tray.resize(tray.size() + kVoxPad, 0);
+            tlen.resize(tlen.size() + kVoxPad, 0.0);
             q = nullptr;
             HIP_TRY(p, hipMalloc(&q, sizeof(int) * tray.size()));
             p->d_vox_tray = (int *)q;

@@ -29,6 +29,11 @@ constexpr int kVoxRaysPerTile = kVoxWaves * kVoxRaysPerWave;
 // voxel indices, may read past the ray's last piece
 constexpr int kVoxBatch = 16;
 constexpr int kVoxPad = 2 * kVoxBatch;
+// most transposed-list entries one gradient work item (one wavefront) sums:
+// a column's list is cut into items of this length, so the columns above the
+// sensors, whose lists run to tens of thousands of entries, do not leave one
+// wavefront working long after the rest
+constexpr int kVoxItemEntries = 1024;
 // float32 sigmoids whose argument exceeds this in magnitude are taken as
 // exactly 0 or 1: the neglected part, below exp(-30) = 9.4e-14, is far
 // under the float32 rounding of the density.
@@ -62,7 +67,9 @@ struct VoxParams {
     const int *t_off;            // [N*n_z + 1] CSR offsets of the voxels' ray lists (the transpose of G's pattern)
     const int *t_ray;            // [nnz] ray index
     const T *t_len;              // [nnz] length of that ray inside the voxel
-    unsigned long long *gfix;    // [n][S][N] fixed-point gradient of the likelihood (every entry written)
+    const int *items;            // [n_items][4] gradient work items: column, first level, entry range [eb, ee)
+    int n_items;
+    unsigned long long *gfix;    // [n][S][N] fixed-point gradient of the likelihood (zeroed, then added into)
 };
 
 // A wavefront-uniform read of a list that no kernel of the launch writes,
@@ -192,17 +199,35 @@ __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> 
 // dLL/dRhat_v = sum_p alpha_p L_pv (a gather over voxel v's ray list, the
 // transpose of G's pattern), and Rhat of voxel (n, k) depends on column n
 // alone: dRhat/dH_l,n = (rho_l - rho_{l+1}) sigma_l (1 - sigma_l) /
-// (gamma (1 - sigma_0)).  One wavefront per (column, 64-chain group), lane =
-// chain: it walks the column's levels, gathers each level's sum (one 64-chain
-// row of alpha per list entry) and adds it into the S height derivatives,
-// then writes them in the 2^-32 fixed point of the march's adjoint.  Sums run
-// in a fixed order: the result is deterministic.
+// (gamma (1 - sigma_0)).  A column's list entries are contiguous, level
+// after level; the list is cut into work items of at most kVoxItemEntries
+// entries.  One wavefront per (item, 64-chain group), lane = chain: it sums
+// the item's entries level by level (one 64-chain row of alpha per entry,
+// kVoxBatch rows in flight, the next batch's ray indices loaded while they
+// are in flight) and adds each level's sum, times the level's sigmoid
+// derivatives, into the S height derivatives.  The gradient is linear in the
+// level sums, so a level split between two items contributes its two parts.
+// Each item adds its derivatives in the 2^-32 fixed point of the march's
+// adjoint to gfix (zeroed beforehand) with integer atomics: exact, so the
+// result does not depend on the order of the items.
+// Blocks of 4 items, in units of kVoxGradUnit blocks; XCD x takes the units
+// u with u % 8 == x of each group in turn: neighbouring columns, which share
+// rays, go through one L2, and the heavy columns near the sensors are spread
+// over all XCDs.
+constexpr int kVoxGradUnit = 16;
 template <typename T, int S>
 __global__ __launch_bounds__(256) void k_vox_grad(VoxParams<T> P) {
+    const int n_ib = (P.n_items + 3) / 4;
+    const int upx = (n_ib + kVoxGradUnit * kXcds - 1) / (kVoxGradUnit * kXcds);   // units per XCD
+    const int b = blockIdx.x, x = b % kXcds, q = b / kXcds;
+    const int group = q / (upx * kVoxGradUnit), j = q % (upx * kVoxGradUnit);
+    const int ib = ((j / kVoxGradUnit) * kXcds + x) * kVoxGradUnit + j % kVoxGradUnit;
+    if (group >= P.n_pad / kVoxLanes || ib >= n_ib) return;
+    const int it = ib * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x / kVoxLanes);
+    if (it >= P.n_items) return;
+    const int col = vox_uniform(P.items, 4 * it), k0 = vox_uniform(P.items, 4 * it + 1);
+    const int eb = vox_uniform(P.items, 4 * it + 2), ee = vox_uniform(P.items, 4 * it + 3);
     const int lane = threadIdx.x & (kVoxLanes - 1);
-    const int col = blockIdx.x * 4 + threadIdx.x / kVoxLanes;
-    const int group = blockIdx.y;
-    if (col >= P.N) return;
     const int c = group * kVoxLanes + lane;
     const bool live = c < P.n_chains;
     T h[S];
@@ -213,26 +238,61 @@ __global__ __launch_bounds__(256) void k_vox_grad(VoxParams<T> P) {
 #pragma unroll
     for (int l = 0; l < S; ++l) g[l] = 0.0;
     const T ig = (T)P.inv_gamma, dz = (T)P.dz;
-    const T *arow = P.alpha + (size_t)group * P.n_ray * kVoxLanes + lane;
-    for (int k = 0; k < P.n_z; ++k) {
-        const int v = col * P.n_z + k;
-        const int beg = P.t_off[v], end = P.t_off[v + 1];
-        if (beg == end) continue;
-        double B = 0.0;
-        for (int e = beg; e < end; ++e) B += (double)arow[(size_t)P.t_ray[e] * kVoxLanes] * (double)P.t_len[e];
-        const T z = ((T)k + T(0.5)) * dz;
-        const double bn = B * P.inv_gamma * P.inv_norm[k];
+    // the group's alpha rows; a row's 64 values sit at a uniform address plus lane * sizeof(T)
+    const T *agrp = P.alpha + (size_t)group * P.n_ray * kVoxLanes;
+    const unsigned ul = (unsigned)lane;
+    auto arow = [&](int r) -> T { return (agrp + (size_t)(unsigned)r * kVoxLanes)[ul]; };
+    const int vb = col * P.n_z;
+    int k = k0, kend = vox_uniform(P.t_off, vb + k0 + 1);   // level k's entries end at kend
+    int ix[kVoxBatch];
 #pragma unroll
-        for (int l = 0; l < S; ++l) {
-            const double sg = (double)vox_sigma((z - h[l]) * ig);
-            g[l] += bn * P.drho[l] * (sg * (1.0 - sg));
+    for (int u = 0; u < kVoxBatch; ++u) ix[u] = vox_uniform(P.t_ray, eb + u);
+    double B = 0.0;
+    for (int e = eb; e < ee;) {
+        // this batch: entries [e, en) of level k; a partial batch reads padding
+        // or the following entries for its missing ones and adds nothing of them
+        const int en = min(min(e + kVoxBatch, kend), ee);
+        T a[kVoxBatch], w[kVoxBatch];
+#pragma unroll
+        for (int u = 0; u < kVoxBatch; ++u) a[u] = arow(ix[u]);
+#pragma unroll
+        for (int u = 0; u < kVoxBatch; ++u) w[u] = vox_uniform(P.t_len, e + u);
+#pragma unroll
+        for (int u = 0; u < kVoxBatch; ++u) {
+            ix[u] = vox_uniform(P.t_ray, en + u);   // the next batch starts at en
+            // keeps the load here, ahead of the sums, instead of sunk to the loop's end
+            asm volatile("" ::"s"(ix[u]));
         }
+        if (en - e == kVoxBatch) {
+#pragma unroll
+            for (int u = 0; u < kVoxBatch; ++u) B += (double)a[u] * (double)w[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < kVoxBatch; ++u)
+                if (u < en - e) B += (double)a[u] * (double)w[u];
+        }
+        if (en == kend || en == ee) {   // level k is complete, or the item ends inside it
+            const T z = ((T)k + T(0.5)) * dz;
+            const double bn = B * P.inv_gamma * vox_uniform(P.inv_norm, k);
+#pragma unroll
+            for (int l = 0; l < S; ++l) {
+                const double sg = (double)vox_sigma((z - h[l]) * ig);
+                g[l] += bn * P.drho[l] * (sg * (1.0 - sg));
+            }
+            B = 0.0;
+            if (en < ee)   // the next level with entries (one exists: the item goes on)
+                while (k + 1 < P.n_z) {
+                    kend = vox_uniform(P.t_off, vb + (++k) + 1);
+                    if (kend > en) break;
+                }
+        }
+        e = en;
     }
     if (!live) return;
 #pragma unroll
     for (int l = 0; l < S; ++l) {
         const double sv = fmin(fmax(g[l] * 4294967296.0, -9.0e18), 9.0e18);
-        P.gfix[((size_t)c * S + l) * P.N + col] = (unsigned long long)(long long)__builtin_rint(sv);
+        atomicAdd(P.gfix + ((size_t)c * S + l) * P.N + col, (unsigned long long)(long long)__builtin_rint(sv));
     }
 }
 

@@ -283,6 +283,64 @@ def test_voxel_gradient_matches_oracle(torch_mod, oracle_mod, tiny, precision):
             assert rel < 1e-4 and worst < 1e-4
 
 
+VOX_ITEM = 1024   # entries per gradient work item (kVoxItemEntries in voxel.h)
+
+
+def test_voxel_gradient_long_column_lists(torch_mod, oracle_mod):
+    """Columns whose transposed lists run to several work items, with item
+    cuts inside a level (two items each add part of that level's sum), and
+    more than one 64-chain group: gradient against the oracle, same bars as
+    the gradient test above."""
+    from paper_2603_28907_amd.binding import Problem
+    torch = torch_mod
+    rng = np.random.default_rng(41)
+    S, R, C, X, Y, n_pix, n_z, gamma = 3, 8, 8, 40.0, 40.0, 1600, 40, 1.5
+    base = 30.0 + 3.0 * rng.standard_normal((R, C))
+    free = np.stack([base + 10.0 * l + rng.random((R, C)) for l in range(S - 1)])
+    top = 70.0 + rng.random((R, C))
+    pos = np.array([[X * 0.45, Y * 0.5, 0.0], [X * 0.6, Y * 0.35, 1.0]])
+    th = np.radians(rng.uniform(1, 35, n_pix))
+    ph = rng.uniform(0, 2 * np.pi, n_pix)
+    d1 = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    sc = make_scenario(S, R, C, X, Y, free, top, (1.8, 0.0, 2.7), pos, np.stack([d1, d1[::-1]]),
+                       car_r=np.full(S - 1, 0.7))
+    sc.counts = oracle_mod.make_counts(sc, seed=5)
+    orc = oracle_vox(oracle_mod, sc, n_z, gamma, free)
+    # the lists really are long and cut inside levels
+    per_voxel = np.zeros(R * C * n_z, np.int64)
+    for r in range(sc.n_rays):
+        v, _ = orc.voxel_pieces(r, n_z)
+        np.add.at(per_voxel, v, 1)
+    toff = np.concatenate([[0], np.cumsum(per_voxel)])
+    inside = 0
+    for col in range(R * C):
+        e0, e1 = toff[col * n_z], toff[(col + 1) * n_z]
+        for cut in range(e0 + VOX_ITEM, e1, VOX_ITEM):
+            inside += int(cut not in set(toff[col * n_z:(col + 1) * n_z + 1]))
+    say(f"longest column list {int(np.diff(toff[::n_z]).max())} entries, {inside} item cuts inside a level")
+    assert np.diff(toff[::n_z]).max() > 3 * VOX_ITEM and inside > 0
+    n_chains = 70
+    states = np.sort(np.stack([free + 0.4 * rng.standard_normal(free.shape) for _ in range(n_chains)]), axis=1)
+    for precision in ("f64", "f32"):
+        prob = Problem.from_scenario(sc, precision=precision)
+        prob.set_voxel_model(n_z, gamma, free)
+        dt = torch.float64 if precision == "f64" else torch.float32
+        lp, g = prob.logpost_grad_batch(to_dev(states, dt))
+        torch.cuda.synchronize()
+        lp, g = lp.cpu().numpy(), g.double().cpu().numpy()
+        st = rounded_states(states, precision)
+        for c in (0, 63, 64, 69):
+            lpo, go = orc.grad(st[c])
+            rel = np.linalg.norm(g[c] - go) / np.linalg.norm(go)
+            worst = np.abs(g[c] - go).max() / np.abs(go).max()
+            say(f"long lists {precision} chain {c}: relative L2 {rel:.2e}, worst coordinate / max|g| {worst:.2e}")
+            if precision == "f64":
+                assert rel < 1e-9
+                assert lp[c] == pytest.approx(lpo, rel=1e-11, abs=1e-6)
+            else:
+                assert rel < 1e-4 and worst < 1e-4
+
+
 def test_voxel_gradient_zero_where_counts_nonpositive(torch_mod, oracle_mod, tiny):
     from paper_2603_28907_amd.binding import Problem
     torch = torch_mod
