@@ -204,7 +204,8 @@ __global__ __launch_bounds__(kVoxWaves * kVoxLanes) void k_vox_lik(VoxParams<T> 
 // entries.  One wavefront per (item, 64-chain group), lane = chain: it sums
 // the item's entries level by level (one 64-chain row of alpha per entry,
 // kVoxBatch rows in flight, the next batch's ray indices loaded while they
-// are in flight) and adds each level's sum, times the level's sigmoid
+// are in flight; products in T, sums in float64, as in the likelihood) and
+// adds each level's sum, times the level's sigmoid
 // derivatives, into the S height derivatives.  The gradient is linear in the
 // level sums, so a level split between two items contributes its two parts.
 // Each item adds its derivatives in the 2^-32 fixed point of the march's
@@ -265,11 +266,11 @@ __global__ __launch_bounds__(256) void k_vox_grad(VoxParams<T> P) {
         }
         if (en - e == kVoxBatch) {
 #pragma unroll
-            for (int u = 0; u < kVoxBatch; ++u) B += (double)a[u] * (double)w[u];
+            for (int u = 0; u < kVoxBatch; ++u) B += (double)(a[u] * w[u]);
         } else {
 #pragma unroll
             for (int u = 0; u < kVoxBatch; ++u)
-                if (u < en - e) B += (double)a[u] * (double)w[u];
+                if (u < en - e) B += (double)(a[u] * w[u]);
         }
         if (en == kend || en == ee) {   // level k is complete, or the item ends inside it
             const T z = ((T)k + T(0.5)) * dz;
