@@ -593,13 +593,17 @@ def bench_nuts(args, torch):
     sc, _, w = make_workload("grf_cave_64")
     sc.counts = gpu_counts(sc, torch)
     prob = Problem.from_scenario(sc, precision="f32")
+    voxel = bool(getattr(args, "nuts_voxel", False))
     n_super, n_within = 32, 8
     n = n_super * n_within
     starts = inputs.init_states(sc, n_super, seed=w["init_seed"], jitter=args.nuts_jitter)
     H = torch.as_tensor(np.repeat(starts, n_within, axis=0), dtype=torch.float32, device="cuda:0").contiguous()
-    tuned = autotune.tune_gradient(prob, H)   # launch shape of the gradient for these chains
-    print(f"[bench] gradient launch shape {tuned['tuning']['block']}x{tuned['tuning']['rays_per_thread']}: "
-          f"{tuned['ms']:.3f} ms per evaluation", file=sys.stderr, flush=True)
+    if voxel:   # the paper's pipeline: NUTS on the linearised, smoothed voxel model
+        prob.set_voxel_model(args.n_z, 1.0, sc.truth)
+    else:
+        tuned = autotune.tune_gradient(prob, H)   # launch shape of the gradient for these chains
+        print(f"[bench] gradient launch shape {tuned['tuning']['block']}x{tuned['tuning']['rays_per_thread']}: "
+              f"{tuned['ms']:.3f} ms per evaluation", file=sys.stderr, flush=True)
     latent = not args.nuts_heights
     if latent:   # the paper's parametrisation: the CAR fields behind the heights
         H = prob.heights_to_latent(H)
@@ -623,15 +627,32 @@ def bench_nuts(args, torch):
     if latent:
         H = prob.latent_to_heights(H)
     rhat = prob.nested_rhat(H, n_super, n_within)
-    ms_adj = binding.time_adjoint(prob, H, iters=args.march_iters)
-    t = prob.get_tuning()
-    abytes = adjoint_bytes("grf_cave_64", sc, n, t["block"], t["rays_per_thread"])
-    achieved = abytes / (ms_adj * 1e-3) / 1e9
-    return {
+    if voxel:   # roofline of the likelihood gather, as in the voxel workload
+        n_z, n_pieces = prob.voxel_info()
+        ms_dens, ms_lik = binding.time_voxel(prob, H, iters=args.march_iters)
+        n_pad = (n + 63) // 64 * 64
+        lik_bytes = sc.n_rows * sc.n_cols * n_z * n_pad * 4 + n_pieces * 8 + sc.n_rays * (4 + 3 * 8)
+        achieved = lik_bytes / (ms_lik * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": lik_bytes,
+                "kernel": "k_vox_lik", "ms_per_launch": ms_lik}
+        model = f"the paper's smoothed voxel model ({sc.n_rows}x{sc.n_cols}x{n_z} voxels, gamma 1 m, linearised " \
+                f"around the synthetic truth)"
+    else:
+        ms_adj = binding.time_adjoint(prob, H, iters=args.march_iters)
+        t = prob.get_tuning()
+        abytes = adjoint_bytes("grf_cave_64", sc, n, t["block"], t["rays_per_thread"])
+        achieved = abytes / (ms_adj * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": abytes,
+                "kernel": "k_adjoint_rec", "ms_per_launch": ms_adj, "rays_per_launch": n * sc.n_rays}
+        model = "the exact march"
+    out = {
         "metric": METRIC, "value": leaps * sc.n_rays / dt, "unit": "ray-evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.nuts_warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"nuts64: the grf_cave_64 geometry and rays ({sc.n_rays}), "
+        "config": {"workload": f"{'nuts64_voxel' if voxel else 'nuts64'}: the grf_cave_64 geometry and rays "
+                               f"({sc.n_rays}) under {model}, "
                                f"{'latent CAR fields' if latent else 'heights'} sampled, {n_super} super-chains x "
                                f"{n_within} chains sharing their starts, NUTS with tree depth cap 8 (256 leapfrog "
                                f"steps), starts at the truth + {args.nuts_jitter} m jitter, {args.nuts_warmup} warm-up transitions "
@@ -644,11 +665,11 @@ def bench_nuts(args, torch):
         "mean_accept_stat": float(st["accept_stat"].mean().item()),
         "step_size_median": float(eps.median().item()),
         "nested_rhat_max": float(rhat.max().item()), "warmup_s": t_warm,
-        "launch_shape": {"block": t["block"], "rays_per_thread": t["rays_per_thread"], "autotuned": True},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": abytes,
-                     "kernel": "k_adjoint_rec", "ms_per_launch": ms_adj, "rays_per_launch": n * sc.n_rays},
+        "roofline": roof,
     }
+    if not voxel:
+        out["launch_shape"] = {"block": t["block"], "rays_per_thread": t["rays_per_thread"], "autotuned": True}
+    return out
 
 
 def bench_quad(args, torch):
@@ -832,6 +853,9 @@ def main():
     ap.add_argument("--nuts-jitter", type=float, default=0.3, help="nuts: jitter of the super-chain starts (m)")
     ap.add_argument("--nuts-heights", action="store_true",
                     help="nuts: sample the heights instead of the latent CAR fields")
+    ap.add_argument("--nuts-voxel", action="store_true",
+                    help="nuts: under the paper's smoothed voxel model (--n-z levels, gamma 1 m, linearised "
+                         "around the truth) instead of the exact march")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the short hetero / grad128 / serve runs summarised after the headline line")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the one-job-at-a-time baseline")
