@@ -68,8 +68,8 @@ MEASURED_TRAFFIC = {
                             fetch_scale=262144 / 131088.5, write_kib=196608.0, write_scale=1.0),
     # k_vox_lik: FETCH_SIZE counts what leaves the L2 for the fabric, so hits
     # in the memory-side cache are included
-    "voxel64": dict(source_sha="6a1bdbb0e0348c61", fetch_kib=2419410.0, fetch_scale=262144 / 131093.3,
-                    write_kib=66329.5, write_scale=1.0),
+    "voxel64": dict(source_sha="f13683eefc9dc6a8", fetch_kib=2417941.5, fetch_scale=262144 / 131092.9,
+                    write_kib=67260.1, write_scale=1.0),
 }
 
 

@@ -109,12 +109,40 @@ __global__ __launch_bounds__(256) void k_vox_density(VoxParams<T> P) {
     const T rho1 = (T)P.rho1, ig = (T)P.inv_gamma, dz = (T)P.dz;
     const size_t V = (size_t)P.N * P.n_z;
     T *out = P.rhat + ((size_t)(c / kVoxLanes) * V + (size_t)col * P.n_z) * kVoxLanes + c % kVoxLanes;
+    // float32: the levels [klo, khi] outside which sigma_l saturates (to 1
+    // below, 0 above) on every live lane of the wavefront, with a margin of
+    // one level; there sigma_l is the constant vox_sigma would return, and
+    // the sum is the same bit for bit.  float64 evaluates every sigmoid.
+    int klo[S], khi[S];
+#pragma unroll
+    for (int l = 0; l < S; ++l) {
+        klo[l] = INT_MIN;
+        khi[l] = INT_MAX;
+        if constexpr (std::is_same<T, float>::value) {
+            const float lim = (float)P.n_z + 2.0f, w = kVoxSatF32 / ig;   // 30 gamma
+            float lo = -lim, hi = lim;   // lanes that are not live widen nothing
+            if (live) {
+                if (__builtin_isfinite(h[l])) {
+                    lo = floorf(fminf(fmaxf((h[l] - w) / dz - 0.5f, -2.0f), lim)) - 1.0f;
+                    hi = ceilf(fminf(fmaxf((h[l] + w) / dz - 0.5f, -2.0f), lim)) + 1.0f;
+                } else {   // evaluated everywhere, as vox_sigma would
+                    lo = -lim - 1.0f;
+                    hi = 2.0f * lim;
+                }
+            }
+            klo[l] = __builtin_amdgcn_readfirstlane((int)wave_min(lo));
+            khi[l] = __builtin_amdgcn_readfirstlane((int)wave_max(hi));
+        }
+    }
 #pragma unroll 2
     for (int k = 0; k < P.n_z; ++k) {
         const T z = ((T)k + T(0.5)) * dz;
         T acc = -rho1 * (T)P.floor_sig[k];
 #pragma unroll
-        for (int l = 0; l < S; ++l) acc += drho[l] * vox_sigma((z - h[l]) * ig);
+        for (int l = 0; l < S; ++l) {
+            const T sg = k < klo[l] ? T(1) : (k > khi[l] ? T(0) : vox_sigma((z - h[l]) * ig));
+            acc += drho[l] * sg;
+        }
         out[(size_t)k * kVoxLanes] = live ? acc * (T)P.inv_norm[k] : T(0);
     }
 }
