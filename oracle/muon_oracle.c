@@ -1360,24 +1360,23 @@ static void nuts_transition(orc_target_fn target, const void *ctx, size_t M, dou
                 lps = lpl;
             }
             logWs = logWs_new;
-            /* block bookkeeping: level j blocks hold 2^j consecutive leaves */
-            for (int j = 0; j <= depth; ++j) {
-                double *Rj = R + (size_t)j * M, *Fj = F + (size_t)j * M;
-                if ((i & ((1 << j) - 1)) == 0) {
-                    memset(Rj, 0, sizeof(double) * M);
-                    memcpy(Fj, pp, sizeof(double) * M);
-                }
-                for (size_t k = 0; k < M; ++k) Rj[k] += pp[k];
-            }
-            for (int j = 1; j <= depth && !(g_nuts_fault & 1); ++j) {
-                if (((i + 1) & ((1 << j) - 1)) != 0) continue;
+            /* block bookkeeping: a level-j block holds 2^j consecutive leaves;
+               its momentum sum is the sum of its two halves' sums, as in the
+               recursive tree (the level-0 block is the leaf itself) */
+            memcpy(R, pp, sizeof(double) * M);
+            memcpy(F, pp, sizeof(double) * M);
+            for (int j = 1; j <= depth; ++j) {
+                if (((i + 1) & ((1 << j) - 1)) != 0) break;   /* blocks complete from level 1 up */
                 /* a level-j block completed: halves A = saved sibling, B = the level j-1 block */
                 const size_t a = (size_t)(j - 1) * M;
-                if (turning3(sR + a, sF + a, sL + a, R + a, F + a, pp, im, M, tmp, &margin)) {
+                if (!(g_nuts_fault & 1) && turning3(sR + a, sF + a, sL + a, R + a, F + a, pp, im, M, tmp, &margin)) {
                     valid = 0;
                     turned_inside = 1;
                     break;
                 }
+                double *Rj = R + (size_t)j * M;
+                for (size_t k = 0; k < M; ++k) Rj[k] = sR[a + k] + R[a + k];
+                memcpy(F + (size_t)j * M, sF + a, sizeof(double) * M);
             }
             if (!valid) break;
             for (int j = 0; j < depth; ++j) {

@@ -69,12 +69,17 @@ __device__ __forceinline__ double im_at(const NutsParams<T> &P, size_t c, int k)
 // it and get the same answer.
 template <typename T>
 __device__ bool nuts_turning(const NutsParams<T> &P, size_t c, const double *rA, const double *aF, const double *aN,
-                             const double *rB, const double *bN, const double *bF, double *red) {
+                             const double *rB, const double *bN, const double *bF, double *red,
+                             double *rAB = nullptr, double *fAB = nullptr) {
     double d[6] = {0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < P.M; k += kNutsBlock) {
         const size_t o = c * P.M + k;
         const double im = im_at(P, c, k);
         const double r1 = rA[o] + rB[o], r2 = rA[o] + bN[o], r3 = aN[o] + rB[o];
+        if (rAB) {   // the merged block's momentum sum and first momentum
+            rAB[o] = r1;
+            fAB[o] = aF[o];
+        }
         d[0] += aF[o] * im * r1;
         d[1] += bF[o] * im * r1;
         d[2] += aF[o] * im * r2;
@@ -221,24 +226,19 @@ __global__ __launch_bounds__(kNutsBlock) void k_nuts_leap_fin(NutsParams<T> P, i
             P.xs[o + k] = xl[k];
             P.gs[o + k] = P.ge[s][o + k];
         }
-        const double p = pl[k];
-        for (int j = 0; j <= d; ++j) {
-            const size_t q = ((size_t)j * P.n + c) * P.M + k;
-            if ((i & ((1 << j) - 1)) == 0) {
-                P.R[q] = p;
-                P.F[q] = p;
-            } else {
-                P.R[q] += p;
-            }
-        }
+        // the level-0 block is the leaf itself
+        P.R[o + k] = pl[k];
+        P.F[o + k] = pl[k];
     }
     __syncthreads();
-    // blocks completed by this leaf: the halves of each must not turn
+    // blocks completed by this leaf, from level 1 up: the halves of each must
+    // not turn, and the block's momentum sum is the sum of its halves' sums
+    // (as in the recursive tree) and its first momentum its first half's
     bool turning = false;
     for (int j = 1; j <= d && !turning; ++j) {
-        if (((i + 1) & ((1 << j) - 1)) != 0) continue;
-        const size_t a = (size_t)(j - 1) * P.n * P.M;
-        turning = nuts_turning(P, c, P.sR + a, P.sF + a, P.sL + a, P.R + a, P.F + a, P.pe[s], red);
+        if (((i + 1) & ((1 << j) - 1)) != 0) break;
+        const size_t a = (size_t)(j - 1) * P.n * P.M, b = (size_t)j * P.n * P.M;
+        turning = nuts_turning(P, c, P.sR + a, P.sF + a, P.sL + a, P.R + a, P.F + a, P.pe[s], red, P.R + b, P.F + b);
     }
     if (turning) {
         if (threadIdx.x == 0) h.active = 0;
