@@ -70,15 +70,16 @@ __device__ __forceinline__ double im_at(const NutsParams<T> &P, size_t c, int k)
 template <typename T>
 __device__ bool nuts_turning(const NutsParams<T> &P, size_t c, const double *rA, const double *aF, const double *aN,
                              const double *rB, const double *bN, const double *bF, double *red,
-                             double *rAB = nullptr, double *fAB = nullptr) {
+                             double *rAB = nullptr, double *fAB = nullptr, double *lAB = nullptr) {
     double d[6] = {0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < P.M; k += kNutsBlock) {
         const size_t o = c * P.M + k;
         const double im = im_at(P, c, k);
         const double r1 = rA[o] + rB[o], r2 = rA[o] + bN[o], r3 = aN[o] + rB[o];
-        if (rAB) {   // the merged block's momentum sum and first momentum
+        if (rAB) {   // the merged block's momentum sum and first momentum (and last)
             rAB[o] = r1;
             fAB[o] = aF[o];
+            if (lAB) lAB[o] = bF[o];
         }
         d[0] += aF[o] * im * r1;
         d[1] += bF[o] * im * r1;
@@ -221,37 +222,41 @@ __global__ __launch_bounds__(kNutsBlock) void k_nuts_leap_fin(NutsParams<T> P, i
     }
     const T *xl = P.xe[s] + o;
     const double *pl = P.pe[s] + o;
+    const bool save0 = d > 0 && ((i + 1) & 1);
     for (int k = threadIdx.x; k < P.M; k += kNutsBlock) {
         if (flag == 2) {
             P.xs[o + k] = xl[k];
             P.gs[o + k] = P.ge[s][o + k];
         }
-        // the level-0 block is the leaf itself
-        P.R[o + k] = pl[k];
-        P.F[o + k] = pl[k];
+        // the level-0 block is the leaf itself; as the first half of its
+        // parent it goes straight to the saved halves
+        if (save0) {
+            P.sR[o + k] = pl[k];
+            P.sF[o + k] = pl[k];
+            P.sL[o + k] = pl[k];
+        } else {
+            P.R[o + k] = pl[k];
+            P.F[o + k] = pl[k];
+        }
     }
     __syncthreads();
     // blocks completed by this leaf, from level 1 up: the halves of each must
     // not turn, and the block's momentum sum is the sum of its halves' sums
-    // (as in the recursive tree) and its first momentum its first half's
+    // (as in the recursive tree) and its first momentum its first half's.  A
+    // block that is the first half of its parent is written to the saved
+    // halves (sum, first and last momentum), a second half or the whole
+    // subtree to R, F.
     bool turning = false;
     for (int j = 1; j <= d && !turning; ++j) {
         if (((i + 1) & ((1 << j) - 1)) != 0) break;
         const size_t a = (size_t)(j - 1) * P.n * P.M, b = (size_t)j * P.n * P.M;
-        turning = nuts_turning(P, c, P.sR + a, P.sF + a, P.sL + a, P.R + a, P.F + a, P.pe[s], red, P.R + b, P.F + b);
+        const bool save = j < d && (((i + 1) >> j) & 1);
+        turning = nuts_turning(P, c, P.sR + a, P.sF + a, P.sL + a, P.R + a, P.F + a, P.pe[s], red,
+                               (save ? P.sR : P.R) + b, (save ? P.sF : P.F) + b, save ? P.sL + b : nullptr);
     }
     if (turning) {
         if (threadIdx.x == 0) h.active = 0;
         return;
-    }
-    for (int j = 0; j < d; ++j) {
-        if (((i + 1) & ((1 << j) - 1)) != 0 || !(((i + 1) >> j) & 1)) continue;
-        const size_t a = (size_t)j * P.n * P.M;
-        for (int k = threadIdx.x; k < P.M; k += kNutsBlock) {
-            P.sR[a + o + k] = P.R[a + o + k];
-            P.sF[a + o + k] = P.F[a + o + k];
-            P.sL[a + o + k] = pl[k];
-        }
     }
     if (i != (1 << d) - 1) return;
     // the subtree is complete and valid: merge it into the tree
