@@ -1961,7 +1961,7 @@ mc_status grad_eval_latent(mc_problem *p, int n, const T *x, double *lp, T *gx, 
     HIP_TRY(p, hipGetLastError());
     mc_status s;
     if (p->n_ray > 0 && (s = lik_grad<T, S>(p, n, L.H, (unsigned long long *)p->gfix.p, st)) != MC_OK) return s;
-    hipLaunchKernelGGL((k_latent_finish<T, 512>), dim3(n), dim3(512), 0, st, L);
+    hipLaunchKernelGGL((k_latent_finish<T, S, 512>), dim3(n), dim3(512), 0, st, L);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
 }
@@ -1984,7 +1984,7 @@ mc_status grad_eval_latent_r(mc_problem *p, int n, const T *z, double *lp, T *gz
     HIP_TRY(p, hipGetLastError());
     mc_status s;
     if (p->n_ray > 0 && (s = lik_grad<T, S>(p, n, L.H, (unsigned long long *)p->gfix.p, st)) != MC_OK) return s;
-    hipLaunchKernelGGL((k_latent_finish<T, 512>), dim3(n), dim3(512), 0, st, L);
+    hipLaunchKernelGGL((k_latent_finish<T, S, 512>), dim3(n), dim3(512), 0, st, L);
     HIP_TRY(p, hipGetLastError());
     return MC_OK;
 }

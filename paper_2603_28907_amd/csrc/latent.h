@@ -122,33 +122,34 @@ __global__ void k_heights_to_latent(const T *H, T *x, const double *top64, int N
 // log(r (1 - r)) per surface (the flat prior's Jacobian in eta = logit r) and
 //   dlogp/deta_l = r (1 - r) (dlogL/dr_l + (d log det Q/dr)/2 + x_l' A x_l / 2) + 1 - 2 r,
 //   dlogL/dr_l = sum_i D_l,i (H_top - H_{l-1}) phi(w) (-w (dSigma11/dr) / (2 Sigma11)).
-template <typename T, int BLOCK>
+template <typename T, int S, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_latent_finish(LatentParams<T> P) {
     __shared__ double red[16];
     const size_t c = blockIdx.x;
     const int tid = threadIdx.x;
+    constexpr int S1 = S - 1, NA = S1 > 0 ? S1 : 1;   // free surfaces; array extent
     double llp = 0.0;
     if (P.has_lik)
         for (int t = tid; t < P.n_tiles; t += BLOCK) llp += P.partials[c * P.n_tiles + t];
-    double sl[kMaxSurfaces], rl[kMaxSurfaces], kr[kMaxSurfaces];
-    for (int l = 0; l < P.S1; ++l) {
-        const double *rc = P.rc ? P.rc + (c * P.S1 + l) * kRc : nullptr;
+    double sl[NA], rl[NA], kr[NA];
+#pragma unroll
+    for (int l = 0; l < S1; ++l) {
+        const double *rc = P.rc ? P.rc + (c * S1 + l) * kRc : nullptr;
         sl[l] = rc ? rc[kRcS] : P.s[l];
         rl[l] = rc ? rc[kRcR] : P.r[l];
         kr[l] = rc ? -rc[kRcDs11] / (2.0 * sl[l] * sl[l]) : 0.0;   // (dw/dr) / w
     }
-    double quadl[kMaxSurfaces] = {0, 0, 0, 0};   // x_l' Q_l x_l, this thread's nodes
-    double xaxl[kMaxSurfaces] = {0, 0, 0, 0};    // x_l' A x_l
-    double drl[kMaxSurfaces] = {0, 0, 0, 0};     // dlogL/dr_l
+    double quadl[NA] = {}, xaxl[NA] = {}, drl[NA] = {};   // x_l' Q_l x_l, x_l' A x_l, dlogL/dr_l of this thread's nodes
     const T *xc = P.x + c * (size_t)P.xs;
     for (int n = tid; n < P.N; n += BLOCK) {
         const int i = n / P.C, j = n - i * P.C;
         const int jr = j + 1 == P.C ? 0 : j + 1, jl = j == 0 ? P.C - 1 : j - 1;
         const int id = i + 1 == P.R ? 0 : i + 1, iu = i == 0 ? P.R - 1 : i - 1;
         const double b = P.top64[n];
-        double xv[kMaxSurfaces], qx[kMaxSurfaces], av[kMaxSurfaces], wv[kMaxSurfaces];
+        double xv[NA], qx[NA], av[NA], wv[NA];
         double a = 0.0;
-        for (int l = 0; l < P.S1; ++l) {
+#pragma unroll
+        for (int l = 0; l < S1; ++l) {
             const T *xl = xc + (size_t)l * P.N;
             xv[l] = (double)xl[n];
             const double nb = (double)xl[i * P.C + jr] + (double)xl[i * P.C + jl] + (double)xl[id * P.C + j] +
@@ -162,22 +163,24 @@ __global__ __launch_bounds__(BLOCK) void k_latent_finish(LatentParams<T> P) {
         }
         // chain rule, top layer first
         double D = 0.0;
-        for (int l = P.S1 - 1; l >= 0; --l) {
+#pragma unroll
+        for (int l = S1 - 1; l >= 0; --l) {
             const size_t o = c * P.SN + (size_t)l * P.N + n;
             const double gh = P.has_lik ? (double)(long long)P.gfix[o] * kGradFixInv : 0.0;
-            D = gh + (l < P.S1 - 1 ? std_cdf(-wv[l + 1]) * D : 0.0);
+            D = gh + (l < S1 - 1 ? std_cdf(-wv[l + 1]) * D : 0.0);
             const double phi = 0.39894228040143267794 * exp(-0.5 * wv[l] * wv[l]);
             const double dh = D * (b - av[l]) * phi;   // dlogL/dw_l
             P.gx[o] = (T)(dh / sl[l] - qx[l]);
             drl[l] += dh * wv[l] * kr[l];
         }
-        P.gx[c * P.SN + (size_t)P.S1 * P.N + n] = T(0);
+        P.gx[c * P.SN + (size_t)S1 * P.N + n] = T(0);
     }
     const double ll = block_sum<BLOCK>(llp, red);
     double prior = 0.0;
-    for (int l = 0; l < P.S1; ++l) {
+#pragma unroll
+    for (int l = 0; l < S1; ++l) {
         const double ql = block_sum<BLOCK>(quadl[l], red);
-        const double *rc = P.rc ? P.rc + (c * P.S1 + l) * kRc : nullptr;
+        const double *rc = P.rc ? P.rc + (c * S1 + l) * kRc : nullptr;
         prior += 0.5 * (rc ? rc[kRcLogdet] : P.logdet[l]) - 0.5 * ql - 0.5 * P.N * 1.83787706640934548356;   // log(2 pi)
         if (rc) {
             const double xax = block_sum<BLOCK>(xaxl[l], red);
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(BLOCK) void k_latent_finish(LatentParams<T> P) {
             const double r = rc[kRcR];
             prior += log(r * (1.0 - r));
             if (tid == 0)
-                P.gx[c * P.SN + (size_t)P.S1 * P.N + l] =
+                P.gx[c * P.SN + (size_t)S1 * P.N + l] =
                     (T)(r * (1.0 - r) * (dr + 0.5 * rc[kRcDlogdet] + 0.5 * xax) + (1.0 - 2.0 * r));
         }
     }
